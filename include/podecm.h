@@ -1,0 +1,166 @@
+/*
+ * podecm.h -- C ABI of the hyper-reduced (POD + ECM + geometrical
+ * transformation) microscale solve of Guo, Rokos & Veroy, arXiv 2307.16894.
+ *
+ * The library solves, for a batch of independent macroscopic points, the
+ * reduced RVE problem of Sec. 3.2 (eqs. forcevector_ecm and
+ * stiffnessmatrix_ecm) by Newton's method on the reduced coordinates
+ * (eq. red_newton), with the finite-strain J2 model of Appendix A at the ECM
+ * points, and returns the effective stress and stiffness of Sec. 3.3
+ * (eqs. eff_stress_1, tangent_problem_red, eff_stiffness_1).  The calls
+ * follow the paper's statement of the two-scale problem (Fig. 1 and
+ * Algorithm 1, online part): given Fbar and mu, with history, return Pbar
+ * and Abar.
+ *
+ * Conventions
+ * -----------
+ * - Every per-call and state buffer is device memory owned by the caller
+ *   (plain pointers).  The library owns only the ROM constants uploaded by
+ *   rom_load.  Nothing in rom_step allocates.
+ * - All device work is enqueued on the caller's stream and is asynchronous;
+ *   the only host synchronisation is inside rom_load (upload) and
+ *   rom_state_init (to report invalid shape parameters).
+ * - 2x2 tensors are stored row-major as [11, 12, 21, 22]; 4x4 tangents
+ *   A[(ij)(kl)] = dP_ij / dF_kl row-major over those index pairs.
+ * - Return value: ROM_OK or a negative ROM_E* code.  Per-point Newton
+ *   failures are not call errors; they are reported in status[].
+ */
+#ifndef PODECM_H
+#define PODECM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define ROM_OK           0
+#define ROM_EINVAL      -1  /* bad argument (null pointer, size out of range) */
+#define ROM_EFORMAT     -2  /* artifact malformed (magic, sizes, non-finite data, w_q <= 0) */
+#define ROM_EVERSION    -3  /* artifact version not supported */
+#define ROM_EHIP        -4  /* a HIP runtime call failed */
+#define ROM_EINVAL_MU   -5  /* some shape parameters give det F_mu <= 0 at an ECM point */
+#define ROM_EUNSUPPORTED -6 /* option combination not built */
+
+/* per-point status written by rom_step */
+#define ROM_ST_CONVERGED 0  /* ||f||_2 <= tol at the returned state */
+#define ROM_ST_MAXITER   1  /* iteration cap reached; nothing committed */
+#define ROM_ST_NONFINITE 2  /* non-finite residual; nothing committed */
+#define ROM_ST_BADMU     4  /* the point's shape parameters were rejected */
+
+/* contraction precision of the reduced tangent K (Sec. 3.2, eq. stiffnessmatrix_ecm) */
+#define ROM_DT_F64  0
+#define ROM_DT_F32  1
+#define ROM_DT_BF16 2
+
+/* execution form of rom_step */
+#define ROM_MODE_STAGED 0  /* one kernel per stage, host-enqueued Newton loop */
+#define ROM_MODE_FUSED  1  /* one persistent kernel, device-side Newton loop */
+
+typedef struct rom_model* rom_handle;
+
+typedef struct rom_opts {
+  double  tol;          /* absolute tolerance on ||f||_2 (default 1e-8) */
+  int32_t max_iter;     /* Newton evaluations per step, >= 1 (default 15) */
+  int32_t fixed_iters;  /* 1: make exactly max_iter evaluations, status from the last (parity mode) */
+  int32_t commit;       /* 1: converged points commit r and history */
+  int32_t contraction;  /* ROM_DT_*: precision of the K contraction; all else is FP64 */
+  int32_t mode;         /* ROM_MODE_* */
+  int32_t reserved[7];
+} rom_opts;
+
+/* Fill *o with the defaults above (mode FUSED when built, contraction F64). */
+int rom_default_opts(rom_opts* o);
+
+/*
+ * rom_load -- parse a ROM artifact (the output of the offline stage of
+ * Algorithm 1: ECM weights and points, parent gradients of the POD modes and
+ * of the auxiliary transformation modes at those points, material constants,
+ * mu -> c map) and upload it to `device`.
+ *   blob/bytes : host memory holding the artifact file; read only, not retained.
+ *   device     : HIP device ordinal; made current during the call.
+ *   out        : receives the handle; release with rom_free.
+ * Errors: ROM_EINVAL, ROM_EFORMAT (bad magic, truncated, non-finite values,
+ * a weight <= 0), ROM_EVERSION, ROM_EHIP.
+ */
+int rom_load(const void* blob, size_t bytes, int device, rom_handle* out);
+int rom_load_file(const char* path, int device, rom_handle* out);
+int rom_free(rom_handle h);
+
+/* Sizes of a loaded ROM: modes n, ECM points m, affine coefficients c, shape parameters per point. */
+int rom_info(rom_handle h, int32_t* n, int32_t* m, int32_t* c, int32_t* n_mu);
+
+/*
+ * State of a batch of macro points, in one caller-allocated device buffer:
+ * committed and trial reduced coordinates r, committed and trial history
+ * (F^pl in-plane, F^pl_33, xi per ECM point: the appendix's internal
+ * variables), the transformation cached at the ECM points, the last
+ * effective stress / stiffness, and Newton workspace.  rom_state_bytes gives
+ * its size (256-byte aligned fields); rom_state_offsets gives the byte offset
+ * of each field (ROM_FIELD_*), for checkpointing and inspection.
+ */
+#define ROM_FIELD_R_COMMITTED 0  /* f64 [batch][n] */
+#define ROM_FIELD_R_TRIAL     1  /* f64 [batch][n] */
+#define ROM_FIELD_H_COMMITTED 2  /* f64 [batch][6][m]: Fp11 Fp12 Fp21 Fp22 Fp33 xi, point fastest */
+#define ROM_FIELD_H_TRIAL     3  /* f64 [batch][6][m] */
+#define ROM_FIELD_TRANSFORM   4  /* f64 [batch][5][m]: F_mu^-1 (4), w_q |det F_mu| */
+#define ROM_FIELD_PBAR        5  /* f64 [batch][4]  last effective stress */
+#define ROM_FIELD_ABAR        6  /* f64 [batch][16] last effective stiffness */
+#define ROM_FIELD_MU_OK       7  /* i32 [batch] 1 if the shape parameters were accepted */
+#define ROM_NFIELDS           8
+int rom_state_bytes(rom_handle h, int32_t batch, size_t* bytes);
+int rom_state_offsets(rom_handle h, int32_t batch, size_t* offsets /* [ROM_NFIELDS] */);
+
+/*
+ * rom_state_init -- Algorithm 1 online, step 1: for each point evaluate the
+ * reduced auxiliary problem (exactly affine here: c(mu)), then F_mu, its
+ * inverse and det at every ECM point (Sec. 3.4); cache F_mu^-1 and
+ * w_q |det F_mu|.  Sets r = 0 and the virgin history (F^pl = I, xi = 0,
+ * Appendix A).
+ *   mu_dev    : f64 [batch][n_mu] device; read only.
+ *   state_dev : rom_state_bytes(h, batch) bytes of device memory.
+ * Synchronises `stream`.  Returns ROM_EINVAL_MU if any point has
+ * det F_mu <= 0 at an ECM point; such points get status ROM_ST_BADMU from
+ * rom_step and are never solved.  The other points are initialised normally.
+ */
+int rom_state_init(rom_handle h, int32_t batch, const double* mu_dev, void* state_dev, hipStream_t stream);
+
+/*
+ * rom_step -- Algorithm 1 online, step 2: Newton on the reduced coordinates
+ * (eq. red_newton) with the hyper-reduced force and stiffness
+ * (eqs. forcevector_ecm, stiffnessmatrix_ecm), from the committed state to
+ * the macroscopic deformation gradient Fbar (absolute, not an increment),
+ * then steps 3-5: effective stress and stiffness (eqs. eff_stress_1,
+ * tangent_problem_red, eff_stiffness_1) at the returned state, stored in the
+ * state.
+ *   Fbar_dev   : f64 [batch][4] device, in-plane Fbar (Fbar_33 = 1).
+ *   opts       : host pointer; NULL means rom_default_opts.
+ *   status_dev : i32 [batch] device out, ROM_ST_*.
+ *   iters_dev  : i32 [batch] device out, Newton evaluations made.
+ *   resnorm_dev: f64 [batch] device out, ||f||_2 at the returned state.
+ * The trial r and history are always written; they replace the committed
+ * ones only where opts->commit is set and the point converged, so a failed
+ * point can be retried with a smaller load step (Appendix A).
+ */
+int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_dev,
+             const rom_opts* opts, int32_t* status_dev, int32_t* iters_dev,
+             double* resnorm_dev, hipStream_t stream);
+
+/*
+ * rom_homogenized_stress_tangent -- effective stress Pbar (eq. eff_stress_1)
+ * and stiffness Abar (eqs. eff_stiffness_1, eff_stress_f11) of the last
+ * rom_step on this state; Abar uses K* = K at the returned state
+ * (Sec. 3.3).  Normalised by the cell area.
+ *   Pbar_dev : f64 [batch][4] device out.
+ *   Abar_dev : f64 [batch][16] device out, row (ij) column (kl).
+ */
+int rom_homogenized_stress_tangent(rom_handle h, int32_t batch, const void* state_dev,
+                                   double* Pbar_dev, double* Abar_dev, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

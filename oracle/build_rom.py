@@ -1,0 +1,153 @@
+"""Offline stage of Algorithm 1: build ROM artifacts from full-order solves.
+
+    python -m oracle.build_rom <name> [--workers K]
+
+Steps (Algorithm 1, offline): parent mesh; auxiliary transformation modes;
+training parameters from a scrambled Sobol design and seeded load paths;
+full-order solves collecting fluctuation and weighted-stress snapshots; POD of
+both; ECM on the products of the two bases; the artifact.  A JSON report
+beside the artifact records the settings, the POD spectra, the ECM residual
+and the ROM-vs-FOM error on held-out paths (eps_P of Sec. 4).
+
+Settings that the paper leaves open and that are chosen here: the number of
+weighted-stress modes L and the ECM stop rule (tolerance or a target point
+count m, whichever comes first), listed per ROM below.
+"""
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+import workloads
+from . import artifact, auxiliary, ecm, fem, fom, mesh as meshmod, pod
+from .rom import ROM
+
+MAT = (1.0, 0.3, 0.01, 0.05)  # E, nu, sigma_y0, H
+
+ROMS = {
+    # one centred void, mu = (a, b) in [0.15, 0.35]^2, ~1.2k T6
+    'onevoid_n20_m120': dict(kind=0, r0=0.25, nt=15, nr=10, n=20, L=7, m=120, eps=1e-3,
+                             n_mu=8, per_mu=3, path='monotone', steps=10, rho=(0.02, 0.05),
+                             seed=1000),
+    # same family, ~8k T6
+    'onevoid_n40_m400': dict(kind=0, r0=0.25, nt=40, nr=25, n=40, L=11, m=400, eps=1e-3,
+                             n_mu=16, per_mu=3, path='cyclic', steps=20, rho=(0.02, 0.08),
+                             seed=2000),
+}
+
+_G = {}
+
+
+def _geometry(spec):
+    if spec['kind'] == 0:
+        m = meshmod.one_void_cell(spec['r0'], spec['nt'], spec['nr'])
+    else:
+        m = meshmod.four_void_cell(spec['r0'], spec['nt'], spec['nr'])
+    space = fem.PeriodicSpace(m)
+    ax = auxiliary.AuxiliaryProblem(m, spec['kind'])
+    grad_modes = ax.gradients(ax.modes())  # (c, nq, 2, 2)
+    return m, space, grad_modes
+
+
+def _mu_coeff(spec, mu):
+    return auxiliary.coefficients(spec['kind'], mu, spec['r0'], spec.get('void_area'))
+
+
+def _fom_job(args):
+    spec, mu, path = args
+    m, space, grad_modes = _G['geom']
+    Fmu = auxiliary.transformation(grad_modes, _mu_coeff(spec, mu))
+    pr = fem.Problem(m, space, Fmu, MAT)
+    res = fom.solve_path(pr, path, tol=1e-10 * max(1.0, 1.0), want_W=True)
+    return np.array(res.w), np.array(res.W), np.array(res.Pbar), res.iters
+
+
+def _paths(spec, seed, count):
+    if spec['path'] == 'monotone':
+        return workloads.monotone_paths(seed, count, spec['steps'], spec['rho'])
+    return workloads.cyclic_paths(seed, count, spec['steps'], spec['rho'])
+
+
+def _training_mu(spec, seed, count):
+    if spec['kind'] == 0:
+        return workloads.one_void_training_mu(seed, count)
+    return workloads.four_void_training_mu(seed, count)
+
+
+def build(name, outdir, workers):
+    spec = dict(ROMS[name])
+    t0 = time.time()
+    geom = _geometry(spec)
+    _G['geom'] = geom
+    m, space, grad_modes = geom
+    print(f"[{name}] mesh: {m.nn} nodes, {m.ne} T6, {m.nq} points, {space.ndof} dofs", flush=True)
+    mus = _training_mu(spec, spec['seed'], spec['n_mu'])
+    paths = _paths(spec, spec['seed'] + 1, spec['n_mu'] * spec['per_mu'])
+    jobs = [(spec, mus[i // spec['per_mu']], paths[i]) for i in range(len(paths))]
+    with mp.get_context('fork').Pool(workers) as pool:
+        results = pool.map(_fom_job, jobs, chunksize=1)
+    print(f"[{name}] {len(jobs)} training solves done in {time.time() - t0:.1f}s", flush=True)
+    Sw = np.concatenate([r[0] for r in results]).T  # (ndof, ns)
+    SW = np.concatenate([r[1] for r in results]).T  # (4 nq, ns)
+    # POD of the fluctuations in V^p and of the weighted stress in L^2(parent)
+    Fid = auxiliary.transformation(grad_modes, np.zeros(grad_modes.shape[0]))
+    pr0 = fem.Problem(m, space, Fid, MAT)
+    MV = pod.v_gram(pr0)
+    Phi, lam_w = pod.pod(Sw, MV, spec['n'])
+    B, lam_W = pod.pod(SW, np.repeat(m.qw, 4), spec['L'])
+    Gfull = (pr0.Gop @ Phi).reshape(m.nq, 4, spec['n'])
+    Bq = B.reshape(m.nq, 4, spec['L'])
+    J = ecm.integrand_matrix(Gfull, Bq, spec['n'], spec['L'])
+    J = np.vstack([J, np.ones((1, m.nq))])  # constant integrand: parent area (build's addition)
+    idx, wq, hist = ecm.greedy(J, m.qw, spec['eps'], spec['m'])
+    print(f"[{name}] ECM: {idx.size} points, relative residual {hist[-1]:.3e}", flush=True)
+    order = np.argsort(idx)
+    idx, wq = idx[order], wq[order]
+    Gd = np.stack([g.reshape(m.nq, 4)[idx] for g in grad_modes], axis=-1)  # (m, 4, c)
+    path = os.path.join(outdir, name + '.rom')
+    n_mu = 2 if spec['kind'] == 0 else 8
+    artifact.write(path, spec['n'], idx.size, grad_modes.shape[0], spec['kind'], n_mu, MAT,
+                   spec['r0'], spec.get('void_area', 0.0), 1.0, wq, Gfull[idx], Gd, idx)
+    # ROM quality on held-out paths (not a parity check)
+    rom = ROM(path)
+    test_mu = (workloads.one_void_mu if spec['kind'] == 0 else workloads.four_void_mu)(spec['seed'] + 7, 4)
+    test_paths = _paths(spec, spec['seed'] + 8, 4)
+    with mp.get_context('fork').Pool(workers) as pool:
+        ref = pool.map(_fom_job, [(spec, test_mu[i], test_paths[i]) for i in range(4)])
+    errs = []
+    for i in range(4):
+        out = rom.run_path(test_mu[i], test_paths[i])
+        Pr = np.array([o['Pbar'] for o in out])
+        Pf = ref[i][2].reshape(-1, 4)
+        errs.append(float(np.sum(np.linalg.norm(Pr - Pf, axis=1)) / np.sum(np.linalg.norm(Pf, axis=1))))
+    report = dict(name=name, spec={k: (list(v) if isinstance(v, tuple) else v) for k, v in spec.items()},
+                  mesh=dict(nodes=m.nn, elements=m.ne, points=m.nq, dofs=space.ndof),
+                  snapshots=int(Sw.shape[1]), pod_w_energy_kept=float(lam_w[:spec['n']].sum() / lam_w[lam_w > 0].sum()),
+                  pod_W_energy_kept=float(lam_W[:spec['L']].sum() / lam_W[lam_W > 0].sum()),
+                  ecm_points=int(idx.size), ecm_residual=float(hist[-1]), ecm_weight_sum=float(wq.sum()),
+                  parent_area=float(m.qw.sum()), heldout_eps_P=errs,
+                  fom_iters_mean=float(np.mean([np.mean(r[3]) for r in results])),
+                  build_seconds=time.time() - t0)
+    with open(os.path.join(outdir, name + '.json'), 'w') as fh:
+        json.dump(report, fh, indent=1)
+    print(json.dumps(report, indent=1), flush=True)
+    return path
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument('names', nargs='+')
+    ap.add_argument('--out', default=os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 'roms'))
+    ap.add_argument('--workers', type=int, default=min(8, os.cpu_count() or 1))
+    a = ap.parse_args(argv)
+    os.makedirs(a.out, exist_ok=True)
+    for n in a.names:
+        build(n, a.out, a.workers)
+
+
+if __name__ == '__main__':
+    sys.exit(main())

@@ -1,0 +1,119 @@
+"""Hyper-reduced online solve (Sec. 3.2-3.3, Algorithm 1 online).
+
+For one macro point with shape parameters mu and committed history:
+
+1. c(mu) and, at every ECM point q, F_mu = I + sum_k c_k grad dhat_k,
+   F_mu^-1 and det F_mu (eq. reduced_aux_problem and the text after it);
+2. Newton on the reduced coordinates r (the paper's a), eq. red_newton, with
+   the hyper-reduced force and stiffness of eqs. forcevector_ecm and
+   stiffnessmatrix_ecm:
+       f_i  = sum_q w_q (grad phi_i F_mu^-1) : P(F_q) |det F_mu|
+       K_ij = sum_q w_q (grad phi_i F_mu^-1) : A(F_q) : (grad phi_j F_mu^-1) |det F_mu|
+   with F_q = Fbar + (sum_n r_n grad phi_n) F_mu^-1;
+3. effective stress by the ECM rule, eq. eff_stress_1;
+4. the four tangent problems K* q = b, eq. tangent_problem_red, and the
+   effective stiffness, eqs. eff_stiffness_1 and eff_stress_f11.
+
+Readings taken (the paper is silent): the initial guess is the previous
+converged r; no line search; convergence when ||f||_2 <= tol (absolute).
+One Newton iteration is one evaluation of (f, K); the loop stops at the
+first evaluation that satisfies the tolerance, so the returned state, stress
+and K* belong to the returned r.  In fixed-iteration mode exactly max_iter
+evaluations are made (updating r after all but the last) and the status is
+decided by the last one; this mode exists so that two implementations can be
+compared along the same Newton map.
+
+Status codes: 0 converged, 1 iteration cap, 2 non-finite residual.
+"""
+import numpy as np
+
+from . import artifact, auxiliary, material
+from .fem import right_map
+
+
+class ROM:
+    def __init__(self, path=None, data=None):
+        d = artifact.read(path) if data is None else data
+        self.__dict__.update(d)
+
+    # -- step 1 -------------------------------------------------------------
+    def transformation(self, mu):
+        c = auxiliary.coefficients(self.kind, mu, self.r0, self.void_area)
+        Fmu = np.einsum('k,qak->qa', c, self.Gd).reshape(self.m, 2, 2)
+        Fmu[:, 0, 0] += 1.0
+        Fmu[:, 1, 1] += 1.0
+        J = np.linalg.det(Fmu)
+        return np.linalg.inv(Fmu), J
+
+    # -- step 2 -------------------------------------------------------------
+    def evaluate(self, r, Fbar, hist, Finv, J):
+        H = (self.G @ r).reshape(self.m, 2, 2)  # sum_n r_n grad phi_n at the points
+        F = Fbar[None] + H @ Finv
+        P, A, Fp, Fp33, xi, gam = material.j2_point(F, *hist, self.mat)
+        wJ = self.w * np.abs(J)
+        T = right_map(Finv)  # vec(Hp F_mu^-1) = T vec(Hp)
+        B = T @ self.G  # mapped mode gradients (m, 4, n)
+        f = np.einsum('qai,qa->i', B, P.reshape(self.m, 4) * wJ[:, None])
+        A4 = A.reshape(self.m, 4, 4)
+        K = np.einsum('qai,qab,qbj->ij', B, A4 * wJ[:, None, None], B)
+        return dict(f=f, K=K, P=P, A=A4, B=B, wJ=wJ, hist=(Fp, Fp33, xi), gamma=gam)
+
+    def newton(self, r0, hist, Fbar, Finv, J, tol=1e-8, max_iter=25, fixed=False):
+        r = np.array(r0, dtype=np.float64)
+        status = 1
+        for it in range(max_iter):
+            ev = self.evaluate(r, Fbar, hist, Finv, J)
+            res = np.linalg.norm(ev['f'])
+            if not np.isfinite(res):
+                return r, ev, 2, it + 1, res
+            last = it == max_iter - 1
+            if fixed:
+                if last:
+                    status = 0 if res <= tol else 1
+                    return r, ev, status, it + 1, res
+            elif res <= tol:
+                return r, ev, 0, it + 1, res
+            elif last:
+                return r, ev, 1, it + 1, res
+            r = r - np.linalg.solve(ev['K'], ev['f'])
+        raise AssertionError("unreachable")
+
+    # -- steps 3, 4 ---------------------------------------------------------
+    def effective(self, ev):
+        wJ, A4, B = ev['wJ'], ev['A'], ev['B']
+        Pbar = np.einsum('q,qa->a', wJ, ev['P'].reshape(self.m, 4)) / self.cell_area
+        Abar = np.zeros((4, 4))
+        for kl in range(4):
+            E = np.zeros(4)
+            E[kl] = 1.0
+            # right-hand side b_i = -(sum_q w_q (grad phi_i F^-1) : A |J|) : E_kl
+            b = -np.einsum('qai,qab,b->i', B, A4 * wJ[:, None, None], E)
+            q = np.linalg.solve(ev['K'], b)
+            dF = E[None, :] + B @ q  # E_kl + grad q_kl F^-1 at each point
+            Abar[:, kl] = np.einsum('q,qab,qb->a', wJ, A4, dF) / self.cell_area
+        return Pbar, Abar
+
+    def step(self, r0, hist, Fbar, Finv, J, tol=1e-8, max_iter=25, fixed=False):
+        r, ev, status, iters, res = self.newton(r0, hist, Fbar, Finv, J, tol, max_iter, fixed)
+        Pbar, Abar = self.effective(ev)
+        return dict(r=r, hist=ev['hist'], status=status, iters=iters, resnorm=res,
+                    Pbar=Pbar, Abar=Abar)
+
+    def virgin(self):
+        return material.virgin_history((self.m,))
+
+    def run_path(self, mu, Fbar_path, tol=1e-8, max_iter=25, fixed=False, commit=True):
+        """Solve a whole load path from the virgin state; commit converged steps."""
+        Finv, J = self.transformation(mu)
+        if np.any(J <= 0):
+            raise ValueError("invalid shape parameters: det F_mu <= 0")
+        hist = self.virgin()
+        r = np.zeros(self.n)
+        out = []
+        for Fb in Fbar_path:
+            s = self.step(r, hist, np.asarray(Fb, dtype=np.float64), Finv, J, tol, max_iter, fixed)
+            out.append(s)
+            if commit and s['status'] == 0:
+                hist = s['hist']
+                r = s['r']
+        return out

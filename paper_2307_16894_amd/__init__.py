@@ -1,0 +1,144 @@
+"""Python binding of libpodecm (the HIP hyper-reduced RVE solve).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  Device buffers are torch tensors (torch is used for device
+memory and streams); the functions take and return raw pointers through the
+C ABI declared in include/podecm.h, under the same names.
+
+The library must be built (``python -m paper_2307_16894_amd.build``); there is
+no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, 'libpodecm.so')
+
+ROM_OK = 0
+ROM_EINVAL = -1
+ROM_EFORMAT = -2
+ROM_EVERSION = -3
+ROM_EHIP = -4
+ROM_EINVAL_MU = -5
+ROM_EUNSUPPORTED = -6
+
+ST_CONVERGED = 0
+ST_MAXITER = 1
+ST_NONFINITE = 2
+ST_BADMU = 4
+
+DT_F64, DT_F32, DT_BF16 = 0, 1, 2
+MODE_STAGED, MODE_FUSED = 0, 1
+
+FIELD_R_COMMITTED, FIELD_R_TRIAL, FIELD_H_COMMITTED, FIELD_H_TRIAL = 0, 1, 2, 3
+FIELD_TRANSFORM, FIELD_PBAR, FIELD_ABAR, FIELD_MU_OK = 4, 5, 6, 7
+NFIELDS = 8
+
+EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_info', 'rom_state_bytes',
+           'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent']
+
+
+class RomError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what} failed with code {code}")
+        self.code = code
+
+
+class rom_opts(ctypes.Structure):
+    _fields_ = [('tol', ctypes.c_double), ('max_iter', ctypes.c_int32), ('fixed_iters', ctypes.c_int32),
+                ('commit', ctypes.c_int32), ('contraction', ctypes.c_int32), ('mode', ctypes.c_int32),
+                ('reserved', ctypes.c_int32 * 7)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpodecm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2307_16894_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        L.rom_default_opts.argtypes = [ctypes.POINTER(rom_opts)]
+        L.rom_load.argtypes = [vp, sz, ctypes.c_int, ctypes.POINTER(vp)]
+        L.rom_load_file.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(vp)]
+        L.rom_free.argtypes = [vp]
+        L.rom_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
+        L.rom_state_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        L.rom_state_offsets.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        L.rom_state_init.argtypes = [vp, i32, vp, vp, vp]
+        L.rom_step.argtypes = [vp, i32, vp, vp, ctypes.POINTER(rom_opts), vp, vp, vp, vp]
+        L.rom_homogenized_stress_tangent.argtypes = [vp, i32, vp, vp, vp, vp]
+        for name in EXPORTS:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != ROM_OK:
+        raise RomError(code, what)
+    return code
+
+
+def rom_default_opts(**kw):
+    o = rom_opts()
+    _check(lib().rom_default_opts(ctypes.byref(o)), 'rom_default_opts')
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def rom_load(blob, device=0):
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    _check(lib().rom_load(buf, len(blob), device, ctypes.byref(h)), 'rom_load')
+    return h
+
+
+def rom_load_file(path, device=0):
+    h = ctypes.c_void_p()
+    _check(lib().rom_load_file(os.fsencode(path), device, ctypes.byref(h)), 'rom_load_file')
+    return h
+
+
+def rom_free(h):
+    _check(lib().rom_free(h), 'rom_free')
+
+
+def rom_info(h):
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().rom_info(h, *[ctypes.byref(x) for x in v]), 'rom_info')
+    return dict(n=v[0].value, m=v[1].value, c=v[2].value, n_mu=v[3].value)
+
+
+def rom_state_bytes(h, batch):
+    s = ctypes.c_size_t()
+    _check(lib().rom_state_bytes(h, batch, ctypes.byref(s)), 'rom_state_bytes')
+    return s.value
+
+
+def rom_state_offsets(h, batch):
+    arr = (ctypes.c_size_t * NFIELDS)()
+    _check(lib().rom_state_offsets(h, batch, arr), 'rom_state_offsets')
+    return list(arr)
+
+
+def rom_state_init(h, batch, mu_ptr, state_ptr, stream):
+    """Returns ROM_OK or ROM_EINVAL_MU (points with det F_mu <= 0 are flagged)."""
+    code = lib().rom_state_init(h, batch, mu_ptr, state_ptr, stream)
+    if code not in (ROM_OK, ROM_EINVAL_MU):
+        raise RomError(code, 'rom_state_init')
+    return code
+
+
+def rom_step(h, batch, Fbar_ptr, state_ptr, opts, status_ptr, iters_ptr, res_ptr, stream):
+    return _check(lib().rom_step(h, batch, Fbar_ptr, state_ptr, ctypes.byref(opts) if opts is not None else None,
+                                 status_ptr, iters_ptr, res_ptr, stream), 'rom_step')
+
+
+def rom_homogenized_stress_tangent(h, batch, state_ptr, Pbar_ptr, Abar_ptr, stream):
+    return _check(lib().rom_homogenized_stress_tangent(h, batch, state_ptr, Pbar_ptr, Abar_ptr, stream),
+                  'rom_homogenized_stress_tangent')

@@ -1,0 +1,78 @@
+// Shared definitions of the ROM library: the loaded model, the state layout
+// and small device helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/podecm.h"
+#include "j2_device.h"
+
+#define ROM_NMAX 128       // largest supported number of modes n
+#define ROM_ALIGN 256
+
+// Loaded ROM (Algorithm 1, offline output) resident on one device.
+struct rom_model {
+  int device;
+  int n, m, c, kind, n_mu;
+  int npad;              // n rounded up to a multiple of 16
+  double E, nu, sy0, H, r0, void_area, cell_area;
+  J2Params mp;
+  double* w;    // [m] ECM weights
+  double* Gt;   // [n][4][m] mode gradients, point fastest (per-lane kinematics)
+  double* Gq;   // [m][4][npad] mode gradients, mode fastest, zero padded (contractions)
+  double* Gd;   // [c][4][m] transformation-mode gradients, point fastest
+  float* Gq32;  // [m][4][npad] FP32 copy of Gq
+  uint16_t* Gq16;  // [m][4][npad] BF16 copy of Gq
+};
+
+// Internal state fields (public ones first, same numbering as ROM_FIELD_*).
+enum {
+  F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK,
+  F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT,
+  F_D, F_W, F_K, F_F, F_PIV,
+  F_NFIELDS
+};
+
+struct StateLayout {
+  size_t off[F_NFIELDS];
+  size_t total;
+};
+
+static inline size_t rom_align_up(size_t x) { return (x + ROM_ALIGN - 1) / ROM_ALIGN * ROM_ALIGN; }
+
+static inline StateLayout rom_state_layout(const rom_model* h, size_t P) {
+  const size_t n = h->n, m = h->m;
+  size_t sz[F_NFIELDS];
+  sz[F_RC] = P * n * 8;
+  sz[F_RT] = P * n * 8;
+  sz[F_HC] = P * 6 * m * 8;
+  sz[F_HT] = P * 6 * m * 8;
+  sz[F_TMU] = P * 5 * m * 8;
+  sz[F_PBAR] = P * 4 * 8;
+  sz[F_ABAR] = P * 16 * 8;
+  sz[F_MUOK] = P * 4;
+  sz[F_DONE] = P * 4;
+  sz[F_STATUS] = P * 4;
+  sz[F_ITERS] = P * 4;
+  sz[F_RES] = P * 8;
+  sz[F_COUNT] = 64;
+  sz[F_D] = P * 16 * m * 8;
+  sz[F_W] = P * 4 * m * 8;
+  sz[F_K] = P * n * n * 8;
+  sz[F_F] = P * n * 8;
+  sz[F_PIV] = P * n * 4;
+  StateLayout L;
+  size_t o = 0;
+  for (int i = 0; i < F_NFIELDS; ++i) {
+    L.off[i] = o;
+    o += rom_align_up(sz[i]);
+  }
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+static inline T* field(void* base, const StateLayout& L, int f) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + L.off[f]);
+}

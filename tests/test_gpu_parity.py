@@ -1,0 +1,99 @@
+"""GPU parity: the HIP solve against the FP64 oracle on the same seeded inputs.
+
+Parity runs in fixed-iteration mode (both sides make the same number of
+Newton evaluations, so they follow the same Newton map to rounding) and
+compares, after every load step, the trial reduced coordinates, the status,
+the effective stress and stiffness, and the committed history.  Tolerance:
+1e-10 relative to the largest entry of each compared quantity (FP64 path).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle.rom import ROM
+from tests.conftest import rom_path
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    scale = max(np.abs(b).max(), 1e-300)
+    return float(np.abs(a - b).max() / scale)
+
+
+def oracle_path(rom, mu, path, max_iter, fixed, tol=1e-8):
+    return rom.run_path(mu, path, tol=tol, max_iter=max_iter, fixed=fixed)
+
+
+def _run_gpu(name, mu, paths, mode, max_iter, fixed, record_hist=True):
+    from paper_2307_16894_amd import batch as B
+    from paper_2307_16894_amd import rom_default_opts
+    rb = B.RomBatch(rom_path(name), mu)
+    P, K = paths.shape[0], paths.shape[1]
+    out = []
+    for k in range(K):
+        print(f"[gpu] {name} mode={mode} step {k}", flush=True)
+        o = rom_default_opts(max_iter=max_iter, fixed_iters=int(fixed), mode=mode)
+        st, it, rn = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), o)
+        torch.cuda.synchronize()
+        rec = dict(status=st.cpu().numpy().copy(), iters=it.cpu().numpy().copy(), res=rn.cpu().numpy().copy(),
+                   r=rb.r(trial=True).cpu().numpy().copy(), Pbar=rb.Pbar.cpu().numpy().copy(),
+                   Abar=rb.Abar.cpu().numpy().copy())
+        if record_hist:
+            rec['hist'] = rb.history().cpu().numpy().copy()
+        out.append(rec)
+    rb.close()
+    return out
+
+
+@pytest.mark.parametrize("mode", [0])
+def test_fixed_iteration_parity_onevoid_n20(gpu, mode):
+    name = 'onevoid_n20_m120'
+    P, K = 16, 10
+    mu = workloads.one_void_mu(0, 64)[:P]
+    paths = workloads.monotone_paths(0, 64, 10)[:P]
+    g = _run_gpu(name, mu, paths, mode, max_iter=6, fixed=True)
+    rom = ROM(rom_path(name))
+    for p in range(P):
+        ref = oracle_path(rom, mu[p], paths[p], max_iter=6, fixed=True)
+        hist = rom.virgin()
+        for k in range(K):
+            s = ref[k]
+            assert g[k]['status'][p] == s['status'], (p, k)
+            assert g[k]['iters'][p] == s['iters']
+            assert rel_err(g[k]['r'][p], s['r']) < TOL, (p, k, rel_err(g[k]['r'][p], s['r']))
+            assert rel_err(g[k]['Pbar'][p], s['Pbar']) < TOL, (p, k)
+            assert rel_err(g[k]['Abar'][p], s['Abar'].reshape(-1)) < TOL, (p, k)
+            if s['status'] == 0:
+                hist = s['hist']
+            Fp, Fp33, xi = hist
+            gh = g[k]['hist'][p]
+            assert rel_err(gh[0:4].T.reshape(-1, 2, 2), Fp) < TOL
+            assert rel_err(gh[4], Fp33) < TOL
+            if np.abs(xi).max() > 0:
+                assert rel_err(gh[5], xi) < TOL
+            else:
+                assert np.abs(gh[5]).max() == 0.0
+
+
+def test_converged_path_onevoid_n20(gpu):
+    """Plain Newton to 1e-8: every step converges, same iteration counts and
+    effective stress as the oracle (to the Newton tolerance)."""
+    name = 'onevoid_n20_m120'
+    P = 64
+    mu = workloads.one_void_mu(0, P)
+    paths = workloads.monotone_paths(0, P, 10)
+    g = _run_gpu(name, mu, paths, 0, max_iter=15, fixed=False, record_hist=False)
+    rom = ROM(rom_path(name))
+    for p in range(0, P, 8):
+        ref = oracle_path(rom, mu[p], paths[p], max_iter=15, fixed=False)
+        for k in range(10):
+            assert g[k]['status'][p] == 0 and ref[k]['status'] == 0
+            assert abs(int(g[k]['iters'][p]) - ref[k]['iters']) <= 1
+            assert rel_err(g[k]['Pbar'][p], ref[k]['Pbar']) < 1e-6
+    assert all((rec['status'] == 0).all() for rec in g)

@@ -1,0 +1,90 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module generates random inputs only (shape parameters and macroscopic
+deformation-gradient paths); it contains none of the method's arithmetic.
+Every draw uses numpy.random.Generator(PCG64(seed)).
+
+Load paths follow the paper's practice of sampling the symmetric stretch
+Ubar (Sec. 4: Fbar = Rbar Ubar, only Ubar needs sampling) and applying it with
+an amplitude function beta(k):
+
+* monotone: Fbar_k = I + (k / K) E, k = 1..K;
+* cyclic:   beta rises 0 -> 1 over K/2 steps and falls back to 0
+            (load / unload, as in the paper's training paths).
+
+E is symmetric with a uniformly random direction in (E_xx, E_yy, E_xy)
+space, normalised to the Frobenius norm rho of the 2x2 tensor.
+"""
+import numpy as np
+from scipy.stats import qmc
+
+ONE_VOID_MU = (0.15, 0.35)          # semi-axes a, b of the elliptical void
+FOUR_VOID_KAPPA = (1.0, 1.5)        # aspect ratio b/a per void
+FOUR_VOID_THETA = (0.0, np.pi)      # orientation per void
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _directions(g, P):
+    d = g.uniform(-1.0, 1.0, size=(P, 3))
+    E = np.zeros((P, 2, 2))
+    E[:, 0, 0] = d[:, 0]
+    E[:, 1, 1] = d[:, 1]
+    E[:, 0, 1] = E[:, 1, 0] = d[:, 2]
+    E /= np.linalg.norm(E.reshape(P, 4), axis=1)[:, None, None]
+    return E
+
+
+def monotone_paths(seed, P, steps=10, rho=(0.02, 0.05)):
+    """(P, steps, 2, 2) monotone paths with |Fbar - I|_F <= rho_max."""
+    g = rng(seed)
+    E = _directions(g, P) * g.uniform(*rho, size=P)[:, None, None]
+    beta = np.arange(1, steps + 1) / steps
+    return np.eye(2)[None, None] + beta[None, :, None, None] * E[:, None]
+
+
+def cyclic_paths(seed, P, steps=20, rho=(0.02, 0.08)):
+    """(P, steps, 2, 2) load / unload paths with amplitude <= rho_max."""
+    g = rng(seed)
+    E = _directions(g, P) * g.uniform(*rho, size=P)[:, None, None]
+    half = steps // 2
+    beta = np.concatenate([np.arange(1, half + 1) / half,
+                           1.0 - np.arange(1, steps - half + 1) / (steps - half)])
+    return np.eye(2)[None, None] + beta[None, :, None, None] * E[:, None]
+
+
+def one_void_mu(seed, P):
+    return rng(seed).uniform(*ONE_VOID_MU, size=(P, 2))
+
+
+def four_void_mu(seed, P):
+    g = rng(seed)
+    mu = np.empty((P, 8))
+    mu[:, 0::2] = g.uniform(*FOUR_VOID_KAPPA, size=(P, 4))
+    mu[:, 1::2] = g.uniform(*FOUR_VOID_THETA, size=(P, 4))
+    return mu
+
+
+def sobol_points(seed, count, lo, hi):
+    """Scrambled Sobol samples in the box [lo, hi] (training designs)."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    s = qmc.Sobol(d=lo.size, scramble=True, seed=rng(seed))
+    return qmc.scale(s.random(count), lo, hi)
+
+
+def one_void_training_mu(seed, count):
+    return sobol_points(seed, count, [ONE_VOID_MU[0]] * 2, [ONE_VOID_MU[1]] * 2)
+
+
+def four_void_training_mu(seed, count):
+    lo = [FOUR_VOID_KAPPA[0], FOUR_VOID_THETA[0]] * 4
+    hi = [FOUR_VOID_KAPPA[1], FOUR_VOID_THETA[1]] * 4
+    return sobol_points(seed, count, lo, hi)
+
+
+def uneven_steps(seed, P, lo=5, hi=40):
+    """Per-point step counts, uniform in [lo, hi]."""
+    return rng(seed).integers(lo, hi + 1, size=P)
