@@ -160,6 +160,17 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
 int rom_homogenized_stress_tangent(rom_handle h, int32_t batch, const void* state_dev,
                                    double* Pbar_dev, double* Abar_dev, hipStream_t stream);
 
+/*
+ * Measurement support.  While enabled, rom_step records a HIP event pair on
+ * the caller's stream around every launch of its dominant kernel (the
+ * reduced-tangent contraction of eq. stiffnessmatrix_ecm in the staged form;
+ * the whole Newton kernel in the fused form).  rom_timing_read waits for the
+ * recorded events and returns the summed kernel time and the number of
+ * launches since the last enable; it is meant for benchmarks, not hot loops.
+ */
+int rom_timing_enable(rom_handle h, int enable);
+int rom_timing_read(rom_handle h, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,4 +80,5 @@ def solve_path(problem, Fbar_path, tol=1e-10, max_iter=25, want_tangent=False,
             out.Abar.append(problem.effective_stiffness(ev, _solve))
         if want_W:
             out.W.append(ev['W'].reshape(-1).copy())
+    out.hist = hist  # committed history after the last step
     return out

@@ -44,7 +44,7 @@ def pod(S, M, n):
     lam, V = np.linalg.eigh(C)
     order = np.argsort(lam)[::-1]
     lam, V = lam[order], V[:, order]
-    if n > np.sum(lam > lam[0] * 1e-24):
+    if n > np.sum(lam > lam[0] * 1e-13):  # below this the Gram eigenvalues are rounding noise
         raise ValueError("requested more modes than the snapshot rank")
     Phi = S @ (V[:, :n] / np.sqrt(lam[:n]))
     # one re-orthonormalisation pass (Cholesky of the Gram matrix)

@@ -35,7 +35,8 @@ FIELD_TRANSFORM, FIELD_PBAR, FIELD_ABAR, FIELD_MU_OK = 4, 5, 6, 7
 NFIELDS = 8
 
 EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_info', 'rom_state_bytes',
-           'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent']
+           'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent',
+           'rom_timing_enable', 'rom_timing_read']
 
 
 class RomError(RuntimeError):
@@ -71,6 +72,8 @@ def lib():
         L.rom_state_init.argtypes = [vp, i32, vp, vp, vp]
         L.rom_step.argtypes = [vp, i32, vp, vp, ctypes.POINTER(rom_opts), vp, vp, vp, vp]
         L.rom_homogenized_stress_tangent.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.rom_timing_enable.argtypes = [vp, ctypes.c_int]
+        L.rom_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -142,3 +145,15 @@ def rom_step(h, batch, Fbar_ptr, state_ptr, opts, status_ptr, iters_ptr, res_ptr
 def rom_homogenized_stress_tangent(h, batch, state_ptr, Pbar_ptr, Abar_ptr, stream):
     return _check(lib().rom_homogenized_stress_tangent(h, batch, state_ptr, Pbar_ptr, Abar_ptr, stream),
                   'rom_homogenized_stress_tangent')
+
+
+def rom_timing_enable(h, enable=True):
+    _check(lib().rom_timing_enable(h, int(bool(enable))), 'rom_timing_enable')
+
+
+def rom_timing_read(h):
+    """(summed milliseconds, launches) of the dominant kernel since enable."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().rom_timing_read(h, ctypes.byref(ms), ctypes.byref(n)), 'rom_timing_read')
+    return ms.value, n.value

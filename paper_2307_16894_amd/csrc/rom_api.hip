@@ -41,6 +41,8 @@ int upload(T** dst, const std::vector<T>& src) {
 
 void release(rom_model* h) {
   if (!h) return;
+  for (int i = 0; i < 2 * h->cap; ++i) (void)hipEventDestroy(h->ev[i]);
+  free(h->ev);
   (void)hipFree(h->w);
   (void)hipFree(h->Gt);
   (void)hipFree(h->Gq);
@@ -52,7 +54,46 @@ void release(rom_model* h) {
 
 }  // namespace
 
+int rom_timing_mark(rom_model* h, int stop, hipStream_t s) {
+  if (!h->timing) return ROM_OK;
+  if (!stop && h->nev == h->cap) {
+    const int ncap = h->cap ? 2 * h->cap : 256;
+    hipEvent_t* ev = static_cast<hipEvent_t*>(realloc(h->ev, sizeof(hipEvent_t) * 2 * ncap));
+    if (!ev) return ROM_EINVAL;
+    h->ev = ev;
+    for (int i = 2 * h->cap; i < 2 * ncap; ++i)
+      if (hipEventCreate(&h->ev[i]) != hipSuccess) return ROM_EHIP;
+    h->cap = ncap;
+  }
+  const int slot = stop ? 2 * (h->nev - 1) + 1 : 2 * h->nev;
+  if (hipEventRecord(h->ev[slot], s) != hipSuccess) return ROM_EHIP;
+  if (!stop) ++h->nev;
+  return ROM_OK;
+}
+
 extern "C" {
+
+int rom_timing_enable(rom_handle h, int enable) {
+  if (!h) return ROM_EINVAL;
+  h->timing = enable ? 1 : 0;
+  h->nev = 0;
+  return ROM_OK;
+}
+
+int rom_timing_read(rom_handle h, double* total_ms, int64_t* launches) {
+  if (!h || !total_ms || !launches) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  double tot = 0.0;
+  for (int i = 0; i < h->nev; ++i) {
+    if (hipEventSynchronize(h->ev[2 * i + 1]) != hipSuccess) return ROM_EHIP;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) != hipSuccess) return ROM_EHIP;
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = h->nev;
+  return ROM_OK;
+}
 
 int rom_default_opts(rom_opts* o) {
   if (!o) return ROM_EINVAL;

@@ -24,7 +24,15 @@ struct rom_model {
   double* Gd;   // [c][4][m] transformation-mode gradients, point fastest
   float* Gq32;  // [m][4][npad] FP32 copy of Gq
   uint16_t* Gq16;  // [m][4][npad] BF16 copy of Gq
+  // kernel timing (measurement support)
+  int timing;
+  int nev;                 // event pairs recorded since enable
+  int cap;                 // event pairs allocated
+  hipEvent_t* ev;          // [2 * cap]
 };
+
+// Record the start / stop event of a timed launch; no-ops unless enabled.
+int rom_timing_mark(rom_model* h, int stop, hipStream_t s);
 
 // Internal state fields (public ones first, same numbering as ROM_FIELD_*).
 enum {

@@ -3,5 +3,5 @@
 #include "rom_common.h"
 
 int rom_fused_setup();
-int rom_launch_step_fused(const rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
+int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
                           int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s);

@@ -4,5 +4,5 @@
 
 int rom_staged_setup();
 int rom_launch_state_init(const rom_model* h, int P, const double* mu, void* state, hipStream_t s);
-int rom_launch_step_staged(const rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
+int rom_launch_step_staged(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
                            int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s);

@@ -578,7 +578,7 @@ int rom_launch_state_init(const rom_model* h, int P, const double* mu, void* sta
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 
-int rom_launch_step_staged(const rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
+int rom_launch_step_staged(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
                            int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
   const StateLayout L = rom_state_layout(h, P);
   const int n = h->n, m = h->m;
@@ -602,7 +602,9 @@ int rom_launch_step_staged(const rom_model* h, int P, const double* Fbar, void* 
   const size_t solve_lds = (size_t)(n * n + n + 8) * 8 + (size_t)n * 4;
   for (int it = 0; it < o.max_iter; ++it) {
     k_eval<<<dim3((m + 63) / 64, P), 64, 0, s>>>(n, m, h->mp, h->Gt, Fbar, rt, hc, ht, tmu, done, D, W);
+    if (rom_timing_mark(h, 0, s) != ROM_OK) return ROM_EHIP;
     k_assemble<<<P, 256, 0, s>>>(n, h->npad, m, h->Gq, D, W, done, K, f);
+    if (rom_timing_mark(h, 1, s) != ROM_OK) return ROM_EHIP;
     k_solve<<<P, 256, solve_lds, s>>>(n, it, o.max_iter, o.fixed_iters, o.tol, K, f, piv, rt, done, status,
                                       iters, res);
   }

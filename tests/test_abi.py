@@ -1,0 +1,72 @@
+"""The C-ABI library loads and exports every symbol the header declares, and
+rom_load rejects malformed artifacts before touching a device (no GPU
+needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2307_16894_amd as L
+from tests.conftest import ROOT, rom_path
+
+HEADER = os.path.join(ROOT, 'include', 'podecm.h')
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r'^int (rom_\w+)\(', txt, flags=re.M)))
+
+
+def test_header_and_binding_agree():
+    assert declared() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    out = subprocess.run(['nm', '-D', '--defined-only', L.LIB_PATH], capture_output=True, text=True, check=True)
+    syms = set(re.findall(r' T (rom_\w+)', out.stdout))
+    for name in declared():
+        assert name in syms, name
+        assert getattr(lib, name) is not None
+
+
+def test_default_opts():
+    o = L.rom_default_opts()
+    assert o.tol == 1e-8 and o.max_iter == 15 and o.commit == 1 and o.fixed_iters == 0
+    assert o.contraction == L.DT_F64
+
+
+def _load_code(blob):
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(bytes(blob), max(len(blob), 1))
+    return L.lib().rom_load(buf, len(blob), 0, ctypes.byref(h))
+
+
+def test_rom_load_rejects_malformed_artifacts():
+    good = open(rom_path('onevoid_n20_m120'), 'rb').read()
+    assert _load_code(b'') == L.ROM_EFORMAT
+    assert _load_code(b'NOTAROM!' + good[8:]) == L.ROM_EFORMAT
+    assert _load_code(good[:-8]) == L.ROM_EFORMAT  # truncated
+    bad = bytearray(good)
+    bad[8:12] = np.array([2], dtype='<u4').tobytes()
+    assert _load_code(bad) == L.ROM_EVERSION
+    bad = bytearray(good)
+    bad[256:264] = np.array([-1.0]).tobytes()  # a non-positive ECM weight
+    assert _load_code(bad) == L.ROM_EFORMAT
+    bad = bytearray(good)
+    bad[264 + 8 * 5:264 + 8 * 6] = np.array([np.nan]).tobytes()
+    assert _load_code(bad) == L.ROM_EFORMAT
+    bad = bytearray(good)
+    bad[12:16] = np.array([1000], dtype='<u4').tobytes()  # n beyond the supported maximum
+    assert _load_code(bad) == L.ROM_EFORMAT
+
+
+def test_null_arguments():
+    lib = L.lib()
+    assert lib.rom_load(None, 0, 0, None) == L.ROM_EINVAL
+    assert lib.rom_state_bytes(None, 4, None) == L.ROM_EINVAL
+    assert lib.rom_step(None, 4, None, None, None, None, None, None, None) == L.ROM_EINVAL
+    assert lib.rom_free(None) == L.ROM_EINVAL

@@ -1,0 +1,128 @@
+"""Pins of the oracle's offline reduction and online hyper-reduced solve
+(Sec. 3): POD orthonormality and reconstruction, ECM exactness and
+positivity, and the reduced solve reproducing the full-order model when the
+basis is the full FE basis and the cubature is the full rule."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import artifact, auxiliary as aux, ecm, fem, fom, pod
+from oracle import mesh as M
+from oracle.rom import ROM
+
+MAT = (1.0, 0.3, 0.01, 0.05)
+
+
+def full_basis_rom(nt=2, nr=1):
+    """A 'ROM' whose modes are the FE basis functions and whose cubature is
+    the full rule: hyper-reduction is then the identity and the reduced
+    solve must equal the full-order solve."""
+    m = M.one_void_cell(0.25, nt, nr)
+    sp = fem.PeriodicSpace(m)
+    ax = aux.AuxiliaryProblem(m, 0)
+    gm = ax.gradients(ax.modes())
+    Gop = fem.gradient_operator(m, sp.node_dof, sp.ndof).toarray().reshape(m.nq, 4, sp.ndof)
+    Gd = np.stack([g.reshape(m.nq, 4) for g in gm], axis=-1)
+    data = dict(n=sp.ndof, m=m.nq, c=2, kind=0, n_mu=2, mat=MAT, r0=0.25, void_area=0.0, cell_area=1.0,
+                w=m.qw.copy(), G=Gop, Gd=Gd, src=np.arange(m.nq))
+    return m, sp, gm, data
+
+
+def test_full_basis_rom_reproduces_fom():
+    m, sp, gm, data = full_basis_rom()
+    rom = ROM(data=data)
+    mu = np.array([0.3, 0.21])
+    E = np.array([[0.003, 0.001], [0.001, -0.002]])
+    path = [np.eye(2) + k * E for k in range(1, 9)]
+    Fmu = aux.transformation(gm, aux.coefficients(0, mu, 0.25))
+    pr = fem.Problem(m, sp, Fmu, MAT)
+    ref = fom.solve_path(pr, path, tol=1e-11, want_tangent=True)
+    out = rom.run_path(mu, path, tol=1e-11)
+    assert sum(o['iters'] for o in out) > 10
+    for k in range(len(path)):
+        assert out[k]['status'] == 0
+        assert np.abs(out[k]['r'] - ref.w[k]).max() < 1e-10 * np.abs(ref.w[k]).max()
+        assert np.abs(out[k]['Pbar'] - ref.Pbar[k].reshape(-1)).max() < 1e-12
+        assert np.abs(out[k]['Abar'] - ref.Abar[k].reshape(4, 4)).max() < 1e-10 * np.abs(ref.Abar[k]).max()
+    assert out[-1]['hist'][2].max() > 0  # the path yields somewhere
+
+
+def test_parent_parameters_give_identity_transformation():
+    _, _, _, data = full_basis_rom()
+    Finv, J = ROM(data=data).transformation([0.25, 0.25])
+    assert np.abs(Finv - np.eye(2)).max() == 0.0 and np.abs(J - 1).max() == 0.0
+
+
+def test_rom_stiffness_symmetric_and_tangent_fd():
+    _, _, _, data = full_basis_rom()
+    rom = ROM(data=data)
+    mu = [0.22, 0.33]
+    Finv, J = rom.transformation(mu)
+    F1 = np.array([[1.006, 0.002], [0.0015, 0.996]])
+    s1 = rom.step(np.zeros(rom.n), rom.virgin(), F1, Finv, J, tol=1e-12)
+    F2 = F1 + np.array([[0.003, 0.001], [0.001, -0.002]])
+    s2 = rom.step(s1['r'], s1['hist'], F2, Finv, J, tol=1e-12)
+    ev = rom.evaluate(s2['r'], F2, s1['hist'], Finv, J)
+    assert np.abs(ev['K'] - ev['K'].T).max() < 1e-12 * np.abs(ev['K']).max()
+    h = 1e-6
+    Afd = np.zeros((4, 4))
+    for kl in range(4):
+        d = np.zeros(4)
+        d[kl] = h
+        sp_ = rom.step(s1['r'], s1['hist'], F2 + d.reshape(2, 2), Finv, J, tol=1e-13)
+        sm_ = rom.step(s1['r'], s1['hist'], F2 - d.reshape(2, 2), Finv, J, tol=1e-13)
+        Afd[:, kl] = (sp_['Pbar'] - sm_['Pbar']) / (2 * h)
+    assert np.abs(s2['Abar'] - Afd).max() < 1e-6 * np.abs(Afd).max()
+
+
+def test_pod_orthonormal_and_reconstructs_snapshots():
+    rng = np.random.default_rng(0)
+    N = 60
+    A = rng.normal(size=(N, N))
+    Mv = A @ A.T + N * np.eye(N)
+    S = rng.normal(size=(N, 5)) @ rng.normal(size=(5, 12))  # rank 5
+    Phi, lam = pod.pod(S, Mv, 5)
+    assert np.abs(Phi.T @ Mv @ Phi - np.eye(5)).max() < 1e-12
+    proj = Phi @ (Phi.T @ Mv @ S)
+    assert np.abs(proj - S).max() < 1e-10 * np.abs(S).max()
+    # the POD error of the leading modes equals the discarded eigenvalues
+    Phi3, lam3 = pod.pod(S, Mv, 3)
+    R = S - Phi3 @ (Phi3.T @ Mv @ S)
+    assert abs(np.trace(R.T @ Mv @ R) - lam3[3:5].sum()) < 1e-9 * lam3.sum()
+    with pytest.raises(ValueError):
+        pod.pod(S, Mv, 7)
+
+
+def test_ecm_integrates_polynomials_with_few_positive_points():
+    m = M.mesh_square(6)
+    x, y = m.qX[:, 0], m.qX[:, 1]
+    J = np.stack([np.ones_like(x), x, y, x * y, x * x, y * y])
+    idx, w, hist = ecm.greedy(J, m.qw, 1e-14, 50)
+    assert len(idx) <= 6 and np.all(w > 0)
+    assert np.abs(J[:, idx] @ w - J @ m.qw).max() < 1e-13
+    assert np.all(np.diff(hist) <= 1e-12)
+
+
+def test_ecm_residual_monotone_and_all_points_exact():
+    rng = np.random.default_rng(1)
+    m = M.mesh_square(3)
+    J = rng.normal(size=(30, m.nq))
+    idx, w, hist = ecm.greedy(J, m.qw, 1e-3, 40)
+    assert np.all(w > 0) and np.all(np.diff(hist) <= 1e-12)
+    # with as many points as the full rule the original weights are a solution
+    idx2, w2, hist2 = ecm.greedy(J, m.qw, 1e-12, m.nq)
+    assert hist2[-1] < 1e-10
+
+
+def test_artifact_round_trip():
+    _, _, _, data = full_basis_rom()
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, 'x.rom')
+        artifact.write(p, data['n'], data['m'], 2, 0, 2, MAT, 0.25, 0.0, 1.0, data['w'], data['G'], data['Gd'],
+                       data['src'])
+        back = artifact.read(p)
+    for k in ('w', 'G', 'Gd', 'src'):
+        assert np.array_equal(back[k], data[k])
+    assert back['n'] == data['n'] and back['m'] == data['m'] and back['mat'] == MAT
