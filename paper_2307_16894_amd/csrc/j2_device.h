@@ -69,11 +69,14 @@ __host__ __device__ inline void cosh_sinhc(double z, double& ch, double& sh) {
 }
 
 // One material evaluation at fixed committed history (Fp, Fp33, xi).
-// Outputs P (4), optionally A (16), and the trial history.
-template <bool WANT_A>
-__host__ __device__ inline void j2_point(const double F[4], const double Fp[4], double Fp33, double xi,
-                                         const J2Params& mp, double P[4], double A[16], double Fpn[4],
-                                         double& Fp33n, double& xin) {
+// Outputs P (4) and the trial history; when WANT_A, the columns of the
+// tangent A[:, v] = dP/dF_v (v = 2k + l) are handed to sink(v, c0, c1, c2, c3)
+// one at a time, so callers can fold them into what they need without
+// holding all of A.
+template <bool WANT_A, typename Sink>
+__host__ __device__ inline void j2_point_cols(const double F[4], const double Fp[4], double Fp33, double xi,
+                                              const J2Params& mp, double P[4], double Fpn[4], double& Fp33n,
+                                              double& xin, Sink&& sink) {
   const double SQ32 = 1.2247448713915890491;  // sqrt(3/2)
   // (C^pl)^-1 = Fp^-1 Fp^-T
   const double dFp = Fp[0] * Fp[3] - Fp[1] * Fp[2];
@@ -196,9 +199,23 @@ __host__ __device__ inline void j2_point(const double F[4], const double Fp[4], 
     const double dt01 = G2 * beta * de01 - cn * n01 * nde;
     const double P0b = bb ? P[1] : P[0];
     const double P1b = bb ? P[3] : P[2];
-    A[0 * 4 + ab] = dt00 * itr[0][0] + dt01 * itr[1][0] - P0b * itr[a][0];
-    A[1 * 4 + ab] = dt00 * itr[0][1] + dt01 * itr[1][1] - P0b * itr[a][1];
-    A[2 * 4 + ab] = dt01 * itr[0][0] + dt11 * itr[1][0] - P1b * itr[a][0];
-    A[3 * 4 + ab] = dt01 * itr[0][1] + dt11 * itr[1][1] - P1b * itr[a][1];
+    sink(ab, dt00 * itr[0][0] + dt01 * itr[1][0] - P0b * itr[a][0],
+         dt00 * itr[0][1] + dt01 * itr[1][1] - P0b * itr[a][1],
+         dt01 * itr[0][0] + dt11 * itr[1][0] - P1b * itr[a][0],
+         dt01 * itr[0][1] + dt11 * itr[1][1] - P1b * itr[a][1]);
   }
+}
+
+// Convenience form returning the whole tangent A[4 * (2i+j) + (2k+l)].
+template <bool WANT_A>
+__host__ __device__ inline void j2_point(const double F[4], const double Fp[4], double Fp33, double xi,
+                                         const J2Params& mp, double P[4], double A[16], double Fpn[4],
+                                         double& Fp33n, double& xin) {
+  j2_point_cols<WANT_A>(F, Fp, Fp33, xi, mp, P, Fpn, Fp33n, xin,
+                        [&](int v, double c0, double c1, double c2, double c3) {
+                          A[v] = c0;
+                          A[4 + v] = c1;
+                          A[8 + v] = c2;
+                          A[12 + v] = c3;
+                        });
 }

@@ -116,7 +116,7 @@ int rom_load(const void* blob, size_t bytes, int device, rom_handle* out) {
   memcpy(hdr, b + 8, sizeof(hdr));
   if (hdr[0] != 1) return ROM_EVERSION;
   const int n = (int)hdr[1], m = (int)hdr[2], c = (int)hdr[3], kind = (int)hdr[4], n_mu = (int)hdr[5];
-  if (n < 1 || n > ROM_NMAX || m < 1 || m > (1 << 24) || c < 1 || c > 12) return ROM_EFORMAT;
+  if (n < 1 || n > ROM_NMAX - 5 || m < 1 || m > (1 << 24) || c < 1 || c > 12) return ROM_EFORMAT;
   if (!((kind == 0 && c == 2 && n_mu == 2) || (kind == 1 && c == 12 && n_mu == 8))) return ROM_EFORMAT;
   double par[7];
   memcpy(par, b + 32, sizeof(par));
@@ -139,7 +139,8 @@ int rom_load(const void* blob, size_t bytes, int device, rom_handle* out) {
     if (!isfinite(v)) return ROM_EFORMAT;
   for (double v : Gd)
     if (!isfinite(v)) return ROM_EFORMAT;
-  const int npad = (n + 15) / 16 * 16;
+  // padded width: the fused contraction carries f and C in columns n .. n+4
+  const int npad = 16 * rom_fused_tiles(n);
   std::vector<double> Gt((size_t)n * 4 * m), Gq((size_t)m * 4 * npad, 0.0), Gdt((size_t)c * 4 * m);
   std::vector<float> Gq32((size_t)m * 4 * npad, 0.0f);
   std::vector<uint16_t> Gq16((size_t)m * 4 * npad, 0);

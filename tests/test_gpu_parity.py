@@ -51,7 +51,7 @@ def _run_gpu(name, mu, paths, mode, max_iter, fixed, record_hist=True):
     return out
 
 
-@pytest.mark.parametrize("mode", [0])
+@pytest.mark.parametrize("mode", [0, 1])
 def test_fixed_iteration_parity_onevoid_n20(gpu, mode):
     name = 'onevoid_n20_m120'
     P, K = 16, 10
@@ -81,14 +81,15 @@ def test_fixed_iteration_parity_onevoid_n20(gpu, mode):
                 assert np.abs(gh[5]).max() == 0.0
 
 
-def test_converged_path_onevoid_n20(gpu):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_converged_path_onevoid_n20(gpu, mode):
     """Plain Newton to 1e-8: every step converges, same iteration counts and
     effective stress as the oracle (to the Newton tolerance)."""
     name = 'onevoid_n20_m120'
     P = 64
     mu = workloads.one_void_mu(0, P)
     paths = workloads.monotone_paths(0, P, 10)
-    g = _run_gpu(name, mu, paths, 0, max_iter=15, fixed=False, record_hist=False)
+    g = _run_gpu(name, mu, paths, mode, max_iter=15, fixed=False, record_hist=False)
     rom = ROM(rom_path(name))
     for p in range(0, P, 8):
         ref = oracle_path(rom, mu[p], paths[p], max_iter=15, fixed=False)
