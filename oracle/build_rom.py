@@ -39,6 +39,15 @@ ROMS = {
                              seed=2000),
 }
 
+# four elliptical voids of fixed area 0.075 each (porosity 0.3), parent circles
+# of equal area; mu = (kappa_i, theta_i) per void; ~30k T6.  The three ROMs
+# share mesh and training data (so they can share a snapshot cache).
+_FOUR = dict(kind=1, r0=float(np.sqrt(0.075 / np.pi)), void_area=0.075, nt=32, nr=29, n_mu=8, per_mu=2,
+             path='cyclic', steps=20, rho=(0.02, 0.08), seed=3000, eps=1e-4)
+ROMS['fourvoid_n100_m1500'] = dict(_FOUR, n=100, L=16, m=1500)
+ROMS['fourvoid_n60_m800'] = dict(_FOUR, n=60, L=15, m=800)
+ROMS['fourvoid_n120_m2000'] = dict(_FOUR, n=120, L=19, m=2000)
+
 _G = {}
 
 
@@ -78,8 +87,9 @@ def _training_mu(spec, seed, count):
     return workloads.four_void_training_mu(seed, count)
 
 
-def build(name, outdir, workers):
+def build(name, outdir, workers, snapshot_cache=None, overrides=None):
     spec = dict(ROMS[name])
+    spec.update(overrides or {})
     t0 = time.time()
     geom = _geometry(spec)
     _G['geom'] = geom
@@ -88,11 +98,18 @@ def build(name, outdir, workers):
     mus = _training_mu(spec, spec['seed'], spec['n_mu'])
     paths = _paths(spec, spec['seed'] + 1, spec['n_mu'] * spec['per_mu'])
     jobs = [(spec, mus[i // spec['per_mu']], paths[i]) for i in range(len(paths))]
-    with mp.get_context('fork').Pool(workers) as pool:
-        results = pool.map(_fom_job, jobs, chunksize=1)
+    if snapshot_cache and os.path.exists(snapshot_cache):
+        z = np.load(snapshot_cache)
+        Sw, SW, fom_iters = z['Sw'], z['SW'], float(z['fom_iters'])
+    else:
+        with mp.get_context('fork').Pool(workers) as pool:
+            results = pool.map(_fom_job, jobs, chunksize=1)
+        Sw = np.concatenate([r[0] for r in results]).T  # (ndof, ns)
+        SW = np.concatenate([r[1] for r in results]).T  # (4 nq, ns)
+        fom_iters = float(np.mean([np.mean(r[3]) for r in results]))
+        if snapshot_cache:
+            np.savez(snapshot_cache, Sw=Sw, SW=SW, fom_iters=fom_iters)
     print(f"[{name}] {len(jobs)} training solves done in {time.time() - t0:.1f}s", flush=True)
-    Sw = np.concatenate([r[0] for r in results]).T  # (ndof, ns)
-    SW = np.concatenate([r[1] for r in results]).T  # (4 nq, ns)
     # POD of the fluctuations in V^p and of the weighted stress in L^2(parent)
     Fid = auxiliary.transformation(grad_modes, np.zeros(grad_modes.shape[0]))
     pr0 = fem.Problem(m, space, Fid, MAT)
@@ -130,7 +147,7 @@ def build(name, outdir, workers):
                   pod_W_energy_kept=float(lam_W[:spec['L']].sum() / lam_W[lam_W > 0].sum()),
                   ecm_points=int(idx.size), ecm_residual=float(hist[-1]), ecm_weight_sum=float(wq.sum()),
                   parent_area=float(m.qw.sum()), heldout_eps_P=errs,
-                  fom_iters_mean=float(np.mean([np.mean(r[3]) for r in results])),
+                  fom_iters_mean=fom_iters,
                   build_seconds=time.time() - t0)
     with open(os.path.join(outdir, name + '.json'), 'w') as fh:
         json.dump(report, fh, indent=1)
@@ -143,10 +160,12 @@ def main(argv=None):
     ap.add_argument('names', nargs='+')
     ap.add_argument('--out', default=os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 'roms'))
     ap.add_argument('--workers', type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument('--snapshots', default=None, help='npz file caching the training snapshots')
+    ap.add_argument('--L', type=int, default=None, help='override the number of weighted-stress modes')
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
     for n in a.names:
-        build(n, a.out, a.workers)
+        build(n, a.out, a.workers, a.snapshots, {'L': a.L} if a.L else None)
 
 
 if __name__ == '__main__':

@@ -61,7 +61,12 @@ def greedy(J, w_hat, eps, m_max, svd_tol=1e-12):
         if score[q] <= 0:
             break
         sel.append(q)
-        w, _ = nnls(Z[:, sel], b, maxiter=50 * len(sel) + 100)
+        # least squares on the selected set; Lawson-Hanson NNLS only when a
+        # weight comes out non-positive (both give the same positive solution
+        # when the unconstrained one is positive)
+        w = np.linalg.lstsq(Z[:, sel], b, rcond=None)[0]
+        if np.any(w <= 0):
+            w, _ = nnls(Z[:, sel], b, maxiter=50 * len(sel) + 100)
         keep = w > 0
         sel = [s_ for s_, k in zip(sel, keep) if k]
         w = w[keep]

@@ -13,7 +13,8 @@ from . import material
 
 
 def _solve(K, B):
-    lu = spla.splu(K.tocsc())
+    # sparse LU; K is structurally symmetric, so order on the pattern of K^T + K
+    lu = spla.splu(K.tocsc(), permc_spec='MMD_AT_PLUS_A')
     return lu.solve(np.asarray(B))
 
 
@@ -27,9 +28,15 @@ class FOMResult:
         self.Fbar = []
 
 
-def newton(problem, w0, Fbar, hist, tol, max_iter=25, material_point=material.j2_point):
-    """Newton iterations at fixed committed history.  Returns (w, ev, iters) or None."""
+def newton(problem, w0, Fbar, hist, tol, max_iter=20, material_point=material.j2_point):
+    """Newton iterations at fixed committed history.  Returns (w, ev, iters),
+    or None when the iteration fails: non-finite residual, the iteration cap,
+    or divergence (three residual increases in a row, or growth by 1e4 over
+    the first residual), after which the caller sub-steps."""
     w = w0.copy()
+    res0 = None
+    prev = np.inf
+    rises = 0
     for it in range(max_iter):
         ev = problem.evaluate(w, Fbar, hist, material_point)
         res = np.linalg.norm(ev['f'])
@@ -37,11 +44,16 @@ def newton(problem, w0, Fbar, hist, tol, max_iter=25, material_point=material.j2
             return None
         if res <= tol:
             return w, ev, it + 1
-        w = w - spla.spsolve(ev['K'], ev['f'])
+        res0 = res if res0 is None else res0
+        rises = rises + 1 if res > prev else 0
+        if rises >= 3 or res > 1e4 * res0:
+            return None
+        prev = res
+        w = w - _solve(ev['K'], ev['f'])
     return None
 
 
-def solve_path(problem, Fbar_path, tol=1e-10, max_iter=25, want_tangent=False,
+def solve_path(problem, Fbar_path, tol=1e-10, max_iter=20, want_tangent=False,
                want_W=True, max_halvings=8):
     """Follow a macroscopic deformation-gradient path from the undeformed state.
 

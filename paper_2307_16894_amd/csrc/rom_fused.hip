@@ -3,24 +3,32 @@
 // on the device.
 //
 // Per Newton evaluation the workgroup walks the ECM points in chunks of 256
-// (one lane per point): kinematics, return map and tangent (Appendix A),
-// then the weighted stress W = w|J| P F_mu^-T, the mapped tangent
-// D = w|J| T^T A T and E = w|J| T^T A (T: right multiplication by F_mu^-1) go
-// to LDS.  Each wave contracts 64 of the chunk's points on FP64 MFMA
-// (v_mfma_f64_16x16x4: the 4-long inner dimension is the 4 gradient
-// components of one ECM point):
-//     K_ext[i][j] = sum_q sum_a G_q[a][i] B_q[a][j],
-//     B_q[:, j] = D_q G_q[:, j] (j < n),  W_q (j = n),  E_q[:, j-n-1] (n < j <= n+4)
-// so the residual f = sum_q G_q^T W_q (eq. forcevector_ecm) and
-// C = sum_q G_q^T E_q (right-hand sides of eq. tangent_problem_red) come out
-// of the padding columns of the stiffness tiles (eq. stiffnessmatrix_ecm).
-// K is symmetric (the tangent of the appendix model is major-symmetric), so
-// only tiles I <= J are contracted and the rest is mirrored.  Gaussian
-// elimination with partial pivoting on [K | f | C] in LDS gives the Newton
-// update and K*^-1 C for the effective stiffness (eq. eff_stiffness_1).
+// (one lane per point): kinematics, return map and tangent (Appendix A), the
+// weighted stress W = w|J| P F_mu^-T and the mapped tangent
+// D = w|J| T^T A T (T: right multiplication by F_mu^-1) go to LDS.  The
+// contraction K = sum_q G_q^T D_q G_q (eq. stiffnessmatrix_ecm) then runs on
+// MFMA with the 4 gradient components of an ECM point as the inner
+// dimension:
+//   FP64  v_mfma_f64_16x16x4: B_q = [D_q G_q | W_q], so the residual
+//         f = sum_q G_q^T W_q (eq. forcevector_ecm) comes out of the padding
+//         column n of the stiffness tiles;
+//   FP32  v_mfma_f32_16x16x4 on FP32 operands, FP32 accumulation;
+//   BF16  v_mfma_f32_16x16x32_bf16, eight ECM points per instruction, FP32
+//         accumulation;
+// in the reduced-precision forms f is accumulated separately in FP64, so the
+// residual, the return map and the solve stay FP64.  K is symmetric (the
+// tangent of the appendix model is major-symmetric), so only tiles I <= J are
+// contracted and the rest is mirrored.  Small n: the four waves split the
+// points; large n: they split the tiles.  Gaussian elimination with partial
+// pivoting in LDS gives the Newton update.  At the returned state one more
+// pass over the ECM points gives Pbar (eq. eff_stress_1), sum w|J| A and
+// C = sum_q G_q^T E_q (E = w|J| T^T A), and Abar = sum w|J| A - C^T K*^-1 C
+// (eqs. tangent_problem_red, eff_stiffness_1) with K* the last K.
 #include "rom_fused.h"
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -59,7 +67,7 @@ constexpr int main_doubles() {
 }
 template <int T>
 constexpr int lds_doubles() {
-  return main_doubles<T>() + 16 * T * 9 + 128 + 16 * T;
+  return main_doubles<T>() + 16 * T * 9 + 128 + 16 * T;  // r, C, solutions, scratch, two int arrays
 }
 
 // F = Fbar + (sum_i r_i G_i(q)) F_mu^-1 at ECM point q (argument of P in
@@ -93,7 +101,238 @@ __device__ __forceinline__ void mapped_left(const double A[16], const double Fi[
         E[4 * (2 * i + r) + y] = wJ * (Fi[2 * r] * A[4 * (2 * i) + y] + Fi[2 * r + 1] * A[4 * (2 * i + 1) + y]);
 }
 
+
+// Solve K X = B in LDS by Gaussian elimination with partial pivoting, rows
+// left in place: at step k the pivot is the remaining row with the largest
+// |a[r][k]| (lowest index on ties), and every other remaining row is
+// eliminated against it.  a has leading dimension ld; B occupies columns
+// rhs0 .. rhs0 + nrhs - 1.  The solution of unknown k is written to
+// x[k * 4 + c].  Two barriers per elimination step, one per back step.
+__device__ void gauss_solve(double* a, int ld, int n, int rhs0, int nrhs, int* sStep, int* sOrder, double* x) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int i = tid; i < n; i += blockDim.x) sStep[i] = n;  // n: not yet a pivot
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = n;
+      for (int i = lane; i < n; i += 64) {
+        if (sStep[i] == n) {
+          const double v = fabs(a[i * ld + k]);
+          if (v > best) {
+            best = v;
+            bi = i;
+          }
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        if (bi == n)  // only non-finite entries left: take the first remaining row
+          for (bi = 0; bi < n - 1 && sStep[bi] != n; ++bi) {
+          }
+        sOrder[k] = bi;
+        sStep[bi] = k;
+      }
+    }
+    __syncthreads();
+    const int pr = sOrder[k];
+    const double inv = 1.0 / a[pr * ld + k];
+    const int nk = n - 1 - k;
+    const int ncols = nk + nrhs;
+    for (int idx = tid; idx < n * ncols; idx += blockDim.x) {
+      const int r = idx / ncols, jj = idx - r * ncols;
+      if (sStep[r] < n) continue;  // already a pivot row (includes pr)
+      const int j = (jj < nk) ? k + 1 + jj : rhs0 + (jj - nk);
+      a[r * ld + j] = fma(-a[r * ld + k] * inv, a[pr * ld + j], a[r * ld + j]);
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int pr = sOrder[k];
+    const double inv = 1.0 / a[pr * ld + k];
+    for (int idx = tid; idx < n * nrhs; idx += blockDim.x) {
+      const int r = idx / nrhs, c = idx - r * nrhs;
+      const double xk = a[pr * ld + rhs0 + c] * inv;
+      if (r == 0) x[k * 4 + c] = xk;
+      if (sStep[r] < k) a[r * ld + rhs0 + c] = fma(-a[r * ld + k], xk, a[r * ld + rhs0 + c]);
+    }
+    __syncthreads();
+  }
+}
+
+// G_q[b][16 J + c] for the four gradient components b and all column blocks J.
 template <int T>
+__device__ __forceinline__ void load_g(double (&g)[4][T], const double* __restrict__ Gp, int c_col) {
+  constexpr int NPAD = 16 * T;
+#pragma unroll
+  for (int J = 0; J < T; ++J)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) g[b][J] = Gp[b * NPAD + 16 * J + c_col];
+}
+
+// Upper-triangle tile t (column-major over J, then I <= J) -> (I, J).
+__host__ __device__ constexpr int tile_I(int t) {
+  int J = 0;
+  while (t > J) {
+    t -= J + 1;
+    ++J;
+  }
+  return t;
+}
+__host__ __device__ constexpr int tile_J(int t) {
+  int J = 0;
+  while (t > J) {
+    t -= J + 1;
+    ++J;
+  }
+  return J;
+}
+
+__device__ __forceinline__ __bf16 to_bf16(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (operands are finite)
+  return __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
+}
+
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+template <int PREC>
+struct Acc {
+  typedef f4 type;
+};
+template <>
+struct Acc<PREC_F64> {
+  typedef d4 type;
+};
+
+// Contraction of points [qa, qb) of the chunk into the tiles t = W, W + TW, ...
+// (TW = 1: all tiles).  FP64 also accumulates f in column n of the tiles; the
+// reduced-precision forms add G_q[k][j] W_q[k] to fpart (FP64) when do_f.
+template <int T, int PREC, int W, int TW>
+__device__ __forceinline__ void contract(typename Acc<PREC>::type* acc, double (&fpart)[T], bool do_f,
+                                         const double* __restrict__ Gq, const double* sQ, int q0, int qa, int qb,
+                                         int n, int k_row, int c_col) {
+  constexpr int NPAD = 16 * T;
+  constexpr int NT = T * (T + 1) / 2;
+  if (qa >= qb) return;
+  if constexpr (PREC != PREC_BF16) {
+    // one ECM point per step; the next point's G is loaded during this point's MFMAs
+    double gc[4][T];
+    load_g<T>(gc, Gq + (size_t)(q0 + qa) * 4 * NPAD, c_col);
+    for (int ql = qa; ql < qb; ++ql) {
+      double gn[4][T];
+      load_g<T>(gn, Gq + (size_t)(q0 + min(ql + 1, qb - 1)) * 4 * NPAD, c_col);
+      const double* rq = sQ + ql * QS;
+      const double d0 = rq[4 * k_row], d1 = rq[4 * k_row + 1], d2 = rq[4 * k_row + 2], d3 = rq[4 * k_row + 3];
+      const double wk = rq[16 + k_row];
+      double Aop[T], Bop[T];
+#pragma unroll
+      for (int J = 0; J < T; ++J) {
+        const int col = 16 * J + c_col;
+        Aop[J] = (k_row == 0) ? gc[0][J] : (k_row == 1) ? gc[1][J] : (k_row == 2) ? gc[2][J] : gc[3][J];
+        const double h = d0 * gc[0][J] + d1 * gc[1][J] + d2 * gc[2][J] + d3 * gc[3][J];
+        if constexpr (PREC == PREC_F64) {
+          Bop[J] = (col < n) ? h : ((col == n) ? wk : 0.0);
+        } else {
+          Bop[J] = (col < n) ? h : 0.0;
+          if (do_f) fpart[J] = fma(Aop[J], wk, fpart[J]);
+        }
+      }
+#pragma unroll
+      for (int t = W, u = 0; t < NT; t += TW, ++u) {
+        if constexpr (PREC == PREC_F64)
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Aop[tile_I(t)], Bop[tile_J(t)], acc[u], 0, 0, 0);
+        else
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)Aop[tile_I(t)], (float)Bop[tile_J(t)], acc[u], 0,
+                                                         0, 0);
+      }
+#pragma unroll
+      for (int b2 = 0; b2 < 4; ++b2)
+#pragma unroll
+        for (int J = 0; J < T; ++J) gc[b2][J] = gn[b2][J];
+    }
+  } else {
+    // eight ECM points per step: lane group g = k_row holds points 2g, 2g + 1
+    // of the step; inner index k = 8 g + 4 h + b (point 2g + h, component b)
+    for (int qs = qa; qs < qb; qs += 8) {
+      float D[2][16];
+      double Wv[2][4];
+      bool live[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int ql = qs + 2 * k_row + h;
+        live[h] = ql < qb;
+        const double* rq = sQ + (live[h] ? ql : qa) * QS;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) D[h][k] = live[h] ? (float)rq[k] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Wv[h][k] = live[h] ? rq[16 + k] : 0.0;
+      }
+      bf8 Aop[T], Bop[T];
+#pragma unroll
+      for (int J = 0; J < T; ++J) {
+        const int col = 16 * J + c_col;
+        double g[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int ql = qs + 2 * k_row + h;
+          const double* Gp = Gq + (size_t)(q0 + (live[h] ? ql : qa)) * 4 * NPAD + col;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) g[h][b] = live[h] ? Gp[b * NPAD] : 0.0;
+        }
+        if (do_f) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) fpart[J] = fma(g[h][b], Wv[h][b], fpart[J]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float g0 = (float)g[h][0], g1 = (float)g[h][1], g2 = (float)g[h][2], g3 = (float)g[h][3];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            Aop[J][4 * h + b] = to_bf16((float)g[h][b]);
+            const float hv = D[h][4 * b] * g0 + D[h][4 * b + 1] * g1 + D[h][4 * b + 2] * g2 + D[h][4 * b + 3] * g3;
+            Bop[J][4 * h + b] = to_bf16(col < n ? hv : 0.0f);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = W, u = 0; t < NT; t += TW, ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[tile_I(t)], Bop[tile_J(t)], acc[u], 0, 0, 0);
+    }
+  }
+}
+
+// Store (ACCUM: add) the tiles t = W, W + TW, ... into sK (ld NPAD); when
+// MIRROR, also the transposed tile below the diagonal.
+template <int T, int PREC, int W, int TW>
+__device__ __forceinline__ void store_acc(const typename Acc<PREC>::type* acc, double* sK, bool accum, bool mirror,
+                                          int k_row, int c_col) {
+  constexpr int NPAD = 16 * T;
+  constexpr int NT = T * (T + 1) / 2;
+#pragma unroll
+  for (int t = W, u = 0; t < NT; t += TW, ++u) {
+    const int I = tile_I(t), J = tile_J(t);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      // output layouts: FP64 row = k_row + 4 j, FP32 accumulators row = 4 k_row + j
+      const int row = 16 * I + (PREC == PREC_F64 ? k_row + 4 * j : 4 * k_row + j), col = 16 * J + c_col;
+      double v = (double)acc[u][j];
+      if (accum) v += sK[row * NPAD + col];
+      sK[row * NPAD + col] = v;
+      if (mirror && I < J) sK[col * NPAD + row] = v;
+    }
+  }
+}
+
+template <int T, int PREC>
 __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
   constexpr int NPAD = 16 * T;
   constexpr int NT = T * (T + 1) / 2;
@@ -105,9 +344,10 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
   double* sE = smem + NPAD * NPAD;  // [ECH][16] E records of the effective-quantity pass
   double* sR = smem + MAT;        // [NPAD] current r
   double* sC = sR + NPAD;         // [NPAD][4] C = sum_q G_q^T E_q, then K^-1 C
-  double* sC0 = sC + 4 * NPAD;    // [NPAD][4] copy of C
-  double* sX = sC0 + 4 * NPAD;    // reduction scratch (128)
-  int* sPiv = reinterpret_cast<int*>(sX + 128);  // [NPAD] pivot rows of the LU
+  double* sSol = sC + 4 * NPAD;   // [NPAD][4] solutions of the eliminations
+  double* sX = sSol + 4 * NPAD;   // reduction scratch (128)
+  int* sStep = reinterpret_cast<int*>(sX + 128);  // [NPAD] elimination step of each row
+  int* sOrder = sStep + NPAD;                     // [NPAD] pivot row of each step
 
   const int p = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -134,9 +374,15 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
   int status = ROM_ST_MAXITER, iters = 0;
   double rn = 0.0;
   for (int it = 0; it < a.max_iter; ++it) {
-    d4 acc[NT];
+    constexpr bool QSPLIT = (T <= 5);                 // small n: waves split the points
+    constexpr int NACC = QSPLIT ? NT : (NT + 3) / 4;  // large n: waves split the tiles
+    typedef typename Acc<PREC>::type AccV;
+    AccV acc[NACC];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NACC; ++t) acc[t] = (AccV){0, 0, 0, 0};
+    double fpart[T];  // FP64 residual partials of the reduced-precision forms
+#pragma unroll
+    for (int J = 0; J < T; ++J) fpart[J] = 0.0;
 
     for (int q0 = 0; q0 < m; q0 += FCH) {
       const int q = q0 + tid;
@@ -183,51 +429,50 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
         rec[19] = wJ * (P[2] * Fi[2] + P[3] * Fi[3]);
       }
       __syncthreads();
-      // contraction of this wave's share of the chunk on FP64 MFMA
+      // contraction of the chunk
       const int qend = min(FCH, m - q0);
-      const int qa = wave * 64, qb = min(qa + 64, qend);
-      for (int ql = qa; ql < qb; ++ql) {
-        const double* Gp = a.Gq + (size_t)(q0 + ql) * 4 * NPAD;
-        const double* rq = sQ + ql * QS;
-        const double d0 = rq[4 * k_row], d1 = rq[4 * k_row + 1], d2 = rq[4 * k_row + 2], d3 = rq[4 * k_row + 3];
-        const double wk = rq[16 + k_row];
-        double Aop[T], Bop[T];
-#pragma unroll
-        for (int J = 0; J < T; ++J) {
-          const int col = 16 * J + c_col;
-          const double g0 = Gp[col], g1 = Gp[NPAD + col], g2 = Gp[2 * NPAD + col], g3 = Gp[3 * NPAD + col];
-          Aop[J] = (k_row == 0) ? g0 : (k_row == 1) ? g1 : (k_row == 2) ? g2 : g3;
-          Bop[J] = (col < n) ? (d0 * g0 + d1 * g1 + d2 * g2 + d3 * g3) : ((col == n) ? wk : 0.0);
+      if constexpr (QSPLIT) {
+        contract<T, PREC, 0, 1>(acc, fpart, true, a.Gq, sQ, q0, wave * 64, min(wave * 64 + 64, qend), n, k_row,
+                                c_col);
+      } else {
+        switch (wave) {
+          case 0: contract<T, PREC, 0, 4>(acc, fpart, true, a.Gq, sQ, q0, 0, qend, n, k_row, c_col); break;
+          case 1: contract<T, PREC, 1, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, n, k_row, c_col); break;
+          case 2: contract<T, PREC, 2, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, n, k_row, c_col); break;
+          default: contract<T, PREC, 3, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, n, k_row, c_col); break;
         }
-        int t = 0;
-#pragma unroll
-        for (int J = 0; J < T; ++J)
-#pragma unroll
-          for (int I = 0; I <= J; ++I) {
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Aop[I], Bop[J], acc[t], 0, 0, 0);
-            ++t;
-          }
       }
       __syncthreads();
     }
-    // reduce the four waves' tiles into [K | f] (ld NPAD), mirror K's lower part
-    for (int w = 0; w < 4; ++w) {
-      if (wave == w) {
-        int t = 0;
+    // [K | f] into LDS (ld NPAD); K's lower part by symmetry
+    if constexpr (QSPLIT) {
+      for (int w = 0; w < 4; ++w) {
+        if (wave == w) store_acc<T, PREC, 0, 1>(acc, sK, w > 0, w == 3, k_row, c_col);
+        __syncthreads();
+      }
+    } else {
+      switch (wave) {
+        case 0: store_acc<T, PREC, 0, 4>(acc, sK, false, true, k_row, c_col); break;
+        case 1: store_acc<T, PREC, 1, 4>(acc, sK, false, true, k_row, c_col); break;
+        case 2: store_acc<T, PREC, 2, 4>(acc, sK, false, true, k_row, c_col); break;
+        default: store_acc<T, PREC, 3, 4>(acc, sK, false, true, k_row, c_col); break;
+      }
+      __syncthreads();
+    }
+    if constexpr (PREC != PREC_F64) {
+      // f in FP64: sum over the lane groups, then over the waves in a fixed order
 #pragma unroll
-        for (int J = 0; J < T; ++J)
-#pragma unroll
-          for (int I = 0; I <= J; ++I) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int row = 16 * I + k_row + 4 * j, col = 16 * J + c_col;
-              double v = acc[t][j];
-              if (w > 0) v += sK[row * NPAD + col];
-              sK[row * NPAD + col] = v;
-              if (I < J && w == 3) sK[col * NPAD + row] = v;
-            }
-            ++t;
-          }
+      for (int J = 0; J < T; ++J) {
+        double v = fpart[J];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (k_row == 0) sSol[wave * NPAD + 16 * J + c_col] = v;
+      }
+      __syncthreads();
+      if (tid < n) {
+        const double v = QSPLIT ? ((sSol[tid] + sSol[NPAD + tid]) + sSol[2 * NPAD + tid]) + sSol[3 * NPAD + tid]
+                                : sSol[tid];
+        sK[tid * NPAD + n] = v;
       }
       __syncthreads();
     }
@@ -256,57 +501,10 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
       stop = last;
       status = ROM_ST_MAXITER;
     }
-    // LU with partial pivoting of K, applied to the column f as it goes
-    const int nc = n + 1;
-    for (int k = 0; k < n; ++k) {
-      if (wave == 0) {
-        double best = -1.0;
-        int bi = k;
-        for (int i = k + lane; i < n; i += 64) {
-          const double v = fabs(sK[i * NPAD + k]);
-          if (v > best) {
-            best = v;
-            bi = i;
-          }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-          const double ob = __shfl_xor(best, o);
-          const int oi = __shfl_xor(bi, o);
-          if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-          }
-        }
-        if (lane == 0) sPiv[k] = bi;
-      }
-      __syncthreads();
-      const int pr = sPiv[k];
-      if (pr != k)
-        for (int j = tid; j < nc; j += 256) {
-          const double t = sK[k * NPAD + j];
-          sK[k * NPAD + j] = sK[pr * NPAD + j];
-          sK[pr * NPAD + j] = t;
-        }
-      __syncthreads();
-      const double inv = 1.0 / sK[k * NPAD + k];
-      const int rows = n - k - 1, cols = nc - k - 1;
-      for (int idx = tid; idx < rows * cols; idx += 256) {
-        const int i = k + 1 + idx / cols, j = k + 1 + idx % cols;
-        sK[i * NPAD + j] = fma(-sK[i * NPAD + k] * inv, sK[k * NPAD + j], sK[i * NPAD + j]);
-      }
-      __syncthreads();
-      for (int i = k + 1 + tid; i < n; i += 256) sK[i * NPAD + k] *= inv;  // store the multiplier
-      __syncthreads();
-    }
-    // back substitution of the f column: x = K^-1 f
-    for (int k = n - 1; k >= 0; --k) {
-      if (tid == 0) sK[k * NPAD + n] /= sK[k * NPAD + k];
-      __syncthreads();
-      for (int i = tid; i < k; i += 256) sK[i * NPAD + n] = fma(-sK[i * NPAD + k], sK[k * NPAD + n], sK[i * NPAD + n]);
-      __syncthreads();
-    }
     if (stop) break;
-    if (tid < n) sR[tid] -= sK[tid * NPAD + n];  // K dr = -f
+    // Newton update: K dr = -f
+    gauss_solve(sK, NPAD, n, n, 1, sStep, sOrder, sSol);
+    if (tid < n) sR[tid] -= sSol[4 * tid];
     __syncthreads();
   }
 
@@ -366,10 +564,7 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int o = tid + 256 * u;
-    if (o < 4 * n) {
-      sC[o] = cacc[u];
-      sC0[o] = cacc[u];
-    }
+    if (o < 4 * n) sC[o] = cacc[u];
   }
 #pragma unroll
   for (int k = 0; k < 20; ++k) {
@@ -378,33 +573,10 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
     if (lane == 0) sX[4 * k + wave] = v;
   }
   __syncthreads();
-  // Y = K*^-1 C in place: row permutation, unit-lower and upper solves (4 RHS)
-  if (tid < 4)
-    for (int k = 0; k < n; ++k) {
-      const int pr = sPiv[k];
-      if (pr != k) {
-        const double t = sC[4 * k + tid];
-        sC[4 * k + tid] = sC[4 * pr + tid];
-        sC[4 * pr + tid] = t;
-      }
-    }
+  // Y = K*^-1 C with K* = K of the last evaluation (still in sK, not eliminated)
+  for (int idx = tid; idx < 4 * n; idx += 256) sK[(idx >> 2) * NPAD + n + 1 + (idx & 3)] = sC[idx];
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    for (int idx = tid; idx < 4 * (n - k - 1); idx += 256) {
-      const int i = k + 1 + (idx >> 2), y = idx & 3;
-      sC[4 * i + y] = fma(-sK[i * NPAD + k], sC[4 * k + y], sC[4 * i + y]);
-    }
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    if (tid < 4) sC[4 * k + tid] /= sK[k * NPAD + k];
-    __syncthreads();
-    for (int idx = tid; idx < 4 * k; idx += 256) {
-      const int i = idx >> 2, y = idx & 3;
-      sC[4 * i + y] = fma(-sK[i * NPAD + k], sC[4 * k + y], sC[4 * i + y]);
-    }
-    __syncthreads();
-  }
+  gauss_solve(sK, NPAD, n, n + 1, 4, sStep, sOrder, sSol);
   if (tid < 20) {
     const double v = ((sX[4 * tid] + sX[4 * tid + 1]) + sX[4 * tid + 2]) + sX[4 * tid + 3];
     if (tid < 4) {
@@ -412,7 +584,7 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
     } else {
       const int e = tid - 4, x = e >> 2, y = e & 3;
       double acc2 = v;
-      for (int i = 0; i < n; ++i) acc2 = fma(-sC0[4 * i + x], sC[4 * i + y], acc2);
+      for (int i = 0; i < n; ++i) acc2 = fma(-sC[4 * i + x], sSol[4 * i + y], acc2);
       a.Abar[16 * (size_t)p + e] = acc2 * a.inv_area;
     }
   }
@@ -432,19 +604,32 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
 }
 
 template <int T>
-int launch_t(const FusedArgs& a, int P, hipStream_t s) {
+int launch_t(const FusedArgs& a, int prec, int P, hipStream_t s) {
   const size_t lds = (size_t)lds_doubles<T>() * 8;
-  k_fused<T><<<P, 256, lds, s>>>(a);
+  if (prec == ROM_DT_F64)
+    k_fused<T, PREC_F64><<<P, 256, lds, s>>>(a);
+  else if (prec == ROM_DT_F32)
+    k_fused<T, PREC_F32><<<P, 256, lds, s>>>(a);
+  else
+    k_fused<T, PREC_BF16><<<P, 256, lds, s>>>(a);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+template <int T, int PREC>
+int setup_one() {
+  const size_t lds = (size_t)lds_doubles<T>() * 8;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<T, PREC>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess
+             ? ROM_OK
+             : ROM_EHIP;
 }
 
 template <int T>
 int setup_t() {
-  const size_t lds = (size_t)lds_doubles<T>() * 8;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<T>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess
-             ? ROM_OK
-             : ROM_EHIP;
+  int rc = setup_one<T, PREC_F64>();
+  if (rc == ROM_OK) rc = setup_one<T, PREC_F32>();
+  if (rc == ROM_OK) rc = setup_one<T, PREC_BF16>();
+  return rc;
 }
 
 }  // namespace
@@ -465,7 +650,6 @@ int rom_fused_setup() {
 
 int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
                           int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
-  if (o.contraction != ROM_DT_F64) return ROM_EUNSUPPORTED;
   const int T = rom_fused_tiles(h->n);
   if (T < 2 || T > 8 || 16 * T != h->npad) return ROM_EUNSUPPORTED;
   const StateLayout L = rom_state_layout(h, P);
@@ -495,13 +679,13 @@ int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, 
   if (rom_timing_mark(h, 0, s) != ROM_OK) return ROM_EHIP;
   int rc;
   switch (T) {
-    case 2: rc = launch_t<2>(a, P, s); break;
-    case 3: rc = launch_t<3>(a, P, s); break;
-    case 4: rc = launch_t<4>(a, P, s); break;
-    case 5: rc = launch_t<5>(a, P, s); break;
-    case 6: rc = launch_t<6>(a, P, s); break;
-    case 7: rc = launch_t<7>(a, P, s); break;
-    default: rc = launch_t<8>(a, P, s); break;
+    case 2: rc = launch_t<2>(a, o.contraction, P, s); break;
+    case 3: rc = launch_t<3>(a, o.contraction, P, s); break;
+    case 4: rc = launch_t<4>(a, o.contraction, P, s); break;
+    case 5: rc = launch_t<5>(a, o.contraction, P, s); break;
+    case 6: rc = launch_t<6>(a, o.contraction, P, s); break;
+    case 7: rc = launch_t<7>(a, o.contraction, P, s); break;
+    default: rc = launch_t<8>(a, o.contraction, P, s); break;
   }
   if (rom_timing_mark(h, 1, s) != ROM_OK) return ROM_EHIP;
   return rc;

@@ -95,8 +95,9 @@ def test_iteration_cap_keeps_committed_state_and_substepping_recovers(gpu, mode)
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-def test_full_basis_rom_on_gpu_reproduces_fom(gpu, mode):
-    m, sp, gm, data = full_basis_rom()
+@pytest.mark.parametrize("blocks", [(2, 1), (3, 1)])  # n = 76 and 116: both contraction layouts
+def test_full_basis_rom_on_gpu_reproduces_fom(gpu, mode, blocks):
+    m, sp, gm, data = full_basis_rom(*blocks)
     assert data['n'] <= 123
     mu = np.array([[0.3, 0.21], [0.22, 0.31]])
     E = np.array([[0.003, 0.001], [0.001, -0.002]])
