@@ -49,6 +49,7 @@ extern "C" {
 #define ROM_ST_CONVERGED 0  /* ||f||_2 <= tol at the returned state */
 #define ROM_ST_MAXITER   1  /* iteration cap reached; nothing committed */
 #define ROM_ST_NONFINITE 2  /* non-finite residual; nothing committed */
+#define ROM_ST_FALLBACK  3  /* converged after the learned warm start fell back to the plain guess */
 #define ROM_ST_BADMU     4  /* the point's shape parameters were rejected */
 
 /* contraction precision of the reduced tangent K (Sec. 3.2, eq. stiffnessmatrix_ecm) */
@@ -60,16 +61,23 @@ extern "C" {
 #define ROM_MODE_STAGED 0  /* one kernel per stage, host-enqueued Newton loop */
 #define ROM_MODE_FUSED  1  /* one persistent kernel, device-side Newton loop */
 
+/* initial guess of the Newton iteration */
+#define ROM_WARM_PREV 0  /* the committed r (plain guess) */
+#define ROM_WARM_MLP  1  /* committed r + the increment predicted by a warm-start network */
+
 typedef struct rom_model* rom_handle;
+typedef struct rom_mlp* rom_mlp_handle;
 
 typedef struct rom_opts {
   double  tol;          /* absolute tolerance on ||f||_2 (default 1e-8) */
   int32_t max_iter;     /* Newton evaluations per step, >= 1 (default 15) */
   int32_t fixed_iters;  /* 1: make exactly max_iter evaluations, status from the last (parity mode) */
-  int32_t commit;       /* 1: converged points commit r and history */
+  int32_t commit;       /* 1: converged points commit r, history and Fbar */
   int32_t contraction;  /* ROM_DT_*: precision of the K contraction; all else is FP64 */
   int32_t mode;         /* ROM_MODE_* */
-  int32_t reserved[7];
+  int32_t warm_start;   /* ROM_WARM_*; ROM_WARM_MLP needs mode FUSED and mlp */
+  int32_t reserved[6];
+  rom_mlp_handle mlp;   /* network for ROM_WARM_MLP (see below), else NULL */
 } rom_opts;
 
 /* Fill *o with the defaults above (mode FUSED when built, contraction F64). */
@@ -110,7 +118,9 @@ int rom_info(rom_handle h, int32_t* n, int32_t* m, int32_t* c, int32_t* n_mu);
 #define ROM_FIELD_PBAR        5  /* f64 [batch][4]  last effective stress */
 #define ROM_FIELD_ABAR        6  /* f64 [batch][16] last effective stiffness */
 #define ROM_FIELD_MU_OK       7  /* i32 [batch] 1 if the shape parameters were accepted */
-#define ROM_NFIELDS           8
+#define ROM_FIELD_FBAR_COMMITTED 8  /* f64 [batch][4] Fbar of the last committed step (I initially) */
+#define ROM_FIELD_R_GUESS     9  /* f64 [batch][n] initial guess used by the last rom_step */
+#define ROM_NFIELDS           10
 int rom_state_bytes(rom_handle h, int32_t batch, size_t* bytes);
 int rom_state_offsets(rom_handle h, int32_t batch, size_t* offsets /* [ROM_NFIELDS] */);
 
@@ -159,6 +169,51 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
  */
 int rom_homogenized_stress_tangent(rom_handle h, int32_t batch, const void* state_dev,
                                    double* Pbar_dev, double* Abar_dev, hipStream_t stream);
+
+/*
+ * Learned warm start.  A fully connected network (n_in -> 3 hidden layers of
+ * `width` SiLU units -> n_out) predicts the Newton increment of the reduced
+ * coordinates of a load step, dr = r_converged - r_committed, from per-point
+ * features (rom_features).  Weights are kept as an FP32 master copy with BF16
+ * copies for the BF16 forward; training runs the library's own forward,
+ * backward (FP32) and Adam kernels.  With opts.warm_start = ROM_WARM_MLP,
+ * rom_step starts Newton from r_committed + dr and falls back to the plain
+ * guess when ||f|| has not dropped tenfold after two Newton updates
+ * (status ROM_ST_FALLBACK when it then converges).  Plain Newton is the judge
+ * of the prediction: the converged state does not depend on the guess.
+ *
+ * Parameter layout (FP32, host): W1 [n_in][width], b1 [width], W2 [width][width],
+ * b2, W3 [width][width], b3, W4 [width][n_out], b4 [n_out].
+ * Precision arguments: ROM_DT_F32 or ROM_DT_BF16 (forward); backward is FP32.
+ */
+int rom_mlp_create(int32_t n_in, int32_t width, int32_t n_out, int32_t max_batch, int device, rom_mlp_handle* out);
+int rom_mlp_free(rom_mlp_handle m);
+int rom_mlp_param_count(rom_mlp_handle m, int64_t* count);
+int rom_mlp_set_params(rom_mlp_handle m, const float* host_params, int64_t count);
+int rom_mlp_get_params(rom_mlp_handle m, float* host_params, int64_t count);
+/* affine scaling of features and targets: x_hat = (x - x_mean) / x_std, y = y_mean + y_std * y_hat (host arrays) */
+int rom_mlp_set_scaling(rom_mlp_handle m, const float* x_mean, const float* x_std, const float* y_mean,
+                        const float* y_std);
+/* raw features X [batch][n_in] (device) -> raw predictions Y [batch][n_out] (device) */
+int rom_mlp_forward(rom_mlp_handle m, int32_t batch, const float* X_dev, float* Y_dev, int32_t precision,
+                    hipStream_t stream);
+/* loss = mean over the batch of sum (y_hat - (Y - y_mean) / y_std)^2, and its parameter gradient
+   (same layout as the parameters) into grads_dev (device, may be NULL) */
+int rom_mlp_gradients(rom_mlp_handle m, int32_t batch, const float* X_dev, const float* Y_dev, int32_t precision,
+                      float* grads_dev, float* loss_dev, hipStream_t stream);
+/* gradients as above, then one Adam update (beta1 0.9, beta2 0.999, eps 1e-8, step counter kept inside) */
+int rom_mlp_train_step(rom_mlp_handle m, int32_t batch, const float* X_dev, const float* Y_dev, float lr,
+                       int32_t precision, float* loss_dev, hipStream_t stream);
+
+/*
+ * rom_features -- per-point inputs of the warm-start network for the step
+ * to Fbar_dev: mu (n_mu), Fbar - Fbar_committed (4), r_committed (n), and eight
+ * statistics of the committed plastic state weighted by w_q |det F_mu|
+ * (mean, max and standard deviation of xi, the yielded fraction, the mean of
+ * F^pl - I).  X_dev: f32 [batch][n_mu + 4 + n + 8] device out.
+ */
+int rom_features(rom_handle h, int32_t batch, const double* Fbar_dev, const void* state_dev, float* X_dev,
+                 hipStream_t stream);
 
 /*
  * Measurement support.  While enabled, rom_step records a HIP event pair on

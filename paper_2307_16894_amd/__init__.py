@@ -25,18 +25,23 @@ ROM_EUNSUPPORTED = -6
 ST_CONVERGED = 0
 ST_MAXITER = 1
 ST_NONFINITE = 2
+ST_FALLBACK = 3
 ST_BADMU = 4
+WARM_PREV, WARM_MLP = 0, 1
 
 DT_F64, DT_F32, DT_BF16 = 0, 1, 2
 MODE_STAGED, MODE_FUSED = 0, 1
 
 FIELD_R_COMMITTED, FIELD_R_TRIAL, FIELD_H_COMMITTED, FIELD_H_TRIAL = 0, 1, 2, 3
 FIELD_TRANSFORM, FIELD_PBAR, FIELD_ABAR, FIELD_MU_OK = 4, 5, 6, 7
-NFIELDS = 8
+FIELD_FBAR_COMMITTED, FIELD_R_GUESS = 8, 9
+NFIELDS = 10
 
 EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_info', 'rom_state_bytes',
            'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent',
-           'rom_timing_enable', 'rom_timing_read']
+           'rom_timing_enable', 'rom_timing_read', 'rom_mlp_create', 'rom_mlp_free', 'rom_mlp_param_count',
+           'rom_mlp_set_params', 'rom_mlp_get_params', 'rom_mlp_set_scaling', 'rom_mlp_forward',
+           'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features']
 
 
 class RomError(RuntimeError):
@@ -48,7 +53,7 @@ class RomError(RuntimeError):
 class rom_opts(ctypes.Structure):
     _fields_ = [('tol', ctypes.c_double), ('max_iter', ctypes.c_int32), ('fixed_iters', ctypes.c_int32),
                 ('commit', ctypes.c_int32), ('contraction', ctypes.c_int32), ('mode', ctypes.c_int32),
-                ('reserved', ctypes.c_int32 * 7)]
+                ('warm_start', ctypes.c_int32), ('reserved', ctypes.c_int32 * 6), ('mlp', ctypes.c_void_p)]
 
 
 _lib = None
@@ -74,6 +79,17 @@ def lib():
         L.rom_homogenized_stress_tangent.argtypes = [vp, i32, vp, vp, vp, vp]
         L.rom_timing_enable.argtypes = [vp, ctypes.c_int]
         L.rom_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.rom_mlp_create.argtypes = [i32, i32, i32, i32, ctypes.c_int, ctypes.POINTER(vp)]
+        L.rom_mlp_free.argtypes = [vp]
+        L.rom_mlp_param_count.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.rom_mlp_set_params.argtypes = [vp, fp, ctypes.c_int64]
+        L.rom_mlp_get_params.argtypes = [vp, fp, ctypes.c_int64]
+        L.rom_mlp_set_scaling.argtypes = [vp, fp, fp, fp, fp]
+        L.rom_mlp_forward.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.rom_mlp_gradients.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp]
+        L.rom_mlp_train_step.argtypes = [vp, i32, vp, vp, ctypes.c_float, i32, vp, vp]
+        L.rom_features.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -157,3 +173,61 @@ def rom_timing_read(h):
     n = ctypes.c_int64()
     _check(lib().rom_timing_read(h, ctypes.byref(ms), ctypes.byref(n)), 'rom_timing_read')
     return ms.value, n.value
+
+
+def _f32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def rom_mlp_create(n_in, width, n_out, max_batch, device=0):
+    h = ctypes.c_void_p()
+    _check(lib().rom_mlp_create(n_in, width, n_out, max_batch, device, ctypes.byref(h)), 'rom_mlp_create')
+    return h
+
+
+def rom_mlp_free(m):
+    _check(lib().rom_mlp_free(m), 'rom_mlp_free')
+
+
+def rom_mlp_param_count(m):
+    c = ctypes.c_int64()
+    _check(lib().rom_mlp_param_count(m, ctypes.byref(c)), 'rom_mlp_param_count')
+    return c.value
+
+
+def rom_mlp_set_params(m, params):
+    a, ptr = _f32(params)
+    _check(lib().rom_mlp_set_params(m, ptr, a.size), 'rom_mlp_set_params')
+
+
+def rom_mlp_get_params(m):
+    import numpy as np
+    out = np.zeros(rom_mlp_param_count(m), dtype=np.float32)
+    _check(lib().rom_mlp_get_params(m, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.size),
+           'rom_mlp_get_params')
+    return out
+
+
+def rom_mlp_set_scaling(m, x_mean, x_std, y_mean, y_std):
+    arrs = [_f32(v) for v in (x_mean, x_std, y_mean, y_std)]
+    _check(lib().rom_mlp_set_scaling(m, *[p for _, p in arrs]), 'rom_mlp_set_scaling')
+
+
+def rom_mlp_forward(m, batch, X_ptr, Y_ptr, precision, stream):
+    _check(lib().rom_mlp_forward(m, batch, X_ptr, Y_ptr, precision, stream), 'rom_mlp_forward')
+
+
+def rom_mlp_gradients(m, batch, X_ptr, Y_ptr, precision, grads_ptr, loss_ptr, stream):
+    _check(lib().rom_mlp_gradients(m, batch, X_ptr, Y_ptr, precision, grads_ptr, loss_ptr, stream),
+           'rom_mlp_gradients')
+
+
+def rom_mlp_train_step(m, batch, X_ptr, Y_ptr, lr, precision, loss_ptr, stream):
+    _check(lib().rom_mlp_train_step(m, batch, X_ptr, Y_ptr, ctypes.c_float(lr), precision, loss_ptr, stream),
+           'rom_mlp_train_step')
+
+
+def rom_features(h, batch, Fbar_ptr, state_ptr, X_ptr, stream):
+    _check(lib().rom_features(h, batch, Fbar_ptr, state_ptr, X_ptr, stream), 'rom_features')

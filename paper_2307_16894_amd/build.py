@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, 'csrc')
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, 'libpodecm.so')
-SOURCES = ['rom_api.hip', 'rom_staged.hip', 'rom_fused.hip']
+SOURCES = ['rom_api.hip', 'rom_staged.hip', 'rom_fused.hip', 'mlp.hip']
 FLAGS = ['--offload-arch=gfx950', '-O3', '-std=c++17', '-fPIC',
          # packed FP32 instructions are left out of every kernel
          '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',

@@ -1,0 +1,487 @@
+// Warm-start network: a fully connected SiLU network predicting the Newton
+// increment of the reduced coordinates, with its own BF16 / FP32 forward,
+// FP32 backward and Adam kernels.
+//
+// Parameters live on the device zero-padded per layer ([Kp][Np] weights,
+// [Np] biases; Kp, Np multiples of 32 / 16) as an FP32 master copy plus a
+// BF16 copy.  Padded rows and columns stay exactly zero: padded inputs are
+// zero, padded output gradients are zero, and Adam leaves a zero-gradient
+// zero-moment entry unchanged.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "rom_common.h"
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+struct rom_mlp {
+  int device, n_in, width, n_out, max_batch;
+  int K[4], N[4];          // padded fan-in / fan-out per layer
+  int64_t off_w[4], off_b[4], npad;  // offsets in the padded parameter vector
+  int64_t nparam;          // unpadded count (host layout)
+  float* P;                // [npad] FP32 master (padded)
+  uint16_t* Pb;            // [npad] BF16 copy
+  float* Mo;               // [npad] Adam first moment
+  float* Vo;               // [npad] Adam second moment
+  float* G;                // [npad] gradient
+  int64_t t;               // Adam step counter
+  float *xm, *xs, *ym, *ys;  // scaling (device)
+  float* A32[4];           // [B][K_l] layer inputs (FP32)
+  uint16_t* A16[4];        // [B][K_l] layer inputs (BF16)
+  float* Z[4];             // [B][N_l] pre-activations
+  float* dZ;               // [B][max N]
+  float* dA;               // [B][max K]
+  float* loss_part;        // [grid] partial losses
+};
+
+namespace {
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu_f(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// C[M][N] (ldc) = sum_k A(m, k) B(k, n) (+ bias[n]); A(m, k) = A[m * sa0 + k * sa1],
+// B(k, n) = B[k * sb0 + n * sb1].  Workgroup tile 64 x 64, wave tile 32 x 32
+// (2 x 2 MFMA tiles of 16 x 16), out-of-range operands read as zero.
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* __restrict__ Av, long sa0, long sa1,
+                                              const void* __restrict__ Bv, long sb0, long sb1, float* __restrict__ C,
+                                              long ldc, const float* __restrict__ bias) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+  if constexpr (BF16) {
+    const uint16_t* A = static_cast<const uint16_t*>(Av);
+    const uint16_t* B = static_cast<const uint16_t*>(Bv);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      bf8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int m = m0 + 16 * i + c;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int k = k0 + 8 * g + t;
+          const uint16_t v = (m < M && k < K) ? A[m * sa0 + k * sa1] : (uint16_t)0;
+          a[i][t] = __builtin_bit_cast(__bf16, v);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + 16 * j + c;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int k = k0 + 8 * g + t;
+          const uint16_t v = (n < N && k < K) ? B[k * sb0 + n * sb1] : (uint16_t)0;
+          b[j][t] = __builtin_bit_cast(__bf16, v);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  } else {
+    const float* A = static_cast<const float*>(Av);
+    const float* B = static_cast<const float*>(Bv);
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + g;
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int m = m0 + 16 * i + c;
+        a[i] = (m < M && k < K) ? A[m * sa0 + k * sa1] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + 16 * j + c;
+        b[j] = (n < N && k < K) ? B[k * sb0 + n * sb1] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // accumulator layout of the 16 x 16 f32-output MFMAs: row 4 g + r, column c
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 16 * i + 4 * g + r, n = n0 + 16 * j + c;
+        if (m < M && n < N) C[m * ldc + n] = acc[i][j][r] + (bias ? bias[n] : 0.f);
+      }
+}
+
+// layer input: x_hat = (x - mean) / std, zero padded to K0 columns
+__global__ void k_scale_in(int B, int n_in, int K0, const float* __restrict__ X, const float* __restrict__ xm,
+                           const float* __restrict__ xs, float* __restrict__ A32, uint16_t* __restrict__ A16) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= (long)B * K0) return;
+  const int b = (int)(i / K0), k = (int)(i % K0);
+  const float v = (k < n_in) ? (X[(long)b * n_in + k] - xm[k]) / xs[k] : 0.f;
+  A32[i] = v;
+  A16[i] = bf16_bits(v);
+}
+
+// next layer input a = silu(z)
+__global__ void k_silu(long count, const float* __restrict__ Z, float* __restrict__ A32, uint16_t* __restrict__ A16) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float v = silu_f(Z[i]);
+  A32[i] = v;
+  A16[i] = bf16_bits(v);
+}
+
+// raw prediction y = y_mean + y_std * z
+__global__ void k_scale_out(int B, int n_out, int Np, const float* __restrict__ Z, const float* __restrict__ ym,
+                            const float* __restrict__ ys, float* __restrict__ Y) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= (long)B * n_out) return;
+  const int b = (int)(i / n_out), k = (int)(i % n_out);
+  Y[i] = ym[k] + ys[k] * Z[(long)b * Np + k];
+}
+
+// dLoss/dout = 2 (out - y_hat) / B on the real outputs, 0 on padding; partial losses per block
+__global__ __launch_bounds__(256) void k_loss(int B, int n_out, int Np, const float* __restrict__ Z,
+                                              const float* __restrict__ Y, const float* __restrict__ ym,
+                                              const float* __restrict__ ys, float* __restrict__ dZ,
+                                              float* __restrict__ part) {
+  __shared__ float red[256];
+  const long i = blockIdx.x * 256L + threadIdx.x;
+  float l = 0.f;
+  if (i < (long)B * Np) {
+    const int b = (int)(i / Np), k = (int)(i % Np);
+    float d = 0.f;
+    if (k < n_out) {
+      const float e = Z[i] - (Y[(long)b * n_out + k] - ym[k]) / ys[k];
+      l = e * e;
+      d = 2.f * e / (float)B;
+    }
+    dZ[i] = d;
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_final(int nblocks, int B, const float* __restrict__ part, float* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float s = 0.f;
+  for (int i = 0; i < nblocks; ++i) s += part[i];
+  *loss = s / (float)B;
+}
+
+// dZ = dA * silu'(Z)
+__global__ void k_dsilu(long count, const float* __restrict__ dA, const float* __restrict__ Z,
+                        float* __restrict__ dZ) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  dZ[i] = dA[i] * dsilu_f(Z[i]);
+}
+
+// db[n] = sum_b dZ[b][n]
+__global__ void k_colsum(int B, int N, const float* __restrict__ dZ, float* __restrict__ db) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) s += dZ[(long)b * N + n];
+  db[n] = s;
+}
+
+__global__ void k_adam(long count, float* __restrict__ P, uint16_t* __restrict__ Pb, float* __restrict__ Mo,
+                       float* __restrict__ Vo, const float* __restrict__ G, float lr, float c1, float c2) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float g = G[i];
+  const float m = 0.9f * Mo[i] + 0.1f * g;
+  const float v = 0.999f * Vo[i] + 0.001f * g * g;
+  Mo[i] = m;
+  Vo[i] = v;
+  const float p = P[i] - lr * (m / c1) / (sqrtf(v / c2) + 1e-8f);
+  P[i] = p;
+  Pb[i] = bf16_bits(p);
+}
+
+__global__ void k_to_bf16(long count, const float* __restrict__ P, uint16_t* __restrict__ Pb) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < count) Pb[i] = bf16_bits(P[i]);
+}
+
+inline unsigned nblk(long count, int bs = 256) { return (unsigned)((count + bs - 1) / bs); }
+
+template <bool BF16>
+void gemm(int M, int N, int K, const void* A, long sa0, long sa1, const void* B, long sb0, long sb1, float* C,
+          long ldc, const float* bias, hipStream_t s) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  k_gemm<BF16><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, C, ldc, bias);
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+void mlp_release(rom_mlp* m) {
+  if (!m) return;
+  void* bufs[] = {m->P, m->Pb, m->Mo, m->Vo, m->G, m->xm, m->xs, m->ym, m->ys, m->dZ, m->dA, m->loss_part};
+  for (void* b : bufs) (void)hipFree(b);
+  for (int l = 0; l < 4; ++l) {
+    (void)hipFree(m->A32[l]);
+    (void)hipFree(m->A16[l]);
+    (void)hipFree(m->Z[l]);
+  }
+  delete m;
+}
+
+// forward from the scaled input already in A32[0] / A16[0]; output pre-activations in Z[3]
+int mlp_forward_scaled(rom_mlp* m, int B, int prec, hipStream_t s) {
+  for (int l = 0; l < 4; ++l) {
+    const int K = m->K[l], N = m->N[l];
+    if (prec == ROM_DT_BF16)
+      gemm<true>(B, N, K, m->A16[l], K, 1, m->Pb + m->off_w[l], N, 1, m->Z[l], N, m->P + m->off_b[l], s);
+    else
+      gemm<false>(B, N, K, m->A32[l], K, 1, m->P + m->off_w[l], N, 1, m->Z[l], N, m->P + m->off_b[l], s);
+    if (l < 3) k_silu<<<nblk((long)B * N), 256, 0, s>>>((long)B * N, m->Z[l], m->A32[l + 1], m->A16[l + 1]);
+  }
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int mlp_gradients(rom_mlp* m, int B, const float* X, const float* Y, int prec, float* loss, hipStream_t s) {
+  k_scale_in<<<nblk((long)B * m->K[0]), 256, 0, s>>>(B, m->n_in, m->K[0], X, m->xm, m->xs, m->A32[0], m->A16[0]);
+  int rc = mlp_forward_scaled(m, B, prec, s);
+  if (rc != ROM_OK) return rc;
+  const int Np = m->N[3];
+  const unsigned nb = nblk((long)B * Np);
+  k_loss<<<nb, 256, 0, s>>>(B, m->n_out, Np, m->Z[3], Y, m->ym, m->ys, m->dZ, m->loss_part);
+  if (loss) k_loss_final<<<1, 64, 0, s>>>((int)nb, B, m->loss_part, loss);
+  for (int l = 3; l >= 0; --l) {
+    const int K = m->K[l], N = m->N[l];
+    if (l < 3) k_dsilu<<<nblk((long)B * N), 256, 0, s>>>((long)B * N, m->dA, m->Z[l], m->dZ);
+    // dW = A^T dZ  (M = K, N = N, inner = B)
+    gemm<false>(K, N, B, m->A32[l], 1, K, m->dZ, N, 1, m->G + m->off_w[l], N, nullptr, s);
+    k_colsum<<<nblk(N), 256, 0, s>>>(B, N, m->dZ, m->G + m->off_b[l]);
+    // dA_prev = dZ W^T  (M = B, N = K, inner = N)
+    if (l > 0) gemm<false>(B, K, N, m->dZ, N, 1, m->P + m->off_w[l], 1, N, m->dA, K, nullptr, s);
+  }
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rom_mlp_create(int32_t n_in, int32_t width, int32_t n_out, int32_t max_batch, int device, rom_mlp_handle* out) {
+  if (!out || n_in < 1 || n_in > 1024 || width < 16 || width > 1024 || width % 32 || n_out < 1 || n_out > 1024 ||
+      max_batch < 1 || max_batch > (1 << 20))
+    return ROM_EINVAL;
+  *out = nullptr;
+  DeviceGuard guard(device);
+  rom_mlp* m = new rom_mlp();
+  memset(m, 0, sizeof(*m));
+  m->device = device;
+  m->n_in = n_in;
+  m->width = width;
+  m->n_out = n_out;
+  m->max_batch = max_batch;
+  const int K0 = (n_in + 31) / 32 * 32, No = (n_out + 15) / 16 * 16;
+  const int Ks[4] = {K0, width, width, width}, Ns[4] = {width, width, width, No};
+  int64_t o = 0;
+  for (int l = 0; l < 4; ++l) {
+    m->K[l] = Ks[l];
+    m->N[l] = Ns[l];
+    m->off_w[l] = o;
+    o += (int64_t)Ks[l] * Ns[l];
+    m->off_b[l] = o;
+    o += Ns[l];
+  }
+  m->npad = o;
+  m->nparam = (int64_t)n_in * width + width + 2 * ((int64_t)width * width + width) + (int64_t)width * n_out + n_out;
+  bool ok = true;
+  auto al = [&](void** p, size_t bytes) {
+    if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
+    if (ok && hipMemset(*p, 0, bytes) != hipSuccess) ok = false;
+  };
+  al((void**)&m->P, 4 * o);
+  al((void**)&m->Pb, 2 * o);
+  al((void**)&m->Mo, 4 * o);
+  al((void**)&m->Vo, 4 * o);
+  al((void**)&m->G, 4 * o);
+  al((void**)&m->xm, 4 * K0);
+  al((void**)&m->xs, 4 * K0);
+  al((void**)&m->ym, 4 * No);
+  al((void**)&m->ys, 4 * No);
+  const int maxKN = width > No ? (width > K0 ? width : K0) : No;
+  for (int l = 0; l < 4; ++l) {
+    al((void**)&m->A32[l], 4L * max_batch * Ks[l]);
+    al((void**)&m->A16[l], 2L * max_batch * Ks[l]);
+    al((void**)&m->Z[l], 4L * max_batch * Ns[l]);
+  }
+  al((void**)&m->dZ, 4L * max_batch * maxKN);
+  al((void**)&m->dA, 4L * max_batch * maxKN);
+  al((void**)&m->loss_part, 4L * ((long)max_batch * No / 256 + 2));
+  if (!ok) {
+    mlp_release(m);
+    return ROM_EHIP;
+  }
+  // unit scaling until set
+  std::vector<float> ones(K0 > No ? K0 : No, 1.0f);
+  (void)hipMemcpy(m->xs, ones.data(), 4 * K0, hipMemcpyHostToDevice);
+  (void)hipMemcpy(m->ys, ones.data(), 4 * No, hipMemcpyHostToDevice);
+  *out = m;
+  return ROM_OK;
+}
+
+int rom_mlp_free(rom_mlp_handle m) {
+  if (!m) return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  mlp_release(m);
+  return ROM_OK;
+}
+
+int rom_mlp_param_count(rom_mlp_handle m, int64_t* count) {
+  if (!m || !count) return ROM_EINVAL;
+  *count = m->nparam;
+  return ROM_OK;
+}
+
+int rom_mlp_set_params(rom_mlp_handle m, const float* host, int64_t count) {
+  if (!m || !host || count != m->nparam) return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  std::vector<float> pad(m->npad, 0.0f);
+  const int fi[4] = {m->n_in, m->width, m->width, m->width}, fo[4] = {m->width, m->width, m->width, m->n_out};
+  int64_t src = 0;
+  for (int l = 0; l < 4; ++l) {
+    for (int i = 0; i < fi[l]; ++i)
+      for (int j = 0; j < fo[l]; ++j) pad[m->off_w[l] + (int64_t)i * m->N[l] + j] = host[src++];
+    for (int j = 0; j < fo[l]; ++j) pad[m->off_b[l] + j] = host[src++];
+  }
+  if (hipMemcpy(m->P, pad.data(), 4 * m->npad, hipMemcpyHostToDevice) != hipSuccess) return ROM_EHIP;
+  k_to_bf16<<<nblk(m->npad), 256>>>(m->npad, m->P, m->Pb);
+  if (hipMemset(m->Mo, 0, 4 * m->npad) != hipSuccess || hipMemset(m->Vo, 0, 4 * m->npad) != hipSuccess)
+    return ROM_EHIP;
+  m->t = 0;
+  return hipDeviceSynchronize() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int rom_mlp_get_params(rom_mlp_handle m, float* host, int64_t count) {
+  if (!m || !host || count != m->nparam) return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  std::vector<float> pad(m->npad);
+  if (hipDeviceSynchronize() != hipSuccess) return ROM_EHIP;
+  if (hipMemcpy(pad.data(), m->P, 4 * m->npad, hipMemcpyDeviceToHost) != hipSuccess) return ROM_EHIP;
+  const int fi[4] = {m->n_in, m->width, m->width, m->width}, fo[4] = {m->width, m->width, m->width, m->n_out};
+  int64_t dst = 0;
+  for (int l = 0; l < 4; ++l) {
+    for (int i = 0; i < fi[l]; ++i)
+      for (int j = 0; j < fo[l]; ++j) host[dst++] = pad[m->off_w[l] + (int64_t)i * m->N[l] + j];
+    for (int j = 0; j < fo[l]; ++j) host[dst++] = pad[m->off_b[l] + j];
+  }
+  return ROM_OK;
+}
+
+int rom_mlp_set_scaling(rom_mlp_handle m, const float* xm, const float* xs, const float* ym, const float* ys) {
+  if (!m || !xm || !xs || !ym || !ys) return ROM_EINVAL;
+  for (int i = 0; i < m->n_in; ++i)
+    if (!(xs[i] > 0) || !isfinite(xm[i])) return ROM_EINVAL;
+  for (int i = 0; i < m->n_out; ++i)
+    if (!(ys[i] > 0) || !isfinite(ym[i])) return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  bool ok = hipMemcpy(m->xm, xm, 4 * m->n_in, hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(m->xs, xs, 4 * m->n_in, hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(m->ym, ym, 4 * m->n_out, hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(m->ys, ys, 4 * m->n_out, hipMemcpyHostToDevice) == hipSuccess;
+  return ok ? ROM_OK : ROM_EHIP;
+}
+
+int rom_mlp_forward(rom_mlp_handle m, int32_t B, const float* X, float* Y, int32_t prec, hipStream_t s) {
+  if (!m || B < 0 || B > m->max_batch || (prec != ROM_DT_F32 && prec != ROM_DT_BF16)) return ROM_EINVAL;
+  if (B == 0) return ROM_OK;
+  if (!X || !Y) return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  k_scale_in<<<nblk((long)B * m->K[0]), 256, 0, s>>>(B, m->n_in, m->K[0], X, m->xm, m->xs, m->A32[0], m->A16[0]);
+  int rc = mlp_forward_scaled(m, B, prec, s);
+  if (rc != ROM_OK) return rc;
+  k_scale_out<<<nblk((long)B * m->n_out), 256, 0, s>>>(B, m->n_out, m->N[3], m->Z[3], m->ym, m->ys, Y);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int rom_mlp_gradients(rom_mlp_handle m, int32_t B, const float* X, const float* Y, int32_t prec, float* grads,
+                      float* loss, hipStream_t s) {
+  if (!m || B < 1 || B > m->max_batch || !X || !Y || (prec != ROM_DT_F32 && prec != ROM_DT_BF16)) return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  int rc = mlp_gradients(m, B, X, Y, prec, loss, s);
+  if (rc != ROM_OK || !grads) return rc;
+  // unpad into the host parameter layout
+  const int fi[4] = {m->n_in, m->width, m->width, m->width}, fo[4] = {m->width, m->width, m->width, m->n_out};
+  int64_t dst = 0;
+  for (int l = 0; l < 4; ++l) {
+    if (hipMemcpy2DAsync(grads + dst, 4 * fo[l], m->G + m->off_w[l], 4 * m->N[l], 4 * fo[l], fi[l],
+                         hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return ROM_EHIP;
+    dst += (int64_t)fi[l] * fo[l];
+    if (hipMemcpyAsync(grads + dst, m->G + m->off_b[l], 4 * fo[l], hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return ROM_EHIP;
+    dst += fo[l];
+  }
+  return ROM_OK;
+}
+
+int rom_mlp_train_step(rom_mlp_handle m, int32_t B, const float* X, const float* Y, float lr, int32_t prec,
+                       float* loss, hipStream_t s) {
+  if (!m || B < 1 || B > m->max_batch || !X || !Y || !(lr > 0) || (prec != ROM_DT_F32 && prec != ROM_DT_BF16))
+    return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  int rc = mlp_gradients(m, B, X, Y, prec, loss, s);
+  if (rc != ROM_OK) return rc;
+  m->t += 1;
+  const float c1 = 1.0f - powf(0.9f, (float)m->t), c2 = 1.0f - powf(0.999f, (float)m->t);
+  k_adam<<<nblk(m->npad), 256, 0, s>>>(m->npad, m->P, m->Pb, m->Mo, m->Vo, m->G, lr, c1, c2);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+}  // extern "C"
+
+// in-library entry for the warm start of rom_step: raw features -> raw dr
+int rom_mlp_predict(rom_mlp* m, int B, const float* X, float* Y, hipStream_t s) {
+  for (int b0 = 0; b0 < B; b0 += m->max_batch) {
+    const int b = B - b0 < m->max_batch ? B - b0 : m->max_batch;
+    const int rc = rom_mlp_forward(m, b, X + (size_t)b0 * m->n_in, Y + (size_t)b0 * m->n_out, ROM_DT_BF16, s);
+    if (rc != ROM_OK) return rc;
+  }
+  return ROM_OK;
+}
+int rom_mlp_dims(const rom_mlp* m, int* n_in, int* n_out) {
+  *n_in = m->n_in;
+  *n_out = m->n_out;
+  return ROM_OK;
+}

@@ -263,14 +263,25 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
     rom_default_opts(&o);
   if (o.max_iter < 1 || o.max_iter > 1000 || !(o.tol >= 0.0)) return ROM_EINVAL;
   if (o.contraction < ROM_DT_F64 || o.contraction > ROM_DT_BF16) return ROM_EINVAL;
+  if (o.warm_start != ROM_WARM_PREV && o.warm_start != ROM_WARM_MLP) return ROM_EINVAL;
+  if (o.warm_start == ROM_WARM_MLP && !o.mlp) return ROM_EINVAL;
   DeviceGuard guard(h->device);
   if (o.mode == ROM_MODE_STAGED) {
-    if (o.contraction != ROM_DT_F64) return ROM_EUNSUPPORTED;
+    if (o.contraction != ROM_DT_F64 || o.warm_start != ROM_WARM_PREV) return ROM_EUNSUPPORTED;
     return rom_launch_step_staged(h, batch, Fbar_dev, state_dev, o, status_dev, iters_dev, resnorm_dev, stream);
   }
   if (o.mode == ROM_MODE_FUSED)
     return rom_launch_step_fused(h, batch, Fbar_dev, state_dev, o, status_dev, iters_dev, resnorm_dev, stream);
   return ROM_EINVAL;
+}
+
+int rom_features(rom_handle h, int32_t batch, const double* Fbar_dev, const void* state_dev, float* X_dev,
+                 hipStream_t stream) {
+  if (!h || batch < 0) return ROM_EINVAL;
+  if (batch == 0) return ROM_OK;
+  if (!Fbar_dev || !state_dev || !X_dev || batch > 65535) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  return rom_launch_features(h, batch, Fbar_dev, state_dev, X_dev, stream);
 }
 
 int rom_homogenized_stress_tangent(rom_handle h, int32_t batch, const void* state_dev, double* Pbar_dev,

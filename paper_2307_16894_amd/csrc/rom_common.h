@@ -34,13 +34,21 @@ struct rom_model {
 // Record the start / stop event of a timed launch; no-ops unless enabled.
 int rom_timing_mark(rom_model* h, int stop, hipStream_t s);
 
+// warm-start network entry points used by rom_step (mlp.hip)
+int rom_mlp_predict(struct rom_mlp* m, int B, const float* X, float* Y, hipStream_t s);
+int rom_mlp_dims(const struct rom_mlp* m, int* n_in, int* n_out);
+int rom_launch_features(const rom_model* h, int P, const double* Fbar, const void* state, float* X, hipStream_t s);
+
 // Internal state fields (public ones first, same numbering as ROM_FIELD_*).
 enum {
-  F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK,
-  F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT,
+  F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK, F_FBC, F_RG,
+  F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT, F_XF, F_DR, F_MU,
   F_D, F_W, F_K, F_F, F_PIV,
   F_NFIELDS
 };
+
+// per-point inputs of the warm-start network: mu, Fbar - Fbar_committed, r, 8 statistics
+static inline int rom_n_features(const rom_model* h) { return h->n_mu + 4 + h->n + 8; }
 
 struct StateLayout {
   size_t off[F_NFIELDS];
@@ -60,11 +68,16 @@ static inline StateLayout rom_state_layout(const rom_model* h, size_t P) {
   sz[F_PBAR] = P * 4 * 8;
   sz[F_ABAR] = P * 16 * 8;
   sz[F_MUOK] = P * 4;
+  sz[F_FBC] = P * 4 * 8;
+  sz[F_RG] = P * n * 8;
   sz[F_DONE] = P * 4;
   sz[F_STATUS] = P * 4;
   sz[F_ITERS] = P * 4;
   sz[F_RES] = P * 8;
   sz[F_COUNT] = 64;
+  sz[F_XF] = P * (size_t)rom_n_features(h) * 4;
+  sz[F_DR] = P * n * 4;
+  sz[F_MU] = P * (size_t)h->n_mu * 8;
   sz[F_D] = P * 16 * m * 8;
   sz[F_W] = P * 4 * m * 8;
   sz[F_K] = P * n * n * 8;

@@ -53,6 +53,9 @@ struct FusedArgs {
   int* st_out;
   int* it_out;
   double* res_out;
+  const float* dr;   // warm-start increments [P][n] (NULL: plain guess)
+  double* rg;        // initial guess actually used [P][n]
+  double* fbc;       // committed Fbar [P][4]
 };
 
 // ECM points per chunk of the effective-quantity pass (E records sit above the LU)
@@ -362,7 +365,16 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
     }
     return;
   }
-  for (int i = tid; i < NPAD; i += 256) sR[i] = (i < n) ? a.rc[(size_t)p * n + i] : 0.0;
+  // initial guess: the committed r, plus the predicted increment with a warm start
+  for (int i = tid; i < NPAD; i += 256) {
+    double v = 0.0;
+    if (i < n) {
+      v = a.rc[(size_t)p * n + i];
+      if (a.dr) v += (double)a.dr[(size_t)p * n + i];
+      a.rg[(size_t)p * n + i] = v;
+    }
+    sR[i] = v;
+  }
   const double Fb[4] = {a.Fbar[4 * (size_t)p], a.Fbar[4 * (size_t)p + 1], a.Fbar[4 * (size_t)p + 2],
                         a.Fbar[4 * (size_t)p + 3]};
   const double* tmu = a.tmu + (size_t)p * 5 * m;
@@ -372,7 +384,8 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
 
   const int k_row = lane >> 4, c_col = lane & 15;
   int status = ROM_ST_MAXITER, iters = 0;
-  double rn = 0.0;
+  double rn = 0.0, rn0 = 0.0;
+  bool fell_back = false;
   for (int it = 0; it < a.max_iter; ++it) {
     constexpr bool QSPLIT = (T <= 5);                 // small n: waves split the points
     constexpr int NACC = QSPLIT ? NT : (NT + 3) / 4;  // large n: waves split the tiles
@@ -501,7 +514,16 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
       stop = last;
       status = ROM_ST_MAXITER;
     }
+    if (it == 0) rn0 = rn;
     if (stop) break;
+    // warm start judged by plain Newton: no tenfold drop of ||f|| after two
+    // updates -> restart from the committed r
+    if (a.dr && !fell_back && it == 2 && !(rn <= 0.1 * rn0)) {
+      fell_back = true;
+      for (int i = tid; i < n; i += 256) sR[i] = a.rc[(size_t)p * n + i];
+      __syncthreads();
+      continue;
+    }
     // Newton update: K dr = -f
     gauss_solve(sK, NPAD, n, n, 1, sStep, sOrder, sSol);
     if (tid < n) sR[tid] -= sSol[4 * tid];
@@ -590,11 +612,12 @@ __global__ __launch_bounds__(256) void k_fused(const FusedArgs a) {
   }
   for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i];
   if (tid == 0) {
-    a.st_out[p] = status;
+    a.st_out[p] = (status == ROM_ST_CONVERGED && fell_back) ? ROM_ST_FALLBACK : status;
     a.it_out[p] = iters;
     a.res_out[p] = rn;
   }
   if (a.commit && status == ROM_ST_CONVERGED) {
+    if (tid < 4) a.fbc[4 * (size_t)p + tid] = Fb[tid];
     for (int i = tid; i < n; i += 256) a.rc[(size_t)p * n + i] = sR[i];
     double* hcw = a.hc + (size_t)p * 6 * m;
     for (int q = tid; q < m; q += 256)
@@ -676,6 +699,21 @@ int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, 
   a.st_out = st_out;
   a.it_out = it_out;
   a.res_out = res_out;
+  a.rg = field<double>(state, L, F_RG);
+  a.fbc = field<double>(state, L, F_FBC);
+  a.dr = nullptr;
+  if (o.warm_start == ROM_WARM_MLP) {
+    int nin = 0, nout = 0;
+    rom_mlp_dims(o.mlp, &nin, &nout);
+    if (nin != rom_n_features(h) || nout != h->n) return ROM_EINVAL;
+    float* X = field<float>(state, L, F_XF);
+    float* DR = field<float>(state, L, F_DR);
+    int rc = rom_launch_features(h, P, Fbar, state, X, s);
+    if (rc != ROM_OK) return rc;
+    rc = rom_mlp_predict(o.mlp, P, X, DR, s);
+    if (rc != ROM_OK) return rc;
+    a.dr = DR;
+  }
   if (rom_timing_mark(h, 0, s) != ROM_OK) return ROM_EHIP;
   int rc;
   switch (T) {

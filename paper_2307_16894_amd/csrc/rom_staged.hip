@@ -48,11 +48,15 @@ __global__ __launch_bounds__(128) void k_state_init(int n, int m, int c, int kin
                                                      const double* __restrict__ w, const double* __restrict__ Gd,
                                                      double* __restrict__ rc, double* __restrict__ hc,
                                                      double* __restrict__ tmu, int* __restrict__ muok,
-                                                     int* __restrict__ count) {
+                                                     int* __restrict__ count, double* __restrict__ fbc,
+                                                     double* __restrict__ mu_copy) {
   const int p = blockIdx.y;
   const int q = blockIdx.x * 128 + threadIdx.x;
-  if (blockIdx.x == 0)
+  if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < n; i += 128) rc[(size_t)p * n + i] = 0.0;
+    if (threadIdx.x < 4) fbc[4 * (size_t)p + threadIdx.x] = (threadIdx.x == 0 || threadIdx.x == 3) ? 1.0 : 0.0;
+    if (threadIdx.x < n_mu) mu_copy[(size_t)p * n_mu + threadIdx.x] = mu[(size_t)p * n_mu + threadIdx.x];
+  }
   if (q >= m) return;
   double cc[12];
   mu_to_c(kind, mu + (size_t)p * n_mu, r0, void_area, cc);
@@ -536,7 +540,8 @@ __global__ __launch_bounds__(128) void k_effective(int n, int npad, int m, doubl
   if (tid < 4) Pbar[4 * (size_t)p + tid] = (red[tid * 2] + red[tid * 2 + 1]) * inv_area;
 }
 
-__global__ __launch_bounds__(256) void k_finish(int n, int m, int commit, const int* __restrict__ status,
+__global__ __launch_bounds__(256) void k_finish(int n, int m, int commit, const double* __restrict__ Fbar,
+                                                double* __restrict__ fbc, const int* __restrict__ status,
                                                 const int* __restrict__ iters, const double* __restrict__ res,
                                                 const double* __restrict__ rt, double* __restrict__ rc,
                                                 const double* __restrict__ ht, double* __restrict__ hc,
@@ -551,11 +556,76 @@ __global__ __launch_bounds__(256) void k_finish(int n, int m, int commit, const 
     res_out[p] = res[p];
   }
   if (!(commit && st == ROM_ST_CONVERGED)) return;
+  if (tid < 4) fbc[4 * (size_t)p + tid] = Fbar[4 * (size_t)p + tid];
   for (int i = tid; i < n; i += 256) rc[(size_t)p * n + i] = rt[(size_t)p * n + i];
   for (int i = tid; i < 6 * m; i += 256) hc[(size_t)p * 6 * m + i] = ht[(size_t)p * 6 * m + i];
 }
 
+// Inputs of the warm-start network for the step to Fbar: mu, Fbar - Fbar_committed,
+// r_committed and eight statistics of the committed plastic state weighted by
+// w_q |det F_mu|: mean / max / standard deviation of xi, yielded fraction,
+// mean of F^pl - I.  One block per point.
+__global__ __launch_bounds__(256) void k_features(int n, int m, int n_mu, const double* __restrict__ mu,
+                                                  const double* __restrict__ Fbar, const double* __restrict__ fbc,
+                                                  const double* __restrict__ rc, const double* __restrict__ hc,
+                                                  const double* __restrict__ tmu, float* __restrict__ X) {
+  const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nf = n_mu + 4 + n + 8;
+  float* x = X + (size_t)p * nf;
+  __shared__ double red[4][10];
+  double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // sum w, w xi, w xi^2, w [xi>0], w (Fp - I) (4), max xi
+  const double* h = hc + (size_t)p * 6 * m;
+  const double* t = tmu + (size_t)p * 5 * m;
+  for (int q = tid; q < m; q += 256) {
+    const double w = t[4 * m + q], xi = h[5 * m + q];
+    s[0] += w;
+    s[1] += w * xi;
+    s[2] += w * xi * xi;
+    s[3] += (xi > 0.0) ? w : 0.0;
+    s[4] += w * (h[q] - 1.0);
+    s[5] += w * h[m + q];
+    s[6] += w * h[2 * m + q];
+    s[7] += w * (h[3 * m + q] - 1.0);
+    s[8] = fmax(s[8], xi);
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double v = s[k];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double u = __shfl_xor(v, o);
+      v = (k == 8) ? fmax(v, u) : v + u;
+    }
+    if (lane == 0) red[wave][k] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tot[9];
+    for (int k = 0; k < 9; ++k) {
+      tot[k] = red[0][k];
+      for (int w = 1; w < 4; ++w) tot[k] = (k == 8) ? fmax(tot[k], red[w][k]) : tot[k] + red[w][k];
+    }
+    const double W = tot[0], mean = tot[1] / W;
+    float* st = x + n_mu + 4 + n;
+    st[0] = (float)mean;
+    st[1] = (float)tot[8];
+    st[2] = (float)sqrt(fmax(tot[2] / W - mean * mean, 0.0));
+    st[3] = (float)(tot[3] / W);
+    for (int k = 0; k < 4; ++k) st[4 + k] = (float)(tot[4 + k] / W);
+  }
+  if (tid < n_mu) x[tid] = (float)mu[(size_t)p * n_mu + tid];
+  if (tid < 4) x[n_mu + tid] = (float)(Fbar[4 * (size_t)p + tid] - fbc[4 * (size_t)p + tid]);
+  for (int i = tid; i < n; i += 256) x[n_mu + 4 + i] = (float)rc[(size_t)p * n + i];
+}
+
 }  // namespace
+
+int rom_launch_features(const rom_model* h, int P, const double* Fbar, const void* state, float* X, hipStream_t s) {
+  const StateLayout L = rom_state_layout(h, P);
+  void* st = const_cast<void*>(state);
+  k_features<<<P, 256, 0, s>>>(h->n, h->m, h->n_mu, field<double>(st, L, F_MU), Fbar, field<double>(st, L, F_FBC),
+                               field<double>(st, L, F_RC), field<double>(st, L, F_HC), field<double>(st, L, F_TMU), X);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
 
 int rom_staged_setup() {
   // k_solve keeps the n x n matrix in LDS: up to ~132 KB at n = 128.
@@ -574,7 +644,8 @@ int rom_launch_state_init(const rom_model* h, int P, const double* mu, void* sta
   dim3 g((h->m + 127) / 128, P);
   k_state_init<<<g, 128, 0, s>>>(h->n, h->m, h->c, h->kind, h->n_mu, h->r0, h->void_area, mu, h->w, h->Gd,
                                  field<double>(state, L, F_RC), field<double>(state, L, F_HC),
-                                 field<double>(state, L, F_TMU), muok, count);
+                                 field<double>(state, L, F_TMU), muok, count, field<double>(state, L, F_FBC),
+                                 field<double>(state, L, F_MU));
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 
@@ -610,6 +681,7 @@ int rom_launch_step_staged(rom_model* h, int P, const double* Fbar, void* state,
   }
   k_effective<<<P, 128, 0, s>>>(n, h->npad, m, 1.0 / h->cell_area, h->mp, h->Gt, h->Gq, Fbar, rt, hc, tmu, muok,
                                 K, piv, field<double>(state, L, F_PBAR), field<double>(state, L, F_ABAR));
-  k_finish<<<P, 256, 0, s>>>(n, m, o.commit, status, iters, res, rt, rc, ht, hc, st_out, it_out, res_out);
+  k_finish<<<P, 256, 0, s>>>(n, m, o.commit, Fbar, field<double>(state, L, F_FBC), status, iters, res, rt, rc, ht,
+                             hc, st_out, it_out, res_out);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }

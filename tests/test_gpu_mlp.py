@@ -1,0 +1,177 @@
+"""Warm-start network kernels against the FP64 oracle network, the feature
+kernel against the oracle's statistics, and what the trained network gains
+over plain Newton (with plain Newton as the judge)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import mlp as OM
+from oracle.rom import ROM
+from tests.conftest import rom_path
+
+import paper_2307_16894_amd as L
+from paper_2307_16894_amd.batch import RomBatch
+from paper_2307_16894_amd.warmstart import WarmStart, generate, init_params
+
+pytestmark = pytest.mark.gpu
+NAME = 'onevoid_n20_m120'
+
+
+def unflatten(flat, dims):
+    out, o = [], 0
+    for fi, fo in zip(dims[:-1], dims[1:]):
+        out.append(flat[o:o + fi * fo].reshape(fi, fo).astype(np.float64))
+        o += fi * fo
+        out.append(flat[o:o + fo].astype(np.float64))
+        o += fo
+    return out
+
+
+def flatten(ps):
+    return np.concatenate([p.reshape(-1) for p in ps])
+
+
+@pytest.fixture(scope='module')
+def net(gpu):
+    dims = [54, 256, 256, 256, 40]
+    ws = WarmStart(54, 40, max_batch=512, seed=3)
+    g = np.random.Generator(np.random.PCG64(4))
+    X = g.normal(size=(300, 54)).astype(np.float32)
+    Y = g.normal(size=(300, 40)).astype(np.float32)
+    return ws, dims, X, Y
+
+
+def test_param_count(net):
+    ws, dims, X, Y = net
+    assert ws.param_count == 155944 == sum(fi * fo + fo for fi, fo in zip(dims[:-1], dims[1:]))
+
+
+def test_fp32_gradients_match_oracle(net):
+    ws, dims, X, Y = net
+    L.rom_mlp_set_scaling(ws.h, np.zeros(54), np.ones(54), np.zeros(40), np.ones(40))
+    p = ws.params()
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    grads = torch.zeros(p.size, dtype=torch.float32, device='cuda')
+    loss = torch.zeros(1, dtype=torch.float32, device='cuda')
+    L.rom_mlp_gradients(ws.h, 300, Xd.data_ptr(), Yd.data_ptr(), L.DT_F32, grads.data_ptr(), loss.data_ptr(),
+                        torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ref_loss, ref = OM.backward(unflatten(p, dims), X.astype(np.float64), Y.astype(np.float64))
+    got = unflatten(grads.cpu().numpy(), dims)
+    assert abs(loss.item() - ref_loss) < 1e-5 * ref_loss
+    for a, b in zip(got, ref):
+        assert np.linalg.norm(a - b) < 1e-4 * max(np.linalg.norm(b), 1e-12)
+
+
+def test_bf16_forward_matches_oracle(net):
+    ws, dims, X, Y = net
+    xm, xs = X.mean(0), X.std(0) * 2
+    ym, ys = np.full(40, 0.3, np.float32), np.full(40, 2.0, np.float32)
+    L.rom_mlp_set_scaling(ws.h, xm, xs, ym, ys)
+    p = ws.params()
+    Xd = torch.from_numpy(X).cuda()
+    out = torch.zeros(300, 40, dtype=torch.float32, device='cuda')
+    for prec, tol in ((L.DT_F32, 1e-5), (L.DT_BF16, 3e-2)):
+        L.rom_mlp_forward(ws.h, 300, Xd.data_ptr(), out.data_ptr(), prec, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        ref = ym + ys * OM.forward(unflatten(p, dims), (X.astype(np.float64) - xm) / xs)[0]
+        err = np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err < tol, (prec, err)
+
+
+def test_adam_step_matches_oracle(net):
+    ws, dims, X, Y = net
+    L.rom_mlp_set_scaling(ws.h, np.zeros(54), np.ones(54), np.zeros(40), np.ones(40))
+    p0 = init_params(54, 256, 40, 11)
+    L.rom_mlp_set_params(ws.h, p0)
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    loss = torch.zeros(1, dtype=torch.float32, device='cuda')
+    s = torch.cuda.current_stream().cuda_stream
+    P = unflatten(p0, dims)
+    m = [np.zeros_like(q) for q in P]
+    v = [np.zeros_like(q) for q in P]
+    for t in range(1, 4):
+        L.rom_mlp_train_step(ws.h, 300, Xd.data_ptr(), Yd.data_ptr(), 1e-3, L.DT_F32, loss.data_ptr(), s)
+        _, g = OM.backward(P, X.astype(np.float64), Y.astype(np.float64))
+        P, m, v = OM.adam(P, g, m, v, t, 1e-3)
+    torch.cuda.synchronize()
+    got = ws.params()
+    ref = flatten(P)
+    moved = np.abs(ref - p0).max()
+    assert np.abs(got - ref).max() < 2e-2 * moved  # Adam normalises steps: compare against the step size
+
+
+def test_features_match_oracle_statistics(gpu):
+    P = 8
+    mu = workloads.one_void_mu(7, P)
+    paths = workloads.monotone_paths(7, P, 10)
+    rb = RomBatch(rom_path(NAME), mu)
+    s = torch.cuda.current_stream().cuda_stream
+    for k in range(4):
+        rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda())
+    Fb = torch.from_numpy(np.ascontiguousarray(paths[:, 4])).cuda()
+    X = torch.zeros(P, 2 + 4 + 20 + 8, dtype=torch.float32, device='cuda')
+    L.rom_features(rb.h, P, Fb.data_ptr(), rb.state.data_ptr(), X.data_ptr(), s)
+    torch.cuda.synchronize()
+    X = X.cpu().numpy()
+    rom = ROM(rom_path(NAME))
+    h = rb.history().cpu().numpy()
+    r = rb.r().cpu().numpy()
+    for p in range(P):
+        Finv, J = rom.transformation(mu[p])
+        wJ = rom.w * np.abs(J)
+        hist = (h[p, 0:4].T.reshape(-1, 2, 2), h[p, 4], h[p, 5])
+        ref = np.concatenate([mu[p], (paths[p, 4] - paths[p, 3]).reshape(-1), r[p],
+                              OM.plastic_statistics(wJ, hist)])
+        assert np.abs(X[p] - ref).max() < 1e-6 * max(1.0, np.abs(ref).max())
+    assert X[:, -7].max() > 0  # some points have yielded
+    rb.close()
+
+
+def test_warm_start_gain_and_fallback(gpu):
+    """Train on ROM trajectories, then compare with plain Newton on held-out
+    paths at the same 1e-8 residual."""
+    Ptr, Pte, K = 4096, 256, 10
+    rb = RomBatch(rom_path(NAME), workloads.one_void_mu(21, Ptr))
+    X, Y = generate(rb, workloads.monotone_paths(21, Ptr, K))
+    rb.close()
+    ws = WarmStart(X.shape[1], Y.shape[1], max_batch=2048, seed=0)
+    ws.fit_scaling(X, Y)
+    hist = ws.train(X, Y, epochs=25, batch=512, lr=2e-3, precision=L.DT_BF16)
+    assert hist[-1] < 0.2 * hist[0]
+    mu = workloads.one_void_mu(22, Pte)
+    paths = workloads.monotone_paths(22, Pte, K)
+    res = {}
+    for name, opts in (('plain', L.rom_default_opts(mode=L.MODE_FUSED)), ('mlp', ws.opts())):
+        rb = RomBatch(rom_path(NAME), mu)
+        its, Pb, st = [], [], []
+        for k in range(K):
+            s_, i_, r_ = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), opts)
+            torch.cuda.synchronize()
+            its.append(i_.cpu().numpy().copy())
+            st.append(s_.cpu().numpy().copy())
+            Pb.append(rb.Pbar.cpu().numpy().copy())
+        rb.close()
+        res[name] = (np.array(its), np.array(st), np.array(Pb))
+    ip, sp, Pp = res['plain']
+    im, sm, Pm = res['mlp']
+    assert (sp == 0).all() and np.isin(sm, [0, 3]).all()
+    assert np.abs(Pm - Pp).max() < 1e-6 * np.abs(Pp).max()
+    print(f"mean Newton evaluations: plain {ip.mean():.3f}, learned warm start {im.mean():.3f}, "
+          f"fallbacks {(sm == 3).mean():.4f}")
+    assert im.mean() < ip.mean()
+    # a scrambled network: the fallback fires and the results still match plain Newton
+    L.rom_mlp_set_params(ws.h, 40.0 * init_params(X.shape[1], 256, Y.shape[1], 99))
+    rb = RomBatch(rom_path(NAME), mu)
+    fell = 0
+    for k in range(K):
+        s_, i_, r_ = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), ws.opts())
+        torch.cuda.synchronize()
+        s_ = s_.cpu().numpy()
+        assert np.isin(s_, [0, 3]).all()
+        fell += int((s_ == 3).sum())
+        assert np.abs(rb.Pbar.cpu().numpy() - Pp[k]).max() < 1e-6 * np.abs(Pp).max()
+    rb.close()
+    assert fell > 0
+    ws.close()

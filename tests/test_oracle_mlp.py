@@ -1,0 +1,56 @@
+"""Pins of the warm-start network oracle: hand-derived gradients against
+central finite differences, the first Adam step in closed form, and the
+plastic summary statistics on a hand-made state."""
+import numpy as np
+
+from oracle import mlp
+
+DIMS = [54, 16, 16, 16, 40]
+
+
+def test_gradients_match_finite_differences():
+    params = mlp.init(DIMS, 0)
+    g = np.random.Generator(np.random.PCG64(1))
+    X = g.normal(size=(7, DIMS[0]))
+    Y = g.normal(size=(7, DIMS[-1]))
+    L0, grads = mlp.backward(params, X, Y)
+    assert abs(L0 - mlp.loss(params, X, Y)) < 1e-14
+    h = 1e-6
+    for pi in range(len(params)):
+        flat = params[pi].reshape(-1)
+        idx = g.choice(flat.size, size=min(6, flat.size), replace=False)
+        for i in idx:
+            old = flat[i]
+            flat[i] = old + h
+            Lp = mlp.loss(params, X, Y)
+            flat[i] = old - h
+            Lm = mlp.loss(params, X, Y)
+            flat[i] = old
+            fd = (Lp - Lm) / (2 * h)
+            an = grads[pi].reshape(-1)[i]
+            assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (pi, i, fd, an)
+
+
+def test_silu_derivative():
+    z = np.linspace(-6, 6, 101)
+    h = 1e-6
+    assert np.abs(mlp.dsilu(z) - (mlp.silu(z + h) - mlp.silu(z - h)) / (2 * h)).max() < 1e-9
+
+
+def test_first_adam_step_closed_form():
+    # with bias correction the first step is lr * g / (|g| + eps)
+    p = [np.array([1.0, -2.0, 3.0])]
+    g = [np.array([0.5, -4.0, 1e-3])]
+    z = [np.zeros(3)]
+    newp, m, v = mlp.adam(p, g, z, z, 1, 0.01)
+    expect = p[0] - 0.01 * g[0] / (np.abs(g[0]) + 1e-8)
+    assert np.abs(newp[0] - expect).max() < 1e-15
+
+
+def test_plastic_statistics_by_hand():
+    wJ = np.array([1.0, 3.0])
+    Fp = np.stack([np.eye(2), np.array([[1.1, 0.2], [0.0, 0.9]])])
+    xi = np.array([0.0, 0.2])
+    s = mlp.plastic_statistics(wJ, (Fp, np.ones(2), xi))
+    assert np.allclose(s, [0.15, 0.2, np.sqrt(0.25 * 0.15 ** 2 + 0.75 * 0.05 ** 2), 0.75,
+                           0.075, 0.15, 0.0, -0.075], atol=1e-15)
