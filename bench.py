@@ -3,14 +3,17 @@
 
 One step = one load step of every macro point of the batch: rom_step (Newton
 on the reduced coordinates to ||f||_2 <= 1e-8, then effective stress and
-stiffness) followed by rom_homogenized_stress_tangent.  The metric is macro-
-point load steps per second with all inputs resident in device memory.
+stiffness) and rom_homogenized_stress_tangent.  The metric is macro-point load
+steps per second with all inputs resident in device memory, for the
+learned + mixed-precision form (BF16 contraction of the reduced tangent, FP64
+everywhere else, learned Newton warm start) next to the plain FP64 form at
+the same 1e-8 residual; the other forms are reported beside them.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--mode fused|staged]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--variants a,b]
 
-Prints one JSON line.  Also reports the dominant kernel against the MI355X
-FP64 peak (measured with HIP events on the stream the kernel runs on) and the
-plain FP64 CPU oracle timed on a bounded sample of the same workload on the
+Prints one JSON line.  The dominant kernel is reported against the MI355X
+FP64 peak (timed with HIP events on the stream the kernel runs on), and the
+plain FP64 CPU oracle is timed on a bounded sample of the same workload on the
 host cores.
 """
 import argparse
@@ -32,25 +35,52 @@ WORKLOADS = {
     # one elliptical void, n = 40 modes, m ~ 400 ECM points, 4096 points,
     # 20-step load / unload paths of amplitude <= 0.08
     'onevoid_n40_m400_P4096_cyclic20': dict(rom='onevoid_n40_m400', P=4096, steps=20, path='cyclic',
-                                            rho=(0.02, 0.08), seed=0),
+                                            rho=(0.02, 0.08), seed=0, train_points=25000, train_seed=1),
     # small case: n = 20, m = 120, 64 points, 10-step monotone paths
     'onevoid_n20_m120_P64_monotone10': dict(rom='onevoid_n20_m120', P=64, steps=10, path='monotone',
-                                            rho=(0.02, 0.05), seed=0),
+                                            rho=(0.02, 0.05), seed=0, train_points=4096, train_seed=1),
 }
 DEFAULT = 'onevoid_n40_m400_P4096_cyclic20'
+VARIANTS = ['fp64', 'fp64_staged', 'fp32', 'bf16', 'fp64_mlp', 'bf16_mlp']
 
 
-def inputs(w):
-    P, K = w['P'], w['steps']
-    mu = workloads.one_void_mu(w['seed'], P)
+def inputs(w, seed=None, P=None):
+    P = w['P'] if P is None else P
+    seed = w['seed'] if seed is None else seed
+    K = w['steps']
+    mu = workloads.one_void_mu(seed, P)
     if w['path'] == 'cyclic':
-        paths = workloads.cyclic_paths(w['seed'], P, K, w['rho'])
+        paths = workloads.cyclic_paths(seed, P, K, w['rho'])
     else:
-        paths = workloads.monotone_paths(w['seed'], P, K, w['rho'])
+        paths = workloads.monotone_paths(seed, P, K, w['rho'])
     return mu, paths
 
 
-def gpu_run(w, steps, warmup, mode, rom_file):
+def train_warm_start(w, rom_file, log):
+    """Samples from FP64 ROM trajectories, then the library's own training kernels."""
+    import torch
+    from paper_2307_16894_amd.batch import RomBatch
+    from paper_2307_16894_amd.warmstart import WarmStart, generate
+    import paper_2307_16894_amd as L
+    t0 = time.perf_counter()
+    mu, paths = inputs(w, seed=w['train_seed'], P=w['train_points'])
+    rb = RomBatch(rom_file, mu)
+    X, Y = generate(rb, paths)
+    rb.close()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ws = WarmStart(X.shape[1], Y.shape[1], max_batch=4096, seed=0)
+    ws.fit_scaling(X, Y)
+    hist = ws.train(X, Y, epochs=12, batch=2048, lr=2e-3, precision=L.DT_BF16)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"warm start: {X.shape[0]} samples in {t1 - t0:.1f}s, trained in {t2 - t1:.1f}s, "
+        f"loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    return ws, dict(samples=int(X.shape[0]), params=int(ws.param_count), epochs=12,
+                    loss_first=hist[0], loss_last=hist[-1], gen_s=t1 - t0, train_s=t2 - t1)
+
+
+def gpu_run(w, steps, warmup, opts, rom_file):
     import torch
     import paper_2307_16894_amd as L
     from paper_2307_16894_amd.batch import RomBatch
@@ -60,7 +90,6 @@ def gpu_run(w, steps, warmup, mode, rom_file):
     Fb = torch.from_numpy(np.ascontiguousarray(paths.reshape(P, K, 4).transpose(1, 0, 2))).to(dev)  # [K][P][4]
     rb = RomBatch(rom_file, mu, dev)
     n, m = rb.info['n'], rb.info['m']
-    opts = L.rom_default_opts(mode=mode)
 
     def run(nsteps, record):
         k = 0
@@ -71,7 +100,7 @@ def gpu_run(w, steps, warmup, mode, rom_file):
                 k = 0
             rb.step(Fb[k], opts)
             if record:  # device-side copies, no synchronisation
-                rec.append((rb.iters.clone(), (rb.status == 0).sum()))
+                rec.append((rb.iters.clone(), (rb.status == 0).sum() + (rb.status == 3).sum(), rb.Pbar.clone()))
             k += 1
         return rec
 
@@ -87,12 +116,13 @@ def gpu_run(w, steps, warmup, mode, rom_file):
     t1 = time.perf_counter()
     kern_ms, launches = L.rom_timing_read(rb.h)
     L.rom_timing_enable(rb.h, False)
-    evals = int(sum(int(it.sum()) for it, _ in rec))
-    conv = int(sum(int(c) for _, c in rec))
-    max_it = int(max(int(it.max()) for it, _ in rec))
+    evals = int(sum(int(it.sum()) for it, _, _ in rec))
+    conv = int(sum(int(c) for _, c, _ in rec))
+    max_it = int(max(int(it.max()) for it, _, _ in rec))
+    Pbars = torch.stack([p for _, _, p in rec]).cpu().numpy()
     rb.close()
     return dict(elapsed=t1 - t0, evals=evals, converged=conv, max_iter=max_it, kern_ms=kern_ms,
-                launches=launches, n=n, m=m)
+                launches=launches, n=n, m=m, Pbar=Pbars)
 
 
 def _oracle_worker(args):
@@ -134,7 +164,7 @@ def main(argv=None):
     ap.add_argument('--steps', type=int, default=20)
     ap.add_argument('--warmup', type=int, default=20)
     ap.add_argument('--workload', default=DEFAULT, choices=sorted(WORKLOADS))
-    ap.add_argument('--mode', default='staged', choices=['staged', 'fused'])
+    ap.add_argument('--variants', default=','.join(VARIANTS))
     ap.add_argument('--no-cpu-baseline', action='store_true')
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -142,34 +172,64 @@ def main(argv=None):
                                     "independent and a single MI355X holds the whole workload; "
                                     "run with --gpus 1")))
         return 2
+    import paper_2307_16894_amd as L
+    log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
     w = WORKLOADS[a.workload]
     rom_file = os.path.join(ROOT, 'roms', w['rom'] + '.rom')
-    mode = 1 if a.mode == 'fused' else 0
-    g = gpu_run(w, a.steps, a.warmup, mode, rom_file)
+    variants = [v for v in a.variants.split(',') if v]
+    ws, wsinfo = (None, None)
+    if any(v.endswith('_mlp') for v in variants):
+        ws, wsinfo = train_warm_start(w, rom_file, log)
     P = w['P']
-    value = P * a.steps / g['elapsed']
-    n, m = g['n'], g['m']
-    # dominant kernel: the reduced-tangent contraction K = sum_q G_q^T D_q G_q
-    # with H = D_q G_q and f = sum_q G_q^T W_q: m (8 n^2 + 40 n) flops per
-    # point-evaluation
+    res = {}
+    for v in variants:
+        dt = {'fp64': L.DT_F64, 'fp32': L.DT_F32, 'bf16': L.DT_BF16}[v.split('_')[0]]
+        if v.endswith('_mlp'):
+            opts = ws.opts(contraction=dt)
+        else:
+            opts = L.rom_default_opts(mode=L.MODE_STAGED if v.endswith('_staged') else L.MODE_FUSED,
+                                      contraction=dt)
+        log(f"[bench] {v}")
+        g = gpu_run(w, a.steps, a.warmup, opts, rom_file)
+        n, m = g['n'], g['m']
+        res[v] = g
+    ref = res.get('fp64')
+    out_var = {}
+    for v, g in res.items():
+        d = dict(value=P * a.steps / g['elapsed'], ms_per_step=1e3 * g['elapsed'] / a.steps,
+                 mean_iters=g['evals'] / (P * a.steps), max_iters=g['max_iter'],
+                 converged_fraction=g['converged'] / (P * a.steps),
+                 kernel_ms_per_step=g['kern_ms'] / a.steps)
+        if ref is not None and v != 'fp64':
+            d['max_rel_diff_Pbar_vs_fp64'] = float(np.abs(g['Pbar'] - ref['Pbar']).max() / np.abs(ref['Pbar']).max())
+        out_var[v] = d
+    head = 'bf16_mlp' if 'bf16_mlp' in out_var else variants[0]
+    g = res[head]
+    # dominant work: the reduced-tangent contraction K = sum_q G_q^T D_q G_q with
+    # H = D_q G_q and f = sum_q G_q^T W_q: m (8 n^2 + 40 n) flops per point-evaluation
+    # (FP64 form: the fused kernel, all of Newton; measured on the plain FP64 run)
+    rf = res.get('fp64', g)
     flops_per_eval = m * (8.0 * n * n + 40.0 * n)
-    per_launch_ms = g['kern_ms'] / max(g['launches'], 1)
-    achieved = flops_per_eval * g['evals'] / (g['kern_ms'] * 1e-3) / 1e12 if g['kern_ms'] > 0 else 0.0
+    achieved = flops_per_eval * rf['evals'] / (rf['kern_ms'] * 1e-3) / 1e12 if rf['kern_ms'] > 0 else 0.0
     out = dict(
-        metric="ROM macro-point load steps/s at 1e-8 residual",
-        value=value, unit="macro-point load steps/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
-        ms_per_step=1e3 * g['elapsed'] / a.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64", data="synthetic",
-        config=dict(workload=a.workload, rom=w['rom'], n=n, m=m, batch=P, load_steps=w['steps'],
-                    mode=a.mode, contraction="f64", tol=1e-8),
-        newton=dict(mean_iters=g['evals'] / (P * a.steps), max_iters=g['max_iter'],
-                    converged_fraction=g['converged'] / (P * a.steps)),
-        roofline=dict(bound="mfma", kernel="k_assemble" if mode == 0 else "k_fused",
-                      achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                      frac=achieved / PEAK_FP64_TFLOPS, traffic=None,
-                      launches=g['launches'], avg_launch_ms=per_launch_ms,
-                      flops_per_point_eval=flops_per_eval, point_evals=g['evals']),
+        metric="ROM macro-point load steps/s at 1e-8 residual; learned+mixed vs plain FP64",
+        value=out_var[head]['value'], unit="macro-point load steps/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+        ms_per_step=out_var[head]['ms_per_step'], higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="bf16+f64" if head.startswith('bf16') else head.split('_')[0].replace('fp', 'f'),
+        data="synthetic",
+        config=dict(workload=a.workload, rom=w['rom'], n=n, m=m, batch=P, load_steps=w['steps'], tol=1e-8,
+                    form=head, contraction=head.split('_')[0], warm_start=head.endswith('_mlp')),
+        plain_fp64=out_var.get('fp64'),
+        speedup_vs_plain_fp64=(out_var[head]['value'] / out_var['fp64']['value']) if 'fp64' in out_var else None,
+        variants=out_var,
+        warm_start=wsinfo,
+        roofline=dict(bound="mfma", kernel="k_fused<fp64>", achieved=achieved, peak=PEAK_FP64_TFLOPS,
+                      unit="TFLOP/s", frac=achieved / PEAK_FP64_TFLOPS, traffic=None,
+                      launches=rf['launches'], avg_launch_ms=rf['kern_ms'] / max(rf['launches'], 1),
+                      flops_per_point_eval=flops_per_eval, point_evals=rf['evals']),
     )
+    if ws is not None:
+        ws.close()
     if not a.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(w, rom_file)
     print(json.dumps(out), flush=True)

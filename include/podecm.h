@@ -76,11 +76,17 @@ typedef struct rom_opts {
   int32_t contraction;  /* ROM_DT_*: precision of the K contraction; all else is FP64 */
   int32_t mode;         /* ROM_MODE_* */
   int32_t warm_start;   /* ROM_WARM_*; ROM_WARM_MLP needs mode FUSED and mlp */
-  int32_t reserved[6];
+  int32_t split;        /* fused form: -1 automatic, 0 the waves of a workgroup split the ECM points,
+                           1 they split the tiles of K (needed for n > 75) */
+  int32_t grid_per_cu;  /* fused form: 0 one workgroup per point; k > 0 persistent grid of k workgroups per
+                           compute unit pulling points from a device-side work list */
+  int32_t reserved[4];
   rom_mlp_handle mlp;   /* network for ROM_WARM_MLP (see below), else NULL */
+  const int32_t* active;  /* device i32 [batch] or NULL: points with active[p] == 0 are skipped, their state
+                             and outputs untouched (fused form) */
 } rom_opts;
 
-/* Fill *o with the defaults above (mode FUSED when built, contraction F64). */
+/* Fill *o with the defaults: tol 1e-8, max_iter 15, commit, FP64, staged form, plain guess, split -1. */
 int rom_default_opts(rom_opts* o);
 
 /*
@@ -214,6 +220,19 @@ int rom_mlp_train_step(rom_mlp_handle m, int32_t batch, const float* X_dev, cons
  */
 int rom_features(rom_handle h, int32_t batch, const double* Fbar_dev, const void* state_dev, float* X_dev,
                  hipStream_t stream);
+
+/*
+ * Uneven batches: every point p follows its own path of nsteps[p] load steps
+ * (paths_dev: f64 [batch][max_steps][4]).  rom_path_gather sets, for the
+ * points with step[p] < nsteps[p], Fbar[p] = paths[p][step[p]] and
+ * active[p] = 1 (else active[p] = 0, Fbar[p] unchanged); rom_path_advance
+ * increments step[p] where active[p].  With rom_step(opts.active = active),
+ * a whole load step of the batch is device-driven and can be captured once
+ * in a HIP graph and replayed (no allocation, memset or synchronisation).
+ */
+int rom_path_gather(int32_t batch, const double* paths_dev, int32_t max_steps, const int32_t* nsteps_dev,
+                    const int32_t* step_dev, double* Fbar_dev, int32_t* active_dev, hipStream_t stream);
+int rom_path_advance(int32_t batch, const int32_t* active_dev, int32_t* step_dev, hipStream_t stream);
 
 /*
  * Measurement support.  While enabled, rom_step records a HIP event pair on

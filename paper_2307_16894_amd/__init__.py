@@ -41,7 +41,7 @@ EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_inf
            'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent',
            'rom_timing_enable', 'rom_timing_read', 'rom_mlp_create', 'rom_mlp_free', 'rom_mlp_param_count',
            'rom_mlp_set_params', 'rom_mlp_get_params', 'rom_mlp_set_scaling', 'rom_mlp_forward',
-           'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features']
+           'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features', 'rom_path_gather', 'rom_path_advance']
 
 
 class RomError(RuntimeError):
@@ -53,7 +53,8 @@ class RomError(RuntimeError):
 class rom_opts(ctypes.Structure):
     _fields_ = [('tol', ctypes.c_double), ('max_iter', ctypes.c_int32), ('fixed_iters', ctypes.c_int32),
                 ('commit', ctypes.c_int32), ('contraction', ctypes.c_int32), ('mode', ctypes.c_int32),
-                ('warm_start', ctypes.c_int32), ('reserved', ctypes.c_int32 * 6), ('mlp', ctypes.c_void_p)]
+                ('warm_start', ctypes.c_int32), ('split', ctypes.c_int32), ('grid_per_cu', ctypes.c_int32),
+                ('reserved', ctypes.c_int32 * 4), ('mlp', ctypes.c_void_p), ('active', ctypes.c_void_p)]
 
 
 _lib = None
@@ -90,6 +91,8 @@ def lib():
         L.rom_mlp_gradients.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp]
         L.rom_mlp_train_step.argtypes = [vp, i32, vp, vp, ctypes.c_float, i32, vp, vp]
         L.rom_features.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.rom_path_gather.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp]
+        L.rom_path_advance.argtypes = [i32, vp, vp, vp]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -231,3 +234,17 @@ def rom_mlp_train_step(m, batch, X_ptr, Y_ptr, lr, precision, loss_ptr, stream):
 
 def rom_features(h, batch, Fbar_ptr, state_ptr, X_ptr, stream):
     _check(lib().rom_features(h, batch, Fbar_ptr, state_ptr, X_ptr, stream), 'rom_features')
+
+
+def rom_path_gather(batch, paths_ptr, max_steps, nsteps_ptr, step_ptr, Fbar_ptr, active_ptr, stream):
+    _check(lib().rom_path_gather(batch, paths_ptr, max_steps, nsteps_ptr, step_ptr, Fbar_ptr, active_ptr, stream),
+           'rom_path_gather')
+
+
+def rom_path_advance(batch, active_ptr, step_ptr, stream):
+    _check(lib().rom_path_advance(batch, active_ptr, step_ptr, stream), 'rom_path_advance')
+
+
+def rom_fused_tiles(n):
+    """16-column blocks of the fused contraction for n modes (f and C ride in columns n .. n+4)."""
+    return (n + 5 + 15) // 16

@@ -104,6 +104,11 @@ int rom_default_opts(rom_opts* o) {
   o->commit = 1;
   o->contraction = ROM_DT_F64;
   o->mode = ROM_MODE_STAGED;
+  o->warm_start = ROM_WARM_PREV;
+  o->split = -1;
+  o->grid_per_cu = 0;
+  o->mlp = nullptr;
+  o->active = nullptr;
   return ROM_OK;
 }
 
@@ -178,6 +183,7 @@ int rom_load(const void* blob, size_t bytes, int device, rom_handle* out) {
   h->mp.sy0 = par[2];
   h->mp.H = par[3];
   int rc = ROM_OK;
+  if (hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) rc = ROM_EHIP;
   if (rc == ROM_OK) rc = upload(&h->w, w);
   if (rc == ROM_OK) rc = upload(&h->Gt, Gt);
   if (rc == ROM_OK) rc = upload(&h->Gq, Gq);
@@ -266,8 +272,10 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
   if (o.warm_start != ROM_WARM_PREV && o.warm_start != ROM_WARM_MLP) return ROM_EINVAL;
   if (o.warm_start == ROM_WARM_MLP && !o.mlp) return ROM_EINVAL;
   DeviceGuard guard(h->device);
+  if (o.grid_per_cu < 0 || o.grid_per_cu > 64) return ROM_EINVAL;
   if (o.mode == ROM_MODE_STAGED) {
-    if (o.contraction != ROM_DT_F64 || o.warm_start != ROM_WARM_PREV) return ROM_EUNSUPPORTED;
+    if (o.contraction != ROM_DT_F64 || o.warm_start != ROM_WARM_PREV || o.active || o.grid_per_cu)
+      return ROM_EUNSUPPORTED;
     return rom_launch_step_staged(h, batch, Fbar_dev, state_dev, o, status_dev, iters_dev, resnorm_dev, stream);
   }
   if (o.mode == ROM_MODE_FUSED)
@@ -282,6 +290,21 @@ int rom_features(rom_handle h, int32_t batch, const double* Fbar_dev, const void
   if (!Fbar_dev || !state_dev || !X_dev || batch > 65535) return ROM_EINVAL;
   DeviceGuard guard(h->device);
   return rom_launch_features(h, batch, Fbar_dev, state_dev, X_dev, stream);
+}
+
+int rom_path_gather(int32_t batch, const double* paths, int32_t max_steps, const int32_t* nsteps,
+                    const int32_t* step, double* Fbar, int32_t* active, hipStream_t stream) {
+  if (batch < 0 || max_steps < 1) return ROM_EINVAL;
+  if (batch == 0) return ROM_OK;
+  if (!paths || !nsteps || !step || !Fbar || !active) return ROM_EINVAL;
+  return rom_launch_path_gather(batch, paths, max_steps, nsteps, step, Fbar, active, stream);
+}
+
+int rom_path_advance(int32_t batch, const int32_t* active, int32_t* step, hipStream_t stream) {
+  if (batch < 0) return ROM_EINVAL;
+  if (batch == 0) return ROM_OK;
+  if (!active || !step) return ROM_EINVAL;
+  return rom_launch_path_advance(batch, active, step, stream);
 }
 
 int rom_homogenized_stress_tangent(rom_handle h, int32_t batch, const void* state_dev, double* Pbar_dev,

@@ -15,7 +15,8 @@
 struct rom_model {
   int device;
   int n, m, c, kind, n_mu;
-  int npad;              // n rounded up to a multiple of 16
+  int npad;              // padded width of the contraction tiles
+  int ncu;               // compute units of the device
   double E, nu, sy0, H, r0, void_area, cell_area;
   J2Params mp;
   double* w;    // [m] ECM weights
@@ -42,7 +43,7 @@ int rom_launch_features(const rom_model* h, int P, const double* Fbar, const voi
 // Internal state fields (public ones first, same numbering as ROM_FIELD_*).
 enum {
   F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK, F_FBC, F_RG,
-  F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT, F_XF, F_DR, F_MU,
+  F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT, F_XF, F_DR, F_MU, F_LIST,
   F_D, F_W, F_K, F_F, F_PIV,
   F_NFIELDS
 };
@@ -78,6 +79,7 @@ static inline StateLayout rom_state_layout(const rom_model* h, size_t P) {
   sz[F_XF] = P * (size_t)rom_n_features(h) * 4;
   sz[F_DR] = P * n * 4;
   sz[F_MU] = P * (size_t)h->n_mu * 8;
+  sz[F_LIST] = P * 4;
   sz[F_D] = P * 16 * m * 8;
   sz[F_W] = P * 4 * m * 8;
   sz[F_K] = P * n * n * 8;

@@ -617,7 +617,34 @@ __global__ __launch_bounds__(256) void k_features(int n, int m, int n_mu, const 
   for (int i = tid; i < n; i += 256) x[n_mu + 4 + i] = (float)rc[(size_t)p * n + i];
 }
 
+__global__ void k_path_gather(int P, const double* __restrict__ paths, int max_steps, const int* __restrict__ nsteps,
+                              const int* __restrict__ step, double* __restrict__ Fbar, int* __restrict__ active) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int k = step[p];
+  const int on = (k < nsteps[p] && k < max_steps) ? 1 : 0;
+  active[p] = on;
+  if (on)
+    for (int c = 0; c < 4; ++c) Fbar[4 * (size_t)p + c] = paths[((size_t)p * max_steps + k) * 4 + c];
+}
+
+__global__ void k_path_advance(int P, const int* __restrict__ active, int* __restrict__ step) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P && active[p]) step[p] += 1;
+}
+
 }  // namespace
+
+int rom_launch_path_gather(int P, const double* paths, int max_steps, const int* nsteps, const int* step, double* Fbar,
+                           int* active, hipStream_t s) {
+  k_path_gather<<<(P + 255) / 256, 256, 0, s>>>(P, paths, max_steps, nsteps, step, Fbar, active);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int rom_launch_path_advance(int P, const int* active, int* step, hipStream_t s) {
+  k_path_advance<<<(P + 255) / 256, 256, 0, s>>>(P, active, step);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
 
 int rom_launch_features(const rom_model* h, int P, const double* Fbar, const void* state, float* X, hipStream_t s) {
   const StateLayout L = rom_state_layout(h, P);

@@ -88,3 +88,20 @@ def four_void_training_mu(seed, count):
 def uneven_steps(seed, P, lo=5, hi=40):
     """Per-point step counts, uniform in [lo, hi]."""
     return rng(seed).integers(lo, hi + 1, size=P)
+
+
+def uneven_cyclic_paths(seed, P, nsteps, rho=(0.02, 0.08)):
+    """Per-point load / unload paths of their own lengths nsteps[p]: beta rises
+    to 1 over the first half of the point's steps and falls back.  Returned
+    as (P, max(nsteps), 2, 2), padded with the last target."""
+    g = rng(seed)
+    E = _directions(g, P) * g.uniform(*rho, size=P)[:, None, None]
+    Kmax = int(np.max(nsteps))
+    out = np.empty((P, Kmax, 2, 2))
+    for p in range(P):
+        K = int(nsteps[p])
+        half = max(K // 2, 1)
+        beta = np.concatenate([np.arange(1, half + 1) / half, 1.0 - np.arange(1, K - half + 1) / max(K - half, 1)])
+        beta = np.concatenate([beta, np.full(Kmax - K, beta[-1])])
+        out[p] = np.eye(2)[None] + beta[:, None, None] * E[p][None]
+    return out
