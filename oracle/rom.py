@@ -24,6 +24,16 @@ decided by the last one; this mode exists so that two implementations can be
 compared along the same Newton map.
 
 Status codes: 0 converged, 1 iteration cap, 2 non-finite residual.
+
+Load-step cutting (the appendix on the material model notes that the global
+Newton solver sometimes needs much smaller load steps): with a depth D >= 1 a
+step that fails is retried towards intermediate targets on the straight line
+from the committed Fbar_c to the requested Fbar,
+    Fbar(t) = Fbar_c + (t / 2^D) (Fbar - Fbar_c),  t = 1 .. 2^D,
+halving the attempted stride on every failure and doubling it (within the
+remaining distance) after every converged sub-step, whose state then becomes
+the start of the next attempt.  The step fails when a stride of 1 / 2^D does
+not converge; D = 0 is the plain method.
 """
 import numpy as np
 
@@ -99,21 +109,57 @@ class ROM:
         return dict(r=r, hist=ev['hist'], status=status, iters=iters, resnorm=res,
                     Pbar=Pbar, Abar=Abar)
 
+    def cut_step(self, r_c, hist_c, Fbar_c, Fbar, Finv, J, tol=1e-8, max_iter=25, fixed=False, max_substeps=0):
+        """One load step with cutting (see the module notes).  Returns the last
+        attempt's step dict with 'iters' summed over all attempts, plus the
+        start state of that attempt ('r_c', 'hist_c', 'Fbar_c': the committed
+        state after the converged sub-steps) and the converged intermediate
+        targets in order ('targets')."""
+        full = 2 ** max_substeps
+        t, dt = 0, full
+        r0, h0, F0 = r_c, hist_c, np.asarray(Fbar_c, dtype=np.float64)
+        Fbar = np.asarray(Fbar, dtype=np.float64)
+        total, targets = 0, []
+        while True:
+            target = Fbar if t + dt == full else Fbar_c + ((t + dt) / full) * (Fbar - Fbar_c)
+            s = self.step(r0, h0, target, Finv, J, tol, max_iter, fixed)
+            total += s['iters']
+            if s['status'] == 0:
+                t += dt
+                if t == full:
+                    break
+                r0, h0, F0 = s['r'], s['hist'], target
+                targets.append(target)
+                dt = min(2 * dt, full - t)
+            else:
+                if dt == 1:
+                    break
+                dt //= 2
+        s.update(iters=total, r_c=r0, hist_c=h0, Fbar_c=F0, targets=targets)
+        return s
+
     def virgin(self):
         return material.virgin_history((self.m,))
 
-    def run_path(self, mu, Fbar_path, tol=1e-8, max_iter=25, fixed=False, commit=True):
-        """Solve a whole load path from the virgin state; commit converged steps."""
+    def run_path(self, mu, Fbar_path, tol=1e-8, max_iter=25, fixed=False, commit=True, max_substeps=0):
+        """Solve a whole load path from the virgin state; commit converged steps
+        (with cutting: also the converged sub-steps of a failed step)."""
         Finv, J = self.transformation(mu)
         if np.any(J <= 0):
             raise ValueError("invalid shape parameters: det F_mu <= 0")
         hist = self.virgin()
         r = np.zeros(self.n)
+        Fc = np.eye(2)
         out = []
         for Fb in Fbar_path:
-            s = self.step(r, hist, np.asarray(Fb, dtype=np.float64), Finv, J, tol, max_iter, fixed)
+            Fb = np.asarray(Fb, dtype=np.float64)
+            if max_substeps == 0:
+                s = self.step(r, hist, Fb, Finv, J, tol, max_iter, fixed)
+            else:
+                s = self.cut_step(r, hist, Fc, Fb, Finv, J, tol, max_iter, fixed, max_substeps)
             out.append(s)
             if commit and s['status'] == 0:
-                hist = s['hist']
-                r = s['r']
+                hist, r, Fc = s['hist'], s['r'], Fb
+            elif commit and max_substeps > 0:
+                hist, r, Fc = s['hist_c'], s['r_c'], s['Fbar_c']
         return out

@@ -1,0 +1,77 @@
+"""Parity at the benchmark's full size: the one-void ROM with n = 40 modes and
+371 ECM points, 4096 macro points on 20-step load / unload paths, launched as
+the benchmark launches it (fused form, automatic layout, one workgroup per
+point).  The oracle recomputes a sample of the points one by one, spread over
+the batch (first, last and points in between)."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2307_16894_amd as L
+from bench import WORKLOADS, inputs
+from oracle.rom import ROM
+from paper_2307_16894_amd.batch import RomBatch
+from tests.conftest import rom_path
+
+pytestmark = pytest.mark.gpu
+
+W = WORKLOADS['onevoid_n40_m400_P4096_cyclic20']
+SAMPLE = np.unique(np.r_[np.linspace(0, W['P'] - 1, 12).astype(int), 1, 255, 256, 2047])
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
+
+
+def run_gpu(opts, K):
+    mu, paths = inputs(W)
+    rb = RomBatch(rom_path(W['rom']), mu)
+    out = []
+    for k in range(K):
+        print(f"[gpu] full size P={W['P']} contraction={opts.contraction} fixed={opts.fixed_iters} step {k}",
+              flush=True)
+        st, it, rn = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), opts)
+        torch.cuda.synchronize()
+        out.append(dict(status=st.cpu().numpy().copy(), iters=it.cpu().numpy().copy(),
+                        r=rb.r(trial=True).cpu().numpy().copy(), Pbar=rb.Pbar.cpu().numpy().copy(),
+                        Abar=rb.Abar.cpu().numpy().copy()))
+    rb.close()
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def oracle(p, K, fixed, max_iter):
+    mu, paths = inputs(W)
+    return ROM(rom_path(W['rom'])).run_path(mu[p], paths[p, :K], tol=1e-8, max_iter=max_iter, fixed=fixed)
+
+
+def test_fixed_iteration_parity_full_size(gpu):
+    K = 6
+    g = run_gpu(L.rom_default_opts(mode=L.MODE_FUSED, fixed_iters=1, max_iter=4), K)
+    for p in SAMPLE:
+        ref = oracle(int(p), K, True, 4)
+        for k in range(K):
+            assert g[k]['status'][p] == ref[k]['status'], (p, k)
+            assert rel(g[k]['r'][p], ref[k]['r']) < 1e-10, (p, k)
+            assert rel(g[k]['Pbar'][p], ref[k]['Pbar']) < 1e-10, (p, k)
+            assert rel(g[k]['Abar'][p], ref[k]['Abar'].reshape(-1)) < 1e-10, (p, k)
+
+
+@pytest.mark.parametrize("dt,tol_P,tol_A", [(L.DT_F64, 1e-6, 1e-6), (L.DT_BF16, 1e-5, 3e-2)])
+def test_converged_paths_full_size(gpu, dt, tol_P, tol_A):
+    K = W['steps']
+    g = run_gpu(L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt), K)
+    conv = np.mean([(rec['status'] == 0).mean() for rec in g])
+    print(f"contraction {dt}: converged fraction {conv:.5f}")
+    assert conv > 0.999
+    for p in SAMPLE:
+        ref = oracle(int(p), K, False, 15)
+        for k in range(K):
+            assert g[k]['status'][p] == ref[k]['status'], (p, k)
+            if ref[k]['status'] != 0:
+                continue
+            assert abs(int(g[k]['iters'][p]) - ref[k]['iters']) <= 1 + (dt != L.DT_F64)
+            assert rel(g[k]['Pbar'][p], ref[k]['Pbar']) < tol_P, (p, k)
+            assert rel(g[k]['Abar'][p], ref[k]['Abar'].reshape(-1)) < tol_A, (p, k)

@@ -30,15 +30,15 @@ def oracle_path(rom, mu, path, max_iter, fixed, tol=1e-8):
     return rom.run_path(mu, path, tol=tol, max_iter=max_iter, fixed=fixed)
 
 
-def _run_gpu(name, mu, paths, mode, max_iter, fixed, record_hist=True):
+def _run_gpu(name, mu, paths, mode, max_iter, fixed, record_hist=True, **extra):
     from paper_2307_16894_amd import batch as B
     from paper_2307_16894_amd import rom_default_opts
     rb = B.RomBatch(rom_path(name), mu)
     P, K = paths.shape[0], paths.shape[1]
     out = []
     for k in range(K):
-        print(f"[gpu] {name} mode={mode} step {k}", flush=True)
-        o = rom_default_opts(max_iter=max_iter, fixed_iters=int(fixed), mode=mode)
+        print(f"[gpu] {name} mode={mode} {extra} step {k}", flush=True)
+        o = rom_default_opts(max_iter=max_iter, fixed_iters=int(fixed), mode=mode, **extra)
         st, it, rn = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), o)
         torch.cuda.synchronize()
         rec = dict(status=st.cpu().numpy().copy(), iters=it.cpu().numpy().copy(), res=rn.cpu().numpy().copy(),
@@ -51,13 +51,19 @@ def _run_gpu(name, mu, paths, mode, max_iter, fixed, record_hist=True):
     return out
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_fixed_iteration_parity_onevoid_n20(gpu, mode):
+# staged form; fused form with the automatic layout, with the tile split, and
+# launched as a persistent grid pulling points from the work list
+FORMS = {'staged': dict(mode=0), 'fused': dict(mode=1), 'fused_tilesplit': dict(mode=1, split=1),
+         'fused_queue': dict(mode=1, grid_per_cu=2), 'fused_tilesplit_queue': dict(mode=1, split=1, grid_per_cu=1)}
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_fixed_iteration_parity_onevoid_n20(gpu, form):
     name = 'onevoid_n20_m120'
     P, K = 16, 10
     mu = workloads.one_void_mu(0, 64)[:P]
     paths = workloads.monotone_paths(0, 64, 10)[:P]
-    g = _run_gpu(name, mu, paths, mode, max_iter=6, fixed=True)
+    g = _run_gpu(name, mu, paths, max_iter=6, fixed=True, **FORMS[form])
     rom = ROM(rom_path(name))
     for p in range(P):
         ref = oracle_path(rom, mu[p], paths[p], max_iter=6, fixed=True)
@@ -98,3 +104,36 @@ def test_converged_path_onevoid_n20(gpu, mode):
             assert abs(int(g[k]['iters'][p]) - ref[k]['iters']) <= 1
             assert rel_err(g[k]['Pbar'][p], ref[k]['Pbar']) < 1e-6
     assert all((rec['status'] == 0).all() for rec in g)
+
+
+def test_active_mask_skips_points(gpu):
+    """Points with active[p] == 0 keep their state and outputs; the others
+    match a run without the mask (fixed iterations, bit-identical)."""
+    import paper_2307_16894_amd as L
+    from paper_2307_16894_amd.batch import RomBatch
+    name = 'onevoid_n20_m120'
+    P = 40
+    mu = workloads.one_void_mu(5, P)
+    paths = workloads.monotone_paths(5, P, 4)
+    act = torch.tensor([(p % 3) != 1 for p in range(P)], dtype=torch.int32, device='cuda')
+    for grid in (0, 2):
+        full, masked = RomBatch(rom_path(name), mu), RomBatch(rom_path(name), mu)
+        for k in range(4):
+            print(f"[gpu] active mask grid={grid} step {k}", flush=True)
+            Fb = torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda()
+            o = L.rom_default_opts(mode=1, fixed_iters=1, max_iter=5, grid_per_cu=grid)
+            full.step(Fb, o)
+            torch.cuda.synchronize()  # the batches run on their own streams
+            r_before = masked.r().clone()
+            masked.iters.fill_(-7)
+            torch.cuda.synchronize()
+            o.active = act.data_ptr()
+            masked.step(Fb, o)
+            torch.cuda.synchronize()
+            on = act.bool()
+            assert torch.equal(masked.r()[on], full.r()[on])
+            assert torch.equal(masked.Pbar[on], full.Pbar[on])
+            assert torch.equal(masked.r()[~on], r_before[~on])
+            assert (masked.iters[~on] == -7).all()
+        full.close()
+        masked.close()

@@ -126,3 +126,43 @@ def test_artifact_round_trip():
     for k in ('w', 'G', 'Gd', 'src'):
         assert np.array_equal(back[k], data[k])
     assert back['n'] == data['n'] and back['m'] == data['m'] and back['mat'] == MAT
+
+
+def test_load_step_cutting_equals_plain_steps_along_its_targets():
+    """A step cut into sub-steps is the plain solve along the sequence of
+    converged intermediate targets: replaying that sequence as an ordinary
+    load path reproduces the state bit for bit.  Targets lie on the segment
+    from the committed to the requested Fbar at increasing dyadic fractions,
+    and depth 0 is the plain step."""
+    rom_file = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 'roms',
+                            'onevoid_n20_m120.rom')
+    if not os.path.exists(rom_file):
+        pytest.skip("ROM artifact not built")
+    import workloads
+    rom = ROM(rom_file)
+    mu = workloads.one_void_mu(7, 40)[6]
+    Fb = workloads.monotone_paths(7, 40, 1, rho=(0.03, 0.06))[6, 0]
+    Finv, J = rom.transformation(mu)
+    r0, h0 = np.zeros(rom.n), rom.virgin()
+    plain = rom.step(r0, h0, Fb, Finv, J, max_iter=15)
+    assert plain['status'] == 1  # the full increment does not converge
+    d0 = rom.cut_step(r0, h0, np.eye(2), Fb, Finv, J, max_iter=15, max_substeps=0)
+    assert d0['status'] == 1 and d0['iters'] == plain['iters'] and np.array_equal(d0['r'], plain['r'])
+    D = 4
+    cut = rom.cut_step(r0, h0, np.eye(2), Fb, Finv, J, max_iter=15, max_substeps=D)
+    assert cut['status'] == 0 and len(cut['targets']) >= 1
+    fr = []
+    for T in cut['targets']:
+        s = (T - np.eye(2)) / (Fb - np.eye(2))
+        assert np.ptp(s) < 1e-12  # on the segment
+        fr.append(s.mean() * 2 ** D)
+    assert np.allclose(fr, np.round(fr), atol=1e-9) and all(np.diff(fr) > 0) and fr[-1] < 2 ** D
+    replay = rom.run_path(mu, cut['targets'] + [Fb], max_iter=15)
+    assert all(s['status'] == 0 for s in replay)
+    assert np.array_equal(replay[-1]['r'], cut['r'])
+    assert all(np.array_equal(a, b) for a, b in zip(replay[-1]['hist'], cut['hist']))
+    assert np.array_equal(replay[-1]['Pbar'], cut['Pbar'])
+    assert cut['iters'] > sum(s['iters'] for s in replay)  # the failed attempts count too
+    # a path through run_path with cutting commits the same state
+    via = rom.run_path(mu, [Fb], max_iter=15, max_substeps=D)[-1]
+    assert np.array_equal(via['r'], cut['r'])
