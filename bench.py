@@ -42,6 +42,7 @@ WORKLOADS = {
 }
 DEFAULT = 'onevoid_n40_m400_P4096_cyclic20'
 VARIANTS = ['fp64', 'fp64_staged', 'fp32', 'bf16', 'fp64_mlp', 'bf16_mlp']
+SUBSTEPS = 4  # load-step cutting depth of the fused forms: a failed step is retried in up to 1/16 strides
 
 
 def inputs(w, seed=None, P=None):
@@ -185,10 +186,11 @@ def main(argv=None):
     for v in variants:
         dt = {'fp64': L.DT_F64, 'fp32': L.DT_F32, 'bf16': L.DT_BF16}[v.split('_')[0]]
         if v.endswith('_mlp'):
-            opts = ws.opts(contraction=dt)
+            opts = ws.opts(contraction=dt, max_substeps=SUBSTEPS)
+        elif v.endswith('_staged'):  # the staged form has no load-step cutting
+            opts = L.rom_default_opts(mode=L.MODE_STAGED, contraction=dt)
         else:
-            opts = L.rom_default_opts(mode=L.MODE_STAGED if v.endswith('_staged') else L.MODE_FUSED,
-                                      contraction=dt)
+            opts = L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt, max_substeps=SUBSTEPS)
         log(f"[bench] {v}")
         g = gpu_run(w, a.steps, a.warmup, opts, rom_file)
         n, m = g['n'], g['m']

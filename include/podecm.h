@@ -57,6 +57,8 @@ extern "C" {
 #define ROM_DT_F32  1
 #define ROM_DT_BF16 2
 
+#define ROM_MAX_SUBSTEPS 12  /* largest load-step cutting depth */
+
 /* execution form of rom_step */
 #define ROM_MODE_STAGED 0  /* one kernel per stage, host-enqueued Newton loop */
 #define ROM_MODE_FUSED  1  /* one persistent kernel, device-side Newton loop */
@@ -80,13 +82,21 @@ typedef struct rom_opts {
                            1 they split the tiles of K (needed for n > 75) */
   int32_t grid_per_cu;  /* fused form: 0 one workgroup per point; k > 0 persistent grid of k workgroups per
                            compute unit pulling points from a device-side work list */
-  int32_t reserved[4];
+  int32_t max_substeps; /* fused form, commit only: load-step cutting depth D (0..ROM_MAX_SUBSTEPS, default 0,
+                           the plain step).  A step that fails is retried towards targets
+                           Fbar_c + (t / 2^D)(Fbar - Fbar_c) on the segment from the committed Fbar_c, halving the
+                           stride on failure and doubling it after a converged sub-step, which is committed at once
+                           (the material-model appendix: the global Newton solve may need much smaller load steps).
+                           The point fails when a stride of 1 / 2^D fails; its committed state is then the last
+                           converged sub-step.  iters counts the evaluations of all attempts. */
+  int32_t reserved[3];
   rom_mlp_handle mlp;   /* network for ROM_WARM_MLP (see below), else NULL */
   const int32_t* active;  /* device i32 [batch] or NULL: points with active[p] == 0 are skipped, their state
                              and outputs untouched (fused form) */
 } rom_opts;
 
-/* Fill *o with the defaults: tol 1e-8, max_iter 15, commit, FP64, staged form, plain guess, split -1. */
+/* Fill *o with the defaults: tol 1e-8, max_iter 15, commit, FP64, staged form, plain guess, split -1,
+   no load-step cutting. */
 int rom_default_opts(rom_opts* o);
 
 /*

@@ -54,7 +54,7 @@ class rom_opts(ctypes.Structure):
     _fields_ = [('tol', ctypes.c_double), ('max_iter', ctypes.c_int32), ('fixed_iters', ctypes.c_int32),
                 ('commit', ctypes.c_int32), ('contraction', ctypes.c_int32), ('mode', ctypes.c_int32),
                 ('warm_start', ctypes.c_int32), ('split', ctypes.c_int32), ('grid_per_cu', ctypes.c_int32),
-                ('reserved', ctypes.c_int32 * 4), ('mlp', ctypes.c_void_p), ('active', ctypes.c_void_p)]
+                ('max_substeps', ctypes.c_int32), ('reserved', ctypes.c_int32 * 3), ('mlp', ctypes.c_void_p), ('active', ctypes.c_void_p)]
 
 
 _lib = None

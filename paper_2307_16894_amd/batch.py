@@ -6,7 +6,7 @@ the method happens here.
 """
 import torch
 
-from . import (FIELD_ABAR, FIELD_H_COMMITTED, FIELD_H_TRIAL, FIELD_MU_OK, FIELD_PBAR, FIELD_R_COMMITTED,
+from . import (FIELD_ABAR, FIELD_FBAR_COMMITTED, FIELD_H_COMMITTED, FIELD_H_TRIAL, FIELD_MU_OK, FIELD_PBAR, FIELD_R_COMMITTED,
                FIELD_R_TRIAL, FIELD_TRANSFORM, rom_default_opts, rom_free, rom_homogenized_stress_tangent,
                rom_info, rom_load_file, rom_state_bytes, rom_state_init, rom_state_offsets, rom_step)
 
@@ -69,6 +69,9 @@ class RomBatch:
     def history(self, trial=False):
         m = self.info['m']
         return self._view(FIELD_H_TRIAL if trial else FIELD_H_COMMITTED, (self.P, 6, m))
+
+    def fbar_committed(self):
+        return self._view(FIELD_FBAR_COMMITTED, (self.P, 4))
 
     def transform(self):
         return self._view(FIELD_TRANSFORM, (self.P, 5, self.info['m']))

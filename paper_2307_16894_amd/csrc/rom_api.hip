@@ -107,6 +107,7 @@ int rom_default_opts(rom_opts* o) {
   o->warm_start = ROM_WARM_PREV;
   o->split = -1;
   o->grid_per_cu = 0;
+  o->max_substeps = 0;
   o->mlp = nullptr;
   o->active = nullptr;
   return ROM_OK;
@@ -273,8 +274,11 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
   if (o.warm_start == ROM_WARM_MLP && !o.mlp) return ROM_EINVAL;
   DeviceGuard guard(h->device);
   if (o.grid_per_cu < 0 || o.grid_per_cu > 64) return ROM_EINVAL;
+  if (o.max_substeps < 0 || o.max_substeps > ROM_MAX_SUBSTEPS) return ROM_EINVAL;
+  if (o.max_substeps > 0 && !o.commit) return ROM_EUNSUPPORTED;  // sub-steps are committed as they converge
   if (o.mode == ROM_MODE_STAGED) {
-    if (o.contraction != ROM_DT_F64 || o.warm_start != ROM_WARM_PREV || o.active || o.grid_per_cu)
+    if (o.contraction != ROM_DT_F64 || o.warm_start != ROM_WARM_PREV || o.active || o.grid_per_cu ||
+        o.max_substeps)
       return ROM_EUNSUPPORTED;
     return rom_launch_step_staged(h, batch, Fbar_dev, state_dev, o, status_dev, iters_dev, resnorm_dev, stream);
   }

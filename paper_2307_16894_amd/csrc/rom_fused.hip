@@ -49,6 +49,7 @@ int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, 
   a.max_iter = o.max_iter;
   a.fixed = o.fixed_iters;
   a.commit = o.commit;
+  a.max_sub = o.max_substeps;
   a.tol = o.tol;
   a.inv_area = 1.0 / h->cell_area;
   a.mp = h->mp;

@@ -5,6 +5,7 @@
 
 struct FusedArgs {
   int n, m, max_iter, fixed, commit;
+  int max_sub;  // load-step cutting depth (0: plain step)
   double tol, inv_area;
   J2Params mp;
   const double* Gt;

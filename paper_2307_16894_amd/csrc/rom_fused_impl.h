@@ -356,8 +356,18 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
     }
     sR[i] = v;
   }
-  const double Fb[4] = {a.Fbar[4 * (size_t)p], a.Fbar[4 * (size_t)p + 1], a.Fbar[4 * (size_t)p + 2],
-                        a.Fbar[4 * (size_t)p + 3]};
+  double Fb[4] = {a.Fbar[4 * (size_t)p], a.Fbar[4 * (size_t)p + 1], a.Fbar[4 * (size_t)p + 2],
+                  a.Fbar[4 * (size_t)p + 3]};
+  // load-step cutting: targets F0 + (t / 2^D) (Fbar - F0) on the segment from
+  // the committed F0; sF0 / sF1 hold the two ends
+  double* sF0 = sX + 96;
+  double* sF1 = sX + 100;
+  if (tid < 4) {
+    sF0[tid] = a.fbc[4 * (size_t)p + tid];
+    sF1[tid] = Fb[tid];
+  }
+  const int full = 1 << a.max_sub;
+  int t_done = 0, stride = full, total = 0;
   const double* tmu = a.tmu + (size_t)p * 5 * m;
   const double* hc = a.hc + (size_t)p * 6 * m;
   double* ht = a.ht + (size_t)p * 6 * m;
@@ -367,6 +377,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
   int status = ROM_ST_MAXITER, iters = 0;
   double rn = 0.0, rn0 = 0.0;
   bool fell_back = false;
+  for (int attempt = 0;; ++attempt) {
   for (int it = 0; it < a.max_iter; ++it) {
     constexpr bool QSPLIT = (SPLIT == 0);             // waves split the points (else the tiles)
     constexpr int NACC = QSPLIT ? NT : (NT + 3) / 4;  // large n: waves split the tiles
@@ -499,7 +510,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
     if (stop) break;
     // warm start judged by plain Newton: no tenfold drop of ||f|| after two
     // updates -> restart from the committed r
-    if (a.dr && !fell_back && it == 2 && !(rn <= 0.1 * rn0)) {
+    if (a.dr && attempt == 0 && !fell_back && it == 2 && !(rn <= 0.1 * rn0)) {
       fell_back = true;
       for (int i = tid; i < n; i += 256) sR[i] = a.rc[(size_t)p * n + i];
       __syncthreads();
@@ -510,6 +521,31 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
     if (tid < n) sR[tid] -= sSol[4 * tid];
     __syncthreads();
   }
+  total += iters;
+  if (status == ROM_ST_CONVERGED) {
+    t_done += stride;
+    if (t_done == full) break;
+    // a converged sub-step becomes the committed start of the next attempt
+    // (each thread copies the ECM points it wrote)
+    double* hcw = a.hc + (size_t)p * 6 * m;
+    for (int q = tid; q < m; q += 256)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) hcw[k * m + q] = ht[k * m + q];
+    for (int i = tid; i < n; i += 256) a.rc[(size_t)p * n + i] = sR[i];
+    if (tid < 4) a.fbc[4 * (size_t)p + tid] = Fb[tid];
+    stride = min(2 * stride, full - t_done);
+  } else {
+    if (stride == 1) break;  // the smallest sub-step failed too
+    stride >>= 1;
+    for (int i = tid; i < n; i += 256) sR[i] = a.rc[(size_t)p * n + i];
+  }
+  const int t_next = t_done + stride;
+  const double frac = ldexp((double)t_next, -a.max_sub);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Fb[k] = (t_next == full) ? sF1[k] : sF0[k] + frac * (sF1[k] - sF0[k]);
+  __syncthreads();
+  }
+  iters = total;
 
   // Effective quantities at the returned state (Sec. 3.3): one more pass over
   // the ECM points for Pbar = sum wJ P, sum wJ A and C = sum_q G_q^T E_q; the

@@ -19,7 +19,7 @@ from .batch import RomBatch
 
 class Group:
     def __init__(self, rom_path, mu, paths, nsteps, contraction=DT_F64, split=-1, grid_per_cu=2, max_iter=15,
-                 device='cuda:0'):
+                 max_substeps=4, device='cuda:0'):
         self.rb = RomBatch(rom_path, mu, device)
         dev = self.rb.device
         self.P = self.rb.P
@@ -33,7 +33,7 @@ class Group:
         self.solved = torch.zeros(self.P, dtype=torch.int64, device=dev)
         self.failed = torch.zeros(self.P, dtype=torch.int64, device=dev)
         self.opts = rom_default_opts(mode=MODE_FUSED, contraction=contraction, split=split, grid_per_cu=grid_per_cu,
-                                     max_iter=max_iter)
+                                     max_iter=max_iter, max_substeps=max_substeps)
         self.opts.active = self.active.data_ptr()
 
     def enqueue(self, stream):

@@ -18,7 +18,9 @@ from tests.conftest import rom_path
 pytestmark = pytest.mark.gpu
 
 W = WORKLOADS['onevoid_n40_m400_P4096_cyclic20']
-SAMPLE = np.unique(np.r_[np.linspace(0, W['P'] - 1, 12).astype(int), 1, 255, 256, 2047])
+# spread over the batch, plus points whose plain Newton step fails somewhere
+# on their path (they converge with load-step cutting)
+SAMPLE = np.unique(np.r_[np.linspace(0, W['P'] - 1, 12).astype(int), 1, 255, 256, 2047, 27, 83, 122, 145])
 
 
 def rel(a, b):
@@ -42,9 +44,10 @@ def run_gpu(opts, K):
 
 
 @functools.lru_cache(maxsize=None)
-def oracle(p, K, fixed, max_iter):
+def oracle(p, K, fixed, max_iter, max_substeps=0):
     mu, paths = inputs(W)
-    return ROM(rom_path(W['rom'])).run_path(mu[p], paths[p, :K], tol=1e-8, max_iter=max_iter, fixed=fixed)
+    return ROM(rom_path(W['rom'])).run_path(mu[p], paths[p, :K], tol=1e-8, max_iter=max_iter, fixed=fixed,
+                                            max_substeps=max_substeps)
 
 
 def test_fixed_iteration_parity_full_size(gpu):
@@ -61,17 +64,32 @@ def test_fixed_iteration_parity_full_size(gpu):
 
 @pytest.mark.parametrize("dt,tol_P,tol_A", [(L.DT_F64, 1e-6, 1e-6), (L.DT_BF16, 1e-5, 3e-2)])
 def test_converged_paths_full_size(gpu, dt, tol_P, tol_A):
+    """Plain Newton with load-step cutting (depth 4), as the benchmark runs it:
+    every point-step of the batch converges, and the sampled points agree with
+    the oracle to the Newton tolerance."""
     K = W['steps']
-    g = run_gpu(L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt), K)
+    g = run_gpu(L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt, max_substeps=4), K)
     conv = np.mean([(rec['status'] == 0).mean() for rec in g])
-    print(f"contraction {dt}: converged fraction {conv:.5f}")
-    assert conv > 0.999
+    print(f"contraction {dt}: converged fraction {conv:.6f}")
+    assert conv > 0.9995
     for p in SAMPLE:
-        ref = oracle(int(p), K, False, 15)
+        ref = oracle(int(p), K, False, 15, 4)
         for k in range(K):
-            assert g[k]['status'][p] == ref[k]['status'], (p, k)
-            if ref[k]['status'] != 0:
-                continue
-            assert abs(int(g[k]['iters'][p]) - ref[k]['iters']) <= 1 + (dt != L.DT_F64)
+            assert g[k]['status'][p] == ref[k]['status'] == 0, (p, k)
+            if dt == L.DT_F64:
+                assert abs(int(g[k]['iters'][p]) - ref[k]['iters']) <= 2, (p, k)
             assert rel(g[k]['Pbar'][p], ref[k]['Pbar']) < tol_P, (p, k)
             assert rel(g[k]['Abar'][p], ref[k]['Abar'].reshape(-1)) < tol_A, (p, k)
+
+
+def test_plain_step_failures_keep_committed_state(gpu):
+    """Without cutting some steps of the workload fail; a failed point keeps
+    its committed state, and the sampled failing points fail on the oracle too."""
+    K = 4
+    g = run_gpu(L.rom_default_opts(mode=L.MODE_FUSED), K)
+    failed = np.flatnonzero(np.any([rec['status'] != 0 for rec in g], axis=0))
+    print(f"points with a failed plain step in the first {K} steps: {failed.size}")
+    assert failed.size > 0
+    for p in failed[:6]:
+        ref = oracle(int(p), K, False, 15)
+        assert [g[k]['status'][p] for k in range(K)] == [ref[k]['status'] for k in range(K)], p

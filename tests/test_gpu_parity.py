@@ -137,3 +137,39 @@ def test_active_mask_skips_points(gpu):
             assert (masked.iters[~on] == -7).all()
         full.close()
         masked.close()
+
+
+@pytest.mark.parametrize("form", ['fused', 'fused_tilesplit_queue'])
+def test_load_step_cutting_parity(gpu, form):
+    """Large increments from the virgin state, where the plain step fails:
+    with cutting depth 4 (fixed evaluations per attempt, so both sides take
+    the same attempts) the kernel follows the oracle's sequence of sub-steps
+    and commits the same state."""
+    from paper_2307_16894_amd import batch as B
+    import paper_2307_16894_amd as L
+    name = 'onevoid_n20_m120'
+    P, K, D, it = 16, 2, 4, 8
+    mu = workloads.one_void_mu(7, 40)[:P]
+    paths = workloads.monotone_paths(7, 40, K, rho=(0.06, 0.1))[:P]
+    rb = B.RomBatch(rom_path(name), mu)
+    rom = ROM(rom_path(name))
+    refs = [rom.run_path(mu[p], paths[p], max_iter=it, fixed=True, max_substeps=D) for p in range(P)]
+    assert sum(len(refs[p][k]['targets']) for p in range(P) for k in range(K)) > 0
+    for k in range(K):
+        print(f"[gpu] cutting {form} step {k}", flush=True)
+        o = L.rom_default_opts(max_iter=it, fixed_iters=1, max_substeps=D, **FORMS[form])
+        st, its, _ = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), o)
+        torch.cuda.synchronize()
+        st, its = st.cpu().numpy(), its.cpu().numpy()
+        Pb, Ab, rc, fbc = (rb.Pbar.cpu().numpy(), rb.Abar.cpu().numpy(), rb.r().cpu().numpy(),
+                           rb.fbar_committed().cpu().numpy())
+        hc = rb.history().cpu().numpy()
+        for p in range(P):
+            s = refs[p][k]
+            assert st[p] == s['status'] and its[p] == s['iters'], (p, k, st[p], s['status'], its[p], s['iters'])
+            assert rel_err(Pb[p], s['Pbar']) < TOL and rel_err(Ab[p], s['Abar'].reshape(-1)) < TOL, (p, k)
+            r_c, h_c, F_c = ((s['r'], s['hist'], paths[p, k]) if s['status'] == 0
+                             else (s['r_c'], s['hist_c'], s['Fbar_c']))
+            assert rel_err(rc[p], r_c) < TOL and rel_err(fbc[p], np.asarray(F_c).reshape(-1)) < 1e-15, (p, k)
+            assert rel_err(hc[p][0:4].T.reshape(-1, 2, 2), h_c[0]) < TOL, (p, k)
+    rb.close()
