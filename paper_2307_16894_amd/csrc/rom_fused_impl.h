@@ -3,27 +3,37 @@
 // on the device.
 //
 // Per Newton evaluation the workgroup walks the ECM points in chunks of 256
-// (one lane per point): kinematics, return map and tangent (Appendix A), the
-// weighted stress W = w|J| P F_mu^-T and the mapped tangent
-// D = w|J| T^T A T (T: right multiplication by F_mu^-1) go to LDS.  The
-// contraction K = sum_q G_q^T D_q G_q (eq. stiffnessmatrix_ecm) then runs on
-// MFMA with the 4 gradient components of an ECM point as the inner
-// dimension:
-//   FP64  v_mfma_f64_16x16x4: B_q = [D_q G_q | W_q], so the residual
-//         f = sum_q G_q^T W_q (eq. forcevector_ecm) comes out of the padding
-//         column n of the stiffness tiles;
-//   FP32  v_mfma_f32_16x16x4 on FP32 operands, FP32 accumulation;
+// (one lane per point): kinematics, return map and tangent (Appendix A), and
+// an LDS record per point with
+//   E = w|J| T^T A      (T: right multiplication by F_mu^-1; D = E T),
+//   W = w|J| P F_mu^-T, F_mu^-1 and F_mu.
+// The contraction then runs on MFMA with the four gradient components of an
+// ECM point as the inner dimension, as sum_q A_q^T B_q with
+//   A_q = [G_q | R_q]            (R_q: four rows carrying F_mu, see below),
+//   B_q = [D_q G_q | W_q | E_q]  (columns n, n + 1 .. n + 4),
+// padded to 16 T rows and columns (16 T >= n + 5).  One contraction therefore
+// gives, at the state of the evaluation,
+//   K = sum_q G_q^T D_q G_q                (eq. stiffnessmatrix_ecm),
+//   f = sum_q G_q^T W_q                    (eq. forcevector_ecm, column n),
+//   C = sum_q G_q^T E_q                    (the right-hand sides of the four
+//                                           tangent problems, eq. tangent_problem_red),
+// and through the rows R_q (row n + 2i + J carries F_mu[J][.] against the
+// components (i, .) of W and E, which undoes the F_mu^-T of W and of T^T)
+//   sum_q w|J| P  and  sum_q w|J| A        (eqs. eff_stress_1, eff_stiffness_1).
+// Only the tiles I <= J are contracted (K and the padding blocks are symmetric
+// or above the diagonal); the rest of K is mirrored.
+//   FP64  v_mfma_f64_16x16x4f64;
+//   FP32  v_mfma_f32_16x16x4f32 on FP32 operands, FP32 accumulation;
 //   BF16  v_mfma_f32_16x16x32_bf16, eight ECM points per instruction, FP32
 //         accumulation;
-// in the reduced-precision forms f is accumulated separately in FP64, so the
-// residual, the return map and the solve stay FP64.  K is symmetric (the
-// tangent of the appendix model is major-symmetric), so only tiles I <= J are
-// contracted and the rest is mirrored.  Small n: the four waves split the
-// points; large n: they split the tiles.  Gaussian elimination with partial
-// pivoting in LDS gives the Newton update.  At the returned state one more
-// pass over the ECM points gives Pbar (eq. eff_stress_1), sum w|J| A and
-// C = sum_q G_q^T E_q (E = w|J| T^T A), and Abar = sum w|J| A - C^T K*^-1 C
-// (eqs. tangent_problem_red, eff_stiffness_1) with K* the last K.
+// in the reduced-precision forms f and sum w|J| P are accumulated separately
+// in FP64, so the residual, the stress, the return map and the solve stay
+// FP64 (K, C and sum w|J| A carry the contraction precision).  Small n: the
+// four waves split the points; large n: they split the tiles.  Gauss-Jordan
+// elimination with partial pivoting on [K | f | C], with the matrix spread
+// over the registers of the workgroup, gives the Newton update and
+// K^-1 C; at the returned state Abar = sum w|J| A - C^T K*^-1 C with K* the K
+// of the last evaluation (Sec. 3.3).
 #pragma once
 #include "rom_fused_args.h"
 
@@ -34,23 +44,22 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 namespace {
 
 constexpr int FCH = 256;  // ECM points per chunk
-constexpr int QS = 20;    // LDS record per point in the Newton loop: D (16), W (4)
+constexpr int QS = 28;    // LDS record per point
+constexpr int R_E = 0, R_W = 16, R_FI = 20, R_FM = 24;
 
-
-
-// ECM points per chunk of the effective-quantity pass (E records sit above the LU)
 template <int T>
-constexpr int ech() {
-  return T >= 8 ? 128 : FCH;
+constexpr int ldk() {
+  return 16 * T + 1;  // leading dimension of [K | f | C] in LDS
 }
-// LDS: chunk records / [K | f] with its LU and the E records, then r, C, C copy, scratch, pivots
 template <int T>
 constexpr int main_doubles() {
-  return (FCH * QS > 256 * T * T + 16 * ech<T>()) ? FCH * QS : 256 * T * T + 16 * ech<T>();
+  return (FCH * QS > 16 * T * ldk<T>()) ? FCH * QS : 16 * T * ldk<T>();
 }
+// LDS: chunk records / [K | f | C]; then r, C copy, multipliers (2 x 128),
+// pivot values (128), misc (32), pivot order and pivot exchange (ints)
 template <int T>
 constexpr int lds_doubles() {
-  return main_doubles<T>() + 16 * T * 9 + 128 + 16 * T;  // r, C, solutions, scratch, two int arrays
+  return main_doubles<T>() + 16 * T + 4 * 16 * T + 256 + 128 + 32 + (16 * T + 8) / 2;
 }
 
 // F = Fbar + (sum_i r_i G_i(q)) F_mu^-1 at ECM point q (argument of P in
@@ -73,109 +82,11 @@ __device__ __forceinline__ void kinematics(int n, int m, int q, const double* __
   F[3] = Fb[3] + H2 * Fi[1] + H3 * Fi[3];
 }
 
-// E[(i r)][y] = w|J| sum_j Fi[r][j] A[(i j)][y]   (E = w|J| T^T A)
-__device__ __forceinline__ void mapped_left(const double A[16], const double Fi[4], double wJ, double E[16]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int y = 0; y < 4; ++y)
-        E[4 * (2 * i + r) + y] = wJ * (Fi[2 * r] * A[4 * (2 * i) + y] + Fi[2 * r + 1] * A[4 * (2 * i + 1) + y]);
-}
-
-
-// Solve K X = B in LDS by Gaussian elimination with partial pivoting, rows
-// left in place: at step k the pivot is the remaining row with the largest
-// |a[r][k]| (lowest index on ties), and every other remaining row is
-// eliminated against it.  a has leading dimension ld; B occupies columns
-// rhs0 .. rhs0 + nrhs - 1.  The solution of unknown k is written to
-// x[k * 4 + c].  Two barriers per elimination step, one per back step.
-__device__ void gauss_solve(double* a, int ld, int n, int rhs0, int nrhs, int* sStep, int* sOrder, double* x) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  for (int i = tid; i < n; i += blockDim.x) sStep[i] = n;  // n: not yet a pivot
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = n;
-      for (int i = lane; i < n; i += 64) {
-        if (sStep[i] == n) {
-          const double v = fabs(a[i * ld + k]);
-          if (v > best) {
-            best = v;
-            bi = i;
-          }
-        }
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        if (bi == n)  // only non-finite entries left: take the first remaining row
-          for (bi = 0; bi < n - 1 && sStep[bi] != n; ++bi) {
-          }
-        sOrder[k] = bi;
-        sStep[bi] = k;
-      }
-    }
-    __syncthreads();
-    const int pr = sOrder[k];
-    const double inv = 1.0 / a[pr * ld + k];
-    const int nk = n - 1 - k;
-    const int ncols = nk + nrhs;
-    for (int idx = tid; idx < n * ncols; idx += blockDim.x) {
-      const int r = idx / ncols, jj = idx - r * ncols;
-      if (sStep[r] < n) continue;  // already a pivot row (includes pr)
-      const int j = (jj < nk) ? k + 1 + jj : rhs0 + (jj - nk);
-      a[r * ld + j] = fma(-a[r * ld + k] * inv, a[pr * ld + j], a[r * ld + j]);
-    }
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    const int pr = sOrder[k];
-    const double inv = 1.0 / a[pr * ld + k];
-    for (int idx = tid; idx < n * nrhs; idx += blockDim.x) {
-      const int r = idx / nrhs, c = idx - r * nrhs;
-      const double xk = a[pr * ld + rhs0 + c] * inv;
-      if (r == 0) x[k * 4 + c] = xk;
-      if (sStep[r] < k) a[r * ld + rhs0 + c] = fma(-a[r * ld + k], xk, a[r * ld + rhs0 + c]);
-    }
-    __syncthreads();
-  }
-}
-
-// G_q[b][16 J + c] for the four gradient components b and all column blocks J.
-template <int T>
-__device__ __forceinline__ void load_g(double (&g)[4][T], const double* __restrict__ Gp, int c_col) {
-  constexpr int NPAD = 16 * T;
-#pragma unroll
-  for (int J = 0; J < T; ++J)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) g[b][J] = Gp[b * NPAD + 16 * J + c_col];
-}
-
-// Upper-triangle tile t (column-major over J, then I <= J) -> (I, J).
-__host__ __device__ constexpr int tile_I(int t) {
-  int J = 0;
-  while (t > J) {
-    t -= J + 1;
-    ++J;
-  }
-  return t;
-}
-__host__ __device__ constexpr int tile_J(int t) {
-  int J = 0;
-  while (t > J) {
-    t -= J + 1;
-    ++J;
-  }
-  return J;
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)u, l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 __device__ __forceinline__ __bf16 to_bf16(float x) {
@@ -194,125 +105,401 @@ struct Acc<PREC_F64> {
   typedef d4 type;
 };
 
-// Contraction of points [qa, qb) of the chunk into the tiles t = W, W + TW, ...
-// (TW = 1: all tiles).  FP64 also accumulates f in column n of the tiles; the
-// reduced-precision forms add G_q[k][j] W_q[k] to fpart (FP64) when do_f.
-template <int T, int PREC, int W, int TW>
-__device__ __forceinline__ void contract(typename Acc<PREC>::type* acc, double (&fpart)[T], bool do_f,
-                                         const double* __restrict__ Gq, const double* sQ, int q0, int qa, int qb,
-                                         int n, int k_row, int c_col) {
+// Per-lane constants of the padding rows and columns (n is the same for all
+// points of a launch):
+//   A side, tile row In = n / 16: lane row 16 In + c_col in [n, n + 4) takes
+//     F_mu[J'][j] from the record when its component i matches (row n + 2i' + J');
+//   B side, tiles In and In + 1: lane column n takes W[k_row], columns
+//     n + 1 .. n + 4 take E[k_row][col - n - 1].
+struct Pad {
+  int In;       // tile row / column of index n
+  bool a_use;   // this lane's A value in tile In comes from the record
+  int a_off;    // its record offset
+  bool b_use0;  // this lane's B value in tile In comes from the record
+  int b_off0;
+  bool b_use1;  // ... in tile In + 1
+  int b_off1;
+};
+
+__device__ __forceinline__ Pad make_pad(int n, int k_row, int c_col) {
+  Pad d;
+  d.In = n >> 4;
+  const int row = 16 * d.In + c_col, ar = row - n;
+  d.a_use = (ar >= 0 && ar < 4 && (ar >> 1) == (k_row >> 1));
+  d.a_off = R_FM + 2 * (ar & 1) + (k_row & 1);
+  const int c0 = 16 * d.In + c_col - n, c1 = c0 + 16;
+  d.b_use0 = (c0 >= 0 && c0 <= 4);
+  d.b_off0 = (c0 == 0) ? R_W + k_row : R_E + 4 * k_row + (c0 - 1);
+  d.b_use1 = (c1 >= 0 && c1 <= 4);
+  d.b_off1 = (c1 == 0) ? R_W + k_row : R_E + 4 * k_row + (c1 - 1);
+  if (!d.a_use) d.a_off = R_FM;
+  if (!d.b_use0) d.b_off0 = R_W;
+  if (!d.b_use1) d.b_off1 = R_W;
+  return d;
+}
+
+// Loads of one ECM point for the FP64 / FP32 contraction: all four
+// components of the lane's column of every tile (B side) and the lane's own
+// component of every tile row (A side).
+template <int T>
+struct GLoad {
+  double g[4][T];
+  double a[T];
+};
+
+template <int T>
+__device__ __forceinline__ void load_g(GLoad<T>& L, const double* __restrict__ Gp, int k_row, int c_col) {
   constexpr int NPAD = 16 * T;
-  constexpr int NT = T * (T + 1) / 2;
-  if (qa >= qb) return;
-  if constexpr (PREC != PREC_BF16) {
-    // one ECM point per step; the next point's G is loaded during this point's MFMAs
-    double gc[4][T];
-    load_g<T>(gc, Gq + (size_t)(q0 + qa) * 4 * NPAD, c_col);
-    for (int ql = qa; ql < qb; ++ql) {
-      double gn[4][T];
-      load_g<T>(gn, Gq + (size_t)(q0 + min(ql + 1, qb - 1)) * 4 * NPAD, c_col);
-      const double* rq = sQ + ql * QS;
-      const double d0 = rq[4 * k_row], d1 = rq[4 * k_row + 1], d2 = rq[4 * k_row + 2], d3 = rq[4 * k_row + 3];
-      const double wk = rq[16 + k_row];
-      double Aop[T], Bop[T];
+#pragma unroll
+  for (int J = 0; J < T; ++J)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) L.g[b][J] = Gp[b * NPAD + 16 * J + c_col];
+#pragma unroll
+  for (int I = 0; I < T; ++I) L.a[I] = Gp[k_row * NPAD + 16 * I + c_col];
+}
+
+// MFMA operands of one ECM point: A[I] for tile row I, B[J] for tile column J.
+template <int T>
+struct Ops {
+  double A[T], B[T];
+};
+
+// Operands of the point with record rq and loads L (and, in the
+// reduced-precision forms, its FP64 residual partial G_q[k_row][col] W_q[k_row]).
+template <int T, int PREC>
+__device__ __forceinline__ void make_ops(Ops<T>& O, double (&fpart)[T], bool do_f, const GLoad<T>& L,
+                                         const double* rq, const Pad& pd, int k_row, int n, int c_col) {
+  // row k_row of D = E T:  D[b][(k, s)] = E[b][2k] Fi[s][0] + E[b][2k + 1] Fi[s][1]
+  const double e0 = rq[R_E + 4 * k_row], e1 = rq[R_E + 4 * k_row + 1];
+  const double e2 = rq[R_E + 4 * k_row + 2], e3 = rq[R_E + 4 * k_row + 3];
+  const double f0 = rq[R_FI], f1 = rq[R_FI + 1], f2 = rq[R_FI + 2], f3 = rq[R_FI + 3];
+  const double d0 = fma(e0, f0, e1 * f1), d1 = fma(e0, f2, e1 * f3);
+  const double d2 = fma(e2, f0, e3 * f1), d3 = fma(e2, f2, e3 * f3);
+  const double xa = rq[pd.a_off], xb0 = rq[pd.b_off0], xb1 = rq[pd.b_off1];
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+    double h = d0 * L.g[0][J];
+    h = fma(d1, L.g[1][J], h);
+    h = fma(d2, L.g[2][J], h);
+    h = fma(d3, L.g[3][J], h);
+    if (J == pd.In) h = pd.b_use0 ? xb0 : h;
+    if (J == pd.In + 1) h = pd.b_use1 ? xb1 : h;
+    O.B[J] = h;
+    double av = L.a[J];
+    if (J == pd.In) av = pd.a_use ? xa : av;
+    O.A[J] = av;
+  }
+  if constexpr (PREC != PREC_F64) {
+    if (do_f) {
+      const double wk = rq[R_W + k_row];
 #pragma unroll
       for (int J = 0; J < T; ++J) {
         const int col = 16 * J + c_col;
-        Aop[J] = (k_row == 0) ? gc[0][J] : (k_row == 1) ? gc[1][J] : (k_row == 2) ? gc[2][J] : gc[3][J];
-        const double h = d0 * gc[0][J] + d1 * gc[1][J] + d2 * gc[2][J] + d3 * gc[3][J];
-        if constexpr (PREC == PREC_F64) {
-          Bop[J] = (col < n) ? h : ((col == n) ? wk : 0.0);
-        } else {
-          Bop[J] = (col < n) ? h : 0.0;
-          if (do_f) fpart[J] = fma(Aop[J], wk, fpart[J]);
-        }
+        fpart[J] = fma(col < n ? L.a[J] : 0.0, wk, fpart[J]);
       }
-#pragma unroll
-      for (int t = W, u = 0; t < NT; t += TW, ++u) {
-        if constexpr (PREC == PREC_F64)
-          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Aop[tile_I(t)], Bop[tile_J(t)], acc[u], 0, 0, 0);
-        else
-          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)Aop[tile_I(t)], (float)Bop[tile_J(t)], acc[u], 0,
-                                                         0, 0);
-      }
-#pragma unroll
-      for (int b2 = 0; b2 < 4; ++b2)
-#pragma unroll
-        for (int J = 0; J < T; ++J) gc[b2][J] = gn[b2][J];
-    }
-  } else {
-    // eight ECM points per step: lane group g = k_row holds points 2g, 2g + 1
-    // of the step; inner index k = 8 g + 4 h + b (point 2g + h, component b)
-    for (int qs = qa; qs < qb; qs += 8) {
-      float D[2][16];
-      double Wv[2][4];
-      bool live[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int ql = qs + 2 * k_row + h;
-        live[h] = ql < qb;
-        const double* rq = sQ + (live[h] ? ql : qa) * QS;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) D[h][k] = live[h] ? (float)rq[k] : 0.0f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Wv[h][k] = live[h] ? rq[16 + k] : 0.0;
-      }
-      bf8 Aop[T], Bop[T];
-#pragma unroll
-      for (int J = 0; J < T; ++J) {
-        const int col = 16 * J + c_col;
-        double g[2][4];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int ql = qs + 2 * k_row + h;
-          const double* Gp = Gq + (size_t)(q0 + (live[h] ? ql : qa)) * 4 * NPAD + col;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) g[h][b] = live[h] ? Gp[b * NPAD] : 0.0;
-        }
-        if (do_f) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) fpart[J] = fma(g[h][b], Wv[h][b], fpart[J]);
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const float g0 = (float)g[h][0], g1 = (float)g[h][1], g2 = (float)g[h][2], g3 = (float)g[h][3];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            Aop[J][4 * h + b] = to_bf16((float)g[h][b]);
-            const float hv = D[h][4 * b] * g0 + D[h][4 * b + 1] * g1 + D[h][4 * b + 2] * g2 + D[h][4 * b + 3] * g3;
-            Bop[J][4 * h + b] = to_bf16(col < n ? hv : 0.0f);
-          }
-        }
-      }
-#pragma unroll
-      for (int t = W, u = 0; t < NT; t += TW, ++u)
-        acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[tile_I(t)], Bop[tile_J(t)], acc[u], 0, 0, 0);
     }
   }
 }
 
-// Store (ACCUM: add) the tiles t = W, W + TW, ... into sK (ld NPAD); when
-// MIRROR, also the transposed tile below the diagonal.
+// The MFMAs of one point into the tiles of this wave (all tiles when TW = 1,
+// else the tiles v = W, W + 4, ... in the order J = 0.., I = 0..J).
+template <int T, int PREC, int W, int TW>
+__device__ __forceinline__ void mfma_ops(typename Acc<PREC>::type* acc, const Ops<T>& O) {
+  int u = 0, v = 0;
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+#pragma unroll
+    for (int I = 0; I <= J; ++I) {
+      if ((v % TW) == W) {
+        if constexpr (PREC == PREC_F64)
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(O.A[I], O.B[J], acc[u], 0, 0, 0);
+        else
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)O.A[I], (float)O.B[J], acc[u], 0, 0, 0);
+        ++u;
+      }
+      ++v;
+    }
+  }
+}
+
+// Contraction of points [qa, qb) of the chunk (FP64 / FP32 operands).  The
+// G loads run two points ahead (three rotating register sets) and the
+// operands of the next point are formed while the current point's MFMAs
+// execute.
+template <int T, int PREC, int W, int TW>
+__device__ __forceinline__ void contract_range(typename Acc<PREC>::type* acc, double (&fpart)[T], bool do_f,
+                                               const double* __restrict__ Gq, const double* sQ, int q0, int qa,
+                                               int qb, const Pad& pd, int n, int k_row, int c_col) {
+  constexpr int NPAD = 16 * T;
+  if (qa >= qb) return;
+  const double* Gb = Gq + (size_t)q0 * 4 * NPAD;
+  const int ql_max = qb - 1;
+  GLoad<T> L0, L1, L2;
+  load_g<T>(L0, Gb + (size_t)qa * 4 * NPAD, k_row, c_col);
+  load_g<T>(L1, Gb + (size_t)min(qa + 1, ql_max) * 4 * NPAD, k_row, c_col);
+  Ops<T> O;
+  make_ops<T, PREC>(O, fpart, do_f, L0, sQ + qa * QS, pd, k_row, n, c_col);
+  for (int ql = qa; ql < qb; ql += 3) {
+    load_g<T>(L2, Gb + (size_t)min(ql + 2, ql_max) * 4 * NPAD, k_row, c_col);
+    mfma_ops<T, PREC, W, TW>(acc, O);
+    if (ql + 1 >= qb) break;
+    make_ops<T, PREC>(O, fpart, do_f, L1, sQ + (ql + 1) * QS, pd, k_row, n, c_col);
+    load_g<T>(L0, Gb + (size_t)min(ql + 3, ql_max) * 4 * NPAD, k_row, c_col);
+    mfma_ops<T, PREC, W, TW>(acc, O);
+    if (ql + 2 >= qb) break;
+    make_ops<T, PREC>(O, fpart, do_f, L2, sQ + (ql + 2) * QS, pd, k_row, n, c_col);
+    load_g<T>(L1, Gb + (size_t)min(ql + 4, ql_max) * 4 * NPAD, k_row, c_col);
+    mfma_ops<T, PREC, W, TW>(acc, O);
+    if (ql + 3 >= qb) break;
+    make_ops<T, PREC>(O, fpart, do_f, L0, sQ + (ql + 3) * QS, pd, k_row, n, c_col);
+  }
+}
+
+// BF16: eight ECM points per instruction; lane group g = k_row holds points
+// 2g, 2g + 1 of the step, inner index k = 8 g + 4 h + b (point 2g + h,
+// component b).  D and the operands are formed in FP32 from the FP64 record.
+template <int T, int W, int TW>
+__device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T], bool do_f,
+                                                    const double* __restrict__ Gq, const double* sQ, int q0, int qa,
+                                                    int qb, const Pad& pd, int n, int k_row, int c_col) {
+  constexpr int NPAD = 16 * T;
+  const int arow = 16 * pd.In + c_col - n;  // padding-row offset of this lane in tile In
+  for (int qs = qa; qs < qb; qs += 8) {
+    float D[2][16];
+    double Wv[2][4];
+    float Ev[2][16], Fm[2][4];
+    bool live[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int ql = qs + 2 * k_row + h;
+      live[h] = ql < qb;
+      const double* rq = sQ + (live[h] ? ql : qa) * QS;
+      float Fi[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Fi[k] = (float)rq[R_FI + k];
+        Fm[h][k] = live[h] ? (float)rq[R_FM + k] : 0.0f;
+        Wv[h][k] = live[h] ? rq[R_W + k] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) Ev[h][k] = live[h] ? (float)rq[R_E + k] : 0.0f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int s = 0; s < 2; ++s)
+            D[h][4 * b + 2 * k + s] = Ev[h][4 * b + 2 * k] * Fi[2 * s] + Ev[h][4 * b + 2 * k + 1] * Fi[2 * s + 1];
+    }
+    bf8 Aop[T], Bop[T];
+#pragma unroll
+    for (int J = 0; J < T; ++J) {
+      const int col = 16 * J + c_col;
+      double g[2][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int ql = qs + 2 * k_row + h;
+        const double* Gp = Gq + (size_t)(q0 + (live[h] ? ql : qa)) * 4 * NPAD + col;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) g[h][b] = live[h] ? Gp[b * NPAD] : 0.0;
+      }
+      if (do_f) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) fpart[J] = fma(col < n ? g[h][b] : 0.0, Wv[h][b], fpart[J]);
+      }
+      const int dc = col - n;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float g0 = (float)g[h][0], g1 = (float)g[h][1], g2 = (float)g[h][2], g3 = (float)g[h][3];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          float av = (float)g[h][b];
+          if (J == pd.In && arow >= 0 && arow < 4)
+            av = ((arow >> 1) == (b >> 1)) ? Fm[h][2 * (arow & 1) + (b & 1)] : 0.0f;
+          Aop[J][4 * h + b] = to_bf16(av);
+          float hv = D[h][4 * b] * g0 + D[h][4 * b + 1] * g1 + D[h][4 * b + 2] * g2 + D[h][4 * b + 3] * g3;
+          if (dc == 0) hv = (float)Wv[h][b];
+          if (dc >= 1 && dc <= 4) hv = Ev[h][4 * b + dc - 1];
+          Bop[J][4 * h + b] = to_bf16(hv);
+        }
+      }
+    }
+    int u = 0, v = 0;
+#pragma unroll
+    for (int J = 0; J < T; ++J) {
+#pragma unroll
+      for (int I = 0; I <= J; ++I) {
+        if ((v % TW) == W) {
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[I], Bop[J], acc[u], 0, 0, 0);
+          ++u;
+        }
+        ++v;
+      }
+    }
+  }
+}
+
+template <int T, int PREC, int W, int TW>
+__device__ __forceinline__ void contract_any(typename Acc<PREC>::type* acc, double (&fpart)[T], bool do_f,
+                                             const double* __restrict__ Gq, const double* sQ, int q0, int qa, int qb,
+                                             const Pad& pd, int n, int k_row, int c_col) {
+  if constexpr (PREC == PREC_BF16)
+    contract_range_bf16<T, W, TW>(acc, fpart, do_f, Gq, sQ, q0, qa, qb, pd, n, k_row, c_col);
+  else
+    contract_range<T, PREC, W, TW>(acc, fpart, do_f, Gq, sQ, q0, qa, qb, pd, n, k_row, c_col);
+}
+
+// Store (ACCUM: add) the tiles of wave W into sK (ld LD); when MIRROR, also
+// the transposed tile below the diagonal.
 template <int T, int PREC, int W, int TW>
 __device__ __forceinline__ void store_acc(const typename Acc<PREC>::type* acc, double* sK, bool accum, bool mirror,
                                           int k_row, int c_col) {
-  constexpr int NPAD = 16 * T;
-  constexpr int NT = T * (T + 1) / 2;
+  constexpr int LD = ldk<T>();
+  int u = 0, v = 0;
 #pragma unroll
-  for (int t = W, u = 0; t < NT; t += TW, ++u) {
-    const int I = tile_I(t), J = tile_J(t);
+  for (int J = 0; J < T; ++J) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      // output layouts: FP64 row = k_row + 4 j, FP32 accumulators row = 4 k_row + j
-      const int row = 16 * I + (PREC == PREC_F64 ? k_row + 4 * j : 4 * k_row + j), col = 16 * J + c_col;
-      double v = (double)acc[u][j];
-      if (accum) v += sK[row * NPAD + col];
-      sK[row * NPAD + col] = v;
-      if (mirror && I < J) sK[col * NPAD + row] = v;
+    for (int I = 0; I <= J; ++I) {
+      if ((v % TW) == W) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          // output layouts: FP64 row = k_row + 4 j, FP32 accumulators row = 4 k_row + j
+          const int row = 16 * I + (PREC == PREC_F64 ? k_row + 4 * j : 4 * k_row + j), col = 16 * J + c_col;
+          double x = (double)acc[u][j];
+          if (accum) x += sK[row * LD + col];
+          sK[row * LD + col] = x;
+          if (mirror && I < J) sK[col * LD + row] = x;
+        }
+        ++u;
+      }
+      ++v;
     }
   }
+}
+
+// Unsigned maximum over the 64 lanes of a wave with DPP moves (quad
+// permutations, row mirrors, row broadcasts); returned uniform.
+__device__ __forceinline__ unsigned int wave_max_u32(unsigned int v) {
+  v = max(v, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = max(v, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = max(v, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+  v = max(v, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast15
+  v = max(v, (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast31
+  return (unsigned int)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Pivot key of a candidate row: the upper 32 bits of |v| (sign, exponent and
+// 20 mantissa bits, monotone in |v|) plus one, so that every candidate beats
+// the rows that are not candidates (key 0).  Candidates within a relative
+// 2^-20 of the largest count as ties and the lowest row index wins, which
+// keeps the choice of partial pivoting (a pivot of maximal magnitude up to
+// that factor).
+__device__ __forceinline__ unsigned int pivot_key(double v, bool cand) {
+  const unsigned int hi = (unsigned int)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffffu;
+  return cand ? hi + 1u : 0u;
+}
+
+// Gauss-Jordan elimination with partial pivoting of the n x (n + 5) system
+// [K | f | C] in sK (ld LD): lane l of wave w holds rows l (and l + 64) in the
+// columns j = w + 4 c.  Step k: the wave owning column k picks the pivot row
+// (largest |a[r][k]| among the rows not yet pivots) and publishes the column
+// and the pivot value; every wave then eliminates column k from all other
+// rows with the pivot row scaled by 1 / a[pr][k] (pivot rows themselves stay
+// unscaled and are divided by their pivot at the end).  One barrier per
+// step.  On return sK[ord[k]][n + y] holds unknown k of right-hand side y
+// (y = 0: f, 1..4: C) with ord[k] = sOrd[k].
+template <int T>
+__device__ void gauss_jordan(double* sK, int n, double* sL, double* sPv, int* sOrd, int* sPiv) {
+  constexpr int NPAD = 16 * T, LD = ldk<T>();
+  constexpr int ROWS = NPAD > 64 ? 2 : 1, COLS = NPAD / 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ncol = n + 5;
+  double a[ROWS][COLS];
+#pragma unroll
+  for (int s = 0; s < ROWS; ++s) {
+    const int r = min(lane + 64 * s, NPAD - 1);
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) a[s][c] = sK[r * LD + wave + 4 * c];
+  }
+#pragma unroll
+  for (int s = 0; s < ROWS; ++s) {
+    const int r = lane + 64 * s;
+#pragma unroll
+    for (int c = 0; c < COLS; ++c)
+      if (r >= n || wave + 4 * c >= ncol) a[s][c] = 0.0;
+  }
+  unsigned int pivmask = 0;  // bit s: row lane + 64 s is already a pivot
+  for (int k = 0; k < n; ++k) {
+    const int ow = k & 3, oc = k >> 2;
+    double* L = sL + (k & 1) * 128;
+    if (wave == ow) {
+      double v[ROWS];
+      unsigned int key[ROWS];
+#pragma unroll
+      for (int s = 0; s < ROWS; ++s) {
+        v[s] = a[s][0];
+#pragma unroll
+        for (int c = 1; c < COLS; ++c) v[s] = (c == oc) ? a[s][c] : v[s];
+        const int r = lane + 64 * s;
+        key[s] = pivot_key(v[s], r < n && !((pivmask >> s) & 1u));
+      }
+      unsigned int kmax = key[0];
+      if constexpr (ROWS == 2) kmax = max(kmax, key[1]);
+      const unsigned int M = wave_max_u32(kmax);
+      const unsigned long long b0 = __ballot(key[0] == M);
+      int pr;
+      if (b0) {
+        pr = __builtin_ctzll(b0);
+      } else {
+        const unsigned long long b1 = __ballot(ROWS == 2 && key[ROWS - 1] == M);
+        pr = 64 + __builtin_ctzll(b1);
+      }
+      // multipliers: column k of every row but the pivot row
+#pragma unroll
+      for (int s = 0; s < ROWS; ++s) {
+        const bool is_p = (lane + 64 * s == pr);
+        L[lane + 64 * s] = is_p ? 0.0 : v[s];
+        if (is_p) sPv[pr] = v[s];
+      }
+      if (lane == 0) {
+        sPiv[k & 1] = pr;
+        sOrd[k] = pr;
+      }
+    }
+    __syncthreads();
+    const int pr = __builtin_amdgcn_readfirstlane(sPiv[k & 1]);
+    const int pl = pr & 63, ps = pr >> 6;
+    const double inv = 1.0 / sPv[pr];
+    double prow[COLS];
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      double src = a[0][c];
+      if constexpr (ROWS == 2) src = ps ? a[1][c] : a[0][c];
+      prow[c] = readlane_d(src, pl) * inv;
+    }
+#pragma unroll
+    for (int s = 0; s < ROWS; ++s) {
+      const double mlt = L[lane + 64 * s];
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) a[s][c] = fma(-mlt, prow[c], a[s][c]);
+      if (lane + 64 * s == pr) pivmask |= 1u << s;
+    }
+  }
+  // the right-hand-side columns, divided by the pivots, back to LDS
+#pragma unroll
+  for (int s = 0; s < ROWS; ++s) {
+    const int r = lane + 64 * s;
+    const double rinv = (r < n) ? 1.0 / sPv[r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      const int j = wave + 4 * c;
+      if (r < n && j >= n && j < ncol) sK[r * LD + j] = a[s][c] * rinv;
+    }
+  }
+  __syncthreads();
 }
 
 // The whole load step of macro point p on one workgroup.  SPLIT 0: the four
@@ -320,18 +507,18 @@ __device__ __forceinline__ void store_acc(const typename Acc<PREC>::type* acc, d
 template <int T, int PREC, int SPLIT>
 __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
   constexpr int NPAD = 16 * T;
+  constexpr int LD = ldk<T>();
   constexpr int NT = T * (T + 1) / 2;
   constexpr int MAT = main_doubles<T>();
-  constexpr int ECH = ech<T>();
   double* sQ = smem;              // [FCH][QS] chunk records
-  double* sK = smem;              // [NPAD][NPAD] [K | f] and its LU (after the contraction)
-  double* sE = smem + NPAD * NPAD;  // [ECH][16] E records of the effective-quantity pass
+  double* sK = smem;              // [NPAD][LD] [K | f | C] (after the contraction)
   double* sR = smem + MAT;        // [NPAD] current r
-  double* sC = sR + NPAD;         // [NPAD][4] C = sum_q G_q^T E_q, then K^-1 C
-  double* sSol = sC + 4 * NPAD;   // [NPAD][4] solutions of the eliminations
-  double* sX = sSol + 4 * NPAD;   // reduction scratch (128)
-  int* sStep = reinterpret_cast<int*>(sX + 128);  // [NPAD] elimination step of each row
-  int* sOrder = sStep + NPAD;                     // [NPAD] pivot row of each step
+  double* sC = sR + NPAD;         // [NPAD][4] C of the evaluation
+  double* sL = sC + 4 * NPAD;     // [2][128] pivot columns of the elimination
+  double* sPv = sL + 256;         // [128] pivot value of each row
+  double* sX = sPv + 128;         // [32] reductions and the load-step ends
+  int* sOrd = reinterpret_cast<int*>(sX + 32);  // [NPAD] pivot row of each step
+  int* sPiv = sOrd + NPAD;                      // [2] pivot exchange
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = a.n, m = a.m;
@@ -360,8 +547,8 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
                   a.Fbar[4 * (size_t)p + 3]};
   // load-step cutting: targets F0 + (t / 2^D) (Fbar - F0) on the segment from
   // the committed F0; sF0 / sF1 hold the two ends
-  double* sF0 = sX + 96;
-  double* sF1 = sX + 100;
+  double* sF0 = sX + 16;
+  double* sF1 = sX + 20;
   if (tid < 4) {
     sF0[tid] = a.fbc[4 * (size_t)p + tid];
     sF1[tid] = Fb[tid];
@@ -371,262 +558,206 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
   const double* tmu = a.tmu + (size_t)p * 5 * m;
   const double* hc = a.hc + (size_t)p * 6 * m;
   double* ht = a.ht + (size_t)p * 6 * m;
+  const int k_row = lane >> 4, c_col = lane & 15;
+  const Pad pd = make_pad(n, k_row, c_col);
   __syncthreads();
 
-  const int k_row = lane >> 4, c_col = lane & 15;
   int status = ROM_ST_MAXITER, iters = 0;
   double rn = 0.0, rn0 = 0.0;
   bool fell_back = false;
   for (int attempt = 0;; ++attempt) {
-  for (int it = 0; it < a.max_iter; ++it) {
-    constexpr bool QSPLIT = (SPLIT == 0);             // waves split the points (else the tiles)
-    constexpr int NACC = QSPLIT ? NT : (NT + 3) / 4;  // large n: waves split the tiles
-    typedef typename Acc<PREC>::type AccV;
-    AccV acc[NACC];
+    for (int it = 0; it < a.max_iter; ++it) {
+      constexpr bool QSPLIT = (SPLIT == 0);             // waves split the points (else the tiles)
+      constexpr int NACC = QSPLIT ? NT : (NT + 3) / 4;  // large n: waves split the tiles
+      typedef typename Acc<PREC>::type AccV;
+      AccV acc[NACC];
 #pragma unroll
-    for (int t = 0; t < NACC; ++t) acc[t] = (AccV){0, 0, 0, 0};
-    double fpart[T];  // FP64 residual partials of the reduced-precision forms
+      for (int t = 0; t < NACC; ++t) acc[t] = (AccV){0, 0, 0, 0};
+      double fpart[T];  // FP64 residual partials of the reduced-precision forms
 #pragma unroll
-    for (int J = 0; J < T; ++J) fpart[J] = 0.0;
+      for (int J = 0; J < T; ++J) fpart[J] = 0.0;
+      double accP[4] = {0.0, 0.0, 0.0, 0.0};  // FP64 sum w|J| P of the reduced-precision forms
 
-    for (int q0 = 0; q0 < m; q0 += FCH) {
-      const int q = q0 + tid;
-      if (q < m) {
-        const double Fi[4] = {tmu[q], tmu[m + q], tmu[2 * m + q], tmu[3 * m + q]};
-        const double wJ = tmu[4 * m + q];
-        double F[4];
-        kinematics(n, m, q, a.Gt, sR, Fb, Fi, F);
-        const double Fp[4] = {hc[q], hc[m + q], hc[2 * m + q], hc[3 * m + q]};
-        double P[4], Fpn[4], Fp33n, xin;
-        double D[16];
+      for (int q0 = 0; q0 < m; q0 += FCH) {
+        const int q = q0 + tid;
+        if (q < m) {
+          const double Fi[4] = {tmu[q], tmu[m + q], tmu[2 * m + q], tmu[3 * m + q]};
+          const double wJ = tmu[4 * m + q];
+          double F[4];
+          kinematics(n, m, q, a.Gt, sR, Fb, Fi, F);
+          const double Fp[4] = {hc[q], hc[m + q], hc[2 * m + q], hc[3 * m + q]};
+          double P[4], Fpn[4], Fp33n, xin;
+          double* rec = sQ + tid * QS;
+          // E = w|J| T^T A, column v of A at a time
+          j2_point_cols<true>(F, Fp, hc[4 * m + q], hc[5 * m + q], a.mp, P, Fpn, Fp33n, xin,
+                              [&](int v, double c0, double c1, double c2, double c3) {
+                                rec[R_E + v] = wJ * (Fi[0] * c0 + Fi[1] * c1);
+                                rec[R_E + 4 + v] = wJ * (Fi[2] * c0 + Fi[3] * c1);
+                                rec[R_E + 8 + v] = wJ * (Fi[0] * c2 + Fi[1] * c3);
+                                rec[R_E + 12 + v] = wJ * (Fi[2] * c2 + Fi[3] * c3);
+                              });
+          ht[q] = Fpn[0];
+          ht[m + q] = Fpn[1];
+          ht[2 * m + q] = Fpn[2];
+          ht[3 * m + q] = Fpn[3];
+          ht[4 * m + q] = Fp33n;
+          ht[5 * m + q] = xin;
+          // W = w|J| P F_mu^-T
+          rec[R_W] = wJ * (P[0] * Fi[0] + P[1] * Fi[1]);
+          rec[R_W + 1] = wJ * (P[0] * Fi[2] + P[1] * Fi[3]);
+          rec[R_W + 2] = wJ * (P[2] * Fi[0] + P[3] * Fi[1]);
+          rec[R_W + 3] = wJ * (P[2] * Fi[2] + P[3] * Fi[3]);
+          const double idet = 1.0 / (Fi[0] * Fi[3] - Fi[1] * Fi[2]);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) D[k] = 0.0;
-        // D = w|J| T^T A T accumulated column by column of A
-        j2_point_cols<true>(F, Fp, hc[4 * m + q], hc[5 * m + q], a.mp, P, Fpn, Fp33n, xin,
-                            [&](int v, double c0, double c1, double c2, double c3) {
-                              const double e0 = wJ * (Fi[0] * c0 + Fi[1] * c1);
-                              const double e1 = wJ * (Fi[2] * c0 + Fi[3] * c1);
-                              const double e2 = wJ * (Fi[0] * c2 + Fi[1] * c3);
-                              const double e3 = wJ * (Fi[2] * c2 + Fi[3] * c3);
-                              const int k = v >> 1, l = v & 1;
+          for (int k = 0; k < 4; ++k) rec[R_FI + k] = Fi[k];
+          rec[R_FM] = Fi[3] * idet;
+          rec[R_FM + 1] = -Fi[1] * idet;
+          rec[R_FM + 2] = -Fi[2] * idet;
+          rec[R_FM + 3] = Fi[0] * idet;
+          if constexpr (PREC != PREC_F64) {
 #pragma unroll
-                              for (int s2 = 0; s2 < 2; ++s2) {
-                                const double t = Fi[2 * s2 + l];
-                                D[0 + 2 * k + s2] = fma(e0, t, D[0 + 2 * k + s2]);
-                                D[4 + 2 * k + s2] = fma(e1, t, D[4 + 2 * k + s2]);
-                                D[8 + 2 * k + s2] = fma(e2, t, D[8 + 2 * k + s2]);
-                                D[12 + 2 * k + s2] = fma(e3, t, D[12 + 2 * k + s2]);
-                              }
-                            });
-        ht[q] = Fpn[0];
-        ht[m + q] = Fpn[1];
-        ht[2 * m + q] = Fpn[2];
-        ht[3 * m + q] = Fpn[3];
-        ht[4 * m + q] = Fp33n;
-        ht[5 * m + q] = xin;
-        double* rec = sQ + tid * QS;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) rec[k] = D[k];
-        // W = w|J| P F_mu^-T
-        rec[16] = wJ * (P[0] * Fi[0] + P[1] * Fi[1]);
-        rec[17] = wJ * (P[0] * Fi[2] + P[1] * Fi[3]);
-        rec[18] = wJ * (P[2] * Fi[0] + P[3] * Fi[1]);
-        rec[19] = wJ * (P[2] * Fi[2] + P[3] * Fi[3]);
-      }
-      __syncthreads();
-      // contraction of the chunk
-      const int qend = min(FCH, m - q0);
-      if constexpr (QSPLIT) {
-        contract<T, PREC, 0, 1>(acc, fpart, true, a.Gq, sQ, q0, wave * 64, min(wave * 64 + 64, qend), n, k_row,
-                                c_col);
-      } else {
-        switch (wave) {
-          case 0: contract<T, PREC, 0, 4>(acc, fpart, true, a.Gq, sQ, q0, 0, qend, n, k_row, c_col); break;
-          case 1: contract<T, PREC, 1, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, n, k_row, c_col); break;
-          case 2: contract<T, PREC, 2, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, n, k_row, c_col); break;
-          default: contract<T, PREC, 3, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, n, k_row, c_col); break;
+            for (int k = 0; k < 4; ++k) accP[k] = fma(wJ, P[k], accP[k]);
+          }
         }
-      }
-      __syncthreads();
-    }
-    // [K | f] into LDS (ld NPAD); K's lower part by symmetry
-    if constexpr (QSPLIT) {
-      for (int w = 0; w < 4; ++w) {
-        if (wave == w) store_acc<T, PREC, 0, 1>(acc, sK, w > 0, w == 3, k_row, c_col);
+        __syncthreads();
+        // contraction of the chunk; the points are shared evenly by the waves
+        const int qend = min(FCH, m - q0);
+        if constexpr (QSPLIT) {
+          const int qa = (wave * qend) >> 2, qb = ((wave + 1) * qend) >> 2;
+          contract_any<T, PREC, 0, 1>(acc, fpart, true, a.Gq, sQ, q0, qa, qb, pd, n, k_row, c_col);
+        } else {
+          switch (wave) {
+            case 0: contract_any<T, PREC, 0, 4>(acc, fpart, true, a.Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
+            case 1: contract_any<T, PREC, 1, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
+            case 2: contract_any<T, PREC, 2, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
+            default: contract_any<T, PREC, 3, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
+          }
+        }
         __syncthreads();
       }
-    } else {
-      switch (wave) {
-        case 0: store_acc<T, PREC, 0, 4>(acc, sK, false, true, k_row, c_col); break;
-        case 1: store_acc<T, PREC, 1, 4>(acc, sK, false, true, k_row, c_col); break;
-        case 2: store_acc<T, PREC, 2, 4>(acc, sK, false, true, k_row, c_col); break;
-        default: store_acc<T, PREC, 3, 4>(acc, sK, false, true, k_row, c_col); break;
+      // [K | f | C] and the padding rows into LDS; K's lower part by symmetry
+      if constexpr (QSPLIT) {
+        for (int w = 0; w < 4; ++w) {
+          if (wave == w) store_acc<T, PREC, 0, 1>(acc, sK, w > 0, w == 3, k_row, c_col);
+          __syncthreads();
+        }
+      } else {
+        switch (wave) {
+          case 0: store_acc<T, PREC, 0, 4>(acc, sK, false, true, k_row, c_col); break;
+          case 1: store_acc<T, PREC, 1, 4>(acc, sK, false, true, k_row, c_col); break;
+          case 2: store_acc<T, PREC, 2, 4>(acc, sK, false, true, k_row, c_col); break;
+          default: store_acc<T, PREC, 3, 4>(acc, sK, false, true, k_row, c_col); break;
+        }
+        __syncthreads();
       }
-      __syncthreads();
-    }
-    if constexpr (PREC != PREC_F64) {
-      // f in FP64: sum over the lane groups, then over the waves in a fixed order
+      if constexpr (PREC != PREC_F64) {
+        // f and sum w|J| P in FP64: over the lane groups and the waves in a fixed order
+        double* sFp = sC;  // [4][NPAD] wave partials of f, before C is copied
 #pragma unroll
-      for (int J = 0; J < T; ++J) {
-        double v = fpart[J];
-        v += __shfl_xor(v, 16);
-        v += __shfl_xor(v, 32);
-        if (k_row == 0) sSol[wave * NPAD + 16 * J + c_col] = v;
+        for (int J = 0; J < T; ++J) {
+          double v = fpart[J];
+          v += __shfl_xor(v, 16);
+          v += __shfl_xor(v, 32);
+          if (k_row == 0) sFp[wave * NPAD + 16 * J + c_col] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          double v = accP[k];
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+          if (lane == 0) sX[4 * k + wave] = v;
+        }
+        __syncthreads();
+        if (tid < n) {
+          const double v = QSPLIT ? ((sFp[tid] + sFp[NPAD + tid]) + sFp[2 * NPAD + tid]) + sFp[3 * NPAD + tid]
+                                  : sFp[tid];
+          sK[tid * LD + n] = v;
+        }
+        if (tid < 4) sK[(n + tid) * LD + n] = ((sX[4 * tid] + sX[4 * tid + 1]) + sX[4 * tid + 2]) + sX[4 * tid + 3];
+        __syncthreads();
       }
-      __syncthreads();
+      // C of this evaluation (kept for Abar), ||f||_2
+      for (int idx = tid; idx < 4 * n; idx += 256) sC[idx] = sK[(idx >> 2) * LD + n + 1 + (idx & 3)];
+      double part = 0.0;
       if (tid < n) {
-        const double v = QSPLIT ? ((sSol[tid] + sSol[NPAD + tid]) + sSol[2 * NPAD + tid]) + sSol[3 * NPAD + tid]
-                                : sSol[tid];
-        sK[tid * NPAD + n] = v;
+        const double fv = sK[tid * LD + n];
+        part = fv * fv;
       }
+      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+      if (lane == 0) sX[wave] = part;
+      __syncthreads();
+      rn = sqrt(sX[0] + sX[1] + sX[2] + sX[3]);
+      iters = it + 1;
+      const bool last = (it == a.max_iter - 1);
+      bool stop;
+      if (!isfinite(rn)) {
+        stop = true;
+        status = ROM_ST_NONFINITE;
+      } else if (a.fixed) {
+        stop = last;
+        status = (rn <= a.tol) ? ROM_ST_CONVERGED : ROM_ST_MAXITER;
+      } else if (rn <= a.tol) {
+        stop = true;
+        status = ROM_ST_CONVERGED;
+      } else {
+        stop = last;
+        status = ROM_ST_MAXITER;
+      }
+      if (it == 0) rn0 = rn;
+      // warm start judged by plain Newton: no tenfold drop of ||f|| after two
+      // updates -> restart from the committed r
+      if (!stop && a.dr && attempt == 0 && !fell_back && it == 2 && !(rn <= 0.1 * rn0)) {
+        fell_back = true;
+        for (int i = tid; i < n; i += 256) sR[i] = a.rc[(size_t)p * n + i];
+        __syncthreads();
+        continue;
+      }
+      // K x = [f | C]: the Newton update and K^-1 C
+      gauss_jordan<T>(sK, n, sL, sPv, sOrd, sPiv);
+      if (stop) {
+        // effective quantities at the returned state: Pbar = sum w|J| P,
+        // Abar = sum w|J| A - C^T K*^-1 C (per unit cell area)
+        if (tid < 20) {
+          const double inv_area = a.inv_area;
+          if (tid < 4) {
+            a.Pbar[4 * (size_t)p + tid] = sK[(n + tid) * LD + n] * inv_area;
+          } else {
+            const int e = tid - 4, x = e >> 2, y = e & 3;
+            double acc2 = sK[(n + x) * LD + n + 1 + y];
+            for (int i = 0; i < n; ++i) acc2 = fma(-sC[4 * i + x], sK[sOrd[i] * LD + n + 1 + y], acc2);
+            a.Abar[16 * (size_t)p + e] = acc2 * inv_area;
+          }
+        }
+        __syncthreads();
+        break;
+      }
+      if (tid < n) sR[tid] -= sK[sOrd[tid] * LD + n];
       __syncthreads();
     }
-    double part = 0.0;
-    if (tid < n) {
-      const double fv = sK[tid * NPAD + n];
-      part = fv * fv;
-    }
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-    if (lane == 0) sX[wave] = part;
-    __syncthreads();
-    rn = sqrt(sX[0] + sX[1] + sX[2] + sX[3]);
-    iters = it + 1;
-    const bool last = (it == a.max_iter - 1);
-    bool stop;
-    if (!isfinite(rn)) {
-      stop = true;
-      status = ROM_ST_NONFINITE;
-    } else if (a.fixed) {
-      stop = last;
-      status = (rn <= a.tol) ? ROM_ST_CONVERGED : ROM_ST_MAXITER;
-    } else if (rn <= a.tol) {
-      stop = true;
-      status = ROM_ST_CONVERGED;
+    total += iters;
+    if (status == ROM_ST_CONVERGED) {
+      t_done += stride;
+      if (t_done == full) break;
+      // a converged sub-step becomes the committed start of the next attempt
+      double* hcw = a.hc + (size_t)p * 6 * m;
+      for (int q = tid; q < m; q += 256)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) hcw[k * m + q] = ht[k * m + q];
+      for (int i = tid; i < n; i += 256) a.rc[(size_t)p * n + i] = sR[i];
+      if (tid < 4) a.fbc[4 * (size_t)p + tid] = Fb[tid];
+      stride = min(2 * stride, full - t_done);
     } else {
-      stop = last;
-      status = ROM_ST_MAXITER;
-    }
-    if (it == 0) rn0 = rn;
-    if (stop) break;
-    // warm start judged by plain Newton: no tenfold drop of ||f|| after two
-    // updates -> restart from the committed r
-    if (a.dr && attempt == 0 && !fell_back && it == 2 && !(rn <= 0.1 * rn0)) {
-      fell_back = true;
+      if (stride == 1) break;  // the smallest sub-step failed too
+      stride >>= 1;
       for (int i = tid; i < n; i += 256) sR[i] = a.rc[(size_t)p * n + i];
-      __syncthreads();
-      continue;
     }
-    // Newton update: K dr = -f
-    gauss_solve(sK, NPAD, n, n, 1, sStep, sOrder, sSol);
-    if (tid < n) sR[tid] -= sSol[4 * tid];
+    const int t_next = t_done + stride;
+    const double frac = ldexp((double)t_next, -a.max_sub);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Fb[k] = (t_next == full) ? sF1[k] : sF0[k] + frac * (sF1[k] - sF0[k]);
     __syncthreads();
-  }
-  total += iters;
-  if (status == ROM_ST_CONVERGED) {
-    t_done += stride;
-    if (t_done == full) break;
-    // a converged sub-step becomes the committed start of the next attempt
-    // (each thread copies the ECM points it wrote)
-    double* hcw = a.hc + (size_t)p * 6 * m;
-    for (int q = tid; q < m; q += 256)
-#pragma unroll
-      for (int k = 0; k < 6; ++k) hcw[k * m + q] = ht[k * m + q];
-    for (int i = tid; i < n; i += 256) a.rc[(size_t)p * n + i] = sR[i];
-    if (tid < 4) a.fbc[4 * (size_t)p + tid] = Fb[tid];
-    stride = min(2 * stride, full - t_done);
-  } else {
-    if (stride == 1) break;  // the smallest sub-step failed too
-    stride >>= 1;
-    for (int i = tid; i < n; i += 256) sR[i] = a.rc[(size_t)p * n + i];
-  }
-  const int t_next = t_done + stride;
-  const double frac = ldexp((double)t_next, -a.max_sub);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) Fb[k] = (t_next == full) ? sF1[k] : sF0[k] + frac * (sF1[k] - sF0[k]);
-  __syncthreads();
   }
   iters = total;
 
-  // Effective quantities at the returned state (Sec. 3.3): one more pass over
-  // the ECM points for Pbar = sum wJ P, sum wJ A and C = sum_q G_q^T E_q; the
-  // LU of K* (= K of the last evaluation) then gives K*^-1 C.
-  double accP[4] = {0.0, 0.0, 0.0, 0.0}, accA[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) accA[k] = 0.0;
-  double cacc[2] = {0.0, 0.0};
-  for (int q0 = 0; q0 < m; q0 += ECH) {
-    const int q = q0 + tid;
-    if (tid < ECH && q < m) {
-      const double Fi[4] = {tmu[q], tmu[m + q], tmu[2 * m + q], tmu[3 * m + q]};
-      const double wJ = tmu[4 * m + q];
-      double F[4];
-      kinematics(n, m, q, a.Gt, sR, Fb, Fi, F);
-      const double Fp[4] = {hc[q], hc[m + q], hc[2 * m + q], hc[3 * m + q]};
-      double P[4], Fpn[4], Fp33n, xin;
-      double* e = sE + tid * 16;
-      // sum w|J| A and the E = w|J| T^T A records, column by column of A
-      j2_point_cols<true>(F, Fp, hc[4 * m + q], hc[5 * m + q], a.mp, P, Fpn, Fp33n, xin,
-                          [&](int v, double c0, double c1, double c2, double c3) {
-                            accA[v] = fma(wJ, c0, accA[v]);
-                            accA[4 + v] = fma(wJ, c1, accA[4 + v]);
-                            accA[8 + v] = fma(wJ, c2, accA[8 + v]);
-                            accA[12 + v] = fma(wJ, c3, accA[12 + v]);
-                            e[0 + v] = wJ * (Fi[0] * c0 + Fi[1] * c1);
-                            e[4 + v] = wJ * (Fi[2] * c0 + Fi[3] * c1);
-                            e[8 + v] = wJ * (Fi[0] * c2 + Fi[1] * c3);
-                            e[12 + v] = wJ * (Fi[2] * c2 + Fi[3] * c3);
-                          });
-#pragma unroll
-      for (int k = 0; k < 4; ++k) accP[k] = fma(wJ, P[k], accP[k]);
-    }
-    __syncthreads();
-    const int nq = min(ECH, m - q0);
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int o = tid + 256 * u;  // output (i, y) = (o / 4, o % 4)
-      if (o < 4 * n) {
-        const int i = o >> 2, y = o & 3;
-        double s = cacc[u];
-        for (int qq = 0; qq < nq; ++qq) {
-          const double* g = a.Gq + (size_t)(q0 + qq) * 4 * NPAD + i;
-          const double* e = sE + qq * 16 + y;
-          s = fma(g[0], e[0], s);
-          s = fma(g[NPAD], e[4], s);
-          s = fma(g[2 * NPAD], e[8], s);
-          s = fma(g[3 * NPAD], e[12], s);
-        }
-        cacc[u] = s;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int o = tid + 256 * u;
-    if (o < 4 * n) sC[o] = cacc[u];
-  }
-#pragma unroll
-  for (int k = 0; k < 20; ++k) {
-    double v = (k < 4) ? accP[k] : accA[k - 4];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0) sX[4 * k + wave] = v;
-  }
-  __syncthreads();
-  // Y = K*^-1 C with K* = K of the last evaluation (still in sK, not eliminated)
-  for (int idx = tid; idx < 4 * n; idx += 256) sK[(idx >> 2) * NPAD + n + 1 + (idx & 3)] = sC[idx];
-  __syncthreads();
-  gauss_solve(sK, NPAD, n, n + 1, 4, sStep, sOrder, sSol);
-  if (tid < 20) {
-    const double v = ((sX[4 * tid] + sX[4 * tid + 1]) + sX[4 * tid + 2]) + sX[4 * tid + 3];
-    if (tid < 4) {
-      a.Pbar[4 * (size_t)p + tid] = v * a.inv_area;
-    } else {
-      const int e = tid - 4, x = e >> 2, y = e & 3;
-      double acc2 = v;
-      for (int i = 0; i < n; ++i) acc2 = fma(-sC[4 * i + x], sSol[4 * i + y], acc2);
-      a.Abar[16 * (size_t)p + e] = acc2 * a.inv_area;
-    }
-  }
   for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i];
   if (tid == 0) {
     a.st_out[p] = (status == ROM_ST_CONVERGED && fell_back) ? ROM_ST_FALLBACK : status;
@@ -710,6 +841,7 @@ int setup_one() {
 
 template <int T>
 int fused_setup() {
+  static_assert(lds_doubles<T>() * 8 <= 160 * 1024, "LDS of the fused kernel exceeds the workgroup limit");
   int rc = ROM_OK;
   if constexpr (T <= 5) {
     if (rc == ROM_OK) rc = setup_one<T, PREC_F64, 0>();
