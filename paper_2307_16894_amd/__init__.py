@@ -60,13 +60,31 @@ class rom_opts(ctypes.Structure):
 _lib = None
 
 
+def _hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open('/proc/self/maps') as fh:
+            return sorted({ln.split()[-1] for ln in fh if 'libamdhip64' in ln})
+    except OSError:
+        return []
+
+
 def lib():
-    """Load libpodecm.so; raises if it has not been built."""
+    """Load libpodecm.so; raises if it has not been built.
+
+    The library takes device pointers and hipStream_t handles from PyTorch, so
+    it must bind to the HIP runtime PyTorch uses: torch is imported first (its
+    runtime then satisfies the library's dependency), and a process holding
+    two HIP runtimes is rejected."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2307_16894_amd.build")
+        import torch  # noqa: F401  (loads the HIP runtime the library must share)
         L = ctypes.CDLL(LIB_PATH)
+        rts = _hip_runtimes()
+        if len(rts) > 1:
+            raise RuntimeError(f"two HIP runtimes are loaded ({rts}); import torch before loading libpodecm")
         vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
         L.rom_default_opts.argtypes = [ctypes.POINTER(rom_opts)]
         L.rom_load.argtypes = [vp, sz, ctypes.c_int, ctypes.POINTER(vp)]

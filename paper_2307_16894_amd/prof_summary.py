@@ -1,0 +1,116 @@
+"""Summaries of rocprofv3 CSV output for the profiles directory.
+
+    python -m paper_2307_16894_amd.prof_summary stats KERNEL_STATS_CSV OUT.md --command "..."
+    python -m paper_2307_16894_amd.prof_summary traffic FETCH_CSV WRITE_CSV OUT_PREFIX \\
+        --workload W --copy-mib N --command-fetch "..." --command-write "..."
+
+`stats` keeps the kernel table of a --kernel-trace --stats run.  `traffic`
+takes the FETCH_SIZE and WRITE_SIZE counter runs (KiB per dispatch), scales
+each by the reading of the same counter for the calibration copy of known
+size (bench.py --calibrate-copy), and writes the HBM bytes per launch of the
+fused FP64 kernel together with the digest of its sources.
+"""
+import argparse
+import csv
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rows(path):
+    with open(path, newline='') as fh:
+        return list(csv.DictReader(fh))
+
+
+def stats(args):
+    rows = _rows(args.csv)
+    rows.sort(key=lambda r: -float(r['TotalDurationNs']))
+    total = sum(float(r['TotalDurationNs']) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics: {args.title}", "", "Command:", "", "```", args.command, "```", "",
+             "| kernel | calls | total ms | average us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:args.top]:
+        name = r['Name']
+        if len(name) > 90:
+            name = name[:87] + '...'
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / total:.1f}% |")
+    with open(args.out, 'w') as fh:
+        fh.write('\n'.join(lines) + '\n')
+
+
+def _per_dispatch(path, counter):
+    out = {}
+    for r in _rows(path):
+        if r.get('Counter_Name') != counter:
+            continue
+        key = r['Dispatch_Id']
+        out.setdefault(key, [r['Kernel_Name'], 0.0])
+        out[key][1] += float(r['Counter_Value'])
+    return list(out.values())
+
+
+def _split(disp, kernel_sub, copy_sub):
+    ker = [v for name, v in disp if kernel_sub in name]
+    cpy = [v for name, v in disp if copy_sub in name]
+    if not ker or not cpy:
+        raise SystemExit(f"kernel or calibration copy not found ({len(ker)} / {len(cpy)} dispatches)")
+    return ker, max(cpy)
+
+
+def traffic(args):
+    sys.path.insert(0, ROOT)
+    from bench import kernel_source_digest
+    copy_bytes = args.copy_mib * (1 << 20)
+    res = {}
+    for counter, path in (('FETCH_SIZE', args.fetch_csv), ('WRITE_SIZE', args.write_csv)):
+        ker, cpy_kib = _split(_per_dispatch(path, counter), args.kernel, args.copy)
+        factor = copy_bytes / (cpy_kib * 1024.0)
+        res[counter] = dict(dispatches=len(ker), mean_kib=sum(ker) / len(ker), copy_kib=cpy_kib, factor=factor,
+                            bytes_per_launch=factor * 1024.0 * sum(ker) / len(ker))
+    hbm = res['FETCH_SIZE']['bytes_per_launch'] + res['WRITE_SIZE']['bytes_per_launch']
+    out = dict(kernel=args.kernel, workload=args.workload, kernel_source_sha256=kernel_source_digest(),
+               copy_mib=args.copy_mib, counters=res, hbm_bytes_per_launch=hbm,
+               commands=dict(fetch=args.command_fetch, write=args.command_write))
+    with open(args.out_prefix + '.json', 'w') as fh:
+        json.dump(out, fh, indent=1)
+    lines = [f"# HBM traffic of `{args.kernel}` ({args.workload})", "",
+             f"Counters per dispatch in KiB, scaled by a {args.copy_mib} MiB calibration copy.", ""]
+    for c in ('FETCH_SIZE', 'WRITE_SIZE'):
+        r = res[c]
+        lines.append(f"- {c}: {r['dispatches']} dispatches, mean {r['mean_kib']:.1f} KiB; copy read "
+                     f"{r['copy_kib']:.1f} KiB for {args.copy_mib * 1024} KiB -> factor {r['factor']:.4f}; "
+                     f"{r['bytes_per_launch'] / 1e6:.3f} MB per launch")
+    lines += [f"- HBM bytes per launch: {hbm / 1e6:.3f} MB", "", "Commands:", "", "```", args.command_fetch,
+              args.command_write, "```"]
+    with open(args.out_prefix + '.md', 'w') as fh:
+        fh.write('\n'.join(lines) + '\n')
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest='what', required=True)
+    s = sub.add_parser('stats')
+    s.add_argument('csv')
+    s.add_argument('out')
+    s.add_argument('--command', required=True)
+    s.add_argument('--title', default='')
+    s.add_argument('--top', type=int, default=15)
+    t = sub.add_parser('traffic')
+    t.add_argument('fetch_csv')
+    t.add_argument('write_csv')
+    t.add_argument('out_prefix')
+    t.add_argument('--workload', required=True)
+    t.add_argument('--copy-mib', type=int, required=True)
+    t.add_argument('--kernel', default='k_fused<3, 0, 0>')
+    t.add_argument('--copy', default='copyBuffer')
+    t.add_argument('--command-fetch', required=True)
+    t.add_argument('--command-write', required=True)
+    a = ap.parse_args(argv)
+    stats(a) if a.what == 'stats' else traffic(a)
+
+
+if __name__ == '__main__':
+    main()
