@@ -5,13 +5,17 @@
 // Per Newton evaluation the workgroup walks the ECM points in chunks of 256
 // (one lane per point): kinematics, return map and tangent (Appendix A), and
 // an LDS record per point with
-//   E = w|J| T^T A      (T: right multiplication by F_mu^-1; D = E T),
-//   W = w|J| P F_mu^-T, F_mu^-1 and F_mu.
+//   D = w|J| T^T A T    (T: right multiplication by F_mu^-1),
+//   W = w|J| P F_mu^-T and F_mu.
 // The contraction then runs on MFMA with the four gradient components of an
 // ECM point as the inner dimension, as sum_q A_q^T B_q with
 //   A_q = [G_q | R_q]            (R_q: four rows carrying F_mu, see below),
-//   B_q = [D_q G_q | W_q | E_q]  (columns n, n + 1 .. n + 4),
-// padded to 16 T rows and columns (16 T >= n + 5).  One contraction therefore
+//   B_q = [D_q G_q | W_q | E_q]  (columns n, n + 1 .. n + 4; E = D T^-1 =
+//                                 w|J| T^T A, the mapped tangent),
+// padded to 16 T rows and columns (16 T >= n + 5).  B_q itself comes out of
+// an MFMA per column tile, D_q [G_q | V_q] with V_q = T^-1 in the columns
+// n + 1 .. n + 4 (and W_q put in column n), so that each lane loads only its
+// own gradient component of G_q.  One contraction therefore
 // gives, at the state of the evaluation,
 //   K = sum_q G_q^T D_q G_q                (eq. stiffnessmatrix_ecm),
 //   f = sum_q G_q^T W_q                    (eq. forcevector_ecm, column n),
@@ -44,8 +48,8 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 namespace {
 
 constexpr int FCH = 256;  // ECM points per chunk
-constexpr int QS = 28;    // LDS record per point
-constexpr int R_E = 0, R_W = 16, R_FI = 20, R_FM = 24;
+constexpr int QS = 24;    // LDS record per point
+constexpr int R_D = 0, R_W = 16, R_FM = 20;
 
 template <int T>
 constexpr int ldk() {
@@ -64,17 +68,38 @@ constexpr int lds_doubles() {
 
 // F = Fbar + (sum_i r_i G_i(q)) F_mu^-1 at ECM point q (argument of P in
 // eq. forcevector_ecm); r is read from LDS.
+// The loads of eight modes are issued before their use, so that they are in
+// flight together (issued one at a time the loop is a chain of memory
+// round trips).
 __device__ __forceinline__ void kinematics(int n, int m, int q, const double* __restrict__ Gt, const double* sR,
                                            const double Fb[4], const double Fi[4], double F[4]) {
   double H0 = 0.0, H1 = 0.0, H2 = 0.0, H3 = 0.0;
   const double* g = Gt + q;
-  for (int i = 0; i < n; ++i) {
+  const size_t st = 4 * (size_t)m;
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    double v[8][4];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) v[u][b] = g[u * st + b * m];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double ri = sR[i + u];
+      H0 = fma(ri, v[u][0], H0);
+      H1 = fma(ri, v[u][1], H1);
+      H2 = fma(ri, v[u][2], H2);
+      H3 = fma(ri, v[u][3], H3);
+    }
+    g += 8 * st;
+  }
+  for (; i < n; ++i) {
     const double ri = sR[i];
     H0 = fma(ri, g[0], H0);
     H1 = fma(ri, g[m], H1);
     H2 = fma(ri, g[2 * m], H2);
     H3 = fma(ri, g[3 * m], H3);
-    g += 4 * (size_t)m;
+    g += st;
   }
   F[0] = Fb[0] + H0 * Fi[0] + H1 * Fi[2];
   F[1] = Fb[1] + H0 * Fi[1] + H1 * Fi[3];
@@ -89,12 +114,6 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ __bf16 to_bf16(float x) {
-  uint32_t u = __builtin_bit_cast(uint32_t, x);
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (operands are finite)
-  return __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
-}
-
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
 template <int PREC>
 struct Acc {
@@ -105,20 +124,56 @@ struct Acc<PREC_F64> {
   typedef d4 type;
 };
 
+// Tile split (large n): the column tiles J (J + 1 tiles I <= J each) are dealt
+// to the four waves largest first, each to the least loaded wave, so that a
+// wave forms B for its own columns only; owns<T, W, TW>(J) is true for the
+// columns of wave W (all columns when TW = 1).
+template <int T>
+constexpr int col_owner(int J) {
+  int load[4] = {0, 0, 0, 0}, owner = 0;
+  for (int c = T - 1; c >= 0; --c) {
+    int w = 0;
+    for (int k = 1; k < 4; ++k)
+      if (load[k] < load[w]) w = k;
+    load[w] += c + 1;
+    if (c == J) owner = w;
+  }
+  return owner;
+}
+template <int T>
+constexpr int split_tiles() {
+  int load[4] = {0, 0, 0, 0};
+  for (int c = T - 1; c >= 0; --c) {
+    int w = 0;
+    for (int k = 1; k < 4; ++k)
+      if (load[k] < load[w]) w = k;
+    load[w] += c + 1;
+  }
+  int mx = 0;
+  for (int k = 0; k < 4; ++k) mx = load[k] > mx ? load[k] : mx;
+  return mx;
+}
+template <int T, int W, int TW>
+constexpr bool owns(int J) {
+  return TW == 1 || col_owner<T>(J) == W;
+}
+
 // Per-lane constants of the padding rows and columns (n is the same for all
 // points of a launch):
 //   A side, tile row In = n / 16: lane row 16 In + c_col in [n, n + 4) takes
 //     F_mu[J'][j] from the record when its component i matches (row n + 2i' + J');
-//   B side, tiles In and In + 1: lane column n takes W[k_row], columns
-//     n + 1 .. n + 4 take E[k_row][col - n - 1].
+//   B side, tiles In and In + 1: lane column n takes W[k_row]; lane columns
+//     n + 1 + (k, l) feed the H MFMA with V[(k', s)][(k, l)] = delta(k', k)
+//     F_mu[l][s] (the entries of T^-1, right multiplication by F_mu) in place
+//     of G, so that H = D V = E there.
 struct Pad {
   int In;       // tile row / column of index n
   bool a_use;   // this lane's A value in tile In comes from the record
   int a_off;    // its record offset
-  bool b_use0;  // this lane's B value in tile In comes from the record
-  int b_off0;
-  bool b_use1;  // ... in tile In + 1
-  int b_off1;
+  int w_use;    // bit t: this lane's B value in tile In + t is W[k_row]
+  int v_use;    // bit t: this lane's H-MFMA B value in tile In + t is V
+  int v_zero;   // bit t: ... and that V entry is zero
+  int v_off0, v_off1;  // record offsets of the V entries
 };
 
 __device__ __forceinline__ Pad make_pad(int n, int k_row, int c_col) {
@@ -126,34 +181,36 @@ __device__ __forceinline__ Pad make_pad(int n, int k_row, int c_col) {
   d.In = n >> 4;
   const int row = 16 * d.In + c_col, ar = row - n;
   d.a_use = (ar >= 0 && ar < 4 && (ar >> 1) == (k_row >> 1));
-  d.a_off = R_FM + 2 * (ar & 1) + (k_row & 1);
-  const int c0 = 16 * d.In + c_col - n, c1 = c0 + 16;
-  d.b_use0 = (c0 >= 0 && c0 <= 4);
-  d.b_off0 = (c0 == 0) ? R_W + k_row : R_E + 4 * k_row + (c0 - 1);
-  d.b_use1 = (c1 >= 0 && c1 <= 4);
-  d.b_off1 = (c1 == 0) ? R_W + k_row : R_E + 4 * k_row + (c1 - 1);
-  if (!d.a_use) d.a_off = R_FM;
-  if (!d.b_use0) d.b_off0 = R_W;
-  if (!d.b_use1) d.b_off1 = R_W;
+  d.a_off = d.a_use ? R_FM + 2 * (ar & 1) + (k_row & 1) : R_FM;
+  d.w_use = d.v_use = d.v_zero = 0;
+  int off[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int dc = 16 * (d.In + t) + c_col - n;
+    off[t] = R_FM;
+    if (dc == 0) d.w_use |= 1 << t;
+    if (dc >= 1 && dc <= 4) {
+      const int y = dc - 1;  // (k, l) = (y >> 1, y & 1); k_row = (k', s)
+      d.v_use |= 1 << t;
+      if ((k_row >> 1) != (y >> 1)) d.v_zero |= 1 << t;
+      off[t] = R_FM + 2 * (y & 1) + (k_row & 1);
+    }
+  }
+  d.v_off0 = off[0];
+  d.v_off1 = off[1];
   return d;
 }
 
-// Loads of one ECM point for the FP64 / FP32 contraction: all four
-// components of the lane's column of every tile (B side) and the lane's own
-// component of every tile row (A side).
+// Loads of one ECM point for the FP64 / FP32 contraction: the lane's own
+// gradient component of every tile (A side of K, B side of H).
 template <int T>
 struct GLoad {
-  double g[4][T];
   double a[T];
 };
 
 template <int T>
 __device__ __forceinline__ void load_g(GLoad<T>& L, const double* __restrict__ Gp, int k_row, int c_col) {
   constexpr int NPAD = 16 * T;
-#pragma unroll
-  for (int J = 0; J < T; ++J)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) L.g[b][J] = Gp[b * NPAD + 16 * J + c_col];
 #pragma unroll
   for (int I = 0; I < T; ++I) L.a[I] = Gp[k_row * NPAD + 16 * I + c_col];
 }
@@ -166,36 +223,52 @@ struct Ops {
 
 // Operands of the point with record rq and loads L (and, in the
 // reduced-precision forms, its FP64 residual partial G_q[k_row][col] W_q[k_row]).
-template <int T, int PREC>
+// H = D [G | V] comes from an MFMA per column tile: A = D, B = the lane's G
+// component, and row k_row of the result is in the first output register of
+// lane (k_row, c_col).  The output rows of the FP64 instruction are
+// k_row + 4 j, those of the FP32 one 4 k_row + j, so D goes into A rows 0..3
+// (lane c_col < 4 holds D[c_col][k_row]) or rows 0, 4, 8, 12.
+template <int T, int PREC, int W, int TW>
 __device__ __forceinline__ void make_ops(Ops<T>& O, double (&fpart)[T], bool do_f, const GLoad<T>& L,
                                          const double* rq, const Pad& pd, int k_row, int n, int c_col) {
-  // row k_row of D = E T:  D[b][(k, s)] = E[b][2k] Fi[s][0] + E[b][2k + 1] Fi[s][1]
-  const double e0 = rq[R_E + 4 * k_row], e1 = rq[R_E + 4 * k_row + 1];
-  const double e2 = rq[R_E + 4 * k_row + 2], e3 = rq[R_E + 4 * k_row + 3];
-  const double f0 = rq[R_FI], f1 = rq[R_FI + 1], f2 = rq[R_FI + 2], f3 = rq[R_FI + 3];
-  const double d0 = fma(e0, f0, e1 * f1), d1 = fma(e0, f2, e1 * f3);
-  const double d2 = fma(e2, f0, e3 * f1), d3 = fma(e2, f2, e3 * f3);
-  const double xa = rq[pd.a_off], xb0 = rq[pd.b_off0], xb1 = rq[pd.b_off1];
+  constexpr bool F64 = (PREC == PREC_F64);
+  const int drow = F64 ? (c_col & 3) : (c_col >> 2);
+  const double dv = rq[R_D + 4 * drow + k_row];
+  const double dop = (F64 ? c_col < 4 : (c_col & 3) == 0) ? dv : 0.0;
+  const double xa = rq[pd.a_off], xw = rq[R_W + k_row], xv0 = rq[pd.v_off0], xv1 = rq[pd.v_off1];
 #pragma unroll
   for (int J = 0; J < T; ++J) {
-    double h = d0 * L.g[0][J];
-    h = fma(d1, L.g[1][J], h);
-    h = fma(d2, L.g[2][J], h);
-    h = fma(d3, L.g[3][J], h);
-    if (J == pd.In) h = pd.b_use0 ? xb0 : h;
-    if (J == pd.In + 1) h = pd.b_use1 ? xb1 : h;
-    O.B[J] = h;
+    double g = L.a[J];
+    bool wsel = false;
+    if (J == pd.In) {
+      g = (pd.v_use & 1) ? ((pd.v_zero & 1) ? 0.0 : xv0) : g;
+      wsel = pd.w_use & 1;
+    }
+    if (J == pd.In + 1) {
+      g = (pd.v_use & 2) ? ((pd.v_zero & 2) ? 0.0 : xv1) : g;
+      wsel = pd.w_use & 2;
+    }
+    double h = 0.0;
+    if (!owns<T, W, TW>(J)) {
+      // not this wave's column: B unused
+    } else if constexpr (PREC == PREC_F64) {
+      const d4 hz = __builtin_amdgcn_mfma_f64_16x16x4f64(dop, g, (d4){0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
+      h = hz[0];
+    } else {
+      const f4 hz = __builtin_amdgcn_mfma_f32_16x16x4f32((float)dop, (float)g, (f4){0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+      h = (double)hz[0];
+    }
+    O.B[J] = wsel ? xw : h;
     double av = L.a[J];
     if (J == pd.In) av = pd.a_use ? xa : av;
     O.A[J] = av;
   }
   if constexpr (PREC != PREC_F64) {
     if (do_f) {
-      const double wk = rq[R_W + k_row];
 #pragma unroll
       for (int J = 0; J < T; ++J) {
         const int col = 16 * J + c_col;
-        fpart[J] = fma(col < n ? L.a[J] : 0.0, wk, fpart[J]);
+        fpart[J] = fma(col < n ? L.a[J] : 0.0, xw, fpart[J]);
       }
     }
   }
@@ -205,19 +278,18 @@ __device__ __forceinline__ void make_ops(Ops<T>& O, double (&fpart)[T], bool do_
 // else the tiles v = W, W + 4, ... in the order J = 0.., I = 0..J).
 template <int T, int PREC, int W, int TW>
 __device__ __forceinline__ void mfma_ops(typename Acc<PREC>::type* acc, const Ops<T>& O) {
-  int u = 0, v = 0;
+  int u = 0;
 #pragma unroll
   for (int J = 0; J < T; ++J) {
 #pragma unroll
     for (int I = 0; I <= J; ++I) {
-      if ((v % TW) == W) {
+      if (owns<T, W, TW>(J)) {
         if constexpr (PREC == PREC_F64)
           acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(O.A[I], O.B[J], acc[u], 0, 0, 0);
         else
           acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)O.A[I], (float)O.B[J], acc[u], 0, 0, 0);
         ++u;
       }
-      ++v;
     }
   }
 }
@@ -238,105 +310,118 @@ __device__ __forceinline__ void contract_range(typename Acc<PREC>::type* acc, do
   load_g<T>(L0, Gb + (size_t)qa * 4 * NPAD, k_row, c_col);
   load_g<T>(L1, Gb + (size_t)min(qa + 1, ql_max) * 4 * NPAD, k_row, c_col);
   Ops<T> O;
-  make_ops<T, PREC>(O, fpart, do_f, L0, sQ + qa * QS, pd, k_row, n, c_col);
+  make_ops<T, PREC, W, TW>(O, fpart, do_f, L0, sQ + qa * QS, pd, k_row, n, c_col);
   for (int ql = qa; ql < qb; ql += 3) {
     load_g<T>(L2, Gb + (size_t)min(ql + 2, ql_max) * 4 * NPAD, k_row, c_col);
     mfma_ops<T, PREC, W, TW>(acc, O);
     if (ql + 1 >= qb) break;
-    make_ops<T, PREC>(O, fpart, do_f, L1, sQ + (ql + 1) * QS, pd, k_row, n, c_col);
+    make_ops<T, PREC, W, TW>(O, fpart, do_f, L1, sQ + (ql + 1) * QS, pd, k_row, n, c_col);
     load_g<T>(L0, Gb + (size_t)min(ql + 3, ql_max) * 4 * NPAD, k_row, c_col);
     mfma_ops<T, PREC, W, TW>(acc, O);
     if (ql + 2 >= qb) break;
-    make_ops<T, PREC>(O, fpart, do_f, L2, sQ + (ql + 2) * QS, pd, k_row, n, c_col);
+    make_ops<T, PREC, W, TW>(O, fpart, do_f, L2, sQ + (ql + 2) * QS, pd, k_row, n, c_col);
     load_g<T>(L1, Gb + (size_t)min(ql + 4, ql_max) * 4 * NPAD, k_row, c_col);
     mfma_ops<T, PREC, W, TW>(acc, O);
     if (ql + 3 >= qb) break;
-    make_ops<T, PREC>(O, fpart, do_f, L0, sQ + (ql + 3) * QS, pd, k_row, n, c_col);
+    make_ops<T, PREC, W, TW>(O, fpart, do_f, L0, sQ + (ql + 3) * QS, pd, k_row, n, c_col);
   }
 }
 
 // BF16: eight ECM points per instruction; lane group g = k_row holds points
 // 2g, 2g + 1 of the step, inner index k = 8 g + 4 h + b (point 2g + h,
-// component b).  D and the operands are formed in FP32 from the FP64 record.
+// component b).  B = D [G | V] is formed in FP32 on the lanes (D is kept as
+// FP32 in the record of this form) and f in FP64 from the FP64 G loads; the
+// loads of one column tile run while the previous tile is formed.
+struct G8 {
+  double g[2][4];  // [point h][component b] of one column tile
+};
+
+template <int T>
+__device__ __forceinline__ void load_g8(G8& L, const double* __restrict__ Gb, int qs, int J, int qa, int qb,
+                                        int k_row, int c_col) {
+  constexpr int NPAD = 16 * T;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ql = qs + 2 * k_row + h;
+    const double* Gp = Gb + (size_t)(ql < qb ? ql : qa) * 4 * NPAD + 16 * J + c_col;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) L.g[h][b] = Gp[b * NPAD];
+  }
+}
+
 template <int T, int W, int TW>
 __device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T], bool do_f,
                                                     const double* __restrict__ Gq, const double* sQ, int q0, int qa,
                                                     int qb, const Pad& pd, int n, int k_row, int c_col) {
   constexpr int NPAD = 16 * T;
+  if (qa >= qb) return;
+  const double* Gb = Gq + (size_t)q0 * 4 * NPAD;
   const int arow = 16 * pd.In + c_col - n;  // padding-row offset of this lane in tile In
+  G8 cur, nxt;
+  load_g8<T>(cur, Gb, qa, 0, qa, qb, k_row, c_col);
   for (int qs = qa; qs < qb; qs += 8) {
-    float D[2][16];
+    float D[2][16], Fm[2][4];
     double Wv[2][4];
-    float Ev[2][16], Fm[2][4];
-    bool live[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int ql = qs + 2 * k_row + h;
-      live[h] = ql < qb;
-      const double* rq = sQ + (live[h] ? ql : qa) * QS;
-      float Fi[4];
+      const bool live = ql < qb;
+      const double* rq = sQ + (live ? ql : qa) * QS;
+      const float* rf = reinterpret_cast<const float*>(rq + R_D);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) D[h][k] = live ? rf[k] : 0.0f;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        Fi[k] = (float)rq[R_FI + k];
-        Fm[h][k] = live[h] ? (float)rq[R_FM + k] : 0.0f;
-        Wv[h][k] = live[h] ? rq[R_W + k] : 0.0;
+        Fm[h][k] = live ? (float)rq[R_FM + k] : 0.0f;
+        Wv[h][k] = live ? rq[R_W + k] : 0.0;
       }
-#pragma unroll
-      for (int k = 0; k < 16; ++k) Ev[h][k] = live[h] ? (float)rq[R_E + k] : 0.0f;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-          for (int s = 0; s < 2; ++s)
-            D[h][4 * b + 2 * k + s] = Ev[h][4 * b + 2 * k] * Fi[2 * s] + Ev[h][4 * b + 2 * k + 1] * Fi[2 * s + 1];
     }
-    bf8 Aop[T], Bop[T];
+    bf8 Aop[T];
+    int u = 0;
 #pragma unroll
     for (int J = 0; J < T; ++J) {
-      const int col = 16 * J + c_col;
-      double g[2][4];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int ql = qs + 2 * k_row + h;
-        const double* Gp = Gq + (size_t)(q0 + (live[h] ? ql : qa)) * 4 * NPAD + col;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) g[h][b] = live[h] ? Gp[b * NPAD] : 0.0;
-      }
+      if (J + 1 < T)
+        load_g8<T>(nxt, Gb, qs, J + 1, qa, qb, k_row, c_col);
+      else
+        load_g8<T>(nxt, Gb, min(qs + 8, qb - 1), 0, qa, qb, k_row, c_col);
+      const int col = 16 * J + c_col, dc = col - n;
       if (do_f) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) fpart[J] = fma(col < n ? g[h][b] : 0.0, Wv[h][b], fpart[J]);
+          for (int b = 0; b < 4; ++b) fpart[J] = fma(col < n ? cur.g[h][b] : 0.0, Wv[h][b], fpart[J]);
       }
-      const int dc = col - n;
+      bf8 Bop;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const float g0 = (float)g[h][0], g1 = (float)g[h][1], g2 = (float)g[h][2], g3 = (float)g[h][3];
+        const float g0 = (float)cur.g[h][0], g1 = (float)cur.g[h][1];
+        const float g2 = (float)cur.g[h][2], g3 = (float)cur.g[h][3];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          float av = (float)g[h][b];
+          float av = (b == 0) ? g0 : (b == 1) ? g1 : (b == 2) ? g2 : g3;
           if (J == pd.In && arow >= 0 && arow < 4)
             av = ((arow >> 1) == (b >> 1)) ? Fm[h][2 * (arow & 1) + (b & 1)] : 0.0f;
-          Aop[J][4 * h + b] = to_bf16(av);
           float hv = D[h][4 * b] * g0 + D[h][4 * b + 1] * g1 + D[h][4 * b + 2] * g2 + D[h][4 * b + 3] * g3;
-          if (dc == 0) hv = (float)Wv[h][b];
-          if (dc >= 1 && dc <= 4) hv = Ev[h][4 * b + dc - 1];
-          Bop[J][4 * h + b] = to_bf16(hv);
+          if (J == pd.In || J == pd.In + 1) {
+            if (dc == 0) hv = (float)Wv[h][b];
+            if (dc >= 1 && dc <= 4) {
+              // E[b][(k, l)] = sum_s D[b][(k, s)] F_mu[l][s]
+              const int y = dc - 1, k = y >> 1, l = y & 1;
+              hv = D[h][4 * b + 2 * k] * Fm[h][2 * l] + D[h][4 * b + 2 * k + 1] * Fm[h][2 * l + 1];
+            }
+          }
+          Aop[J][4 * h + b] = (__bf16)av;
+          Bop[4 * h + b] = (__bf16)hv;
         }
       }
-    }
-    int u = 0, v = 0;
+      if (owns<T, W, TW>(J)) {
 #pragma unroll
-    for (int J = 0; J < T; ++J) {
-#pragma unroll
-      for (int I = 0; I <= J; ++I) {
-        if ((v % TW) == W) {
-          acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[I], Bop[J], acc[u], 0, 0, 0);
+        for (int I = 0; I <= J; ++I) {
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[I], Bop, acc[u], 0, 0, 0);
           ++u;
         }
-        ++v;
       }
+      cur = nxt;
     }
   }
 }
@@ -357,12 +442,12 @@ template <int T, int PREC, int W, int TW>
 __device__ __forceinline__ void store_acc(const typename Acc<PREC>::type* acc, double* sK, bool accum, bool mirror,
                                           int k_row, int c_col) {
   constexpr int LD = ldk<T>();
-  int u = 0, v = 0;
+  int u = 0;
 #pragma unroll
   for (int J = 0; J < T; ++J) {
 #pragma unroll
     for (int I = 0; I <= J; ++I) {
-      if ((v % TW) == W) {
+      if (owns<T, W, TW>(J)) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           // output layouts: FP64 row = k_row + 4 j, FP32 accumulators row = 4 k_row + j
@@ -374,7 +459,6 @@ __device__ __forceinline__ void store_acc(const typename Acc<PREC>::type* acc, d
         }
         ++u;
       }
-      ++v;
     }
   }
 }
@@ -568,7 +652,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
   for (int attempt = 0;; ++attempt) {
     for (int it = 0; it < a.max_iter; ++it) {
       constexpr bool QSPLIT = (SPLIT == 0);             // waves split the points (else the tiles)
-      constexpr int NACC = QSPLIT ? NT : (NT + 3) / 4;  // large n: waves split the tiles
+      constexpr int NACC = QSPLIT ? NT : split_tiles<T>();  // large n: waves split the column tiles
       typedef typename Acc<PREC>::type AccV;
       AccV acc[NACC];
 #pragma unroll
@@ -588,14 +672,35 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
           const double Fp[4] = {hc[q], hc[m + q], hc[2 * m + q], hc[3 * m + q]};
           double P[4], Fpn[4], Fp33n, xin;
           double* rec = sQ + tid * QS;
-          // E = w|J| T^T A, column v of A at a time
+          // D = w|J| T^T A T, accumulated column v = (k, l) of A at a time:
+          // E[.][v] = w|J| T^T A[.][v], D[b][(k, s)] += E[b][(k, l)] F_mu^-1[s][l]
+          double D[16];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) D[k] = 0.0;
           j2_point_cols<true>(F, Fp, hc[4 * m + q], hc[5 * m + q], a.mp, P, Fpn, Fp33n, xin,
                               [&](int v, double c0, double c1, double c2, double c3) {
-                                rec[R_E + v] = wJ * (Fi[0] * c0 + Fi[1] * c1);
-                                rec[R_E + 4 + v] = wJ * (Fi[2] * c0 + Fi[3] * c1);
-                                rec[R_E + 8 + v] = wJ * (Fi[0] * c2 + Fi[1] * c3);
-                                rec[R_E + 12 + v] = wJ * (Fi[2] * c2 + Fi[3] * c3);
+                                const double e0 = wJ * (Fi[0] * c0 + Fi[1] * c1);
+                                const double e1 = wJ * (Fi[2] * c0 + Fi[3] * c1);
+                                const double e2 = wJ * (Fi[0] * c2 + Fi[1] * c3);
+                                const double e3 = wJ * (Fi[2] * c2 + Fi[3] * c3);
+                                const int k = v >> 1, l = v & 1;
+#pragma unroll
+                                for (int s2 = 0; s2 < 2; ++s2) {
+                                  const double t = Fi[2 * s2 + l];
+                                  D[0 + 2 * k + s2] = fma(e0, t, D[0 + 2 * k + s2]);
+                                  D[4 + 2 * k + s2] = fma(e1, t, D[4 + 2 * k + s2]);
+                                  D[8 + 2 * k + s2] = fma(e2, t, D[8 + 2 * k + s2]);
+                                  D[12 + 2 * k + s2] = fma(e3, t, D[12 + 2 * k + s2]);
+                                }
                               });
+          if constexpr (PREC == PREC_BF16) {
+            float* rf = reinterpret_cast<float*>(rec + R_D);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) rf[k] = (float)D[k];
+          } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) rec[R_D + k] = D[k];
+          }
           ht[q] = Fpn[0];
           ht[m + q] = Fpn[1];
           ht[2 * m + q] = Fpn[2];
@@ -608,8 +713,6 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
           rec[R_W + 2] = wJ * (P[2] * Fi[0] + P[3] * Fi[1]);
           rec[R_W + 3] = wJ * (P[2] * Fi[2] + P[3] * Fi[3]);
           const double idet = 1.0 / (Fi[0] * Fi[3] - Fi[1] * Fi[2]);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) rec[R_FI + k] = Fi[k];
           rec[R_FM] = Fi[3] * idet;
           rec[R_FM + 1] = -Fi[1] * idet;
           rec[R_FM + 2] = -Fi[2] * idet;

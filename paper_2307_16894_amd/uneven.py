@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import (DT_F64, MODE_FUSED, rom_default_opts, rom_homogenized_stress_tangent, rom_path_advance,
-               rom_path_gather, rom_step)
+               rom_path_gather, rom_state_init, rom_step)
 from .batch import RomBatch
 
 
@@ -50,6 +50,13 @@ class Group:
             self.solved += act
             self.failed += act * ((rb.status != 0) & (rb.status != 3)).to(torch.int64)
         rom_path_advance(self.P, self.active.data_ptr(), self.step.data_ptr(), s)
+
+    def reset(self):
+        """Back to the virgin state at step 0 (outside any capture)."""
+        rb = self.rb
+        rom_state_init(rb.h, self.P, rb.mu.data_ptr(), rb.state.data_ptr(), rb.stream.cuda_stream)
+        for t in (self.step, self.active, self.evals, self.solved, self.failed):
+            t.zero_()
 
     def close(self):
         self.rb.close()
@@ -93,6 +100,12 @@ class UnevenBatch:
                 self.graph.replay()
             else:
                 self.step_eager()
+
+    def reset(self):
+        torch.cuda.synchronize()
+        for g in self.groups:
+            g.reset()
+        torch.cuda.synchronize()
 
     def totals(self):
         return dict(point_steps=int(sum(int(g.solved.sum()) for g in self.groups)),

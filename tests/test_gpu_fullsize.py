@@ -93,3 +93,62 @@ def test_plain_step_failures_keep_committed_state(gpu):
     for p in failed[:6]:
         ref = oracle(int(p), K, False, 15)
         assert [g[k]['status'][p] for k in range(K)] == [ref[k]['status'] for k in range(K)], p
+
+
+W4 = WORKLOADS['fourvoid_n100_m1500_P16384_cyclic20']
+SAMPLE4 = [0, 5461, 10922, W4['P'] - 1]
+
+
+def run_gpu4(opts, K):
+    mu, paths = inputs(W4)
+    rb = RomBatch(rom_path(W4['rom']), mu)
+    out = []
+    for k in range(K):
+        print(f"[gpu] four-void P={W4['P']} contraction={opts.contraction} fixed={opts.fixed_iters} step {k}",
+              flush=True)
+        st, it, rn = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), opts)
+        torch.cuda.synchronize()
+        out.append(dict(status=st.cpu().numpy()[SAMPLE4].copy(), iters=it.cpu().numpy()[SAMPLE4].copy(),
+                        all_status=st.cpu().numpy().copy(),
+                        r=rb.r(trial=True).cpu().numpy()[SAMPLE4].copy(), Pbar=rb.Pbar.cpu().numpy()[SAMPLE4].copy(),
+                        Abar=rb.Abar.cpu().numpy()[SAMPLE4].copy()))
+    rb.close()
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def oracle4(p, K, fixed, max_iter):
+    mu, paths = inputs(W4)
+    return ROM(rom_path(W4['rom'])).run_path(mu[p], paths[p, :K], tol=1e-8, max_iter=max_iter, fixed=fixed)
+
+
+def test_fourvoid_fixed_iteration_parity_full_size(gpu):
+    """n = 100 (seven column tiles, the tile split of the waves), 16384 points."""
+    K = 3
+    g = run_gpu4(L.rom_default_opts(mode=L.MODE_FUSED, fixed_iters=1, max_iter=4), K)
+    for i, p in enumerate(SAMPLE4[:3]):
+        ref = oracle4(p, K, True, 4)
+        for k in range(K):
+            assert g[k]['status'][i] == ref[k]['status'], (p, k)
+            assert rel(g[k]['r'][i], ref[k]['r']) < 1e-10, (p, k)
+            assert rel(g[k]['Pbar'][i], ref[k]['Pbar']) < 1e-10, (p, k)
+            assert rel(g[k]['Abar'][i], ref[k]['Abar'].reshape(-1)) < 1e-10, (p, k)
+
+
+@pytest.mark.parametrize("dt,tol_A", [(L.DT_F32, 1e-4), (L.DT_BF16, 3e-2)])
+def test_fourvoid_reduced_precision_full_size(gpu, dt, tol_A):
+    """FP32 / BF16 contraction at n = 100: converged to the same 1e-8 residual,
+    Pbar within 1e-5 of the FP64 oracle, Abar within the dtype's bound."""
+    K = 3
+    g = run_gpu4(L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt, max_substeps=4), K)
+    assert all((rec['all_status'] == 0).mean() > 0.999 for rec in g)
+    eP, eA = [], []
+    for i, p in enumerate(SAMPLE4[:2]):
+        ref = oracle4(p, K, False, 15)
+        for k in range(K):
+            assert g[k]['status'][i] == 0 and ref[k]['status'] == 0, (p, k)
+            eP.append(rel(g[k]['Pbar'][i], ref[k]['Pbar']))
+            eA.append(rel(g[k]['Abar'][i], ref[k]['Abar'].reshape(-1)))
+    print(f"four-void contraction {dt}: max rel err Pbar {max(eP):.2e}, Abar {max(eA):.2e}")
+    assert max(eP) < 1e-5
+    assert max(eA) < tol_A
