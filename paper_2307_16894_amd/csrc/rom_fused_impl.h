@@ -489,10 +489,10 @@ __device__ __forceinline__ unsigned int pivot_key(double v, bool cand) {
 // Gauss-Jordan elimination with partial pivoting of the n x (n + 5) system
 // [K | f | C] in sK (ld LD): lane l of wave w holds rows l (and l + 64) in the
 // columns j = w + 4 c.  Step k: the wave owning column k picks the pivot row
-// (largest |a[r][k]| among the rows not yet pivots) and publishes the column
-// and the pivot value; every wave then eliminates column k from all other
-// rows with the pivot row scaled by 1 / a[pr][k] (pivot rows themselves stay
-// unscaled and are divided by their pivot at the end).  One barrier per
+// (largest |a[r][k]| among the rows not yet pivots) and publishes it with the
+// multipliers a[r][k] / a[pr][k] of all other rows; every wave then
+// eliminates column k from those rows with the unscaled pivot row (pivot rows
+// stay unscaled and are divided by their pivot at the end).  One barrier per
 // step.  On return sK[ord[k]][n + y] holds unknown k of right-hand side y
 // (y = 0: f, 1..4: C) with ord[k] = sOrd[k].
 template <int T>
@@ -541,34 +541,39 @@ __device__ void gauss_jordan(double* sK, int n, double* sL, double* sPv, int* sO
         const unsigned long long b1 = __ballot(ROWS == 2 && key[ROWS - 1] == M);
         pr = 64 + __builtin_ctzll(b1);
       }
-      // multipliers: column k of every row but the pivot row
+      // multipliers of every row but the pivot row (the pivot is uniform:
+      // read from its lane)
+      double pv = readlane_d(v[0], pr & 63);
+      if constexpr (ROWS == 2) pv = (pr >> 6) ? readlane_d(v[ROWS - 1], pr & 63) : pv;
+      const double inv = 1.0 / pv;
 #pragma unroll
       for (int s = 0; s < ROWS; ++s) {
         const bool is_p = (lane + 64 * s == pr);
-        L[lane + 64 * s] = is_p ? 0.0 : v[s];
-        if (is_p) sPv[pr] = v[s];
+        L[lane + 64 * s] = is_p ? 0.0 : v[s] * inv;
       }
+      if (lane == 0) sPv[pr] = pv;
       if (lane == 0) {
         sPiv[k & 1] = pr;
         sOrd[k] = pr;
       }
     }
     __syncthreads();
+    double mlt[ROWS];
+#pragma unroll
+    for (int s = 0; s < ROWS; ++s) mlt[s] = L[lane + 64 * s];
     const int pr = __builtin_amdgcn_readfirstlane(sPiv[k & 1]);
     const int pl = pr & 63, ps = pr >> 6;
-    const double inv = 1.0 / sPv[pr];
     double prow[COLS];
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
       double src = a[0][c];
       if constexpr (ROWS == 2) src = ps ? a[1][c] : a[0][c];
-      prow[c] = readlane_d(src, pl) * inv;
+      prow[c] = readlane_d(src, pl);
     }
 #pragma unroll
     for (int s = 0; s < ROWS; ++s) {
-      const double mlt = L[lane + 64 * s];
 #pragma unroll
-      for (int c = 0; c < COLS; ++c) a[s][c] = fma(-mlt, prow[c], a[s][c]);
+      for (int c = 0; c < COLS; ++c) a[s][c] = fma(-mlt[s], prow[c], a[s][c]);
       if (lane + 64 * s == pr) pivmask |= 1u << s;
     }
   }
