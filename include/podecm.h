@@ -79,7 +79,7 @@ typedef struct rom_opts {
   int32_t mode;         /* ROM_MODE_* */
   int32_t warm_start;   /* ROM_WARM_*; ROM_WARM_MLP needs mode FUSED and mlp */
   int32_t split;        /* fused form: -1 automatic, 0 the waves of a workgroup split the ECM points,
-                           1 they split the tiles of K (needed for n > 75) */
+                           1 they split the column tiles of K (needed for n > 75 in FP64) */
   int32_t grid_per_cu;  /* fused form: 0 one workgroup per point; k > 0 persistent grid of k workgroups per
                            compute unit pulling points from a device-side work list */
   int32_t max_substeps; /* fused form, commit only: load-step cutting depth D (0..ROM_MAX_SUBSTEPS, default 0,

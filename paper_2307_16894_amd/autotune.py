@@ -2,7 +2,7 @@
 
 Candidates: how the four waves of a workgroup share the contraction (split
 the ECM points, or the tiles of K; the point split keeps every tile in
-registers and exists for n <= 75), and the launch form (one workgroup per
+registers: FP64 for n <= 75, the reduced forms for n <= 123), and the launch form (one workgroup per
 point, or a persistent grid of k workgroups per compute unit pulling points
 from a work list).  Each candidate is timed with HIP events on the same
 sample load step from the same state; the fastest is kept in a table keyed by
@@ -13,15 +13,17 @@ import json
 import numpy as np
 import torch
 
-from . import (MODE_FUSED, rom_default_opts, rom_homogenized_stress_tangent, rom_state_init, rom_step,
+from . import (DT_F64, MODE_FUSED, rom_default_opts, rom_homogenized_stress_tangent, rom_state_init, rom_step,
                rom_fused_tiles)
 from .batch import RomBatch
 
 GRIDS = (0, 1, 2, 4)
 
 
-def candidates(n):
-    splits = (0, 1) if rom_fused_tiles(n) <= 5 else (1,)
+def candidates(n, contraction=DT_F64):
+    """Point split (FP64 up to five column tiles, reduced forms up to eight)
+    and tile split, each with every launch form."""
+    splits = (0, 1) if (rom_fused_tiles(n) <= 5 or contraction != DT_F64) else (1,)
     return [(s, g) for s in splits for g in GRIDS]
 
 
@@ -48,7 +50,7 @@ def tune(rom_path, mu, Fbar, contraction, reps=3):
     Fb = torch.as_tensor(np.ascontiguousarray(Fbar), dtype=torch.float64).reshape(rb.P, 4).to(rb.device)
     n, m = rb.info['n'], rb.info['m']
     times = {}
-    for split, grid in candidates(n):
+    for split, grid in candidates(n, contraction):
         times[(split, grid)] = time_config(rb, Fb, contraction, split, grid, reps)
     rb.close()
     best = min(times, key=times.get)

@@ -38,10 +38,13 @@ int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, 
                           int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
   const int T = rom_fused_tiles(h->n);
   if (T < 2 || T > 8 || 16 * T != h->npad) return ROM_EUNSUPPORTED;
+  // the point split needs every tile's accumulator in registers: FP64 up to
+  // five column tiles, the FP32 accumulators of the reduced forms up to eight
+  const bool point_ok = (T <= 5) || (o.contraction != ROM_DT_F64);
   int split = o.split;
-  if (split < 0) split = (T <= 5) ? 0 : 1;
+  if (split < 0) split = point_ok ? 0 : 1;
   if (split != 0 && split != 1) return ROM_EINVAL;
-  if (split == 0 && T > 5) return ROM_EUNSUPPORTED;  // point split needs every tile in registers
+  if (split == 0 && !point_ok) return ROM_EUNSUPPORTED;
   const StateLayout L = rom_state_layout(h, P);
   FusedArgs a;
   a.n = h->n;

@@ -357,6 +357,8 @@ __device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T],
   if (qa >= qb) return;
   const double* Gb = Gq + (size_t)q0 * 4 * NPAD;
   const int arow = 16 * pd.In + c_col - n;  // padding-row offset of this lane in tile In
+  const bool apad = arow >= 0 && arow < 4, aodd = arow & 1;
+  // E columns: B = D V with V[(k', s)][(k, l)] = delta(k', k) F_mu[l][s] in place of G
   G8 cur, nxt;
   load_g8<T>(cur, Gb, qa, 0, qa, qb, k_row, c_col);
   for (int qs = qa; qs < qb; qs += 8) {
@@ -385,6 +387,8 @@ __device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T],
       else
         load_g8<T>(nxt, Gb, min(qs + 8, qb - 1), 0, qa, qb, k_row, c_col);
       const int col = 16 * J + c_col, dc = col - n;
+      const bool ecol = dc >= 1 && dc <= 4, wcol = dc == 0;
+      const int ek = (dc - 1) >> 1, el = (dc - 1) & 1;
       if (do_f) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -394,22 +398,23 @@ __device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T],
       bf8 Bop;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const float g0 = (float)cur.g[h][0], g1 = (float)cur.g[h][1];
-        const float g2 = (float)cur.g[h][2], g3 = (float)cur.g[h][3];
+        float g[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) g[c] = (float)cur.g[h][c];
+        float gb[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          // V[c][(ek, el)] for c = (k', s): F_mu[el][s] when k' = ek
+          const float fv = el ? Fm[h][2 + (c & 1)] : Fm[h][c & 1];
+          gb[c] = ecol ? (((c >> 1) == ek) ? fv : 0.0f) : g[c];
+        }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          float av = (b == 0) ? g0 : (b == 1) ? g1 : (b == 2) ? g2 : g3;
-          if (J == pd.In && arow >= 0 && arow < 4)
-            av = ((arow >> 1) == (b >> 1)) ? Fm[h][2 * (arow & 1) + (b & 1)] : 0.0f;
-          float hv = D[h][4 * b] * g0 + D[h][4 * b + 1] * g1 + D[h][4 * b + 2] * g2 + D[h][4 * b + 3] * g3;
-          if (J == pd.In || J == pd.In + 1) {
-            if (dc == 0) hv = (float)Wv[h][b];
-            if (dc >= 1 && dc <= 4) {
-              // E[b][(k, l)] = sum_s D[b][(k, s)] F_mu[l][s]
-              const int y = dc - 1, k = y >> 1, l = y & 1;
-              hv = D[h][4 * b + 2 * k] * Fm[h][2 * l] + D[h][4 * b + 2 * k + 1] * Fm[h][2 * l + 1];
-            }
-          }
+          float av = g[b];
+          if (J == pd.In && apad)
+            av = ((arow >> 1) == (b >> 1)) ? (aodd ? Fm[h][2 + (b & 1)] : Fm[h][b & 1]) : 0.0f;
+          float hv = D[h][4 * b] * gb[0] + D[h][4 * b + 1] * gb[1] + D[h][4 * b + 2] * gb[2] + D[h][4 * b + 3] * gb[3];
+          if (wcol) hv = (float)Wv[h][b];
           Aop[J][4 * h + b] = (__bf16)av;
           Bop[4 * h + b] = (__bf16)hv;
         }
@@ -916,9 +921,16 @@ int launch_one(const FusedArgs& a, int grid, int P, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 
+// The point split keeps every tile's accumulator in each wave: FP64 up to
+// five column tiles, FP32 accumulators (half the registers) up to eight.
+template <int T, int PREC>
+constexpr bool point_split_ok() {
+  return T <= 5 || PREC != PREC_F64;
+}
+
 template <int T, int PREC>
 int launch_prec(const FusedArgs& a, int split, int grid, int P, hipStream_t s) {
-  if constexpr (T <= 5) {
+  if constexpr (point_split_ok<T, PREC>()) {
     if (split == 0) return launch_one<T, PREC, 0>(a, grid, P, s);
   }
   return launch_one<T, PREC, 1>(a, grid, P, s);
@@ -951,11 +963,10 @@ template <int T>
 int fused_setup() {
   static_assert(lds_doubles<T>() * 8 <= 160 * 1024, "LDS of the fused kernel exceeds the workgroup limit");
   int rc = ROM_OK;
-  if constexpr (T <= 5) {
+  if constexpr (point_split_ok<T, PREC_F64>())
     if (rc == ROM_OK) rc = setup_one<T, PREC_F64, 0>();
-    if (rc == ROM_OK) rc = setup_one<T, PREC_F32, 0>();
-    if (rc == ROM_OK) rc = setup_one<T, PREC_BF16, 0>();
-  }
+  if (rc == ROM_OK) rc = setup_one<T, PREC_F32, 0>();
+  if (rc == ROM_OK) rc = setup_one<T, PREC_BF16, 0>();
   if (rc == ROM_OK) rc = setup_one<T, PREC_F64, 1>();
   if (rc == ROM_OK) rc = setup_one<T, PREC_F32, 1>();
   if (rc == ROM_OK) rc = setup_one<T, PREC_BF16, 1>();
