@@ -288,18 +288,27 @@ def main(argv=None):
     rom_file = os.path.join(ROOT, 'roms', w['rom'] + '.rom')
     variants = [v for v in (a.variants or ','.join(w['variants'])).split(',') if v]
     ws, wsinfo = (None, None)
-    if any(v.endswith('_mlp') for v in variants):
+    if any('_mlp' in v for v in variants):
         ws, wsinfo = train_warm_start(w, rom_file, log)
     P = w['P']
     res = {}
     for v in variants:
+        # <precision>[_mlp][_phased[K[eE]] | _staged]  (K: phased evaluations, E: early hand-over,
+        # -1 none; library defaults when left out)
         dt = {'fp64': L.DT_F64, 'fp32': L.DT_F32, 'bf16': L.DT_BF16}[v.split('_')[0]]
-        if v.endswith('_mlp'):
-            opts = ws.opts(contraction=dt, max_substeps=SUBSTEPS)
+        last = v.split('_')[-1]
+        mode = L.MODE_PHASED if last.startswith('phased') else L.MODE_FUSED
+        kph, kearly = 0, 0
+        if mode == L.MODE_PHASED and last[6:]:
+            ks, _, es = last[6:].partition('e')
+            kph, kearly = int(ks or 0), int(es or 0)
+        ph = dict(mode=mode, phased_evals=kph, phased_early=kearly)
+        if '_mlp' in v:
+            opts = ws.opts(contraction=dt, max_substeps=SUBSTEPS, **ph)
         elif v.endswith('_staged'):  # the staged form has no load-step cutting
             opts = L.rom_default_opts(mode=L.MODE_STAGED, contraction=dt)
         else:
-            opts = L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt, max_substeps=SUBSTEPS)
+            opts = L.rom_default_opts(contraction=dt, max_substeps=SUBSTEPS, **ph)
         log(f"[bench] {v}")
         g = gpu_run(w, a.steps, a.warmup, opts, rom_file)
         n, m = g['n'], g['m']

@@ -62,6 +62,10 @@ extern "C" {
 /* execution form of rom_step */
 #define ROM_MODE_STAGED 0  /* one kernel per stage, host-enqueued Newton loop */
 #define ROM_MODE_FUSED  1  /* one persistent kernel, device-side Newton loop */
+#define ROM_MODE_PHASED 2  /* the first Newton evaluations of every point as a material launch (one lane per
+                              ECM point of every point) and a contraction + elimination launch each, the points
+                              still running after them finished by the fused kernel from where they stand
+                              (n <= 75); same arithmetic, and bit for bit the same results, as ROM_MODE_FUSED */
 
 /* initial guess of the Newton iteration */
 #define ROM_WARM_PREV 0  /* the committed r (plain guess) */
@@ -77,22 +81,30 @@ typedef struct rom_opts {
   int32_t commit;       /* 1: converged points commit r, history and Fbar */
   int32_t contraction;  /* ROM_DT_*: precision of the K contraction; all else is FP64 */
   int32_t mode;         /* ROM_MODE_* */
-  int32_t warm_start;   /* ROM_WARM_*; ROM_WARM_MLP needs mode FUSED and mlp */
-  int32_t split;        /* fused form: -1 automatic, 0 the waves of a workgroup split the ECM points,
+  int32_t warm_start;   /* ROM_WARM_*; ROM_WARM_MLP needs mode FUSED or PHASED and mlp */
+  int32_t split;        /* fused and phased forms: -1 automatic, 0 the waves of a workgroup split the ECM points,
                            1 they split the column tiles of K (needed for n > 75 in FP64) */
   int32_t grid_per_cu;  /* fused form: 0 one workgroup per point; k > 0 persistent grid of k workgroups per
-                           compute unit pulling points from a device-side work list */
-  int32_t max_substeps; /* fused form, commit only: load-step cutting depth D (0..ROM_MAX_SUBSTEPS, default 0,
+                           compute unit pulling points from a device-side work list (phased form: the grid of
+                           its fused part, 0 meaning 2) */
+  int32_t max_substeps; /* fused and phased forms, commit only: load-step cutting depth D (0..ROM_MAX_SUBSTEPS, default 0,
                            the plain step).  A step that fails is retried towards targets
                            Fbar_c + (t / 2^D)(Fbar - Fbar_c) on the segment from the committed Fbar_c, halving the
                            stride on failure and doubling it after a converged sub-step, which is committed at once
                            (the material-model appendix: the global Newton solve may need much smaller load steps).
                            The point fails when a stride of 1 / 2^D fails; its committed state is then the last
                            converged sub-step.  iters counts the evaluations of all attempts. */
-  int32_t reserved[3];
+  int32_t phased_evals; /* phased form: evaluations made by the phased launches (0: 6, at most max_iter); the
+                           rest of the step runs in the fused kernel, and so does an attempt that fails with
+                           load-step cutting on (from its start) */
+  int32_t phased_early; /* phased form: after this many evaluations the points whose ||f|| stayed above 0.3 of
+                           the previous evaluation's (slow convergence: likely to fail the plain step and be cut
+                           into sub-steps) go to a fused kernel on a side stream, beside the remaining phased
+                           evaluations (0: 3; -1: none; used when below phased_evals) */
+  int32_t reserved[1];
   rom_mlp_handle mlp;   /* network for ROM_WARM_MLP (see below), else NULL */
   const int32_t* active;  /* device i32 [batch] or NULL: points with active[p] == 0 are skipped, their state
-                             and outputs untouched (fused form) */
+                             and outputs untouched (fused and phased forms) */
 } rom_opts;
 
 /* Fill *o with the defaults: tol 1e-8, max_iter 15, commit, FP64, staged form, plain guess, split -1,

@@ -30,7 +30,7 @@ ST_BADMU = 4
 WARM_PREV, WARM_MLP = 0, 1
 
 DT_F64, DT_F32, DT_BF16 = 0, 1, 2
-MODE_STAGED, MODE_FUSED = 0, 1
+MODE_STAGED, MODE_FUSED, MODE_PHASED = 0, 1, 2
 
 FIELD_R_COMMITTED, FIELD_R_TRIAL, FIELD_H_COMMITTED, FIELD_H_TRIAL = 0, 1, 2, 3
 FIELD_TRANSFORM, FIELD_PBAR, FIELD_ABAR, FIELD_MU_OK = 4, 5, 6, 7
@@ -54,7 +54,9 @@ class rom_opts(ctypes.Structure):
     _fields_ = [('tol', ctypes.c_double), ('max_iter', ctypes.c_int32), ('fixed_iters', ctypes.c_int32),
                 ('commit', ctypes.c_int32), ('contraction', ctypes.c_int32), ('mode', ctypes.c_int32),
                 ('warm_start', ctypes.c_int32), ('split', ctypes.c_int32), ('grid_per_cu', ctypes.c_int32),
-                ('max_substeps', ctypes.c_int32), ('reserved', ctypes.c_int32 * 3), ('mlp', ctypes.c_void_p), ('active', ctypes.c_void_p)]
+                ('max_substeps', ctypes.c_int32), ('phased_evals', ctypes.c_int32), ('phased_early', ctypes.c_int32),
+                ('reserved', ctypes.c_int32 * 1),
+                ('mlp', ctypes.c_void_p), ('active', ctypes.c_void_p)]
 
 
 _lib = None

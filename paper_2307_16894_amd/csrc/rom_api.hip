@@ -43,6 +43,12 @@ void release(rom_model* h) {
   if (!h) return;
   for (int i = 0; i < 2 * h->cap; ++i) (void)hipEventDestroy(h->ev[i]);
   free(h->ev);
+  if (h->aux) {
+    (void)hipStreamSynchronize(h->aux);
+    (void)hipStreamDestroy(h->aux);
+    (void)hipEventDestroy(h->ev_fork);
+    (void)hipEventDestroy(h->ev_join);
+  }
   (void)hipFree(h->w);
   (void)hipFree(h->Gt);
   (void)hipFree(h->Gq);
@@ -108,6 +114,8 @@ int rom_default_opts(rom_opts* o) {
   o->split = -1;
   o->grid_per_cu = 0;
   o->max_substeps = 0;
+  o->phased_evals = 0;
+  o->phased_early = 0;
   o->mlp = nullptr;
   o->active = nullptr;
   return ROM_OK;
@@ -284,6 +292,10 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
   }
   if (o.mode == ROM_MODE_FUSED)
     return rom_launch_step_fused(h, batch, Fbar_dev, state_dev, o, status_dev, iters_dev, resnorm_dev, stream);
+  if (o.mode == ROM_MODE_PHASED) {
+    if (o.phased_evals < 0 || o.phased_early < -1) return ROM_EINVAL;
+    return rom_launch_step_phased(h, batch, Fbar_dev, state_dev, o, status_dev, iters_dev, resnorm_dev, stream);
+  }
   return ROM_EINVAL;
 }
 

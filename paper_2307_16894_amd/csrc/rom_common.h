@@ -9,6 +9,8 @@
 #include "j2_device.h"
 
 #define ROM_NMAX 128       // largest supported number of modes n
+#define ROM_REC_ROWS 28    // phased-form ECM-point record: D (16), W (4), F_mu (4), P (4)
+#define ROM_PHASED_NPAD 80  // widest contraction tile set of the phased form (n <= 75)
 #define ROM_ALIGN 256
 
 // Loaded ROM (Algorithm 1, offline output) resident on one device.
@@ -25,6 +27,10 @@ struct rom_model {
   double* Gd;   // [c][4][m] transformation-mode gradients, point fastest
   float* Gq32;  // [m][4][npad] FP32 copy of Gq
   uint16_t* Gq16;  // [m][4][npad] BF16 copy of Gq
+  // phased form: side stream of the fused kernel that finishes the slow
+  // points while the phased evaluations go on (created at first use)
+  hipStream_t aux;
+  hipEvent_t ev_fork, ev_join;
   // kernel timing (measurement support)
   int timing;
   int nev;                 // event pairs recorded since enable
@@ -45,6 +51,7 @@ enum {
   F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK, F_FBC, F_RG,
   F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT, F_XF, F_DR, F_MU, F_LIST,
   F_D, F_W, F_K, F_F, F_PIV,
+  F_REC, F_PHI, F_PHD, F_LIST2, F_LIST3, F_LIST4,
   F_NFIELDS
 };
 
@@ -85,6 +92,13 @@ static inline StateLayout rom_state_layout(const rom_model* h, size_t P) {
   sz[F_K] = P * n * n * 8;
   sz[F_F] = P * n * 8;
   sz[F_PIV] = P * n * 4;
+  // phased form: per-point records between the material and contraction launches
+  sz[F_REC] = (h->npad <= ROM_PHASED_NPAD) ? P * m * ROM_REC_ROWS * 8 : 0;
+  sz[F_PHI] = P * 2 * 4;
+  sz[F_PHD] = P * 2 * 8;
+  sz[F_LIST2] = P * 4;
+  sz[F_LIST3] = P * 4;
+  sz[F_LIST4] = P * 4;
   StateLayout L;
   size_t o = 0;
   for (int i = 0; i < F_NFIELDS; ++i) {

@@ -6,3 +6,5 @@ int rom_fused_setup();
 int rom_fused_tiles(int n);  // 16-column tiles of the padded system (n + 5 columns)
 int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
                           int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s);
+int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
+                           int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s);

@@ -1,5 +1,7 @@
 // Dispatcher of the fused online solve: argument set-up, the learned warm
 // start, the work list of the persistent form, and the per-tile-count launch.
+#include <string.h>
+
 #include "rom_fused.h"
 #include "rom_fused_args.h"
 
@@ -34,19 +36,21 @@ int rom_fused_setup() {
   return rc;
 }
 
-int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
-                          int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
+// Kernel arguments of a fused or phased step, the wave split, and the
+// learned warm start (features and network prediction enqueued on s).
+int rom_fused_prepare(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o, int32_t* st_out,
+                      int32_t* it_out, double* res_out, hipStream_t s, FusedArgs& a, int& split) {
   const int T = rom_fused_tiles(h->n);
   if (T < 2 || T > 8 || 16 * T != h->npad) return ROM_EUNSUPPORTED;
   // the point split needs every tile's accumulator in registers: FP64 up to
   // five column tiles, the FP32 accumulators of the reduced forms up to eight
   const bool point_ok = (T <= 5) || (o.contraction != ROM_DT_F64);
-  int split = o.split;
+  split = o.split;
   if (split < 0) split = point_ok ? 0 : 1;
   if (split != 0 && split != 1) return ROM_EINVAL;
   if (split == 0 && !point_ok) return ROM_EUNSUPPORTED;
   const StateLayout L = rom_state_layout(h, P);
-  FusedArgs a;
+  memset(&a, 0, sizeof(a));
   a.n = h->n;
   a.m = h->m;
   a.max_iter = o.max_iter;
@@ -73,10 +77,6 @@ int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, 
   a.rg = field<double>(state, L, F_RG);
   a.fbc = field<double>(state, L, F_FBC);
   a.active = o.active;
-  a.list = nullptr;
-  a.nlist = nullptr;
-  a.counter = nullptr;
-  a.dr = nullptr;
   if (o.warm_start == ROM_WARM_MLP) {
     int nin = 0, nout = 0;
     rom_mlp_dims(o.mlp, &nin, &nout);
@@ -89,8 +89,41 @@ int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, 
     if (rc != ROM_OK) return rc;
     a.dr = DR;
   }
+  return ROM_OK;
+}
+
+int rom_fused_launch(int T, const FusedArgs& a, int prec, int split, int grid, int P, hipStream_t s) {
+  switch (T) {
+    case 2: return rom_fused_launch_2(a, prec, split, grid, P, s);
+    case 3: return rom_fused_launch_3(a, prec, split, grid, P, s);
+    case 4: return rom_fused_launch_4(a, prec, split, grid, P, s);
+    case 5: return rom_fused_launch_5(a, prec, split, grid, P, s);
+    case 6: return rom_fused_launch_6(a, prec, split, grid, P, s);
+    case 7: return rom_fused_launch_7(a, prec, split, grid, P, s);
+    case 8: return rom_fused_launch_8(a, prec, split, grid, P, s);
+    default: return ROM_EUNSUPPORTED;
+  }
+}
+
+int rom_phased_cs(int T, const FusedArgs& a, int prec, int split, int P, hipStream_t s) {
+  switch (T) {
+    case 2: return rom_phased_cs_2(a, prec, split, P, s);
+    case 3: return rom_phased_cs_3(a, prec, split, P, s);
+    case 4: return rom_phased_cs_4(a, prec, split, P, s);
+    case 5: return rom_phased_cs_5(a, prec, split, P, s);
+    default: return ROM_EUNSUPPORTED;
+  }
+}
+
+int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
+                          int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
+  FusedArgs a;
+  int split = 0;
+  int rc = rom_fused_prepare(h, P, Fbar, state, o, st_out, it_out, res_out, s, a, split);
+  if (rc != ROM_OK) return rc;
   int grid = 0;
   if (o.grid_per_cu > 0) {
+    const StateLayout L = rom_state_layout(h, P);
     int* cnt = field<int>(state, L, F_COUNT) + 4;
     int* list = field<int>(state, L, F_LIST);
     k_zero2<<<1, 64, 0, s>>>(cnt);
@@ -102,16 +135,7 @@ int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, 
     if (hipGetLastError() != hipSuccess) return ROM_EHIP;
   }
   if (rom_timing_mark(h, 0, s) != ROM_OK) return ROM_EHIP;
-  int rc;
-  switch (T) {
-    case 2: rc = rom_fused_launch_2(a, o.contraction, split, grid, P, s); break;
-    case 3: rc = rom_fused_launch_3(a, o.contraction, split, grid, P, s); break;
-    case 4: rc = rom_fused_launch_4(a, o.contraction, split, grid, P, s); break;
-    case 5: rc = rom_fused_launch_5(a, o.contraction, split, grid, P, s); break;
-    case 6: rc = rom_fused_launch_6(a, o.contraction, split, grid, P, s); break;
-    case 7: rc = rom_fused_launch_7(a, o.contraction, split, grid, P, s); break;
-    default: rc = rom_fused_launch_8(a, o.contraction, split, grid, P, s); break;
-  }
+  rc = rom_fused_launch(rom_fused_tiles(h->n), a, o.contraction, split, grid, P, s);
   if (rom_timing_mark(h, 1, s) != ROM_OK) return ROM_EHIP;
   return rc;
 }

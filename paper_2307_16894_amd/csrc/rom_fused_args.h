@@ -29,6 +29,24 @@ struct FusedArgs {
   const float* dr;   // warm-start increments [P][n] (NULL: plain guess)
   double* rg;        // initial guess actually used [P][n]
   double* fbc;       // committed Fbar [P][4]
+  // phased form: the first evaluations of attempt 0 as a material launch and a
+  // contraction launch per evaluation, the points still running after them
+  // handed to the fused kernel, which resumes them from this state
+  int ph_k;          // evaluations made by the phased launches
+  double* rec;       // ECM-point records [P][ROM_REC_ROWS][m]
+  int* phi;          // per point: evaluations made, fell back to the plain guess [P][2]
+  double* phd;       // per point: ||f|| of the first and of the latest evaluation [P][2]
+  const int* lin;    // points of this evaluation
+  const int* cin;    // their count (device)
+  int* lout;         // points making the next phased evaluation
+  int* cout;         // their count (device)
+  int* hand;         // points handed to the fused kernel
+  int* chand;        // their count (device)
+  int ph_early;      // evaluations after which slow points go to the early list (0: none)
+  double ph_slow;    // slow: ||f|| above this fraction of the previous evaluation's
+  int* early;        // points handed to the fused kernel on the side stream
+  int* cearly;       // their count (device)
+  int resume;        // fused kernel: start each point from phi / phd (evaluation phi[0] of attempt 0)
 };
 
 // per tile-count entry points (rom_fused_t<T>.hip): launch with the given
@@ -37,6 +55,7 @@ struct FusedArgs {
 // grid == 0: one workgroup per point)
 #define ROM_FUSED_DECL(T)                                                                              \
   int rom_fused_launch_##T(const FusedArgs& a, int prec, int split, int grid, int P, hipStream_t s);  \
+  int rom_phased_cs_##T(const FusedArgs& a, int prec, int split, int P, hipStream_t s);               \
   int rom_fused_setup_##T();
 ROM_FUSED_DECL(2)
 ROM_FUSED_DECL(3)
@@ -45,3 +64,9 @@ ROM_FUSED_DECL(5)
 ROM_FUSED_DECL(6)
 ROM_FUSED_DECL(7)
 ROM_FUSED_DECL(8)
+
+// shared by the fused and phased dispatchers (rom_fused.hip)
+int rom_fused_prepare(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o, int32_t* st_out,
+                      int32_t* it_out, double* res_out, hipStream_t s, FusedArgs& a, int& split);
+int rom_fused_launch(int T, const FusedArgs& a, int prec, int split, int grid, int P, hipStream_t s);
+int rom_phased_cs(int T, const FusedArgs& a, int prec, int split, int P, hipStream_t s);

@@ -47,7 +47,9 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
-constexpr int FCH = 256;  // ECM points per chunk
+constexpr int FCH = 256;  // ECM points per chunk of the material phase
+constexpr int CCH = 128;  // ECM points per contraction chunk (records staged in LDS by the phased kernel)
+static_assert(FCH % CCH == 0 && CCH * 2 == 256, "contraction chunks tile the material chunks; two lanes per record");
 constexpr int QS = 24;    // LDS record per point
 constexpr int R_D = 0, R_W = 16, R_FM = 20;
 
@@ -64,6 +66,15 @@ constexpr int main_doubles() {
 template <int T>
 constexpr int lds_doubles() {
   return main_doubles<T>() + 16 * T + 4 * 16 * T + 256 + 128 + 32 + (16 * T + 8) / 2;
+}
+// phased contraction kernel: records of one contraction chunk / [K | f | C]
+template <int T>
+constexpr int cs_main_doubles() {
+  return (CCH * QS > 16 * T * ldk<T>()) ? CCH * QS : 16 * T * ldk<T>();
+}
+template <int T>
+constexpr int cs_lds_doubles() {
+  return cs_main_doubles<T>() + 16 * T + 4 * 16 * T + 256 + 128 + 32 + (16 * T + 8) / 2;
 }
 
 // F = Fbar + (sum_i r_i G_i(q)) F_mu^-1 at ECM point q (argument of P in
@@ -596,44 +607,303 @@ __device__ void gauss_jordan(double* sK, int n, double* sL, double* sPv, int* sO
   __syncthreads();
 }
 
+// Two FP32 values in one record slot (the BF16 form keeps D in FP32): the
+// first in the low half, as in an FP32 array over the slots.
+__device__ __forceinline__ double pack_f32x2(float lo, float hi) {
+  const unsigned long long u =
+      ((unsigned long long)__float_as_uint(hi) << 32) | (unsigned long long)__float_as_uint(lo);
+  return __longlong_as_double((long long)u);
+}
+
+// Kinematics, return map and tangent (Appendix A) of ECM point q at the trial
+// state r (sR): the contraction record goes to rec[k * rs] (rs = 1: a record
+// in LDS; rs = m: the point-fastest records of the phased form), the trial
+// history to ht (point fastest); P and w|J| are returned.
+//   D = w|J| T^T A T, accumulated column v = (k, l) of A at a time:
+//     E[.][v] = w|J| T^T A[.][v], D[b][(k, s)] += E[b][(k, l)] F_mu^-1[s][l];
+//   W = w|J| P F_mu^-T;  F_mu from the stored F_mu^-1.
+template <int PREC>
+__device__ __forceinline__ void point_record(int n, int m, int q, const double* __restrict__ Gt, const double* sR,
+                                             const double Fb[4], const double* __restrict__ tmu,
+                                             const double* __restrict__ hc, double* __restrict__ ht,
+                                             const J2Params& mp, double* rec, int rs, double P[4], double& wJ) {
+  const double Fi[4] = {tmu[q], tmu[m + q], tmu[2 * m + q], tmu[3 * m + q]};
+  const double w = tmu[4 * m + q];
+  wJ = w;
+  double F[4];
+  kinematics(n, m, q, Gt, sR, Fb, Fi, F);
+  const double Fp[4] = {hc[q], hc[m + q], hc[2 * m + q], hc[3 * m + q]};
+  double Fpn[4], Fp33n, xin;
+  double D[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) D[k] = 0.0;
+  j2_point_cols<true>(F, Fp, hc[4 * m + q], hc[5 * m + q], mp, P, Fpn, Fp33n, xin,
+                      [&](int v, double c0, double c1, double c2, double c3) {
+                        const double e0 = w * (Fi[0] * c0 + Fi[1] * c1);
+                        const double e1 = w * (Fi[2] * c0 + Fi[3] * c1);
+                        const double e2 = w * (Fi[0] * c2 + Fi[1] * c3);
+                        const double e3 = w * (Fi[2] * c2 + Fi[3] * c3);
+                        const int k = v >> 1, l = v & 1;
+#pragma unroll
+                        for (int s2 = 0; s2 < 2; ++s2) {
+                          const double t = Fi[2 * s2 + l];
+                          D[0 + 2 * k + s2] = fma(e0, t, D[0 + 2 * k + s2]);
+                          D[4 + 2 * k + s2] = fma(e1, t, D[4 + 2 * k + s2]);
+                          D[8 + 2 * k + s2] = fma(e2, t, D[8 + 2 * k + s2]);
+                          D[12 + 2 * k + s2] = fma(e3, t, D[12 + 2 * k + s2]);
+                        }
+                      });
+  if constexpr (PREC == PREC_BF16) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) rec[(R_D + j) * rs] = pack_f32x2((float)D[2 * j], (float)D[2 * j + 1]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) rec[(R_D + k) * rs] = D[k];
+  }
+  ht[q] = Fpn[0];
+  ht[m + q] = Fpn[1];
+  ht[2 * m + q] = Fpn[2];
+  ht[3 * m + q] = Fpn[3];
+  ht[4 * m + q] = Fp33n;
+  ht[5 * m + q] = xin;
+  rec[R_W * rs] = w * (P[0] * Fi[0] + P[1] * Fi[1]);
+  rec[(R_W + 1) * rs] = w * (P[0] * Fi[2] + P[1] * Fi[3]);
+  rec[(R_W + 2) * rs] = w * (P[2] * Fi[0] + P[3] * Fi[1]);
+  rec[(R_W + 3) * rs] = w * (P[2] * Fi[2] + P[3] * Fi[3]);
+  const double idet = 1.0 / (Fi[0] * Fi[3] - Fi[1] * Fi[2]);
+  rec[R_FM * rs] = Fi[3] * idet;
+  rec[(R_FM + 1) * rs] = -Fi[1] * idet;
+  rec[(R_FM + 2) * rs] = -Fi[2] * idet;
+  rec[(R_FM + 3) * rs] = Fi[0] * idet;
+}
+
+// Accumulators of one evaluation: the MFMA tiles of this wave, and in the
+// reduced-precision forms the FP64 residual partials and sum w|J| P.
+template <int T, int PREC, int SPLIT>
+struct EvalAcc {
+  static constexpr int NACC = (SPLIT == 0) ? T * (T + 1) / 2 : split_tiles<T>();
+  typename Acc<PREC>::type acc[NACC];
+  double fpart[T];
+  double accP[4];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int t = 0; t < NACC; ++t) acc[t] = (typename Acc<PREC>::type){0, 0, 0, 0};
+#pragma unroll
+    for (int J = 0; J < T; ++J) fpart[J] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) accP[k] = 0.0;
+  }
+};
+
+// Contraction of the records sQ of chunk [q0, q0 + qend): SPLIT 0 the waves
+// take a quarter of the points each, SPLIT 1 every wave takes all points for
+// its column tiles.
+template <int T, int PREC, int SPLIT>
+__device__ __forceinline__ void contract_chunk(EvalAcc<T, PREC, SPLIT>& E, const double* __restrict__ Gq,
+                                               const double* sQ, int q0, int qend, const Pad& pd, int n, int wave,
+                                               int k_row, int c_col) {
+  if constexpr (SPLIT == 0) {
+    const int qa = (wave * qend) >> 2, qb = ((wave + 1) * qend) >> 2;
+    contract_any<T, PREC, 0, 1>(E.acc, E.fpart, true, Gq, sQ, q0, qa, qb, pd, n, k_row, c_col);
+  } else {
+    switch (wave) {
+      case 0: contract_any<T, PREC, 0, 4>(E.acc, E.fpart, true, Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
+      case 1: contract_any<T, PREC, 1, 4>(E.acc, E.fpart, false, Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
+      case 2: contract_any<T, PREC, 2, 4>(E.acc, E.fpart, false, Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
+      default: contract_any<T, PREC, 3, 4>(E.acc, E.fpart, false, Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
+    }
+  }
+}
+
+// [K | f | C] and the padding rows into LDS (K's lower part by symmetry; in
+// the reduced-precision forms f and sum w|J| P from the FP64 partials, over
+// the lane groups and the waves in a fixed order), C of the evaluation to sC
+// (kept for Abar); returns ||f||_2, the same on every lane.
+template <int T, int PREC, int SPLIT>
+__device__ __forceinline__ double assemble(const EvalAcc<T, PREC, SPLIT>& E, double* sK, double* sC, double* sX,
+                                           int n, int tid, int lane, int wave, int k_row, int c_col) {
+  constexpr int NPAD = 16 * T, LD = ldk<T>();
+  if constexpr (SPLIT == 0) {
+    for (int w = 0; w < 4; ++w) {
+      if (wave == w) store_acc<T, PREC, 0, 1>(E.acc, sK, w > 0, w == 3, k_row, c_col);
+      __syncthreads();
+    }
+  } else {
+    switch (wave) {
+      case 0: store_acc<T, PREC, 0, 4>(E.acc, sK, false, true, k_row, c_col); break;
+      case 1: store_acc<T, PREC, 1, 4>(E.acc, sK, false, true, k_row, c_col); break;
+      case 2: store_acc<T, PREC, 2, 4>(E.acc, sK, false, true, k_row, c_col); break;
+      default: store_acc<T, PREC, 3, 4>(E.acc, sK, false, true, k_row, c_col); break;
+    }
+    __syncthreads();
+  }
+  if constexpr (PREC != PREC_F64) {
+    double* sFp = sC;  // [4][NPAD] wave partials of f, before C is copied
+#pragma unroll
+    for (int J = 0; J < T; ++J) {
+      double v = E.fpart[J];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (k_row == 0) sFp[wave * NPAD + 16 * J + c_col] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double v = E.accP[k];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) sX[4 * k + wave] = v;
+    }
+    __syncthreads();
+    if (tid < n) {
+      const double v = (SPLIT == 0) ? ((sFp[tid] + sFp[NPAD + tid]) + sFp[2 * NPAD + tid]) + sFp[3 * NPAD + tid]
+                                    : sFp[tid];
+      sK[tid * LD + n] = v;
+    }
+    if (tid < 4) sK[(n + tid) * LD + n] = ((sX[4 * tid] + sX[4 * tid + 1]) + sX[4 * tid + 2]) + sX[4 * tid + 3];
+    __syncthreads();
+  }
+  for (int idx = tid; idx < 4 * n; idx += 256) sC[idx] = sK[(idx >> 2) * LD + n + 1 + (idx & 3)];
+  double part = 0.0;
+  if (tid < n) {
+    const double fv = sK[tid * LD + n];
+    part = fv * fv;
+  }
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+  if (lane == 0) sX[wave] = part;
+  __syncthreads();
+  return sqrt(sX[0] + sX[1] + sX[2] + sX[3]);
+}
+
+// Status of evaluation it (0-based) of an attempt with residual norm rn;
+// returns whether the attempt stops here.
+__device__ __forceinline__ bool eval_status(const FusedArgs& a, int it, double rn, int& status) {
+  const bool last = (it == a.max_iter - 1);
+  if (!isfinite(rn)) {
+    status = ROM_ST_NONFINITE;
+    return true;
+  }
+  if (a.fixed) {
+    status = (rn <= a.tol) ? ROM_ST_CONVERGED : ROM_ST_MAXITER;
+    return last;
+  }
+  if (rn <= a.tol) {
+    status = ROM_ST_CONVERGED;
+    return true;
+  }
+  status = ROM_ST_MAXITER;
+  return last;
+}
+
+// Effective quantities at the returned state (after the elimination of the
+// evaluation): Pbar = sum w|J| P, Abar = sum w|J| A - C^T K*^-1 C, per unit
+// cell area (Sec. 3.3).
+template <int T>
+__device__ __forceinline__ void write_effective(const FusedArgs& a, int p, const double* sK, const double* sC,
+                                                const int* sOrd, int n, int tid) {
+  constexpr int LD = ldk<T>();
+  if (tid < 20) {
+    const double inv_area = a.inv_area;
+    if (tid < 4) {
+      a.Pbar[4 * (size_t)p + tid] = sK[(n + tid) * LD + n] * inv_area;
+    } else {
+      const int e = tid - 4, x = e >> 2, y = e & 3;
+      double acc2 = sK[(n + x) * LD + n + 1 + y];
+      for (int i = 0; i < n; ++i) acc2 = fma(-sC[4 * i + x], sK[sOrd[i] * LD + n + 1 + y], acc2);
+      a.Abar[16 * (size_t)p + e] = acc2 * inv_area;
+    }
+  }
+  __syncthreads();
+}
+
+// Outputs of a finished load step, and the commit of a converged one (r,
+// history and the Fbar reached).
+__device__ __forceinline__ void finish_point(const FusedArgs& a, int p, const double* sR, const double Fb[4],
+                                             int status, bool fell_back, int iters, double rn, int tid) {
+  const int n = a.n, m = a.m;
+  for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i];
+  if (tid == 0) {
+    a.st_out[p] = (status == ROM_ST_CONVERGED && fell_back) ? ROM_ST_FALLBACK : status;
+    a.it_out[p] = iters;
+    a.res_out[p] = rn;
+  }
+  if (a.commit && status == ROM_ST_CONVERGED) {
+    if (tid < 4) a.fbc[4 * (size_t)p + tid] = Fb[tid];
+    for (int i = tid; i < n; i += 256) a.rc[(size_t)p * n + i] = sR[i];
+    double* hcw = a.hc + (size_t)p * 6 * m;
+    const double* ht = a.ht + (size_t)p * 6 * m;
+    for (int q = tid; q < m; q += 256)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) hcw[k * m + q] = ht[k * m + q];
+  }
+}
+
+// NaN outputs of a point whose shape parameters were rejected.
+__device__ __forceinline__ void bad_mu_outputs(const FusedArgs& a, int p, int tid) {
+  if (tid < 4) a.Pbar[4 * (size_t)p + tid] = __builtin_nan("");
+  if (tid < 16) a.Abar[16 * (size_t)p + tid] = __builtin_nan("");
+  if (tid == 0) {
+    a.st_out[p] = ROM_ST_BADMU;
+    a.it_out[p] = 0;
+    a.res_out[p] = __builtin_nan("");
+  }
+}
+
+// LDS of the fused and phased contraction kernels (computed in each kernel:
+// pointers returned in a struct upset the instruction selection of the
+// compiler for some tile counts):
+//   sQ [FCH or CCH][QS] chunk records, shared with sK [NPAD][LD] [K | f | C] (after
+//   the contraction); then sR [NPAD] current r, sC [NPAD][4] C of the
+//   evaluation, sL [2][128] pivot columns of the elimination, sPv [128] pivot
+//   value of each row, sX [32] reductions and the load-step ends, sOrd [NPAD]
+//   pivot row of each step, sPiv [2] pivot exchange.
+#define ROM_SOLVE_LDS(T, smem, MAT)                             \
+  double* sQ = (smem);                                          \
+  double* sK = (smem);                                          \
+  double* sR = (smem) + (MAT);                                  \
+  double* sC = sR + 16 * (T);                                   \
+  double* sL = sC + 4 * 16 * (T);                               \
+  double* sPv = sL + 256;                                       \
+  double* sX = sPv + 128;                                       \
+  int* sOrd = reinterpret_cast<int*>(sX + 32);                  \
+  int* sPiv = sOrd + 16 * (T);
+
 // The whole load step of macro point p on one workgroup.  SPLIT 0: the four
-// waves split the ECM points of a chunk; SPLIT 1: they split the tiles.
+// waves split the ECM points of a chunk; SPLIT 1: they split the tiles.  With
+// a.resume the point starts at evaluation phi[0] of attempt 0 from the trial
+// r in rt (the state left by the phased launches; phi[0] = 0: from the start).
 template <int T, int PREC, int SPLIT>
 __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
   constexpr int NPAD = 16 * T;
   constexpr int LD = ldk<T>();
-  constexpr int NT = T * (T + 1) / 2;
-  constexpr int MAT = main_doubles<T>();
-  double* sQ = smem;              // [FCH][QS] chunk records
-  double* sK = smem;              // [NPAD][LD] [K | f | C] (after the contraction)
-  double* sR = smem + MAT;        // [NPAD] current r
-  double* sC = sR + NPAD;         // [NPAD][4] C of the evaluation
-  double* sL = sC + 4 * NPAD;     // [2][128] pivot columns of the elimination
-  double* sPv = sL + 256;         // [128] pivot value of each row
-  double* sX = sPv + 128;         // [32] reductions and the load-step ends
-  int* sOrd = reinterpret_cast<int*>(sX + 32);  // [NPAD] pivot row of each step
-  int* sPiv = sOrd + NPAD;                      // [2] pivot exchange
+  ROM_SOLVE_LDS(T, smem, main_doubles<T>())
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = a.n, m = a.m;
   if (a.active && !a.active[p]) return;  // skipped: state and outputs untouched
   if (!a.muok[p]) {
-    if (tid < 4) a.Pbar[4 * (size_t)p + tid] = __builtin_nan("");
-    if (tid < 16) a.Abar[16 * (size_t)p + tid] = __builtin_nan("");
-    if (tid == 0) {
-      a.st_out[p] = ROM_ST_BADMU;
-      a.it_out[p] = 0;
-      a.res_out[p] = __builtin_nan("");
-    }
+    bad_mu_outputs(a, p, tid);
     return;
   }
-  // initial guess: the committed r, plus the predicted increment with a warm start
+  int it0 = 0;
+  bool fell_back = false;
+  double rn = 0.0, rn0 = 0.0;
+  if (a.resume) {
+    // per-point values, the same on every lane
+    it0 = __builtin_amdgcn_readfirstlane(a.phi[2 * (size_t)p]);
+    fell_back = __builtin_amdgcn_readfirstlane(a.phi[2 * (size_t)p + 1]) != 0;
+    rn0 = a.phd[2 * (size_t)p];
+  }
+  // initial guess: the committed r, plus the predicted increment with a warm
+  // start (resumed: the trial r reached)
   for (int i = tid; i < NPAD; i += 256) {
     double v = 0.0;
     if (i < n) {
-      v = a.rc[(size_t)p * n + i];
-      if (a.dr) v += (double)a.dr[(size_t)p * n + i];
-      a.rg[(size_t)p * n + i] = v;
+      if (it0 > 0) {
+        v = a.rt[(size_t)p * n + i];
+      } else {
+        v = a.rc[(size_t)p * n + i];
+        if (a.dr) v += (double)a.dr[(size_t)p * n + i];
+        a.rg[(size_t)p * n + i] = v;
+      }
     }
     sR[i] = v;
   }
@@ -657,164 +927,31 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
   __syncthreads();
 
   int status = ROM_ST_MAXITER, iters = 0;
-  double rn = 0.0, rn0 = 0.0;
-  bool fell_back = false;
   for (int attempt = 0;; ++attempt) {
-    for (int it = 0; it < a.max_iter; ++it) {
-      constexpr bool QSPLIT = (SPLIT == 0);             // waves split the points (else the tiles)
-      constexpr int NACC = QSPLIT ? NT : split_tiles<T>();  // large n: waves split the column tiles
-      typedef typename Acc<PREC>::type AccV;
-      AccV acc[NACC];
-#pragma unroll
-      for (int t = 0; t < NACC; ++t) acc[t] = (AccV){0, 0, 0, 0};
-      double fpart[T];  // FP64 residual partials of the reduced-precision forms
-#pragma unroll
-      for (int J = 0; J < T; ++J) fpart[J] = 0.0;
-      double accP[4] = {0.0, 0.0, 0.0, 0.0};  // FP64 sum w|J| P of the reduced-precision forms
-
+    for (int it = (attempt == 0) ? it0 : 0; it < a.max_iter; ++it) {
+      EvalAcc<T, PREC, SPLIT> E;
+      E.zero();
       for (int q0 = 0; q0 < m; q0 += FCH) {
         const int q = q0 + tid;
         if (q < m) {
-          const double Fi[4] = {tmu[q], tmu[m + q], tmu[2 * m + q], tmu[3 * m + q]};
-          const double wJ = tmu[4 * m + q];
-          double F[4];
-          kinematics(n, m, q, a.Gt, sR, Fb, Fi, F);
-          const double Fp[4] = {hc[q], hc[m + q], hc[2 * m + q], hc[3 * m + q]};
-          double P[4], Fpn[4], Fp33n, xin;
-          double* rec = sQ + tid * QS;
-          // D = w|J| T^T A T, accumulated column v = (k, l) of A at a time:
-          // E[.][v] = w|J| T^T A[.][v], D[b][(k, s)] += E[b][(k, l)] F_mu^-1[s][l]
-          double D[16];
-#pragma unroll
-          for (int k = 0; k < 16; ++k) D[k] = 0.0;
-          j2_point_cols<true>(F, Fp, hc[4 * m + q], hc[5 * m + q], a.mp, P, Fpn, Fp33n, xin,
-                              [&](int v, double c0, double c1, double c2, double c3) {
-                                const double e0 = wJ * (Fi[0] * c0 + Fi[1] * c1);
-                                const double e1 = wJ * (Fi[2] * c0 + Fi[3] * c1);
-                                const double e2 = wJ * (Fi[0] * c2 + Fi[1] * c3);
-                                const double e3 = wJ * (Fi[2] * c2 + Fi[3] * c3);
-                                const int k = v >> 1, l = v & 1;
-#pragma unroll
-                                for (int s2 = 0; s2 < 2; ++s2) {
-                                  const double t = Fi[2 * s2 + l];
-                                  D[0 + 2 * k + s2] = fma(e0, t, D[0 + 2 * k + s2]);
-                                  D[4 + 2 * k + s2] = fma(e1, t, D[4 + 2 * k + s2]);
-                                  D[8 + 2 * k + s2] = fma(e2, t, D[8 + 2 * k + s2]);
-                                  D[12 + 2 * k + s2] = fma(e3, t, D[12 + 2 * k + s2]);
-                                }
-                              });
-          if constexpr (PREC == PREC_BF16) {
-            float* rf = reinterpret_cast<float*>(rec + R_D);
-#pragma unroll
-            for (int k = 0; k < 16; ++k) rf[k] = (float)D[k];
-          } else {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) rec[R_D + k] = D[k];
-          }
-          ht[q] = Fpn[0];
-          ht[m + q] = Fpn[1];
-          ht[2 * m + q] = Fpn[2];
-          ht[3 * m + q] = Fpn[3];
-          ht[4 * m + q] = Fp33n;
-          ht[5 * m + q] = xin;
-          // W = w|J| P F_mu^-T
-          rec[R_W] = wJ * (P[0] * Fi[0] + P[1] * Fi[1]);
-          rec[R_W + 1] = wJ * (P[0] * Fi[2] + P[1] * Fi[3]);
-          rec[R_W + 2] = wJ * (P[2] * Fi[0] + P[3] * Fi[1]);
-          rec[R_W + 3] = wJ * (P[2] * Fi[2] + P[3] * Fi[3]);
-          const double idet = 1.0 / (Fi[0] * Fi[3] - Fi[1] * Fi[2]);
-          rec[R_FM] = Fi[3] * idet;
-          rec[R_FM + 1] = -Fi[1] * idet;
-          rec[R_FM + 2] = -Fi[2] * idet;
-          rec[R_FM + 3] = Fi[0] * idet;
+          double P[4], wJ;
+          point_record<PREC>(n, m, q, a.Gt, sR, Fb, tmu, hc, ht, a.mp, sQ + tid * QS, 1, P, wJ);
           if constexpr (PREC != PREC_F64) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) accP[k] = fma(wJ, P[k], accP[k]);
+            for (int k = 0; k < 4; ++k) E.accP[k] = fma(wJ, P[k], E.accP[k]);
           }
         }
         __syncthreads();
-        // contraction of the chunk; the points are shared evenly by the waves
+        // contraction in chunks of CCH points, as the phased kernel makes it
         const int qend = min(FCH, m - q0);
-        if constexpr (QSPLIT) {
-          const int qa = (wave * qend) >> 2, qb = ((wave + 1) * qend) >> 2;
-          contract_any<T, PREC, 0, 1>(acc, fpart, true, a.Gq, sQ, q0, qa, qb, pd, n, k_row, c_col);
-        } else {
-          switch (wave) {
-            case 0: contract_any<T, PREC, 0, 4>(acc, fpart, true, a.Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
-            case 1: contract_any<T, PREC, 1, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
-            case 2: contract_any<T, PREC, 2, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
-            default: contract_any<T, PREC, 3, 4>(acc, fpart, false, a.Gq, sQ, q0, 0, qend, pd, n, k_row, c_col); break;
-          }
-        }
+        for (int c0 = 0; c0 < qend; c0 += CCH)
+          contract_chunk<T, PREC, SPLIT>(E, a.Gq, sQ + c0 * QS, q0 + c0, min(CCH, qend - c0), pd, n, wave, k_row,
+                                         c_col);
         __syncthreads();
       }
-      // [K | f | C] and the padding rows into LDS; K's lower part by symmetry
-      if constexpr (QSPLIT) {
-        for (int w = 0; w < 4; ++w) {
-          if (wave == w) store_acc<T, PREC, 0, 1>(acc, sK, w > 0, w == 3, k_row, c_col);
-          __syncthreads();
-        }
-      } else {
-        switch (wave) {
-          case 0: store_acc<T, PREC, 0, 4>(acc, sK, false, true, k_row, c_col); break;
-          case 1: store_acc<T, PREC, 1, 4>(acc, sK, false, true, k_row, c_col); break;
-          case 2: store_acc<T, PREC, 2, 4>(acc, sK, false, true, k_row, c_col); break;
-          default: store_acc<T, PREC, 3, 4>(acc, sK, false, true, k_row, c_col); break;
-        }
-        __syncthreads();
-      }
-      if constexpr (PREC != PREC_F64) {
-        // f and sum w|J| P in FP64: over the lane groups and the waves in a fixed order
-        double* sFp = sC;  // [4][NPAD] wave partials of f, before C is copied
-#pragma unroll
-        for (int J = 0; J < T; ++J) {
-          double v = fpart[J];
-          v += __shfl_xor(v, 16);
-          v += __shfl_xor(v, 32);
-          if (k_row == 0) sFp[wave * NPAD + 16 * J + c_col] = v;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          double v = accP[k];
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-          if (lane == 0) sX[4 * k + wave] = v;
-        }
-        __syncthreads();
-        if (tid < n) {
-          const double v = QSPLIT ? ((sFp[tid] + sFp[NPAD + tid]) + sFp[2 * NPAD + tid]) + sFp[3 * NPAD + tid]
-                                  : sFp[tid];
-          sK[tid * LD + n] = v;
-        }
-        if (tid < 4) sK[(n + tid) * LD + n] = ((sX[4 * tid] + sX[4 * tid + 1]) + sX[4 * tid + 2]) + sX[4 * tid + 3];
-        __syncthreads();
-      }
-      // C of this evaluation (kept for Abar), ||f||_2
-      for (int idx = tid; idx < 4 * n; idx += 256) sC[idx] = sK[(idx >> 2) * LD + n + 1 + (idx & 3)];
-      double part = 0.0;
-      if (tid < n) {
-        const double fv = sK[tid * LD + n];
-        part = fv * fv;
-      }
-      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-      if (lane == 0) sX[wave] = part;
-      __syncthreads();
-      rn = sqrt(sX[0] + sX[1] + sX[2] + sX[3]);
+      rn = assemble<T, PREC, SPLIT>(E, sK, sC, sX, n, tid, lane, wave, k_row, c_col);
       iters = it + 1;
-      const bool last = (it == a.max_iter - 1);
-      bool stop;
-      if (!isfinite(rn)) {
-        stop = true;
-        status = ROM_ST_NONFINITE;
-      } else if (a.fixed) {
-        stop = last;
-        status = (rn <= a.tol) ? ROM_ST_CONVERGED : ROM_ST_MAXITER;
-      } else if (rn <= a.tol) {
-        stop = true;
-        status = ROM_ST_CONVERGED;
-      } else {
-        stop = last;
-        status = ROM_ST_MAXITER;
-      }
+      bool stop = eval_status(a, it, rn, status);
       if (it == 0) rn0 = rn;
       // warm start judged by plain Newton: no tenfold drop of ||f|| after two
       // updates -> restart from the committed r
@@ -827,20 +964,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
       // K x = [f | C]: the Newton update and K^-1 C
       gauss_jordan<T>(sK, n, sL, sPv, sOrd, sPiv);
       if (stop) {
-        // effective quantities at the returned state: Pbar = sum w|J| P,
-        // Abar = sum w|J| A - C^T K*^-1 C (per unit cell area)
-        if (tid < 20) {
-          const double inv_area = a.inv_area;
-          if (tid < 4) {
-            a.Pbar[4 * (size_t)p + tid] = sK[(n + tid) * LD + n] * inv_area;
-          } else {
-            const int e = tid - 4, x = e >> 2, y = e & 3;
-            double acc2 = sK[(n + x) * LD + n + 1 + y];
-            for (int i = 0; i < n; ++i) acc2 = fma(-sC[4 * i + x], sK[sOrd[i] * LD + n + 1 + y], acc2);
-            a.Abar[16 * (size_t)p + e] = acc2 * inv_area;
-          }
-        }
-        __syncthreads();
+        write_effective<T>(a, p, sK, sC, sOrd, n, tid);
         break;
       }
       if (tid < n) sR[tid] -= sK[sOrd[tid] * LD + n];
@@ -869,21 +993,100 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
     for (int k = 0; k < 4; ++k) Fb[k] = (t_next == full) ? sF1[k] : sF0[k] + frac * (sF1[k] - sF0[k]);
     __syncthreads();
   }
-  iters = total;
+  finish_point(a, p, sR, Fb, status, fell_back, total, rn, tid);
+}
 
-  for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i];
-  if (tid == 0) {
-    a.st_out[p] = (status == ROM_ST_CONVERGED && fell_back) ? ROM_ST_FALLBACK : status;
-    a.it_out[p] = iters;
-    a.res_out[p] = rn;
-  }
-  if (a.commit && status == ROM_ST_CONVERGED) {
-    if (tid < 4) a.fbc[4 * (size_t)p + tid] = Fb[tid];
-    for (int i = tid; i < n; i += 256) a.rc[(size_t)p * n + i] = sR[i];
-    double* hcw = a.hc + (size_t)p * 6 * m;
-    for (int q = tid; q < m; q += 256)
+// Phased form, contraction launch: one evaluation of each listed point from
+// the records of the material launch (same chunks and order as the fused
+// kernel, so the two forms agree bit for bit), then the elimination and the
+// Newton / status logic of attempt 0.  A point that stops is finished here;
+// one that goes on is listed for the next phased evaluation, or after ph_k
+// evaluations for the fused kernel; an attempt that fails with load-step
+// cutting on is handed to the fused kernel from its start.
+template <int T, int PREC, int SPLIT>
+__global__ __launch_bounds__(256) void k_ph_cs(const FusedArgs a) {
+  extern __shared__ double smem[];
+  constexpr int NPAD = 16 * T;
+  constexpr int LD = ldk<T>();
+  const int idx = blockIdx.x;
+  if (idx >= *a.cin) return;
+  const int p = a.lin[idx];
+  ROM_SOLVE_LDS(T, smem, cs_main_doubles<T>())
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = a.n, m = a.m;
+  for (int i = tid; i < NPAD; i += 256) sR[i] = (i < n) ? a.rt[(size_t)p * n + i] : 0.0;
+  const int it = __builtin_amdgcn_readfirstlane(a.phi[2 * (size_t)p]);
+  bool fell_back = __builtin_amdgcn_readfirstlane(a.phi[2 * (size_t)p + 1]) != 0;
+  double rn0 = a.phd[2 * (size_t)p];
+  const double rn_prev = a.phd[2 * (size_t)p + 1];
+  const double* rec = a.rec + (size_t)p * ROM_REC_ROWS * m;
+  const int k_row = lane >> 4, c_col = lane & 15;
+  const Pad pd = make_pad(n, k_row, c_col);
+
+  EvalAcc<T, PREC, SPLIT> E;
+  E.zero();
+  if constexpr (PREC != PREC_F64) {
+    // FP64 sum of w|J| P, lane tid over the points q = tid mod FCH (the fused kernel's order)
+    const double* tmu = a.tmu + (size_t)p * 5 * m;
+    for (int q = tid; q < m; q += FCH) {
+      const double wJ = tmu[4 * m + q];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) hcw[k * m + q] = ht[k * m + q];
+      for (int k = 0; k < 4; ++k) E.accP[k] = fma(wJ, rec[(size_t)(QS + k) * m + q], E.accP[k]);
+    }
+  }
+  for (int q0 = 0; q0 < m; q0 += CCH) {
+    const int qend = min(CCH, m - q0);
+    // records of the chunk into LDS: lane pair (tid, tid + 128) splits a point's record
+    const int j = tid & (CCH - 1), kh = tid / CCH;
+    if (j < qend) {
+      double v[QS / 2];
+#pragma unroll
+      for (int k = 0; k < QS / 2; ++k) v[k] = rec[(size_t)(kh * (QS / 2) + k) * m + q0 + j];
+#pragma unroll
+      for (int k = 0; k < QS / 2; ++k) sQ[j * QS + kh * (QS / 2) + k] = v[k];
+    }
+    __syncthreads();
+    contract_chunk<T, PREC, SPLIT>(E, a.Gq, sQ, q0, qend, pd, n, wave, k_row, c_col);
+    __syncthreads();
+  }
+  const double rn = assemble<T, PREC, SPLIT>(E, sK, sC, sX, n, tid, lane, wave, k_row, c_col);
+  int status;
+  const bool stop = eval_status(a, it, rn, status);
+  if (it == 0) rn0 = rn;
+  int next = it + 1;
+  if (!stop && a.dr && !fell_back && it == 2 && !(rn <= 0.1 * rn0)) {
+    // the warm start is dropped: the next evaluation starts from the committed r
+    fell_back = true;
+    for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = a.rc[(size_t)p * n + i];
+  } else {
+    gauss_jordan<T>(sK, n, sL, sPv, sOrd, sPiv);
+    if (stop) {
+      if (status == ROM_ST_CONVERGED || a.max_sub == 0) {
+        write_effective<T>(a, p, sK, sC, sOrd, n, tid);
+        const double Fb[4] = {a.Fbar[4 * (size_t)p], a.Fbar[4 * (size_t)p + 1], a.Fbar[4 * (size_t)p + 2],
+                              a.Fbar[4 * (size_t)p + 3]};
+        finish_point(a, p, sR, Fb, status, fell_back, it + 1, rn, tid);
+        return;
+      }
+      next = 0;  // failed attempt: the fused kernel redoes the point with load-step cutting
+      fell_back = false;
+    } else {
+      for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i] - sK[sOrd[i] * LD + n];
+    }
+  }
+  if (tid == 0) {
+    a.phi[2 * (size_t)p] = next;
+    a.phi[2 * (size_t)p + 1] = fell_back ? 1 : 0;
+    a.phd[2 * (size_t)p] = rn0;
+    a.phd[2 * (size_t)p + 1] = rn;
+    // a point converging slowly at the early hand-over goes to the side stream
+    const bool slow = a.ph_early > 0 && next == a.ph_early && it > 0 && !(rn <= a.ph_slow * rn_prev);
+    if (next > 0 && next < a.ph_k && !slow)
+      a.lout[atomicAdd(a.cout, 1)] = p;
+    else if (slow)
+      a.early[atomicAdd(a.cearly, 1)] = p;
+    else
+      a.hand[atomicAdd(a.chand, 1)] = p;
   }
 }
 
@@ -956,7 +1159,34 @@ int setup_one() {
   const size_t lds = (size_t)lds_doubles<T>() * 8;
   int rc = set_lds(&k_fused<T, PREC, SPLIT>, lds);
   if (rc == ROM_OK) rc = set_lds(&k_fused_queue<T, PREC, SPLIT>, lds);
+  if constexpr (16 * T <= ROM_PHASED_NPAD)
+    if (rc == ROM_OK) rc = set_lds(&k_ph_cs<T, PREC, SPLIT>, (size_t)cs_lds_doubles<T>() * 8);
   return rc;
+}
+
+template <int T, int PREC>
+int phased_cs_prec(const FusedArgs& a, int split, int P, hipStream_t s) {
+  if constexpr (16 * T > ROM_PHASED_NPAD) {
+    return ROM_EUNSUPPORTED;
+  } else {
+    const size_t lds = (size_t)cs_lds_doubles<T>() * 8;
+    bool done = false;
+    if constexpr (point_split_ok<T, PREC>()) {
+      if (split == 0) {
+        k_ph_cs<T, PREC, 0><<<P, 256, lds, s>>>(a);
+        done = true;
+      }
+    }
+    if (!done) k_ph_cs<T, PREC, 1><<<P, 256, lds, s>>>(a);
+    return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+  }
+}
+
+template <int T>
+int phased_cs(const FusedArgs& a, int prec, int split, int P, hipStream_t s) {
+  if (prec == ROM_DT_F64) return phased_cs_prec<T, PREC_F64>(a, split, P, s);
+  if (prec == ROM_DT_F32) return phased_cs_prec<T, PREC_F32>(a, split, P, s);
+  return phased_cs_prec<T, PREC_BF16>(a, split, P, s);
 }
 
 template <int T>
@@ -978,5 +1208,8 @@ int fused_setup() {
 #define ROM_FUSED_DEFINE(T)                                                                             \
   int rom_fused_launch_##T(const FusedArgs& a, int prec, int split, int grid, int P, hipStream_t s) { \
     return fused_launch<T>(a, prec, split, grid, P, s);                                                \
+  }                                                                                                    \
+  int rom_phased_cs_##T(const FusedArgs& a, int prec, int split, int P, hipStream_t s) {              \
+    return phased_cs<T>(a, prec, split, P, s);                                                         \
   }                                                                                                    \
   int rom_fused_setup_##T() { return fused_setup<T>(); }

@@ -1,0 +1,190 @@
+// Phased form of the online solve.  The first evaluations of the Newton
+// iteration (eq. red_newton) of every point of the batch run as two launches
+// each:
+//   material:    one lane per ECM point of every listed point (kinematics,
+//                return map, tangent and the contraction record of Appendix A
+//                and eqs. forcevector_ecm / stiffnessmatrix_ecm), the lanes
+//                packed across points;
+//   contraction: one workgroup per listed point (the MFMA contraction of the
+//                records, the elimination, the status and Newton update), a
+//                kernel with a register budget of its own.
+// After ph_k evaluations the points still running (and any attempt that
+// failed with load-step cutting on) are finished by the fused kernel as a
+// persistent grid, which resumes each point from the state left here.  Points
+// that converge slowly at evaluation ph_early (likely to fail the plain step
+// and be cut into sub-steps, a long chain of evaluations) are handed over
+// then, to a fused kernel on a side stream that runs beside the remaining
+// phased evaluations.  Where a point's evaluations run does not change them:
+// the results are the same bit for bit.  The list lengths stay on the device:
+// nothing is read back, and the sequence (a fork to the side stream and a
+// join) can be captured in a graph.
+#include <string.h>
+
+#include "rom_fused.h"
+#include "rom_fused_impl.h"
+
+namespace {
+
+constexpr int PH_RCAP = 2048;  // r values of the points one material workgroup touches
+constexpr int PH_EVALS = 6;    // phased evaluations (default)
+// early hand-over (default): after this many evaluations, points whose ||f||
+// fell by less than the factor PH_SLOW in the last update
+constexpr int PH_EARLY = 3;
+constexpr double PH_SLOW = 0.3;
+constexpr int PH_EARLY_GRID = 1;  // workgroups per compute unit of the side-stream fused kernel
+
+__global__ void k_zero6(int* __restrict__ c) {
+  if (threadIdx.x < 6) c[threadIdx.x] = 0;
+}
+
+// initial guess (committed r plus the predicted increment), the evaluation
+// state, and the list of the points taking part
+__global__ void k_ph_begin(const FusedArgs a, int P) {
+  const int n = a.n;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (long long)P * n) return;
+  const int p = (int)(g / n), i = (int)(g - (long long)p * n);
+  if (a.active && !a.active[p]) return;
+  if (!a.muok[p]) {
+    if (i == 0)
+      for (int k = 0; k < 16; ++k) bad_mu_outputs(a, p, k);
+    return;
+  }
+  double v = a.rc[(size_t)p * n + i];
+  if (a.dr) v += (double)a.dr[(size_t)p * n + i];
+  a.rg[(size_t)p * n + i] = v;
+  a.rt[(size_t)p * n + i] = v;
+  if (i == 0) {
+    a.phi[2 * (size_t)p] = 0;
+    a.phi[2 * (size_t)p + 1] = 0;
+    a.lout[atomicAdd(a.cout, 1)] = p;
+  }
+}
+
+// Material launch: lane g of the grid takes ECM point g mod m of list entry
+// g / m.  The r of the points a workgroup touches are staged in LDS.  Block 0
+// also clears the count of the list the following contraction launch fills.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_ph_mat(const FusedArgs a) {
+  __shared__ double sRr[PH_RCAP];
+  const int tid = threadIdx.x, n = a.n, m = a.m;
+  if (blockIdx.x == 0 && tid == 0) *a.cout = 0;
+  const long long cnt = *a.cin;
+  const long long g0 = (long long)blockIdx.x * 256, total = cnt * m;
+  if (g0 >= total) return;
+  const int i0 = (int)(g0 / m);
+  const int i1 = (int)min((g0 + 255) / m, cnt - 1);
+  for (int e = tid; e < (i1 - i0 + 1) * n; e += 256) {
+    const int k = e / n;
+    sRr[e] = a.rt[(size_t)a.lin[i0 + k] * n + (e - k * n)];
+  }
+  __syncthreads();
+  const long long g = g0 + tid;
+  if (g >= total) return;
+  const int idx = (int)(g / m), q = (int)(g - (long long)idx * m), p = a.lin[idx];
+  const double Fb[4] = {a.Fbar[4 * (size_t)p], a.Fbar[4 * (size_t)p + 1], a.Fbar[4 * (size_t)p + 2],
+                        a.Fbar[4 * (size_t)p + 3]};
+  double* rec = a.rec + (size_t)p * ROM_REC_ROWS * m + q;
+  double P[4], wJ;
+  point_record<PREC>(n, m, q, a.Gt, sRr + (idx - i0) * n, Fb, a.tmu + (size_t)p * 5 * m, a.hc + (size_t)p * 6 * m,
+                     a.ht + (size_t)p * 6 * m, a.mp, rec, m, P, wJ);
+  if constexpr (PREC != PREC_F64) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rec[(size_t)(QS + k) * m] = P[k];
+  }
+}
+
+int launch_mat(const FusedArgs& a, int prec, long long lanes, hipStream_t s) {
+  const unsigned int blocks = (unsigned int)((lanes + 255) / 256);
+  if (prec == ROM_DT_F64)
+    k_ph_mat<PREC_F64><<<blocks, 256, 0, s>>>(a);
+  else if (prec == ROM_DT_F32)
+    k_ph_mat<PREC_F32><<<blocks, 256, 0, s>>>(a);
+  else
+    k_ph_mat<PREC_BF16><<<blocks, 256, 0, s>>>(a);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+}  // namespace
+
+int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
+                           int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
+  if (h->npad > ROM_PHASED_NPAD) return ROM_EUNSUPPORTED;
+  if ((255 / h->m + 2) * h->n > PH_RCAP) return ROM_EUNSUPPORTED;
+  if ((long long)P * h->m > (1LL << 31) - 256) return ROM_EUNSUPPORTED;
+  const int kph = min(o.phased_evals > 0 ? o.phased_evals : PH_EVALS, o.max_iter);
+  if (kph < 1) return rom_launch_step_fused(h, P, Fbar, state, o, st_out, it_out, res_out, s);
+  FusedArgs a;
+  int split = 0;
+  int rc = rom_fused_prepare(h, P, Fbar, state, o, st_out, it_out, res_out, s, a, split);
+  if (rc != ROM_OK) return rc;
+  const StateLayout L = rom_state_layout(h, P);
+  // counts of list A, list B, the hand-over list, its queue head, the early list, its queue head
+  int* cnt = field<int>(state, L, F_COUNT) + 8;
+  int* listA = field<int>(state, L, F_LIST);
+  int* listB = field<int>(state, L, F_LIST2);
+  int* hand = field<int>(state, L, F_LIST3);
+  int* early = field<int>(state, L, F_LIST4);
+  a.ph_k = kph;
+  const int ke = o.phased_early == 0 ? PH_EARLY : o.phased_early;
+  a.ph_early = (ke > 1 && ke < kph) ? ke : 0;
+  a.ph_slow = PH_SLOW;
+  a.early = early;
+  a.cearly = cnt + 4;
+  a.rec = field<double>(state, L, F_REC);
+  a.phi = field<int>(state, L, F_PHI);
+  a.phd = field<double>(state, L, F_PHD);
+  a.hand = hand;
+  a.chand = cnt + 2;
+  const int T = rom_fused_tiles(h->n);
+  if (rom_timing_mark(h, 0, s) != ROM_OK) return ROM_EHIP;
+  k_zero6<<<1, 64, 0, s>>>(cnt);
+  {
+    FusedArgs b = a;
+    b.lout = listA;
+    b.cout = cnt;
+    k_ph_begin<<<(unsigned int)(((long long)P * h->n + 255) / 256), 256, 0, s>>>(b, P);
+  }
+  if (hipGetLastError() != hipSuccess) return ROM_EHIP;
+  bool forked = false;
+  for (int e = 0; e < kph && rc == ROM_OK; ++e) {
+    FusedArgs b = a;
+    b.lin = (e & 1) ? listB : listA;
+    b.cin = cnt + (e & 1);
+    b.lout = (e & 1) ? listA : listB;
+    b.cout = cnt + 1 - (e & 1);
+    rc = launch_mat(b, o.contraction, (long long)P * h->m, s);
+    if (rc == ROM_OK) rc = rom_phased_cs(T, b, o.contraction, split, P, s);
+    if (rc == ROM_OK && a.ph_early > 0 && e + 1 == a.ph_early) {
+      // fork: the early list to the fused kernel on the side stream
+      if (!h->aux) {
+        if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return ROM_EHIP;
+        if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess) return ROM_EHIP;
+        if (hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) return ROM_EHIP;
+      }
+      if (hipEventRecord(h->ev_fork, s) != hipSuccess) return ROM_EHIP;
+      if (hipStreamWaitEvent(h->aux, h->ev_fork, 0) != hipSuccess) return ROM_EHIP;
+      FusedArgs f = a;
+      f.resume = 1;
+      f.list = early;
+      f.nlist = cnt + 4;
+      f.counter = cnt + 5;
+      rc = rom_fused_launch(T, f, o.contraction, split, PH_EARLY_GRID * h->ncu, P, h->aux);
+      if (hipEventRecord(h->ev_join, h->aux) != hipSuccess) return ROM_EHIP;
+      forked = true;
+    }
+  }
+  if (rc == ROM_OK) {
+    FusedArgs f = a;
+    f.resume = 1;
+    f.list = hand;
+    f.nlist = cnt + 2;
+    f.counter = cnt + 3;
+    const int grid = (o.grid_per_cu > 0 ? o.grid_per_cu : 2) * h->ncu;
+    rc = rom_fused_launch(T, f, o.contraction, split, grid, P, s);
+  }
+  // join: the step ends when the side stream's points are done too
+  if (forked && hipStreamWaitEvent(s, h->ev_join, 0) != hipSuccess) return ROM_EHIP;
+  if (rom_timing_mark(h, 1, s) != ROM_OK) return ROM_EHIP;
+  return rc;
+}

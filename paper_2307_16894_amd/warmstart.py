@@ -117,6 +117,7 @@ class WarmStart:
         return hist
 
     def opts(self, **kw):
-        o = rom_default_opts(mode=MODE_FUSED, warm_start=WARM_MLP, **kw)
+        kw.setdefault('mode', MODE_FUSED)
+        o = rom_default_opts(warm_start=WARM_MLP, **kw)
         o.mlp = self.h.value
         return o

@@ -95,6 +95,32 @@ def test_plain_step_failures_keep_committed_state(gpu):
         assert [g[k]['status'][p] for k in range(K)] == [ref[k]['status'] for k in range(K)], p
 
 
+@pytest.mark.parametrize("dt", [L.DT_F64, L.DT_BF16])
+def test_phased_matches_fused_bitwise_full_size(gpu, dt):
+    """The phased form (material and contraction launches for the first
+    evaluations, the fused kernel resuming the rest) gives the fused form's
+    results bit for bit: same statuses (cut steps included), iteration counts,
+    residuals, r, history, Pbar and Abar."""
+    K = 6
+    mu, paths = inputs(W)
+    fu, ph = RomBatch(rom_path(W['rom']), mu), RomBatch(rom_path(W['rom']), mu)
+    for k in range(K):
+        print(f"[gpu] phased vs fused P={W['P']} contraction={dt} step {k}", flush=True)
+        Fb = torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda()
+        a = fu.step(Fb, L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt, max_substeps=4))
+        torch.cuda.synchronize()
+        b = ph.step(Fb, L.rom_default_opts(mode=L.MODE_PHASED, contraction=dt, max_substeps=4))
+        torch.cuda.synchronize()
+        for x, y in zip(a, b):
+            assert torch.equal(x, y), k
+        assert torch.equal(fu.Pbar, ph.Pbar) and torch.equal(fu.Abar, ph.Abar)
+        assert torch.equal(fu.r(), ph.r()) and torch.equal(fu.r(trial=True), ph.r(trial=True))
+        assert torch.equal(fu.history(), ph.history()) and torch.equal(fu.fbar_committed(), ph.fbar_committed())
+    print(f"iterations in the last step: mean {b[1].double().mean().item():.3f}, max {b[1].max().item()}")
+    fu.close()
+    ph.close()
+
+
 W4 = WORKLOADS['fourvoid_n100_m1500_P16384_cyclic20']
 SAMPLE4 = [0, 5461, 10922, W4['P'] - 1]
 

@@ -161,17 +161,26 @@ def test_warm_start_gain_and_fallback(gpu):
     print(f"mean Newton evaluations: plain {ip.mean():.3f}, learned warm start {im.mean():.3f}, "
           f"fallbacks {(sm == 3).mean():.4f}")
     assert im.mean() < ip.mean()
-    # a scrambled network: the fallback fires and the results still match plain Newton
+    # a scrambled network: the fallback fires and the results still match plain
+    # Newton; the phased form (fallback inside its phased evaluations) gives the
+    # fused form's results bit for bit
     L.rom_mlp_set_params(ws.h, 40.0 * init_params(X.shape[1], 256, Y.shape[1], 99))
     rb = RomBatch(rom_path(NAME), mu)
+    rp = RomBatch(rom_path(NAME), mu)
     fell = 0
     for k in range(K):
-        s_, i_, r_ = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), ws.opts())
+        Fb = torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda()
+        s_, i_, r_ = rb.step(Fb, ws.opts())
         torch.cuda.synchronize()
+        sp_, ip_, rp_ = rp.step(Fb, ws.opts(mode=L.MODE_PHASED))
+        torch.cuda.synchronize()
+        assert torch.equal(s_, sp_) and torch.equal(i_, ip_) and torch.equal(r_, rp_)
+        assert torch.equal(rb.Pbar, rp.Pbar) and torch.equal(rb.Abar, rp.Abar) and torch.equal(rb.r(), rp.r())
         s_ = s_.cpu().numpy()
         assert np.isin(s_, [0, 3]).all()
         fell += int((s_ == 3).sum())
         assert np.abs(rb.Pbar.cpu().numpy() - Pp[k]).max() < 1e-6 * np.abs(Pp).max()
     rb.close()
+    rp.close()
     assert fell > 0
     ws.close()

@@ -52,9 +52,15 @@ def _run_gpu(name, mu, paths, mode, max_iter, fixed, record_hist=True, **extra):
 
 
 # staged form; fused form with the automatic layout, with the tile split, and
-# launched as a persistent grid pulling points from the work list
+# launched as a persistent grid pulling points from the work list; phased form
+# (its evaluations, then the fused kernel resuming the points from their state)
 FORMS = {'staged': dict(mode=0), 'fused': dict(mode=1), 'fused_tilesplit': dict(mode=1, split=1),
-         'fused_queue': dict(mode=1, grid_per_cu=2), 'fused_tilesplit_queue': dict(mode=1, split=1, grid_per_cu=1)}
+         'fused_queue': dict(mode=1, grid_per_cu=2), 'fused_tilesplit_queue': dict(mode=1, split=1, grid_per_cu=1),
+         'phased': dict(mode=2), 'phased_tilesplit_k2': dict(mode=2, split=1, phased_evals=2),
+         # slow points after two evaluations to the side stream
+         'phased_early2': dict(mode=2, phased_evals=5, phased_early=2),
+         # every evaluation of the first attempt phased: a failed attempt is redone by the fused kernel
+         'phased_all': dict(mode=2, phased_evals=1000, phased_early=-1)}
 
 
 @pytest.mark.parametrize("form", sorted(FORMS))
@@ -87,7 +93,7 @@ def test_fixed_iteration_parity_onevoid_n20(gpu, form):
                 assert np.abs(gh[5]).max() == 0.0
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_converged_path_onevoid_n20(gpu, mode):
     """Plain Newton to 1e-8: every step converges, same iteration counts and
     effective stress as the oracle (to the Newton tolerance)."""
@@ -116,12 +122,12 @@ def test_active_mask_skips_points(gpu):
     mu = workloads.one_void_mu(5, P)
     paths = workloads.monotone_paths(5, P, 4)
     act = torch.tensor([(p % 3) != 1 for p in range(P)], dtype=torch.int32, device='cuda')
-    for grid in (0, 2):
+    for mode, grid in ((1, 0), (1, 2), (2, 0)):
         full, masked = RomBatch(rom_path(name), mu), RomBatch(rom_path(name), mu)
         for k in range(4):
-            print(f"[gpu] active mask grid={grid} step {k}", flush=True)
+            print(f"[gpu] active mask mode={mode} grid={grid} step {k}", flush=True)
             Fb = torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda()
-            o = L.rom_default_opts(mode=1, fixed_iters=1, max_iter=5, grid_per_cu=grid)
+            o = L.rom_default_opts(mode=mode, fixed_iters=1, max_iter=5, grid_per_cu=grid)
             full.step(Fb, o)
             torch.cuda.synchronize()  # the batches run on their own streams
             r_before = masked.r().clone()
@@ -139,7 +145,7 @@ def test_active_mask_skips_points(gpu):
         masked.close()
 
 
-@pytest.mark.parametrize("form", ['fused', 'fused_tilesplit_queue'])
+@pytest.mark.parametrize("form", ['fused', 'fused_tilesplit_queue', 'phased', 'phased_early2', 'phased_all'])
 def test_load_step_cutting_parity(gpu, form):
     """Large increments from the virgin state, where the plain step fails:
     with cutting depth 4 (fixed evaluations per attempt, so both sides take
