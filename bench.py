@@ -37,13 +37,15 @@ WORKLOADS = {
     'onevoid_n40_m400_P4096_cyclic20': dict(rom='onevoid_n40_m400', cell='onevoid', P=4096, steps=20,
                                             path='cyclic', rho=(0.02, 0.08), seed=0, train_points=25000,
                                             train_seed=1, timed=20, warm=20,
-                                            variants=['fp64', 'fp64_staged', 'fp32', 'bf16', 'fp64_mlp',
-                                                      'fp32_mlp', 'bf16_mlp']),
+                                            variants=['fp64', 'fp64_phased', 'fp64_staged', 'fp32_phased', 'bf16',
+                                                      'bf16_phased', 'fp64_mlp_phased', 'fp32_mlp_phased',
+                                                      'bf16_mlp', 'bf16_mlp_phased']),
     # small case: n = 20, m = 120, 64 points, 10-step monotone paths
     'onevoid_n20_m120_P64_monotone10': dict(rom='onevoid_n20_m120', cell='onevoid', P=64, steps=10,
                                             path='monotone', rho=(0.02, 0.05), seed=0, train_points=4096,
                                             train_seed=1, timed=20, warm=20,
-                                            variants=['fp64', 'fp64_staged', 'fp32', 'bf16']),
+                                            variants=['fp64', 'fp64_phased', 'fp64_staged', 'fp32_phased',
+                                                      'bf16_phased']),
     # four elliptical voids (mu in R^8), n = 100 modes, m ~ 1500 ECM points,
     # 16384 points, 20-step load / unload paths: the reduced-precision contraction
     'fourvoid_n100_m1500_P16384_cyclic20': dict(rom='fourvoid_n100_m1500', cell='fourvoid', P=16384, steps=20,
@@ -53,7 +55,8 @@ WORKLOADS = {
 # uneven persistent batch: several ROMs in one captured step, per-point step
 # counts U[5, 40], Newton cap 15 per step; the points are shared out by cost
 UNEVEN = {'uneven_mixed_P32768': dict(
-    roms=[('onevoid_n20_m120', 16384), ('onevoid_n40_m400', 12288), ('fourvoid_n100_m1500', 4096)],
+    roms=[('onevoid_n20_m120', 12288), ('onevoid_n40_m400', 10240), ('fourvoid_n60_m800', 6144),
+          ('fourvoid_n100_m1500', 2048), ('fourvoid_n120_m2000', 2048)],
     steps=(5, 40), rho=(0.01, 0.04), seed=0, max_iter=15, tune_points=1024)}
 DEFAULT = 'onevoid_n40_m400_P4096_cyclic20'
 VARIANTS = WORKLOADS[DEFAULT]['variants']
@@ -122,7 +125,9 @@ def gpu_run(w, steps, warmup, opts, rom_file):
         return rec
 
     L.rom_state_init(rb.h, P, rb.mu.data_ptr(), rb.state.data_ptr(), rb.stream.cuda_stream)
-    run(warmup, False)
+    # the warm-up records too, so that the timed steps find the memory of their
+    # device-side copies in torch's cache instead of allocating it
+    run(warmup, True)
     torch.cuda.synchronize()
     L.rom_state_init(rb.h, P, rb.mu.data_ptr(), rb.state.data_ptr(), rb.stream.cuda_stream)
     L.rom_timing_enable(rb.h, True)
@@ -193,11 +198,13 @@ def uneven_main(a, log):
         paths = workloads.uneven_cyclic_paths(seed, P, ns, u['rho'])
         rom_file = os.path.join(ROOT, 'roms', name + '.rom')
         tp = min(P, u['tune_points'])
-        t = autotune.tune(rom_file, mu[:tp], paths[:tp, 0], L.DT_F64, reps=2)
-        tuned[name] = dict(n=t['n'], m=t['m'], split=t['split'], grid_per_cu=t['grid_per_cu'], trials_ms=t['trials'])
-        log(f"[bench] {name}: P={P}, n={t['n']}, m={t['m']}, tuned split={t['split']} grid_per_cu={t['grid_per_cu']}")
+        t = autotune.tune(rom_file, mu[:tp], paths[:tp, 0], L.DT_F64, reps=2, graph=True)
+        tuned[name] = dict(n=t['n'], m=t['m'], mode={L.MODE_FUSED: 'fused', L.MODE_PHASED: 'phased'}[t['mode']],
+                           split=t['split'], grid_per_cu=t['grid_per_cu'], trials_ms=t['trials'])
+        log(f"[bench] {name}: P={P}, n={t['n']}, m={t['m']}, tuned {tuned[name]['mode']} split={t['split']} "
+            f"grid_per_cu={t['grid_per_cu']}")
         groups.append(Group(rom_file, mu, paths, ns, split=t['split'], grid_per_cu=t['grid_per_cu'],
-                            max_iter=u['max_iter'], max_substeps=SUBSTEPS))
+                            max_iter=u['max_iter'], max_substeps=SUBSTEPS, mode=t['mode']))
     ub = UnevenBatch(groups)
     ub.capture()
     K = ub.max_steps
@@ -227,22 +234,24 @@ def uneven_main(a, log):
 
 
 def kernel_source_digest():
-    """SHA-256 over the sources of the fused kernel (a recorded traffic
-    measurement is reported only while they are unchanged)."""
+    """SHA-256 over the sources of the fused and phased kernels (a recorded
+    traffic measurement is reported only while they are unchanged)."""
     import hashlib
     csrc = os.path.join(ROOT, 'paper_2307_16894_amd', 'csrc')
     h = hashlib.sha256()
     for f in sorted(os.listdir(csrc)):
-        if f.startswith('rom_fused') or f in ('j2_device.h', 'rom_common.h'):
+        if f.startswith(('rom_fused', 'rom_phased')) or f in ('j2_device.h', 'rom_common.h'):
             with open(os.path.join(csrc, f), 'rb') as fh:
                 h.update(f.encode() + b'\0' + fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload, launches):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or None."""
-    path = os.path.join(ROOT, 'profiles', f'k_fused_fp64_{workload}_traffic.json')
+def measured_traffic(workload, form):
+    """HBM bytes per timed unit (fused form: one kernel launch; phased form:
+    the launches of one step) from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a copy of known size), or None."""
+    name = 'k_fused_fp64' if form == 'fused' else 'phased_fp64'
+    path = os.path.join(ROOT, 'profiles', f'{name}_{workload}_traffic.json')
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -333,16 +342,22 @@ def main(argv=None):
     # form) of highest throughput whose Pbar stays within PBAR_TOL of plain FP64
     def admitted(v):
         return v in out_var and out_var[v].get('max_rel_diff_Pbar_vs_fp64_step1', 1.0) <= PBAR_TOL
-    cands = [v for v in ('fp32_mlp', 'bf16_mlp') if admitted(v)] or [v for v in ('fp32', 'bf16') if admitted(v)]
+    reduced = [v for v in out_var if v.split('_')[0] in ('fp32', 'bf16')]
+    cands = [v for v in reduced if '_mlp' in v and admitted(v)] or [v for v in reduced if admitted(v)]
     head = max(cands, key=lambda v: out_var[v]['value']) if cands else ('fp64' if 'fp64' in out_var else variants[0])
-    g = res[head]
+    # plain FP64 Newton: the faster of its fused and phased executions (the same
+    # arithmetic, the same results bit for bit)
+    plain = [v for v in ('fp64', 'fp64_phased') if v in out_var]
+    plain_best = max(plain, key=lambda v: out_var[v]['value']) if plain else None
     # dominant work, per point-evaluation and ECM point: the reduced tangent
     # K = sum_q G_q^T (D_q G_q) (8 n^2 + 32 n), the residual f = sum_q G_q^T W_q
     # (8 n), the tangent right-hand sides C = sum_q G_q^T E_q (32 n) and the
     # kinematics sum_i r_i G_i(q) (8 n): m (8 n^2 + 80 n) flops.  The return map
-    # and the n x n solve are not counted.  (FP64 form: the fused kernel, all of
-    # Newton; measured on the plain FP64 run.)
-    rf = res.get('fp64', g)
+    # and the n x n solve are not counted.  Measured on the plain FP64 run over
+    # all kernels of its steps (fused form: the one kernel; phased form: the
+    # material, contraction and fused-finish launches).
+    rf = res[plain_best] if plain_best else res[head]
+    rf_form = 'phased' if (plain_best or '').endswith('_phased') else 'fused'
     flops_per_eval = m * (8.0 * n * n + 80.0 * n)
     achieved = flops_per_eval * rf['evals'] / (rf['kern_ms'] * 1e-3) / 1e12 if rf['kern_ms'] > 0 else 0.0
     out = dict(
@@ -353,15 +368,18 @@ def main(argv=None):
         data="synthetic",
         config=dict(workload=a.workload, rom=w['rom'], n=n, m=m, batch=P, load_steps=w['steps'], tol=1e-8,
                     form=head, contraction=head.split('_')[0], warm_start=head.endswith('_mlp')),
-        plain_fp64=out_var.get('fp64'),
-        speedup_vs_plain_fp64=(out_var[head]['value'] / out_var['fp64']['value']) if 'fp64' in out_var else None,
+        plain_fp64=dict(out_var[plain_best], form=plain_best) if plain_best else None,
+        speedup_vs_plain_fp64=(out_var[head]['value'] / out_var[plain_best]['value']) if plain_best else None,
         head_rule=f"learned+reduced-precision form (else reduced-precision form) of highest throughput with "
                   f"max |Pbar - Pbar_fp64| / max |Pbar_fp64| <= {PBAR_TOL:g} on the first load step",
         variants=out_var,
         warm_start=wsinfo,
-        roofline=dict(bound="mfma", kernel="k_fused<fp64>", achieved=achieved, peak=PEAK_FP64_TFLOPS,
+        roofline=dict(bound="mfma",
+                      kernel=("k_fused<fp64>" if rf_form == 'fused' else
+                              "phased step <fp64>: k_ph_mat + k_ph_cs + k_fused_queue"),
+                      achieved=achieved, peak=PEAK_FP64_TFLOPS,
                       unit="TFLOP/s", frac=achieved / PEAK_FP64_TFLOPS,
-                      traffic=measured_traffic(a.workload, rf['launches']),
+                      traffic=measured_traffic(a.workload, rf_form),
                       launches=rf['launches'], avg_launch_ms=rf['kern_ms'] / max(rf['launches'], 1),
                       flops_per_point_eval=flops_per_eval, point_evals=rf['evals']),
     )

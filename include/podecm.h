@@ -65,7 +65,8 @@ extern "C" {
 #define ROM_MODE_PHASED 2  /* the first Newton evaluations of every point as a material launch (one lane per
                               ECM point of every point) and a contraction + elimination launch each, the points
                               still running after them finished by the fused kernel from where they stand
-                              (n <= 75); same arithmetic, and bit for bit the same results, as ROM_MODE_FUSED */
+                              (n <= 75); same arithmetic, and bit for bit the same results, as ROM_MODE_FUSED.
+                              Eager launches only: inside a stream capture rom_step returns ROM_EUNSUPPORTED */
 
 /* initial guess of the Newton iteration */
 #define ROM_WARM_PREV 0  /* the committed r (plain guess) */

@@ -1,35 +1,44 @@
-"""Autotuner of the fused kernel's configuration per ROM size (n, m).
+"""Autotuner of the solve's configuration per ROM size (n, m).
 
-Candidates: how the four waves of a workgroup share the contraction (split
-the ECM points, or the tiles of K; the point split keeps every tile in
-registers: FP64 for n <= 75, the reduced forms for n <= 123), and the launch form (one workgroup per
-point, or a persistent grid of k workgroups per compute unit pulling points
-from a work list).  Each candidate is timed with HIP events on the same
-sample load step from the same state; the fastest is kept in a table keyed by
-(n, m, contraction) that can be saved as JSON.
+Candidates: the execution form (fused: the whole Newton loop in one kernel,
+launched with one workgroup per point or as a persistent grid of k
+workgroups per compute unit pulling points from a work list; phased, n <= 75:
+the first evaluations as separate material and contraction launches), and
+how the four waves of a workgroup share the contraction (split the ECM
+points, or the tiles of K; the point split keeps every tile in registers:
+FP64 for n <= 75, the reduced forms for n <= 123).  Each candidate is timed
+with HIP events on the same sample load step from the same state; the
+fastest is kept in a table keyed by (n, m, contraction) that can be saved as
+JSON.
 """
 import json
 
 import numpy as np
 import torch
 
-from . import (DT_F64, MODE_FUSED, rom_default_opts, rom_homogenized_stress_tangent, rom_state_init, rom_step,
-               rom_fused_tiles)
+from . import (DT_F64, MODE_FUSED, MODE_PHASED, rom_default_opts, rom_homogenized_stress_tangent, rom_state_init,
+               rom_step, rom_fused_tiles)
 from .batch import RomBatch
 
 GRIDS = (0, 1, 2, 4)
 
 
-def candidates(n, contraction=DT_F64):
-    """Point split (FP64 up to five column tiles, reduced forms up to eight)
-    and tile split, each with every launch form."""
-    splits = (0, 1) if (rom_fused_tiles(n) <= 5 or contraction != DT_F64) else (1,)
-    return [(s, g) for s in splits for g in GRIDS]
+def candidates(n, contraction=DT_F64, graph=False):
+    """(mode, split, grid_per_cu): point split (FP64 up to five column tiles,
+    reduced forms up to eight) and tile split, each with every launch form of
+    the fused kernel, and the phased form up to five column tiles (not for
+    steps captured in a graph, which it does not support)."""
+    T = rom_fused_tiles(n)
+    splits = (0, 1) if (T <= 5 or contraction != DT_F64) else (1,)
+    out = [(MODE_FUSED, s, g) for s in splits for g in GRIDS]
+    if T <= 5 and not graph:
+        out += [(MODE_PHASED, s, 2) for s in splits]
+    return out
 
 
-def time_config(rb, Fb, contraction, split, grid, reps=3, warm=1):
+def time_config(rb, Fb, contraction, mode, split, grid, reps=3, warm=1):
     s = rb.stream
-    o = rom_default_opts(mode=MODE_FUSED, contraction=contraction, split=split, grid_per_cu=grid)
+    o = rom_default_opts(mode=mode, contraction=contraction, split=split, grid_per_cu=grid)
     best = np.inf
     for r in range(warm + reps):
         rom_state_init(rb.h, rb.P, rb.mu.data_ptr(), rb.state.data_ptr(), s.cuda_stream)
@@ -44,18 +53,19 @@ def time_config(rb, Fb, contraction, split, grid, reps=3, warm=1):
     return best
 
 
-def tune(rom_path, mu, Fbar, contraction, reps=3):
-    """Time every candidate on one load step of the batch (mu, Fbar (P, 2, 2))."""
+def tune(rom_path, mu, Fbar, contraction, reps=3, graph=False):
+    """Time every candidate on one load step of the batch (mu, Fbar (P, 2, 2));
+    graph: only the configurations that can be captured in a graph."""
     rb = RomBatch(rom_path, mu)
     Fb = torch.as_tensor(np.ascontiguousarray(Fbar), dtype=torch.float64).reshape(rb.P, 4).to(rb.device)
     n, m = rb.info['n'], rb.info['m']
     times = {}
-    for split, grid in candidates(n, contraction):
-        times[(split, grid)] = time_config(rb, Fb, contraction, split, grid, reps)
+    for cfg in candidates(n, contraction, graph):
+        times[cfg] = time_config(rb, Fb, contraction, *cfg, reps=reps)
     rb.close()
     best = min(times, key=times.get)
-    return dict(n=n, m=m, contraction=contraction, split=best[0], grid_per_cu=best[1], ms=times[best],
-                trials={f"split{s}_grid{g}": t for (s, g), t in times.items()})
+    return dict(n=n, m=m, contraction=contraction, mode=best[0], split=best[1], grid_per_cu=best[2],
+                ms=times[best], trials={f"mode{md}_split{s}_grid{g}": t for (md, s, g), t in times.items()})
 
 
 class Table:

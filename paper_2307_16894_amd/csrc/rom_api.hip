@@ -46,9 +46,9 @@ void release(rom_model* h) {
   if (h->aux) {
     (void)hipStreamSynchronize(h->aux);
     (void)hipStreamDestroy(h->aux);
-    (void)hipEventDestroy(h->ev_fork);
-    (void)hipEventDestroy(h->ev_join);
   }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   (void)hipFree(h->w);
   (void)hipFree(h->Gt);
   (void)hipFree(h->Gq);
@@ -201,6 +201,11 @@ int rom_load(const void* blob, size_t bytes, int device, rom_handle* out) {
   if (rc == ROM_OK) rc = upload(&h->Gq16, Gq16);
   if (rc == ROM_OK) rc = rom_staged_setup();
   if (rc == ROM_OK) rc = rom_fused_setup();
+  // side stream and events of the phased form (created here, not inside a
+  // caller's graph capture)
+  if (rc == ROM_OK && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) rc = ROM_EHIP;
+  if (rc == ROM_OK && hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess) rc = ROM_EHIP;
+  if (rc == ROM_OK && hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) rc = ROM_EHIP;
   if (rc != ROM_OK) {
     release(h);
     return rc;

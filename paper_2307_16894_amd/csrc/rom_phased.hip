@@ -16,8 +16,8 @@
 // then, to a fused kernel on a side stream that runs beside the remaining
 // phased evaluations.  Where a point's evaluations run does not change them:
 // the results are the same bit for bit.  The list lengths stay on the device:
-// nothing is read back, and the sequence (a fork to the side stream and a
-// join) can be captured in a graph.
+// nothing is read back.  The step is launched eagerly (not inside a graph
+// capture, which it refuses).
 #include <string.h>
 
 #include "rom_fused.h"
@@ -110,6 +110,12 @@ int launch_mat(const FusedArgs& a, int prec, long long lanes, hipStream_t s) {
 int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
                            int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
   if (h->npad > ROM_PHASED_NPAD) return ROM_EUNSUPPORTED;
+  // eager launches only: a graph capture of the step with its side-stream fork
+  // and join has crashed the runtime's end of capture (host side), so the
+  // phased form refuses capture
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) return ROM_EHIP;
+  if (cap != hipStreamCaptureStatusNone) return ROM_EUNSUPPORTED;
   if ((255 / h->m + 2) * h->n > PH_RCAP) return ROM_EUNSUPPORTED;
   if ((long long)P * h->m > (1LL << 31) - 256) return ROM_EUNSUPPORTED;
   const int kph = min(o.phased_evals > 0 ? o.phased_evals : PH_EVALS, o.max_iter);
@@ -157,11 +163,6 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
     if (rc == ROM_OK) rc = rom_phased_cs(T, b, o.contraction, split, P, s);
     if (rc == ROM_OK && a.ph_early > 0 && e + 1 == a.ph_early) {
       // fork: the early list to the fused kernel on the side stream
-      if (!h->aux) {
-        if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) return ROM_EHIP;
-        if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess) return ROM_EHIP;
-        if (hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) return ROM_EHIP;
-      }
       if (hipEventRecord(h->ev_fork, s) != hipSuccess) return ROM_EHIP;
       if (hipStreamWaitEvent(h->aux, h->ev_fork, 0) != hipSuccess) return ROM_EHIP;
       FusedArgs f = a;

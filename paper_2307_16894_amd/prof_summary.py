@@ -4,11 +4,14 @@
     python -m paper_2307_16894_amd.prof_summary traffic FETCH_CSV WRITE_CSV OUT_PREFIX \\
         --workload W --copy-mib N --command-fetch "..." --command-write "..."
 
-`stats` keeps the kernel table of a --kernel-trace --stats run.  `traffic`
-takes the FETCH_SIZE and WRITE_SIZE counter runs (KiB per dispatch), scales
-each by the reading of the same counter for the calibration copy of known
-size (bench.py --calibrate-copy), and writes the HBM bytes per launch of the
-fused FP64 kernel together with the digest of its sources.
+`stats` keeps the kernel table of a --kernel-trace --stats run (with
+--unit-kernel K also the summed duration per call of K, e.g. per phased step).
+`traffic` takes the FETCH_SIZE and WRITE_SIZE counter runs (KiB per
+dispatch), scales each by the reading of the same counter for the calibration
+copy of known size (bench.py --calibrate-copy), and writes the HBM bytes per
+launch of the kernel (--kernel: comma-separated name parts; with --unit-kernel
+the bytes of all matching dispatches per call of that kernel, e.g. per phased
+step) together with the digest of the kernel sources.
 """
 import argparse
 import csv
@@ -37,6 +40,14 @@ def stats(args):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                      f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / total:.1f}% |")
+    if args.unit_kernel:
+        units = sum(int(r['Calls']) for r in rows if args.unit_kernel in r['Name'])
+        parts = [k for k in args.kernels.split(',') if k] if args.kernels else None
+        sel = [r for r in rows if parts is None or any(k in r['Name'] for k in parts)]
+        if units:
+            tot = sum(float(r['TotalDurationNs']) for r in sel)
+            lines += ["", f"Per call of `{args.unit_kernel}` ({units} calls): {tot / units / 1e3:.1f} us of "
+                      f"{'the kernels ' + ', '.join(parts) if parts else 'all kernels'}."]
     with open(args.out, 'w') as fh:
         fh.write('\n'.join(lines) + '\n')
 
@@ -52,8 +63,8 @@ def _per_dispatch(path, counter):
     return list(out.values())
 
 
-def _split(disp, kernel_sub, copy_sub):
-    ker = [v for name, v in disp if kernel_sub in name]
+def _split(disp, kernel_subs, copy_sub):
+    ker = [v for name, v in disp if any(k in name for k in kernel_subs)]
     cpy = [v for name, v in disp if copy_sub in name]
     if not ker or not cpy:
         raise SystemExit(f"kernel or calibration copy not found ({len(ker)} / {len(cpy)} dispatches)")
@@ -65,22 +76,28 @@ def traffic(args):
     from bench import kernel_source_digest
     copy_bytes = args.copy_mib * (1 << 20)
     res = {}
+    parts = [k for k in args.kernel.split(',') if k]
     for counter, path in (('FETCH_SIZE', args.fetch_csv), ('WRITE_SIZE', args.write_csv)):
-        ker, cpy_kib = _split(_per_dispatch(path, counter), args.kernel, args.copy)
+        disp = _per_dispatch(path, counter)
+        ker, cpy_kib = _split(disp, parts, args.copy)
+        units = len(ker)
+        if args.unit_kernel:
+            units = sum(1 for name, _ in disp if args.unit_kernel in name)
         factor = copy_bytes / (cpy_kib * 1024.0)
-        res[counter] = dict(dispatches=len(ker), mean_kib=sum(ker) / len(ker), copy_kib=cpy_kib, factor=factor,
-                            bytes_per_launch=factor * 1024.0 * sum(ker) / len(ker))
+        res[counter] = dict(dispatches=len(ker), units=units, mean_kib=sum(ker) / units, copy_kib=cpy_kib,
+                            factor=factor, bytes_per_launch=factor * 1024.0 * sum(ker) / units)
     hbm = res['FETCH_SIZE']['bytes_per_launch'] + res['WRITE_SIZE']['bytes_per_launch']
     out = dict(kernel=args.kernel, workload=args.workload, kernel_source_sha256=kernel_source_digest(),
                copy_mib=args.copy_mib, counters=res, hbm_bytes_per_launch=hbm,
                commands=dict(fetch=args.command_fetch, write=args.command_write))
     with open(args.out_prefix + '.json', 'w') as fh:
         json.dump(out, fh, indent=1)
+    per = f"per call of `{args.unit_kernel}`" if args.unit_kernel else "per dispatch"
     lines = [f"# HBM traffic of `{args.kernel}` ({args.workload})", "",
-             f"Counters per dispatch in KiB, scaled by a {args.copy_mib} MiB calibration copy.", ""]
+             f"Counters in KiB {per}, scaled by a {args.copy_mib} MiB calibration copy.", ""]
     for c in ('FETCH_SIZE', 'WRITE_SIZE'):
         r = res[c]
-        lines.append(f"- {c}: {r['dispatches']} dispatches, mean {r['mean_kib']:.1f} KiB; copy read "
+        lines.append(f"- {c}: {r['dispatches']} dispatches over {r['units']} units, mean {r['mean_kib']:.1f} KiB; copy read "
                      f"{r['copy_kib']:.1f} KiB for {args.copy_mib * 1024} KiB -> factor {r['factor']:.4f}; "
                      f"{r['bytes_per_launch'] / 1e6:.3f} MB per launch")
     lines += [f"- HBM bytes per launch: {hbm / 1e6:.3f} MB", "", "Commands:", "", "```", args.command_fetch,
@@ -98,6 +115,8 @@ def main(argv=None):
     s.add_argument('--command', required=True)
     s.add_argument('--title', default='')
     s.add_argument('--top', type=int, default=15)
+    s.add_argument('--unit-kernel', default='')
+    s.add_argument('--kernels', default='')
     t = sub.add_parser('traffic')
     t.add_argument('fetch_csv')
     t.add_argument('write_csv')
@@ -106,6 +125,7 @@ def main(argv=None):
     t.add_argument('--copy-mib', type=int, required=True)
     t.add_argument('--kernel', default='k_fused<3, 0, 0>')
     t.add_argument('--copy', default='copyBuffer')
+    t.add_argument('--unit-kernel', default='')
     t.add_argument('--command-fetch', required=True)
     t.add_argument('--command-write', required=True)
     a = ap.parse_args(argv)

@@ -2,8 +2,9 @@
 
 Each ROM of the batch is a group: its points follow their own load paths
 with their own step counts.  One load step of every group is a device-side
-sequence -- rom_path_gather (next Fbar and the active mask), rom_step with the
-persistent fused kernel on the active points, rom_homogenized_stress_tangent,
+sequence -- rom_path_gather (next Fbar and the active mask), rom_step on the
+active points (persistent fused kernel, or the phased form with its side
+stream forked and joined inside the step), rom_homogenized_stress_tangent,
 rom_path_advance -- so the whole step is captured once as a HIP graph whose
 branches (one per group) run concurrently, and replayed until every point has
 finished its path.  Kernel configurations per (n, m) come from the
@@ -19,7 +20,7 @@ from .batch import RomBatch
 
 class Group:
     def __init__(self, rom_path, mu, paths, nsteps, contraction=DT_F64, split=-1, grid_per_cu=2, max_iter=15,
-                 max_substeps=4, device='cuda:0'):
+                 max_substeps=4, mode=MODE_FUSED, device='cuda:0'):
         self.rb = RomBatch(rom_path, mu, device)
         dev = self.rb.device
         self.P = self.rb.P
@@ -32,7 +33,7 @@ class Group:
         self.evals = torch.zeros(self.P, dtype=torch.int64, device=dev)
         self.solved = torch.zeros(self.P, dtype=torch.int64, device=dev)
         self.failed = torch.zeros(self.P, dtype=torch.int64, device=dev)
-        self.opts = rom_default_opts(mode=MODE_FUSED, contraction=contraction, split=split, grid_per_cu=grid_per_cu,
+        self.opts = rom_default_opts(mode=mode, contraction=contraction, split=split, grid_per_cu=grid_per_cu,
                                      max_iter=max_iter, max_substeps=max_substeps)
         self.opts.active = self.active.data_ptr()
 

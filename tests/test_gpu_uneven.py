@@ -20,27 +20,31 @@ from paper_2307_16894_amd.uneven import Group, UnevenBatch
 pytestmark = pytest.mark.gpu
 
 
-def _groups(specs, grid):
+def _groups(specs, grid, mode):
     out = []
     for name, P, seed in specs:
         ns = workloads.uneven_steps(seed, P, 6, 14)
         mu = workloads.one_void_mu(seed, P)
         paths = workloads.uneven_cyclic_paths(seed, P, ns, (0.005, 0.015))
-        out.append((name, mu, paths, ns, Group(rom_path(name), mu, paths, ns, grid_per_cu=grid)))
+        out.append((name, mu, paths, ns, Group(rom_path(name), mu, paths, ns, grid_per_cu=grid, mode=mode)))
     return out
 
 
-def test_graph_replays_match_eager_and_oracle(gpu):
+@pytest.mark.parametrize("mode", [L.MODE_FUSED, pytest.param(L.MODE_PHASED, marks=pytest.mark.skip(
+    reason="graph capture of the phased step (side-stream fork and join) crashed the runtime's end of capture; "
+           "the phased form now refuses capture (test_phased_form_refuses_graph_capture)"))])
+def test_graph_replays_match_eager_and_oracle(gpu, mode):
+    """Fused form captured as a graph; the phased form runs eagerly only."""
     specs = [('onevoid_n20_m120', 96, 31)]
     if os.path.exists(rom_path("onevoid_n40_m400")):
         specs.append(('onevoid_n40_m400', 64, 32))
-    eager = _groups(specs, grid=2)
-    graph = _groups(specs, grid=2)
+    eager = _groups(specs, grid=2, mode=mode)
+    graph = _groups(specs, grid=2, mode=mode)
     be = UnevenBatch([g for *_, g in eager])
     bg = UnevenBatch([g for *_, g in graph])
     bg.capture()
     for k in range(bg.max_steps):
-        print(f"[gpu] uneven step {k}", flush=True)
+        print(f"[gpu] uneven mode {mode} step {k}", flush=True)
         be.step_eager()
         bg.graph.replay()
         torch.cuda.synchronize()
@@ -68,21 +72,49 @@ def test_autotuner_pick_reproduces_default(gpu):
     mu = workloads.one_void_mu(41, P)
     F = workloads.monotone_paths(41, P, 10)[:, 2]
     res = autotune.tune(rom_path(name), mu, F, L.DT_F64, reps=2)
-    assert (res['split'], res['grid_per_cu']) in autotune.candidates(20)
+    pick = (res['mode'], res['split'], res['grid_per_cu'])
+    assert pick in autotune.candidates(20)
     assert len(res['trials']) == len(autotune.candidates(20))
     out = {}
-    pick = (res['split'], res['grid_per_cu'])
-    for split, grid in ((-1, 0), (pick[0], 0), pick):
-        g = Group(rom_path(name), mu, F[:, None], np.ones(P, dtype=np.int32), split=split, grid_per_cu=grid)
+    for cfg in ((L.MODE_FUSED, -1, 0), (L.MODE_FUSED, pick[1], 0), pick):
+        mode, split, grid = cfg
+        g = Group(rom_path(name), mu, F[:, None], np.ones(P, dtype=np.int32), split=split, grid_per_cu=grid,
+                  mode=mode)
         g.opts.fixed_iters, g.opts.max_iter = 1, 6  # same Newton map on every side
         b = UnevenBatch([g])
         b.step_eager()
         torch.cuda.synchronize()
-        out[(split, grid)] = g.rb.Pbar.cpu().numpy().copy()
+        out[cfg] = g.rb.Pbar.cpu().numpy().copy()
         b.close()
-    # the launch form (one workgroup per point or the persistent grid) leaves
-    # every point's arithmetic unchanged: bit-identical
-    assert np.array_equal(out[(pick[0], 0)], out[pick])
+    # the execution form (one workgroup per point, the persistent grid, the
+    # phased launches) leaves every point's arithmetic unchanged: bit-identical
+    assert np.array_equal(out[(L.MODE_FUSED, pick[1], 0)], out[pick])
     # the split changes the summation order of K and f only
-    ref = out[(-1, 0)]
+    ref = out[(L.MODE_FUSED, -1, 0)]
     assert np.abs(out[pick] - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_phased_form_refuses_graph_capture(gpu):
+    """rom_step in the phased form returns ROM_EUNSUPPORTED inside a stream
+    capture (checked before anything is enqueued); the capture is then ended
+    with only a trivial kernel in it."""
+    from paper_2307_16894_amd.batch import RomBatch
+    name = 'onevoid_n20_m120'
+    P = 8
+    rb = RomBatch(rom_path(name), workloads.one_void_mu(3, P))
+    Fb = torch.eye(2, dtype=torch.float64, device='cuda').reshape(1, 4).repeat(P, 1).contiguous()
+    o = L.rom_default_opts(mode=L.MODE_PHASED)
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    code = None
+    with torch.cuda.graph(g, stream=cap):
+        try:
+            L.rom_step(rb.h, P, Fb.data_ptr(), rb.state.data_ptr(), o, rb.status.data_ptr(), rb.iters.data_ptr(),
+                       rb.resnorm.data_ptr(), cap.cuda_stream)
+        except L.RomError as e:
+            code = e.code
+        Fb.add_(0.0)
+    torch.cuda.synchronize()
+    assert code == L.ROM_EUNSUPPORTED
+    rb.close()
