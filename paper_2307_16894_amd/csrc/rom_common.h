@@ -9,7 +9,7 @@
 #include "j2_device.h"
 
 #define ROM_NMAX 128       // largest supported number of modes n
-#define ROM_REC_ROWS 28    // phased-form ECM-point record: D (16), W (4), F_mu (4), P (4)
+#define ROM_REC_ROWS 20    // phased-form ECM-point record: D (16, FP32 pairs in 8 in the BF16 form), P (4)
 #define ROM_PHASED_NPAD 80  // widest contraction tile set of the phased form (n <= 75)
 #define ROM_ALIGN 256
 
@@ -51,7 +51,7 @@ enum {
   F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK, F_FBC, F_RG,
   F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT, F_XF, F_DR, F_MU, F_LIST,
   F_D, F_W, F_K, F_F, F_PIV,
-  F_REC, F_PHI, F_PHD, F_LIST2, F_LIST3, F_LIST4,
+  F_REC, F_PHI, F_PHD, F_LIST2, F_LIST3, F_LIST4, F_HKIN,
   F_NFIELDS
 };
 
@@ -99,6 +99,7 @@ static inline StateLayout rom_state_layout(const rom_model* h, size_t P) {
   sz[F_LIST2] = P * 4;
   sz[F_LIST3] = P * 4;
   sz[F_LIST4] = P * 4;
+  sz[F_HKIN] = (h->npad <= ROM_PHASED_NPAD) ? P * 4 * m * 8 : 0;
   StateLayout L;
   size_t o = 0;
   for (int i = 0; i < F_NFIELDS; ++i) {

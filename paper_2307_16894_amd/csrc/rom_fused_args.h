@@ -33,7 +33,8 @@ struct FusedArgs {
   // contraction launch per evaluation, the points still running after them
   // handed to the fused kernel, which resumes them from this state
   int ph_k;          // evaluations made by the phased launches
-  double* rec;       // ECM-point records [P][ROM_REC_ROWS][m]
+  double* rec;       // ECM-point records [P][ROM_REC_ROWS][m] (point fastest)
+  double* hkin;      // H = sum_i r_i G_i(q) of the listed points [list entry][4][m]
   int* phi;          // per point: evaluations made, fell back to the plain guess [P][2]
   double* phd;       // per point: ||f|| of the first and of the latest evaluation [P][2]
   const int* lin;    // points of this evaluation

@@ -77,11 +77,20 @@ constexpr int cs_lds_doubles() {
   return cs_main_doubles<T>() + 16 * T + 4 * 16 * T + 256 + 128 + 32 + (16 * T + 8) / 2;
 }
 
-// F = Fbar + (sum_i r_i G_i(q)) F_mu^-1 at ECM point q (argument of P in
-// eq. forcevector_ecm); r is read from LDS.
-// The loads of eight modes are issued before their use, so that they are in
-// flight together (issued one at a time the loop is a chain of memory
-// round trips).
+// F = Fbar + H F_mu^-1 with H = sum_i r_i G_i(q) (argument of P in eq.
+// forcevector_ecm), from the four components of H.
+__device__ __forceinline__ void kin_F(const double Fb[4], double H0, double H1, double H2, double H3,
+                                      const double Fi[4], double F[4]) {
+  F[0] = Fb[0] + H0 * Fi[0] + H1 * Fi[2];
+  F[1] = Fb[1] + H0 * Fi[1] + H1 * Fi[3];
+  F[2] = Fb[2] + H2 * Fi[0] + H3 * Fi[2];
+  F[3] = Fb[3] + H2 * Fi[1] + H3 * Fi[3];
+}
+
+// F at ECM point q with H = sum_i r_i G_i(q) accumulated mode by mode (one
+// fma per mode and component, in mode order); r is read from LDS.  The loads
+// of eight modes are issued before their use, so that they are in flight
+// together (issued one at a time the loop is a chain of memory round trips).
 __device__ __forceinline__ void kinematics(int n, int m, int q, const double* __restrict__ Gt, const double* sR,
                                            const double Fb[4], const double Fi[4], double F[4]) {
   double H0 = 0.0, H1 = 0.0, H2 = 0.0, H3 = 0.0;
@@ -112,10 +121,7 @@ __device__ __forceinline__ void kinematics(int n, int m, int q, const double* __
     H3 = fma(ri, g[3 * m], H3);
     g += st;
   }
-  F[0] = Fb[0] + H0 * Fi[0] + H1 * Fi[2];
-  F[1] = Fb[1] + H0 * Fi[1] + H1 * Fi[3];
-  F[2] = Fb[2] + H2 * Fi[0] + H3 * Fi[2];
-  F[3] = Fb[3] + H2 * Fi[1] + H3 * Fi[3];
+  kin_F(Fb, H0, H1, H2, H3, Fi, F);
 }
 
 __device__ __forceinline__ double readlane_d(double x, int l) {
@@ -615,44 +621,54 @@ __device__ __forceinline__ double pack_f32x2(float lo, float hi) {
   return __longlong_as_double((long long)u);
 }
 
-// Kinematics, return map and tangent (Appendix A) of ECM point q at the trial
-// state r (sR): the contraction record goes to rec[k * rs] (rs = 1: a record
-// in LDS; rs = m: the point-fastest records of the phased form), the trial
-// history to ht (point fastest); P and w|J| are returned.
-//   D = w|J| T^T A T, accumulated column v = (k, l) of A at a time:
-//     E[.][v] = w|J| T^T A[.][v], D[b][(k, s)] += E[b][(k, l)] F_mu^-1[s][l];
-//   W = w|J| P F_mu^-T;  F_mu from the stored F_mu^-1.
-template <int PREC>
-__device__ __forceinline__ void point_record(int n, int m, int q, const double* __restrict__ Gt, const double* sR,
-                                             const double Fb[4], const double* __restrict__ tmu,
-                                             const double* __restrict__ hc, double* __restrict__ ht,
-                                             const J2Params& mp, double* rec, int rs, double P[4], double& wJ) {
-  const double Fi[4] = {tmu[q], tmu[m + q], tmu[2 * m + q], tmu[3 * m + q]};
-  const double w = tmu[4 * m + q];
-  wJ = w;
-  double F[4];
-  kinematics(n, m, q, Gt, sR, Fb, Fi, F);
+// Return map and tangent (Appendix A) of ECM point q at the deformation
+// gradient F: P, the trial history (to ht, point fastest), and
+//   D = w|J| T^T A T (T: right multiplication by F_mu^-1), accumulated column
+//     v = (k, l) of A at a time: E[.][v] = w|J| T^T A[.][v],
+//     D[b][(k, s)] += E[b][(k, l)] F_mu^-1[s][l];
+// Fi = F_mu^-1 and w = w|J| are returned with them.
+__device__ __forceinline__ void point_material(const double F[4], int m, int q, const double* __restrict__ tmu,
+                                               const double* __restrict__ hc, double* __restrict__ ht,
+                                               const J2Params& mp, double D[16], double P[4], double Fi[4],
+                                               double& w) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Fi[k] = tmu[k * m + q];
+  const double wl = tmu[4 * m + q];
+  w = wl;
   const double Fp[4] = {hc[q], hc[m + q], hc[2 * m + q], hc[3 * m + q]};
   double Fpn[4], Fp33n, xin;
-  double D[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) D[k] = 0.0;
+  const double Fi0 = Fi[0], Fi1 = Fi[1], Fi2 = Fi[2], Fi3 = Fi[3];
   j2_point_cols<true>(F, Fp, hc[4 * m + q], hc[5 * m + q], mp, P, Fpn, Fp33n, xin,
                       [&](int v, double c0, double c1, double c2, double c3) {
-                        const double e0 = w * (Fi[0] * c0 + Fi[1] * c1);
-                        const double e1 = w * (Fi[2] * c0 + Fi[3] * c1);
-                        const double e2 = w * (Fi[0] * c2 + Fi[1] * c3);
-                        const double e3 = w * (Fi[2] * c2 + Fi[3] * c3);
+                        const double e0 = wl * (Fi0 * c0 + Fi1 * c1);
+                        const double e1 = wl * (Fi2 * c0 + Fi3 * c1);
+                        const double e2 = wl * (Fi0 * c2 + Fi1 * c3);
+                        const double e3 = wl * (Fi2 * c2 + Fi3 * c3);
                         const int k = v >> 1, l = v & 1;
+                        const double t0 = l ? Fi1 : Fi0, t1 = l ? Fi3 : Fi2;
 #pragma unroll
                         for (int s2 = 0; s2 < 2; ++s2) {
-                          const double t = Fi[2 * s2 + l];
+                          const double t = s2 ? t1 : t0;
                           D[0 + 2 * k + s2] = fma(e0, t, D[0 + 2 * k + s2]);
                           D[4 + 2 * k + s2] = fma(e1, t, D[4 + 2 * k + s2]);
                           D[8 + 2 * k + s2] = fma(e2, t, D[8 + 2 * k + s2]);
                           D[12 + 2 * k + s2] = fma(e3, t, D[12 + 2 * k + s2]);
                         }
                       });
+  ht[q] = Fpn[0];
+  ht[m + q] = Fpn[1];
+  ht[2 * m + q] = Fpn[2];
+  ht[3 * m + q] = Fpn[3];
+  ht[4 * m + q] = Fp33n;
+  ht[5 * m + q] = xin;
+}
+
+// D of a contraction record at rec[k * rs] (rows R_D ..): FP64, or in the
+// BF16 form FP32 values two per slot.
+template <int PREC>
+__device__ __forceinline__ void put_record_d(double* rec, int rs, const double D[16]) {
   if constexpr (PREC == PREC_BF16) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) rec[(R_D + j) * rs] = pack_f32x2((float)D[2 * j], (float)D[2 * j + 1]);
@@ -660,21 +676,27 @@ __device__ __forceinline__ void point_record(int n, int m, int q, const double* 
 #pragma unroll
     for (int k = 0; k < 16; ++k) rec[(R_D + k) * rs] = D[k];
   }
-  ht[q] = Fpn[0];
-  ht[m + q] = Fpn[1];
-  ht[2 * m + q] = Fpn[2];
-  ht[3 * m + q] = Fpn[3];
-  ht[4 * m + q] = Fp33n;
-  ht[5 * m + q] = xin;
-  rec[R_W * rs] = w * (P[0] * Fi[0] + P[1] * Fi[1]);
-  rec[(R_W + 1) * rs] = w * (P[0] * Fi[2] + P[1] * Fi[3]);
-  rec[(R_W + 2) * rs] = w * (P[2] * Fi[0] + P[3] * Fi[1]);
-  rec[(R_W + 3) * rs] = w * (P[2] * Fi[2] + P[3] * Fi[3]);
+}
+
+// W = w|J| P F_mu^-T and F_mu (from the stored F_mu^-1) of an LDS record.
+__device__ __forceinline__ void put_record_wf(double* rec, const double P[4], const double Fi[4], double w) {
+  rec[R_W] = w * (P[0] * Fi[0] + P[1] * Fi[1]);
+  rec[R_W + 1] = w * (P[0] * Fi[2] + P[1] * Fi[3]);
+  rec[R_W + 2] = w * (P[2] * Fi[0] + P[3] * Fi[1]);
+  rec[R_W + 3] = w * (P[2] * Fi[2] + P[3] * Fi[3]);
   const double idet = 1.0 / (Fi[0] * Fi[3] - Fi[1] * Fi[2]);
-  rec[R_FM * rs] = Fi[3] * idet;
-  rec[(R_FM + 1) * rs] = -Fi[1] * idet;
-  rec[(R_FM + 2) * rs] = -Fi[2] * idet;
-  rec[(R_FM + 3) * rs] = Fi[0] * idet;
+  rec[R_FM] = Fi[3] * idet;
+  rec[R_FM + 1] = -Fi[1] * idet;
+  rec[R_FM + 2] = -Fi[2] * idet;
+  rec[R_FM + 3] = Fi[0] * idet;
+}
+
+// Rows of the phased form's point-fastest records in global memory: D (16
+// rows, 8 in the BF16 form) then P (4); W and F_mu are formed again when the
+// records are staged for the contraction.
+template <int PREC>
+constexpr int rec_p_row() {
+  return PREC == PREC_BF16 ? 8 : 16;
 }
 
 // Accumulators of one evaluation: the MFMA tiles of this wave, and in the
@@ -934,8 +956,13 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
       for (int q0 = 0; q0 < m; q0 += FCH) {
         const int q = q0 + tid;
         if (q < m) {
-          double P[4], wJ;
-          point_record<PREC>(n, m, q, a.Gt, sR, Fb, tmu, hc, ht, a.mp, sQ + tid * QS, 1, P, wJ);
+          double F[4], D[16], P[4], Fi[4], wJ;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) Fi[k] = tmu[k * m + q];
+          kinematics(n, m, q, a.Gt, sR, Fb, Fi, F);
+          point_material(F, m, q, tmu, hc, ht, a.mp, D, P, Fi, wJ);
+          put_record_d<PREC>(sQ + tid * QS, 1, D);
+          put_record_wf(sQ + tid * QS, P, Fi, wJ);
           if constexpr (PREC != PREC_F64) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) E.accP[k] = fma(wJ, P[k], E.accP[k]);
@@ -1003,8 +1030,17 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
 // one that goes on is listed for the next phased evaluation, or after ph_k
 // evaluations for the fused kernel; an attempt that fails with load-step
 // cutting on is handed to the fused kernel from its start.
+// waves per SIMD the contraction kernel is compiled for: four workgroups per
+// compute unit for the FP64 forms of up to three column tiles (measured 4%
+// faster than three at n = 40), the compiler's choice otherwise
+template <int T, int PREC>
+constexpr int cs_waves() {
+  return (T <= 3 && PREC == PREC_F64) ? 4 : 1;
+}
+
 template <int T, int PREC, int SPLIT>
-__global__ __launch_bounds__(256) void k_ph_cs(const FusedArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cs_waves<T, PREC>()))) void k_ph_cs(
+    const FusedArgs a) {
   extern __shared__ double smem[];
   constexpr int NPAD = 16 * T;
   constexpr int LD = ldk<T>();
@@ -1025,25 +1061,46 @@ __global__ __launch_bounds__(256) void k_ph_cs(const FusedArgs a) {
 
   EvalAcc<T, PREC, SPLIT> E;
   E.zero();
+  const double* tmu = a.tmu + (size_t)p * 5 * m;
+  constexpr int RP = rec_p_row<PREC>();
   if constexpr (PREC != PREC_F64) {
     // FP64 sum of w|J| P, lane tid over the points q = tid mod FCH (the fused kernel's order)
-    const double* tmu = a.tmu + (size_t)p * 5 * m;
     for (int q = tid; q < m; q += FCH) {
       const double wJ = tmu[4 * m + q];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) E.accP[k] = fma(wJ, rec[(size_t)(QS + k) * m + q], E.accP[k]);
+      for (int k = 0; k < 4; ++k) E.accP[k] = fma(wJ, rec[(size_t)(RP + k) * m + q], E.accP[k]);
     }
   }
   for (int q0 = 0; q0 < m; q0 += CCH) {
     const int qend = min(CCH, m - q0);
-    // records of the chunk into LDS: lane pair (tid, tid + 128) splits a point's record
-    const int j = tid & (CCH - 1), kh = tid / CCH;
+    // records of the chunk into LDS, two lanes per point: D (the first eight
+    // rows), and the rest of D with W and F_mu formed from P and F_mu^-1
+    const int j = tid & (CCH - 1), kh = tid / CCH, q = q0 + j;
     if (j < qend) {
-      double v[QS / 2];
+      double* dst = sQ + j * QS;
+      if (kh == 0) {
+        double v[8];
 #pragma unroll
-      for (int k = 0; k < QS / 2; ++k) v[k] = rec[(size_t)(kh * (QS / 2) + k) * m + q0 + j];
+        for (int k = 0; k < 8; ++k) v[k] = rec[(size_t)k * m + q];
 #pragma unroll
-      for (int k = 0; k < QS / 2; ++k) sQ[j * QS + kh * (QS / 2) + k] = v[k];
+        for (int k = 0; k < 8; ++k) dst[R_D + k] = v[k];
+      } else {
+        double v[8], P[4], Fi[4];
+        if constexpr (PREC != PREC_BF16) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = rec[(size_t)(8 + k) * m + q];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) P[k] = rec[(size_t)(RP + k) * m + q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Fi[k] = tmu[k * m + q];
+        const double w = tmu[4 * m + q];
+        if constexpr (PREC != PREC_BF16) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) dst[R_D + 8 + k] = v[k];
+        }
+        put_record_wf(dst, P, Fi, w);
+      }
     }
     __syncthreads();
     contract_chunk<T, PREC, SPLIT>(E, a.Gq, sQ, q0, qend, pd, n, wave, k_row, c_col);

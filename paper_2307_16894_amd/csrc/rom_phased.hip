@@ -1,10 +1,12 @@
 // Phased form of the online solve.  The first evaluations of the Newton
-// iteration (eq. red_newton) of every point of the batch run as two launches
-// each:
-//   material:    one lane per ECM point of every listed point (kinematics,
-//                return map, tangent and the contraction record of Appendix A
-//                and eqs. forcevector_ecm / stiffnessmatrix_ecm), the lanes
-//                packed across points;
+// iteration (eq. red_newton) of every point of the batch run as three
+// launches each:
+//   kinematics:  H = sum_i r_i G_i(q) of every listed point as one FP64
+//                MFMA product (the mode gradients read once for all points);
+//   material:    one lane per ECM point of every listed point (return map,
+//                tangent and the contraction record of Appendix A and eqs.
+//                forcevector_ecm / stiffnessmatrix_ecm), the lanes packed
+//                across points;
 //   contraction: one workgroup per listed point (the MFMA contraction of the
 //                records, the elimination, the status and Newton update), a
 //                kernel with a register budget of its own.
@@ -25,7 +27,6 @@
 
 namespace {
 
-constexpr int PH_RCAP = 2048;  // r values of the points one material workgroup touches
 constexpr int PH_EVALS = 6;    // phased evaluations (default)
 // early hand-over (default): after this many evaluations, points whose ||f||
 // fell by less than the factor PH_SLOW in the last update
@@ -61,41 +62,86 @@ __global__ void k_ph_begin(const FusedArgs a, int P) {
   }
 }
 
+// Kinematics launch: H = G R for the listed points as an FP64 MFMA product,
+// rows (b, q) of the mode gradients (Gt, [n][4][m]) against the trial r of
+// each listed point, four modes per instruction in mode order.  The FP64
+// instruction adds its four products to the accumulator as a chain of fma
+// in that order, so each H entry is the same fma chain over the modes as the
+// fused kernel's per-lane kinematics (zero modes past n add nothing).
+// Workgroup: 64 rows (a wave each 16) by 64 list entries (four 16-column
+// tiles per wave).
+__global__ __launch_bounds__(256) void k_ph_kin(const FusedArgs a) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = a.n, m = a.m, rows = 4 * m;
+  const int cnt = *a.cin;
+  const int j0 = blockIdx.y * 64;
+  if (j0 >= cnt) return;
+  const int r0 = blockIdx.x * 64 + wave * 16;
+  if (r0 >= rows) return;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ra = min(r0 + li, rows - 1);  // A row of this lane (rows past the end repeat the last; not stored)
+  int pj[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = j0 + 16 * t + li;
+    pj[t] = (j < cnt) ? a.lin[j] : -1;
+  }
+  d4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < n; s += 4) {
+    const int i = s + lk;
+    const double av = (i < n) ? a.Gt[(size_t)i * rows + ra] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double bv = (i < n && pj[t] >= 0) ? a.rt[(size_t)pj[t] * n + i] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+    }
+  }
+  // output: register jj of lane l is row (l >> 4) + 4 jj, column l & 15
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = j0 + 16 * t + li;
+    if (j >= cnt) continue;
+    double* Hj = a.hkin + (size_t)j * rows;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = r0 + lk + 4 * jj;
+      if (r < rows) Hj[r] = acc[t][jj];
+    }
+  }
+}
+
 // Material launch: lane g of the grid takes ECM point g mod m of list entry
-// g / m.  The r of the points a workgroup touches are staged in LDS.  Block 0
-// also clears the count of the list the following contraction launch fills.
+// g / m: F from the kinematics launch's H, the return map, and the record.
+// Block 0 also clears the count of the list the following contraction
+// launch fills.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_ph_mat(const FusedArgs a) {
-  __shared__ double sRr[PH_RCAP];
-  const int tid = threadIdx.x, n = a.n, m = a.m;
+  const int tid = threadIdx.x, m = a.m;
   if (blockIdx.x == 0 && tid == 0) *a.cout = 0;
   const long long cnt = *a.cin;
-  const long long g0 = (long long)blockIdx.x * 256, total = cnt * m;
-  if (g0 >= total) return;
-  const int i0 = (int)(g0 / m);
-  const int i1 = (int)min((g0 + 255) / m, cnt - 1);
-  for (int e = tid; e < (i1 - i0 + 1) * n; e += 256) {
-    const int k = e / n;
-    sRr[e] = a.rt[(size_t)a.lin[i0 + k] * n + (e - k * n)];
-  }
-  __syncthreads();
-  const long long g = g0 + tid;
-  if (g >= total) return;
+  const long long g = (long long)blockIdx.x * 256 + tid;
+  if (g >= cnt * m) return;
   const int idx = (int)(g / m), q = (int)(g - (long long)idx * m), p = a.lin[idx];
   const double Fb[4] = {a.Fbar[4 * (size_t)p], a.Fbar[4 * (size_t)p + 1], a.Fbar[4 * (size_t)p + 2],
                         a.Fbar[4 * (size_t)p + 3]};
   double* rec = a.rec + (size_t)p * ROM_REC_ROWS * m + q;
-  double P[4], wJ;
-  point_record<PREC>(n, m, q, a.Gt, sRr + (idx - i0) * n, Fb, a.tmu + (size_t)p * 5 * m, a.hc + (size_t)p * 6 * m,
-                     a.ht + (size_t)p * 6 * m, a.mp, rec, m, P, wJ);
-  if constexpr (PREC != PREC_F64) {
+  const double* tmu = a.tmu + (size_t)p * 5 * m;
+  const double* H = a.hkin + (size_t)idx * 4 * m + q;
+  double F[4], D[16], P[4], Fi[4], wJ;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) rec[(size_t)(QS + k) * m] = P[k];
-  }
+  for (int k = 0; k < 4; ++k) Fi[k] = tmu[k * m + q];
+  kin_F(Fb, H[0], H[m], H[2 * m], H[3 * m], Fi, F);
+  point_material(F, m, q, tmu, a.hc + (size_t)p * 6 * m, a.ht + (size_t)p * 6 * m, a.mp, D, P, Fi, wJ);
+  put_record_d<PREC>(rec, m, D);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) rec[(size_t)(rec_p_row<PREC>() + k) * m] = P[k];
 }
 
-int launch_mat(const FusedArgs& a, int prec, long long lanes, hipStream_t s) {
-  const unsigned int blocks = (unsigned int)((lanes + 255) / 256);
+int launch_mat(const FusedArgs& a, int prec, int P, int m, hipStream_t s) {
+  k_ph_kin<<<dim3((unsigned int)((4 * m + 63) / 64), (unsigned int)((P + 63) / 64)), 256, 0, s>>>(a);
+  const unsigned int blocks = (unsigned int)(((long long)P * m + 255) / 256);
   if (prec == ROM_DT_F64)
     k_ph_mat<PREC_F64><<<blocks, 256, 0, s>>>(a);
   else if (prec == ROM_DT_F32)
@@ -116,7 +162,6 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess) return ROM_EHIP;
   if (cap != hipStreamCaptureStatusNone) return ROM_EUNSUPPORTED;
-  if ((255 / h->m + 2) * h->n > PH_RCAP) return ROM_EUNSUPPORTED;
   if ((long long)P * h->m > (1LL << 31) - 256) return ROM_EUNSUPPORTED;
   const int kph = min(o.phased_evals > 0 ? o.phased_evals : PH_EVALS, o.max_iter);
   if (kph < 1) return rom_launch_step_fused(h, P, Fbar, state, o, st_out, it_out, res_out, s);
@@ -138,6 +183,7 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
   a.early = early;
   a.cearly = cnt + 4;
   a.rec = field<double>(state, L, F_REC);
+  a.hkin = field<double>(state, L, F_HKIN);
   a.phi = field<int>(state, L, F_PHI);
   a.phd = field<double>(state, L, F_PHD);
   a.hand = hand;
@@ -159,7 +205,7 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
     b.cin = cnt + (e & 1);
     b.lout = (e & 1) ? listA : listB;
     b.cout = cnt + 1 - (e & 1);
-    rc = launch_mat(b, o.contraction, (long long)P * h->m, s);
+    rc = launch_mat(b, o.contraction, P, h->m, s);
     if (rc == ROM_OK) rc = rom_phased_cs(T, b, o.contraction, split, P, s);
     if (rc == ROM_OK && a.ph_early > 0 && e + 1 == a.ph_early) {
       // fork: the early list to the fused kernel on the side stream
