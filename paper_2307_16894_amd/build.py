@@ -15,6 +15,10 @@ SOURCES = ['rom_api.hip', 'rom_staged.hip', 'rom_fused.hip', 'rom_phased.hip', '
 FLAGS = ['--offload-arch=gfx950', '-O3', '-std=c++17', '-fPIC',
          # packed FP32 instructions are left out of every kernel
          '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
+         # multiply-adds are fused within an expression only, the same way in
+         # every kernel that inlines a shared helper (the fused and phased forms
+         # agree bit for bit)
+         '-ffp-contract=on',
          '-I' + os.path.join(ROOT, 'include')]
 
 

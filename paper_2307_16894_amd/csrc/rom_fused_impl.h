@@ -78,13 +78,17 @@ constexpr int cs_lds_doubles() {
 }
 
 // F = Fbar + H F_mu^-1 with H = sum_i r_i G_i(q) (argument of P in eq.
-// forcevector_ecm), from the four components of H.
+// forcevector_ecm), from the four components of H.  Helpers that different
+// kernels share are written with explicit fma (and the library is built with
+// multiply-add fusion within expressions only): fusion left to the code
+// generator depends on the surrounding code, and the fused and phased kernels
+// would round differently.
 __device__ __forceinline__ void kin_F(const double Fb[4], double H0, double H1, double H2, double H3,
                                       const double Fi[4], double F[4]) {
-  F[0] = Fb[0] + H0 * Fi[0] + H1 * Fi[2];
-  F[1] = Fb[1] + H0 * Fi[1] + H1 * Fi[3];
-  F[2] = Fb[2] + H2 * Fi[0] + H3 * Fi[2];
-  F[3] = Fb[3] + H2 * Fi[1] + H3 * Fi[3];
+  F[0] = fma(H1, Fi[2], fma(H0, Fi[0], Fb[0]));
+  F[1] = fma(H1, Fi[3], fma(H0, Fi[1], Fb[1]));
+  F[2] = fma(H3, Fi[2], fma(H2, Fi[0], Fb[2]));
+  F[3] = fma(H3, Fi[3], fma(H2, Fi[1], Fb[3]));
 }
 
 // F at ECM point q with H = sum_i r_i G_i(q) accumulated mode by mode (one
@@ -678,13 +682,14 @@ __device__ __forceinline__ void put_record_d(double* rec, int rs, const double D
   }
 }
 
-// W = w|J| P F_mu^-T and F_mu (from the stored F_mu^-1) of an LDS record.
+// W = w|J| P F_mu^-T and F_mu (from the stored F_mu^-1) of an LDS record
+// (explicit fma, see kin_F).
 __device__ __forceinline__ void put_record_wf(double* rec, const double P[4], const double Fi[4], double w) {
-  rec[R_W] = w * (P[0] * Fi[0] + P[1] * Fi[1]);
-  rec[R_W + 1] = w * (P[0] * Fi[2] + P[1] * Fi[3]);
-  rec[R_W + 2] = w * (P[2] * Fi[0] + P[3] * Fi[1]);
-  rec[R_W + 3] = w * (P[2] * Fi[2] + P[3] * Fi[3]);
-  const double idet = 1.0 / (Fi[0] * Fi[3] - Fi[1] * Fi[2]);
+  rec[R_W] = w * fma(P[1], Fi[1], P[0] * Fi[0]);
+  rec[R_W + 1] = w * fma(P[1], Fi[3], P[0] * Fi[2]);
+  rec[R_W + 2] = w * fma(P[3], Fi[1], P[2] * Fi[0]);
+  rec[R_W + 3] = w * fma(P[3], Fi[3], P[2] * Fi[2]);
+  const double idet = 1.0 / fma(Fi[0], Fi[3], -(Fi[1] * Fi[2]));
   rec[R_FM] = Fi[3] * idet;
   rec[R_FM + 1] = -Fi[1] * idet;
   rec[R_FM + 2] = -Fi[2] * idet;
@@ -1071,40 +1076,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cs_waves<T,
       for (int k = 0; k < 4; ++k) E.accP[k] = fma(wJ, rec[(size_t)(RP + k) * m + q], E.accP[k]);
     }
   }
-  for (int q0 = 0; q0 < m; q0 += CCH) {
-    const int qend = min(CCH, m - q0);
-    // records of the chunk into LDS, two lanes per point: D (the first eight
-    // rows), and the rest of D with W and F_mu formed from P and F_mu^-1
-    const int j = tid & (CCH - 1), kh = tid / CCH, q = q0 + j;
-    if (j < qend) {
-      double* dst = sQ + j * QS;
-      if (kh == 0) {
+  // records of a chunk into LDS, two lanes per point: D (the first eight rows),
+  // and the rest of D with W and F_mu formed from P and F_mu^-1
+  const int j = tid & (CCH - 1), kh = tid / CCH;
+  constexpr int DR = (PREC == PREC_BF16) ? 1 : 2;  // record rows of D in halves of eight
+  if constexpr (PREC == PREC_F64 || T > 4) {
+    for (int q0 = 0; q0 < m; q0 += CCH) {
+      const int qend = min(CCH, m - q0), q = q0 + j;
+      if (j < qend) {
+        double* dst = sQ + j * QS;
         double v[8];
+        if (DR == 2 || kh == 0) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = rec[(size_t)k * m + q];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) dst[R_D + k] = v[k];
-      } else {
-        double v[8], P[4], Fi[4];
-        if constexpr (PREC != PREC_BF16) {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) v[k] = rec[(size_t)(8 + k) * m + q];
+          for (int k = 0; k < 8; ++k) v[k] = rec[(size_t)(8 * kh + k) * m + q];
         }
+        if (kh == 1) {
+          double P[4], Fi[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) P[k] = rec[(size_t)(RP + k) * m + q];
+          for (int k = 0; k < 4; ++k) P[k] = rec[(size_t)(RP + k) * m + q];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) Fi[k] = tmu[k * m + q];
-        const double w = tmu[4 * m + q];
-        if constexpr (PREC != PREC_BF16) {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) dst[R_D + 8 + k] = v[k];
+          for (int k = 0; k < 4; ++k) Fi[k] = tmu[k * m + q];
+          const double w = tmu[4 * m + q];
+          put_record_wf(dst, P, Fi, w);
         }
-        put_record_wf(dst, P, Fi, w);
+        if (DR == 2 || kh == 0) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) dst[R_D + 8 * kh + k] = v[k];
+        }
       }
+      __syncthreads();
+      contract_chunk<T, PREC, SPLIT>(E, a.Gq, sQ, q0, qend, pd, n, wave, k_row, c_col);
+      __syncthreads();
     }
-    __syncthreads();
-    contract_chunk<T, PREC, SPLIT>(E, a.Gq, sQ, q0, qend, pd, n, wave, k_row, c_col);
-    __syncthreads();
+  } else {
+    // reduced precision up to four column tiles: the global loads of the
+    // next chunk are issued before the current chunk is contracted (the FP64
+    // contraction and the wider ones need these registers themselves)
+    double v[8], Pv[4], Fv[4], wv = 0.0;
+    auto load_chunk = [&](int q0) {
+      const int q = q0 + j;
+      if (q < m) {
+        if (DR == 2 || kh == 0) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = rec[(size_t)(8 * kh + k) * m + q];
+        }
+        if (kh == 1) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) Pv[k] = rec[(size_t)(RP + k) * m + q];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) Fv[k] = tmu[k * m + q];
+          wv = tmu[4 * m + q];
+        }
+      }
+    };
+    load_chunk(0);
+    for (int q0 = 0; q0 < m; q0 += CCH) {
+      const int qend = min(CCH, m - q0);
+      if (j < qend) {
+        double* dst = sQ + j * QS;
+        if (DR == 2 || kh == 0) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) dst[R_D + 8 * kh + k] = v[k];
+        }
+        if (kh == 1) put_record_wf(dst, Pv, Fv, wv);
+      }
+      __syncthreads();
+      load_chunk(q0 + CCH);
+      contract_chunk<T, PREC, SPLIT>(E, a.Gq, sQ, q0, qend, pd, n, wave, k_row, c_col);
+      __syncthreads();
+    }
   }
   const double rn = assemble<T, PREC, SPLIT>(E, sK, sC, sX, n, tid, lane, wave, k_row, c_col);
   int status;
