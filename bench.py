@@ -240,7 +240,8 @@ def kernel_source_digest():
     csrc = os.path.join(ROOT, 'paper_2307_16894_amd', 'csrc')
     h = hashlib.sha256()
     for f in sorted(os.listdir(csrc)):
-        if f.startswith(('rom_fused', 'rom_phased')) or f in ('j2_device.h', 'rom_common.h'):
+        if (f.startswith(('rom_fused', 'rom_phased')) and f.endswith(('.hip', '.h'))) or f in ('j2_device.h',
+                                                                                              'rom_common.h'):
             with open(os.path.join(csrc, f), 'rb') as fh:
                 h.update(f.encode() + b'\0' + fh.read())
     return h.hexdigest()
