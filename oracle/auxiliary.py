@@ -89,6 +89,33 @@ def coefficients(kind, mu, r0, void_area=None):
     raise ValueError(kind)
 
 
+def coefficient_jacobian(kind, mu, r0, void_area=None):
+    """d c / d mu, shape (c, n_mu), of coefficients(): kind 0 is linear in
+    (a, b); kind 1 per void from S = R(theta) diag(a, b) R(theta)^T / r0 with
+    a = sqrt(A_v / (pi kappa)), da/dkappa = -a / (2 kappa), b = kappa a,
+    db/dkappa = a / 2."""
+    mu = np.asarray(mu, dtype=np.float64)
+    if kind == 0:
+        return np.eye(2) / r0
+    if kind == 1:
+        Jc = np.zeros((12, 8))
+        for v in range(4):
+            kappa, theta = mu[2 * v], mu[2 * v + 1]
+            a = np.sqrt(void_area / (np.pi * kappa))
+            b = kappa * a
+            da, db = -a / (2.0 * kappa), a / 2.0
+            cs, sn = np.cos(theta), np.sin(theta)
+            # S11 = (a c^2 + b s^2) / r0, S22 = (a s^2 + b c^2) / r0, S12 = (a - b) s c / r0
+            Jc[3 * v + 0, 2 * v] = (da * cs * cs + db * sn * sn) / r0
+            Jc[3 * v + 1, 2 * v] = (da * sn * sn + db * cs * cs) / r0
+            Jc[3 * v + 2, 2 * v] = (da - db) * sn * cs / r0
+            Jc[3 * v + 0, 2 * v + 1] = 2.0 * sn * cs * (b - a) / r0
+            Jc[3 * v + 1, 2 * v + 1] = 2.0 * sn * cs * (a - b) / r0
+            Jc[3 * v + 2, 2 * v + 1] = (a - b) * (cs * cs - sn * sn) / r0
+        return Jc
+    raise ValueError(kind)
+
+
 class AuxiliaryProblem:
     """Linear-elastic transformation problem on a parent mesh."""
 

@@ -103,6 +103,37 @@ class ROM:
             Abar[:, kl] = np.einsum('q,qab,qb->a', wJ, A4, dF) / self.cell_area
         return Pbar, Abar
 
+    # -- shape sensitivities -----------------------------------------------
+    def shape_sensitivity(self, mu, r, Fbar, hist):
+        """dPbar / dmu at the state r of load Fbar reached from the committed
+        history hist, which is held fixed: eq. eff_sensitivities_full with the
+        ECM rule, where d/dmu (dw/dX) = sum_i (dr_i/dmu) grad phi_i and dr/dmu
+        follows from the reduced equilibrium, K dr/dmu = -df/dmu at fixed r
+        (f of eq. forcevector_ecm, K of eq. stiffnessmatrix_ecm).  Returns
+        (4, n_mu): component (i J) of Pbar by shape parameter."""
+        Finv, J = self.transformation(mu)
+        ev = self.evaluate(r, Fbar, hist, Finv, J)
+        m, n = self.m, self.n
+        dc = auxiliary.coefficient_jacobian(self.kind, mu, self.r0, self.void_area)  # (c, n_mu)
+        n_mu = dc.shape[1]
+        dFmu = np.einsum('qak,kj->jqa', self.Gd, dc).reshape(n_mu, m, 2, 2)  # dF_mu / dmu_j
+        dFinv = -Finv[None] @ dFmu @ Finv[None]                              # d(F_mu^-1) / dmu_j
+        dJ = J[None] * np.einsum('qab,jqba->jq', Finv, dFmu)                 # d det F_mu / dmu_j
+        dwJ = self.w[None] * np.sign(J)[None] * dJ                           # d(w |det F_mu|) / dmu_j
+        wJ, P4, A4, B = ev['wJ'], ev['P'].reshape(m, 4), ev['A'], ev['B']
+        H = (self.G @ r).reshape(m, 2, 2)
+        dFr = (H[None] @ dFinv).reshape(n_mu, m, 4)                          # dF / dmu_j at fixed r
+        out = np.zeros((4, n_mu))
+        for j in range(n_mu):
+            Bd = right_map(dFinv[j]) @ self.G                                 # vec(grad phi_i dF_mu^-1/dmu_j)
+            AdF = np.einsum('qab,qb->qa', A4, dFr[j])
+            df = (np.einsum('qai,qa->i', B, P4 * dwJ[j][:, None]) + np.einsum('qai,qa->i', Bd, P4 * wJ[:, None])
+                  + np.einsum('qai,qa->i', B, AdF * wJ[:, None]))
+            dr = -np.linalg.solve(ev['K'], df)
+            dF = B @ dr + dFr[j]                                              # total dF / dmu_j
+            out[:, j] = (np.einsum('q,qab,qb->a', wJ, A4, dF) + np.einsum('q,qa->a', dwJ[j], P4)) / self.cell_area
+        return out
+
     def step(self, r0, hist, Fbar, Finv, J, tol=1e-8, max_iter=25, fixed=False):
         r, ev, status, iters, res = self.newton(r0, hist, Fbar, Finv, J, tol, max_iter, fixed)
         Pbar, Abar = self.effective(ev)
