@@ -147,6 +147,37 @@ def gpu_run(w, steps, warmup, opts, rom_file):
                 launches=launches, n=n, m=m, Pbar=Pbars)
 
 
+def sensitivity_rate(w, rom_file, at_step=5, reps=5):
+    """Shape sensitivities dPbar/dmu of the whole batch after a trial step:
+    the batch is driven (fused FP64, cutting) through the first at_step load
+    steps, then a trial step (no commit) to the next one; the sensitivity call
+    is timed with HIP events on its stream."""
+    import torch
+    import paper_2307_16894_amd as L
+    from paper_2307_16894_amd.batch import RomBatch
+    mu, paths = inputs(w)
+    rb = RomBatch(rom_file, mu)
+    for k in range(at_step + 1):
+        o = L.rom_default_opts(mode=L.MODE_FUSED, max_substeps=SUBSTEPS if k < at_step else 0, commit=int(k < at_step))
+        rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), o)
+    Fb = torch.from_numpy(np.ascontiguousarray(paths[:, at_step])).cuda()
+    S = rb.shape_sensitivity(Fb)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(rb.stream)
+        S = rb.shape_sensitivity(Fb)
+        e1.record(rb.stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    finite = bool(torch.isfinite(S).all())
+    rb.close()
+    ms = float(np.median(times))
+    return dict(value=w['P'] / (ms * 1e-3), unit="macro points/s", ms_per_call=ms, n_mu=int(S.shape[2]),
+                after_steps=at_step, all_finite=finite)
+
+
 def _oracle_worker(args):
     rom_file, mu, path = args
     from threadpoolctl import threadpool_limits
@@ -386,6 +417,8 @@ def main(argv=None):
     )
     if ws is not None:
         ws.close()
+    log("[bench] shape sensitivities")
+    out['shape_sensitivity'] = sensitivity_rate(w, rom_file)
     if not a.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(w, rom_file)
     print(json.dumps(out), flush=True)

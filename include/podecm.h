@@ -200,6 +200,24 @@ int rom_homogenized_stress_tangent(rom_handle h, int32_t batch, const void* stat
                                    double* Pbar_dev, double* Abar_dev, hipStream_t stream);
 
 /*
+ * rom_shape_sensitivity -- sensitivities of the effective stress to the shape
+ * parameters, dPbar/dmu (eq. eff_sensitivities_full with the ECM rule), at
+ * the returned state of the last rom_step on this state, with the committed
+ * history held fixed: call it after a step made with opts.commit = 0 (a
+ * trial solve; the committed history is then the one the step started from),
+ * with the same Fbar.  The fluctuation's share follows from the reduced
+ * equilibrium, dr/dmu = -K*^-1 df/dmu, using the K*^-1 C the step kept (the
+ * consistent tangent is symmetric).  Asynchronous on `stream`.
+ *   Fbar_dev  : f64 [batch][4] device, the load of that step.
+ *   dPdmu_dev : f64 [batch][4][n_mu] device out, component (iJ) of Pbar by
+ *               shape parameter (in the order of rom_state_init's mu); NaN for
+ *               points whose mu was rejected.
+ * Returns ROM_EUNSUPPORTED when n * n_mu > 1024.
+ */
+int rom_shape_sensitivity(rom_handle h, int32_t batch, const double* Fbar_dev, const void* state_dev,
+                          double* dPdmu_dev, hipStream_t stream);
+
+/*
  * Learned warm start.  A fully connected network (n_in -> 3 hidden layers of
  * `width` SiLU units -> n_out) predicts the Newton increment of the reduced
  * coordinates of a load step, dr = r_converged - r_committed, from per-point

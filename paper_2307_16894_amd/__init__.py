@@ -38,7 +38,7 @@ FIELD_FBAR_COMMITTED, FIELD_R_GUESS = 8, 9
 NFIELDS = 10
 
 EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_info', 'rom_state_bytes',
-           'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent',
+           'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent', 'rom_shape_sensitivity',
            'rom_timing_enable', 'rom_timing_read', 'rom_mlp_create', 'rom_mlp_free', 'rom_mlp_param_count',
            'rom_mlp_set_params', 'rom_mlp_get_params', 'rom_mlp_set_scaling', 'rom_mlp_forward',
            'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features', 'rom_path_gather', 'rom_path_advance']
@@ -97,6 +97,7 @@ def lib():
         L.rom_state_offsets.argtypes = [vp, i32, ctypes.POINTER(sz)]
         L.rom_state_init.argtypes = [vp, i32, vp, vp, vp]
         L.rom_step.argtypes = [vp, i32, vp, vp, ctypes.POINTER(rom_opts), vp, vp, vp, vp]
+        L.rom_shape_sensitivity.argtypes = [vp, i32, vp, vp, vp, vp]
         L.rom_homogenized_stress_tangent.argtypes = [vp, i32, vp, vp, vp, vp]
         L.rom_timing_enable.argtypes = [vp, ctypes.c_int]
         L.rom_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -184,6 +185,11 @@ def rom_step(h, batch, Fbar_ptr, state_ptr, opts, status_ptr, iters_ptr, res_ptr
 def rom_homogenized_stress_tangent(h, batch, state_ptr, Pbar_ptr, Abar_ptr, stream):
     return _check(lib().rom_homogenized_stress_tangent(h, batch, state_ptr, Pbar_ptr, Abar_ptr, stream),
                   'rom_homogenized_stress_tangent')
+
+
+def rom_shape_sensitivity(h, batch, Fbar_ptr, state_ptr, dPdmu_ptr, stream):
+    return _check(lib().rom_shape_sensitivity(h, batch, Fbar_ptr, state_ptr, dPdmu_ptr, stream),
+                  'rom_shape_sensitivity')
 
 
 def rom_timing_enable(h, enable=True):

@@ -8,7 +8,8 @@ import torch
 
 from . import (FIELD_ABAR, FIELD_FBAR_COMMITTED, FIELD_H_COMMITTED, FIELD_H_TRIAL, FIELD_MU_OK, FIELD_PBAR, FIELD_R_COMMITTED,
                FIELD_R_TRIAL, FIELD_TRANSFORM, rom_default_opts, rom_free, rom_homogenized_stress_tangent,
-               rom_info, rom_load_file, rom_state_bytes, rom_state_init, rom_state_offsets, rom_step)
+               rom_info, rom_load_file, rom_shape_sensitivity, rom_state_bytes, rom_state_init, rom_state_offsets,
+               rom_step)
 
 
 class RomBatch:
@@ -53,6 +54,16 @@ class RomBatch:
                                        self.Abar.data_ptr(), self.stream.cuda_stream)
         self._keep = Fb  # keep alive until the stream has consumed it
         return self.status, self.iters, self.resnorm
+
+    def shape_sensitivity(self, Fbar):
+        """dPbar/dmu (P, 4, n_mu) at the returned state of the last step, which
+        must have been a trial step (commit = 0) to the same Fbar."""
+        Fb = torch.as_tensor(Fbar, dtype=torch.float64, device=self.device).reshape(self.P, 4).contiguous()
+        out = torch.empty(self.P, 4, self.info['n_mu'], dtype=torch.float64, device=self.device)
+        rom_shape_sensitivity(self.h, self.P, Fb.data_ptr(), self.state.data_ptr(), out.data_ptr(),
+                              self.stream.cuda_stream)
+        self._keep_s = Fb
+        return out
 
     def _view(self, field, shape, dtype=torch.float64):
         off = self.offsets[field]

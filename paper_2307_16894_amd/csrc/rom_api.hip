@@ -304,6 +304,15 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
   return ROM_EINVAL;
 }
 
+int rom_shape_sensitivity(rom_handle h, int32_t batch, const double* Fbar_dev, const void* state_dev,
+                          double* dPdmu_dev, hipStream_t stream) {
+  if (!h || batch < 0) return ROM_EINVAL;
+  if (batch == 0) return ROM_OK;
+  if (!Fbar_dev || !state_dev || !dPdmu_dev || batch > 65535) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  return rom_launch_shape_sensitivity(h, batch, Fbar_dev, state_dev, dPdmu_dev, stream);
+}
+
 int rom_features(rom_handle h, int32_t batch, const double* Fbar_dev, const void* state_dev, float* X_dev,
                  hipStream_t stream) {
   if (!h || batch < 0) return ROM_EINVAL;

@@ -51,7 +51,7 @@ enum {
   F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK, F_FBC, F_RG,
   F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT, F_XF, F_DR, F_MU, F_LIST,
   F_D, F_W, F_K, F_F, F_PIV,
-  F_REC, F_PHI, F_PHD, F_LIST2, F_LIST3, F_LIST4, F_HKIN,
+  F_REC, F_PHI, F_PHD, F_LIST2, F_LIST3, F_LIST4, F_HKIN, F_ZK,
   F_NFIELDS
 };
 
@@ -100,6 +100,7 @@ static inline StateLayout rom_state_layout(const rom_model* h, size_t P) {
   sz[F_LIST3] = P * 4;
   sz[F_LIST4] = P * 4;
   sz[F_HKIN] = (h->npad <= ROM_PHASED_NPAD) ? P * 4 * m * 8 : 0;
+  sz[F_ZK] = P * n * 4 * 8;  // K*^-1 C at the returned state (shape sensitivities)
   StateLayout L;
   size_t o = 0;
   for (int i = 0; i < F_NFIELDS; ++i) {

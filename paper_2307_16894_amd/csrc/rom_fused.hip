@@ -76,6 +76,7 @@ int rom_fused_prepare(rom_model* h, int P, const double* Fbar, void* state, cons
   a.res_out = res_out;
   a.rg = field<double>(state, L, F_RG);
   a.fbc = field<double>(state, L, F_FBC);
+  a.zk = field<double>(state, L, F_ZK);
   a.active = o.active;
   if (o.warm_start == ROM_WARM_MLP) {
     int nin = 0, nout = 0;

@@ -29,6 +29,7 @@ struct FusedArgs {
   const float* dr;   // warm-start increments [P][n] (NULL: plain guess)
   double* rg;        // initial guess actually used [P][n]
   double* fbc;       // committed Fbar [P][4]
+  double* zk;        // K*^-1 C at the returned state [P][n][4]
   // phased form: the first evaluations of attempt 0 as a material launch and a
   // contraction launch per evaluation, the points still running after them
   // handed to the fused kernel, which resumes them from this state

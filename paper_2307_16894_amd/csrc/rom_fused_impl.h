@@ -822,7 +822,7 @@ __device__ __forceinline__ bool eval_status(const FusedArgs& a, int it, double r
 
 // Effective quantities at the returned state (after the elimination of the
 // evaluation): Pbar = sum w|J| P, Abar = sum w|J| A - C^T K*^-1 C, per unit
-// cell area (Sec. 3.3).
+// cell area (Sec. 3.3); K*^-1 C itself to the state.
 template <int T>
 __device__ __forceinline__ void write_effective(const FusedArgs& a, int p, const double* sK, const double* sC,
                                                 const int* sOrd, int n, int tid) {
@@ -838,6 +838,9 @@ __device__ __forceinline__ void write_effective(const FusedArgs& a, int p, const
       a.Abar[16 * (size_t)p + e] = acc2 * inv_area;
     }
   }
+  // K*^-1 C, kept for the shape sensitivities of the returned state
+  for (int idx = tid; idx < 4 * n; idx += 256)
+    a.zk[(size_t)p * 4 * n + idx] = sK[sOrd[idx >> 2] * LD + n + 1 + (idx & 3)];
   __syncthreads();
 }
 

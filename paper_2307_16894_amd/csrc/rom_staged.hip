@@ -411,7 +411,7 @@ __global__ __launch_bounds__(128) void k_effective(int n, int npad, int m, doubl
                                                    const double* __restrict__ hc, const double* __restrict__ tmu,
                                                    const int* __restrict__ muok, const double* __restrict__ LU,
                                                    const int* __restrict__ piv, double* __restrict__ Pbar,
-                                                   double* __restrict__ Abar) {
+                                                   double* __restrict__ Abar, double* __restrict__ zk) {
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   if (!muok[p]) {
@@ -531,6 +531,7 @@ __global__ __launch_bounds__(128) void k_effective(int n, int npad, int m, doubl
     }
     __syncthreads();
   }
+  for (int idx = tid; idx < 4 * n; idx += 128) zk[(size_t)p * 4 * n + idx] = Y[idx];  // K*^-1 C
   if (tid < 16) {
     const int x = tid / 4, y = tid % 4;
     double s = red[(4 + tid) * 2] + red[(4 + tid) * 2 + 1];
@@ -707,7 +708,8 @@ int rom_launch_step_staged(rom_model* h, int P, const double* Fbar, void* state,
                                       iters, res);
   }
   k_effective<<<P, 128, 0, s>>>(n, h->npad, m, 1.0 / h->cell_area, h->mp, h->Gt, h->Gq, Fbar, rt, hc, tmu, muok,
-                                K, piv, field<double>(state, L, F_PBAR), field<double>(state, L, F_ABAR));
+                                K, piv, field<double>(state, L, F_PBAR), field<double>(state, L, F_ABAR),
+                                field<double>(state, L, F_ZK));
   k_finish<<<P, 256, 0, s>>>(n, m, o.commit, Fbar, field<double>(state, L, F_FBC), status, iters, res, rt, rc, ht,
                              hc, st_out, it_out, res_out);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
