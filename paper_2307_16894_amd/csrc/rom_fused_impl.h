@@ -1038,12 +1038,13 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
 // one that goes on is listed for the next phased evaluation, or after ph_k
 // evaluations for the fused kernel; an attempt that fails with load-step
 // cutting on is handed to the fused kernel from its start.
-// waves per SIMD the contraction kernel is compiled for: four workgroups per
-// compute unit for the FP64 forms of up to three column tiles (measured 4%
-// faster than three at n = 40), the compiler's choice otherwise
+// waves per SIMD the contraction kernel is compiled for, up to three column
+// tiles: four for FP64 (measured 4% faster than three at n = 40), three for
+// BF16 (7% faster than the compiler's two, with the record loads not
+// prefetched); the compiler's choice otherwise
 template <int T, int PREC>
 constexpr int cs_waves() {
-  return (T <= 3 && PREC == PREC_F64) ? 4 : 1;
+  return (T <= 3 && PREC == PREC_F64) ? 4 : ((T <= 3 && PREC == PREC_BF16) ? 3 : 1);
 }
 
 template <int T, int PREC, int SPLIT>
@@ -1083,7 +1084,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cs_waves<T,
   // and the rest of D with W and F_mu formed from P and F_mu^-1
   const int j = tid & (CCH - 1), kh = tid / CCH;
   constexpr int DR = (PREC == PREC_BF16) ? 1 : 2;  // record rows of D in halves of eight
-  if constexpr (PREC == PREC_F64 || T > 4) {
+  if constexpr (PREC != PREC_F32 || T > 4) {
     for (int q0 = 0; q0 < m; q0 += CCH) {
       const int qend = min(CCH, m - q0), q = q0 + j;
       if (j < qend) {
@@ -1112,9 +1113,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cs_waves<T,
       __syncthreads();
     }
   } else {
-    // reduced precision up to four column tiles: the global loads of the
-    // next chunk are issued before the current chunk is contracted (the FP64
-    // contraction and the wider ones need these registers themselves)
+    // FP32 up to four column tiles: the global loads of the next chunk are
+    // issued before the current chunk is contracted (the FP64, BF16 and wider
+    // contractions are faster with these registers for themselves)
     double v[8], Pv[4], Fv[4], wv = 0.0;
     auto load_chunk = [&](int q0) {
       const int q = q0 + j;
