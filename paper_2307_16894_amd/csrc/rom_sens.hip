@@ -46,8 +46,8 @@ __device__ void mu_to_dc(int kind, const double* mu, double r0, double void_area
 }
 
 // One workgroup per point.  Lanes take the ECM points of a chunk (material
-// and the per-parameter b, d); then lane pairs (mode i, parameter k)
-// accumulate df/dmu = sum_q G_q^T b over the chunk from LDS.
+// and the per-parameter b, d); then df/dmu = sum_q G_q^T b over the chunk on
+// MFMA, the waves splitting its points.
 __global__ __launch_bounds__(256) void k_sens(int n, int npad, int m, int c, int kind, int n_mu, double r0,
                                               double void_area, double inv_area, J2Params mp,
                                               const double* __restrict__ Gt, const double* __restrict__ Gq,
@@ -79,7 +79,15 @@ __global__ __launch_bounds__(256) void k_sens(int n, int npad, int m, int c, int
   for (int k = 0; k < SENS_MU; ++k)
 #pragma unroll
     for (int r = 0; r < 4; ++r) d[k][r] = 0.0;
-  double bacc[4] = {0.0, 0.0, 0.0, 0.0};  // df/dmu entries t = tid + 256 j: mode t % n, parameter t / n
+  // df/dmu = sum_q G_q^T b_q on MFMA: A = G_q^T (row tile I: lane (k, i) holds
+  // component k of mode 16 I + i), B = b_q (lane (k, j) holds b_q[k] of
+  // parameter j), the four components as the inner dimension; each wave takes
+  // a quarter of a chunk's points, the wave sums are added at the end
+  constexpr int TMAX = ROM_NMAX / 16;
+  const int T = npad / 16, k_row = lane >> 4, c_col = lane & 15;
+  d4 acc[TMAX];
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
   for (int q0 = 0; q0 < m; q0 += SCH) {
     const int q = q0 + tid;
     if (tid < SCH && q < m) {
@@ -134,22 +142,13 @@ __global__ __launch_bounds__(256) void k_sens(int n, int npad, int m, int c, int
     }
     __syncthreads();
     const int qend = min(SCH, m - q0);
+    const int qa = (wave * qend) >> 2, qb = ((wave + 1) * qend) >> 2;
+    for (int ql = qa; ql < qb; ++ql) {
+      const double* g = Gq + ((size_t)(q0 + ql) * 4 + k_row) * npad + c_col;
+      const double bv = (c_col < n_mu) ? sB[((size_t)ql * SENS_MU + c_col) * 4 + k_row] : 0.0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int t = tid + 256 * j;
-      if (t < n * n_mu) {
-        const int i = t % n, k = t / n;
-        double s = bacc[j];
-        for (int ql = 0; ql < qend; ++ql) {
-          const double* g = Gq + (size_t)(q0 + ql) * 4 * npad + i;
-          const double* bb = sB + ((size_t)ql * SENS_MU + k) * 4;
-          s = fma(g[0], bb[0], s);
-          s = fma(g[npad], bb[1], s);
-          s = fma(g[2 * npad], bb[2], s);
-          s = fma(g[3 * npad], bb[3], s);
-        }
-        bacc[j] = s;
-      }
+      for (int t = 0; t < TMAX; ++t)
+        if (t < T) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[16 * t], bv, acc[t], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -164,12 +163,25 @@ __global__ __launch_bounds__(256) void k_sens(int n, int npad, int m, int c, int
       if (lane == 0) sDw[(k * 4 + r) * 4 + wave] = v;
     }
   }
+  // wave sums of df/dmu in a fixed order (output row k_row + 4 j of tile t,
+  // column c_col); sB is free after the last chunk
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int t = tid + 256 * j;
-    if (t < n * n_mu) sBf[t] = bacc[j];
+      for (int t = 0; t < TMAX; ++t) {
+        if (t >= T) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = 16 * t + k_row + 4 * j;
+          if (i < n && c_col < n_mu) {
+            const double v = acc[t][j];
+            sBf[i + n * c_col] = (w == 0) ? v : sBf[i + n * c_col] + v;
+          }
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (tid < 4 * n_mu) {
     const int r = tid / n_mu, k = tid % n_mu;
     const double* w4 = sDw + (k * 4 + r) * 4;
@@ -184,7 +196,7 @@ __global__ __launch_bounds__(256) void k_sens(int n, int npad, int m, int c, int
 
 int rom_launch_shape_sensitivity(rom_model* h, int P, const double* Fbar, const void* state, double* out,
                                  hipStream_t s) {
-  if (h->n_mu > SENS_MU || h->c > 12 || h->n * h->n_mu > 1024) return ROM_EUNSUPPORTED;
+  if (h->n_mu > SENS_MU || h->n_mu > 16 || h->c > 12 || h->npad > ROM_NMAX) return ROM_EUNSUPPORTED;
   const StateLayout L = rom_state_layout(h, P);
   void* st = const_cast<void*>(state);
   k_sens<<<P, 256, 0, s>>>(h->n, h->npad, h->m, h->c, h->kind, h->n_mu, h->r0, h->void_area, 1.0 / h->cell_area,
