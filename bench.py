@@ -63,7 +63,7 @@ VARIANTS = WORKLOADS[DEFAULT]['variants']
 # warm-start training: 40 epochs of minibatch Adam, cosine-decayed from 4e-3
 # (measured on the n = 40 workload: 3.29 Newton evaluations per point-step
 # against 3.51 after 12 epochs at 2e-3; training is set-up, not timed)
-WS_EPOCHS = 40
+WS_EPOCHS = 80
 PBAR_TOL = 1e-5  # reduced-precision forms: largest admitted |Pbar - Pbar_FP64| / max |Pbar_FP64|
 SUBSTEPS = 4  # load-step cutting depth of the fused forms: a failed step is retried in up to 1/16 strides
 

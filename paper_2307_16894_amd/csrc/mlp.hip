@@ -35,9 +35,14 @@ struct rom_mlp {
   float* dZ;               // [B][max N]
   float* dA;               // [B][max K]
   float* loss_part;        // [grid] partial losses
+  float* kpart;            // [MLP_KSPLIT][max K][max N] partial products of a split inner dimension
+  float* cpart;            // [MLP_CSPLIT][max N] partial column sums
 };
 
 namespace {
+
+constexpr int MLP_KSPLIT = 16;  // most slices of a split inner dimension
+constexpr int MLP_CSPLIT = 32;  // row slices of the bias-gradient column sum
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
 __device__ __forceinline__ float dsilu_f(float z) {
@@ -54,12 +59,16 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 
 // C[M][N] (ldc) = sum_k A(m, k) B(k, n) (+ bias[n]); A(m, k) = A[m * sa0 + k * sa1],
 // B(k, n) = B[k * sb0 + n * sb1].  Workgroup tile 64 x 64, wave tile 32 x 32
-// (2 x 2 MFMA tiles of 16 x 16), out-of-range operands read as zero.
+// (2 x 2 MFMA tiles of 16 x 16), out-of-range operands read as zero.  With
+// gridDim.z > 1 workgroup z sums k in [z kchunk, (z + 1) kchunk) only and
+// writes its product to C + z cstride (kchunk a multiple of 32).
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* __restrict__ Av, long sa0, long sa1,
                                               const void* __restrict__ Bv, long sb0, long sb1, float* __restrict__ C,
-                                              long ldc, const float* __restrict__ bias) {
+                                              long ldc, const float* __restrict__ bias, int kchunk, long cstride) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  C += blockIdx.z * cstride;
   const int g = lane >> 4, c = lane & 15;
   const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
   const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
@@ -71,7 +80,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* _
   if constexpr (BF16) {
     const uint16_t* A = static_cast<const uint16_t*>(Av);
     const uint16_t* B = static_cast<const uint16_t*>(Bv);
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int k0 = kb; k0 < ke; k0 += 32) {
       bf8 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
@@ -79,7 +88,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* _
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           const int k = k0 + 8 * g + t;
-          const uint16_t v = (m < M && k < K) ? A[m * sa0 + k * sa1] : (uint16_t)0;
+          const uint16_t v = (m < M && k < ke) ? A[m * sa0 + k * sa1] : (uint16_t)0;
           a[i][t] = __builtin_bit_cast(__bf16, v);
         }
       }
@@ -89,7 +98,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* _
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           const int k = k0 + 8 * g + t;
-          const uint16_t v = (n < N && k < K) ? B[k * sb0 + n * sb1] : (uint16_t)0;
+          const uint16_t v = (n < N && k < ke) ? B[k * sb0 + n * sb1] : (uint16_t)0;
           b[j][t] = __builtin_bit_cast(__bf16, v);
         }
       }
@@ -101,18 +110,18 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* _
   } else {
     const float* A = static_cast<const float*>(Av);
     const float* B = static_cast<const float*>(Bv);
-    for (int k0 = 0; k0 < K; k0 += 4) {
+    for (int k0 = kb; k0 < ke; k0 += 4) {
       const int k = k0 + g;
       float a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int m = m0 + 16 * i + c;
-        a[i] = (m < M && k < K) ? A[m * sa0 + k * sa1] : 0.f;
+        a[i] = (m < M && k < ke) ? A[m * sa0 + k * sa1] : 0.f;
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int n = n0 + 16 * j + c;
-        b[j] = (n < N && k < K) ? B[k * sb0 + n * sb1] : 0.f;
+        b[j] = (n < N && k < ke) ? B[k * sb0 + n * sb1] : 0.f;
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -188,11 +197,19 @@ __global__ __launch_bounds__(256) void k_loss(int B, int n_out, int Np, const fl
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_loss_final(int nblocks, int B, const float* __restrict__ part, float* __restrict__ loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// one workgroup of 256: strided partial sums, then a fixed-order tree
+__global__ __launch_bounds__(256) void k_loss_final(int nblocks, int B, const float* __restrict__ part,
+                                                    float* __restrict__ loss) {
+  __shared__ float red[256];
   float s = 0.f;
-  for (int i = 0; i < nblocks; ++i) s += part[i];
-  *loss = s / (float)B;
+  for (int i = threadIdx.x; i < nblocks; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] / (float)B;
 }
 
 // dZ = dA * silu'(Z)
@@ -203,13 +220,30 @@ __global__ void k_dsilu(long count, const float* __restrict__ dA, const float* _
   dZ[i] = dA[i] * dsilu_f(Z[i]);
 }
 
-// db[n] = sum_b dZ[b][n]
-__global__ void k_colsum(int B, int N, const float* __restrict__ dZ, float* __restrict__ db) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// partial column sums part[y][n] = sum of dZ[b][n] over the rows of slice y
+// (gridDim.y slices of the batch); lanes take 64 consecutive columns, the
+// four waves every fourth row, added in a fixed order
+__global__ __launch_bounds__(256) void k_colsum_part(int B, int N, const float* __restrict__ dZ,
+                                                     float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = blockIdx.x * 64 + lane;
+  const int rows = (B + gridDim.y - 1) / gridDim.y, b0 = blockIdx.y * rows, b1 = min(B, b0 + rows);
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += dZ[(long)b * N + n];
-  db[n] = s;
+  if (n < N)
+    for (int b = b0 + wave; b < b1; b += 4) s += dZ[(long)b * N + n];
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && n < N) part[(long)blockIdx.y * N + n] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// out[i] = sum over s < S of part[s * stride + i], in order of s
+__global__ void k_sum_slices(long count, int S, long stride, const float* __restrict__ part,
+                             float* __restrict__ out) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float s = 0.f;
+  for (int z = 0; z < S; ++z) s += part[z * stride + i];
+  out[i] = s;
 }
 
 __global__ void k_adam(long count, float* __restrict__ P, uint16_t* __restrict__ Pb, float* __restrict__ Mo,
@@ -237,7 +271,27 @@ template <bool BF16>
 void gemm(int M, int N, int K, const void* A, long sa0, long sa1, const void* B, long sb0, long sb1, float* C,
           long ldc, const float* bias, hipStream_t s) {
   dim3 grid((N + 63) / 64, (M + 63) / 64);
-  k_gemm<BF16><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, C, ldc, bias);
+  k_gemm<BF16><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, C, ldc, bias, K + 31, 0);
+}
+
+// C[M][N] (dense, ldc = N, no bias) with a long inner dimension: the grid of
+// output tiles is small, so the inner dimension is split into slices whose
+// products land in kpart and are then added in slice order
+void gemm_split(rom_mlp* m, int M, int N, int K, const float* A, long sa0, long sa1, const float* B, long sb0,
+                long sb1, float* C, hipStream_t s) {
+  const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
+  int S = (256 + tiles - 1) / tiles;
+  S = S < K / 128 ? S : K / 128;
+  S = S < MLP_KSPLIT ? S : MLP_KSPLIT;
+  if (S <= 1) {
+    gemm<false>(M, N, K, A, sa0, sa1, B, sb0, sb1, C, N, nullptr, s);
+    return;
+  }
+  const int kchunk = ((K + S - 1) / S + 31) / 32 * 32;
+  S = (K + kchunk - 1) / kchunk;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, S);
+  k_gemm<false><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, m->kpart, N, nullptr, kchunk, (long)M * N);
+  k_sum_slices<<<nblk((long)M * N), 256, 0, s>>>((long)M * N, S, (long)M * N, m->kpart, C);
 }
 
 struct DeviceGuard {
@@ -253,7 +307,8 @@ struct DeviceGuard {
 
 void mlp_release(rom_mlp* m) {
   if (!m) return;
-  void* bufs[] = {m->P, m->Pb, m->Mo, m->Vo, m->G, m->xm, m->xs, m->ym, m->ys, m->dZ, m->dA, m->loss_part};
+  void* bufs[] = {m->P, m->Pb, m->Mo, m->Vo, m->G, m->xm, m->xs, m->ym, m->ys, m->dZ, m->dA, m->loss_part,
+                  m->kpart, m->cpart};
   for (void* b : bufs) (void)hipFree(b);
   for (int l = 0; l < 4; ++l) {
     (void)hipFree(m->A32[l]);
@@ -283,13 +338,15 @@ int mlp_gradients(rom_mlp* m, int B, const float* X, const float* Y, int prec, f
   const int Np = m->N[3];
   const unsigned nb = nblk((long)B * Np);
   k_loss<<<nb, 256, 0, s>>>(B, m->n_out, Np, m->Z[3], Y, m->ym, m->ys, m->dZ, m->loss_part);
-  if (loss) k_loss_final<<<1, 64, 0, s>>>((int)nb, B, m->loss_part, loss);
+  if (loss) k_loss_final<<<1, 256, 0, s>>>((int)nb, B, m->loss_part, loss);
   for (int l = 3; l >= 0; --l) {
     const int K = m->K[l], N = m->N[l];
     if (l < 3) k_dsilu<<<nblk((long)B * N), 256, 0, s>>>((long)B * N, m->dA, m->Z[l], m->dZ);
     // dW = A^T dZ  (M = K, N = N, inner = B)
-    gemm<false>(K, N, B, m->A32[l], 1, K, m->dZ, N, 1, m->G + m->off_w[l], N, nullptr, s);
-    k_colsum<<<nblk(N), 256, 0, s>>>(B, N, m->dZ, m->G + m->off_b[l]);
+    gemm_split(m, K, N, B, m->A32[l], 1, K, m->dZ, N, 1, m->G + m->off_w[l], s);
+    const int cs = B / 64 < MLP_CSPLIT ? (B / 64 > 0 ? B / 64 : 1) : MLP_CSPLIT;
+    k_colsum_part<<<dim3((N + 63) / 64, cs), 256, 0, s>>>(B, N, m->dZ, m->cpart);
+    k_sum_slices<<<nblk(N), 256, 0, s>>>(N, cs, N, m->cpart, m->G + m->off_b[l]);
     // dA_prev = dZ W^T  (M = B, N = K, inner = N)
     if (l > 0) gemm<false>(B, K, N, m->dZ, N, 1, m->P + m->off_w[l], 1, N, m->dA, K, nullptr, s);
   }
@@ -349,6 +406,10 @@ int rom_mlp_create(int32_t n_in, int32_t width, int32_t n_out, int32_t max_batch
   al((void**)&m->dZ, 4L * max_batch * maxKN);
   al((void**)&m->dA, 4L * max_batch * maxKN);
   al((void**)&m->loss_part, 4L * ((long)max_batch * No / 256 + 2));
+  long maxKxN = 0;
+  for (int l = 0; l < 4; ++l) maxKxN = maxKxN > (long)Ks[l] * Ns[l] ? maxKxN : (long)Ks[l] * Ns[l];
+  al((void**)&m->kpart, 4L * MLP_KSPLIT * maxKxN);
+  al((void**)&m->cpart, 4L * MLP_CSPLIT * maxKN);
   if (!ok) {
     mlp_release(m);
     return ROM_EHIP;
