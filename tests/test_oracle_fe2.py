@@ -1,0 +1,122 @@
+"""The oracle's two-scale macro solve (Sec. 4.2 setting) against what fixes
+it independently of its own code: the interpolation properties of the
+eight-node serendipity element (Kronecker property, partition of unity,
+exact reproduction of its eight-term polynomial space), the block's area
+and first moment, the resultant and moment of the parabolic traction in
+closed form, the patch test (a homogeneous block under boundary
+displacements of a uniform deformation gradient must deform uniformly,
+whatever the material), and the assembled macro tangent against central
+differences of the internal force through the RVE solves."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fe2
+from oracle.rom import ROM
+from tests.conftest import rom_path
+
+MONOMIALS = [lambda x, y: np.ones_like(x), lambda x, y: x, lambda x, y: y, lambda x, y: x * x,
+             lambda x, y: x * y, lambda x, y: y * y, lambda x, y: x * x * y, lambda x, y: x * y * y]
+D_MONOMIALS = [lambda x, y: (0 * x, 0 * x), lambda x, y: (1 + 0 * x, 0 * x), lambda x, y: (0 * x, 1 + 0 * x),
+               lambda x, y: (2 * x, 0 * x), lambda x, y: (y, x), lambda x, y: (0 * x, 2 * y),
+               lambda x, y: (2 * x * y, x * x), lambda x, y: (y * y, 2 * x * y)]
+
+
+def test_q8_kronecker_and_partition_of_unity():
+    for a, (xi, eta) in enumerate(fe2.Q8_NODES):
+        N, _ = fe2.q8_shape(xi, eta)
+        assert np.allclose(N, np.eye(8)[a], atol=1e-15)
+    g = workloads.rng(5)
+    for xi, eta in g.uniform(-1, 1, size=(20, 2)):
+        N, dN = fe2.q8_shape(xi, eta)
+        assert abs(N.sum() - 1) < 1e-14
+        assert np.abs(dN.sum(axis=0)).max() < 1e-14
+
+
+def test_q8_reproduces_its_polynomial_space():
+    g = workloads.rng(6)
+    for f, df in zip(MONOMIALS, D_MONOMIALS):
+        nodal = f(fe2.Q8_NODES[:, 0], fe2.Q8_NODES[:, 1])
+        for xi, eta in g.uniform(-1, 1, size=(10, 2)):
+            N, dN = fe2.q8_shape(xi, eta)
+            assert abs(N @ nodal - f(xi, eta)) < 1e-14
+            assert np.allclose(dN.T @ nodal, df(xi, eta), atol=1e-13)
+
+
+def test_geometry_area_and_first_moment():
+    mesh = workloads.fe2_mesh(4, 3)
+    geo = fe2.geometry(mesh)
+    W, H = mesh['width'], mesh['height']
+    assert abs(geo['wJ'].sum() - W * H) < 1e-13
+    assert np.allclose(geo['wJ'] @ geo['Xg'], [W * W * H / 2, W * H * H / 2], atol=1e-13)
+    # a quadratic displacement field: dF is its exact gradient at every point
+    X = mesh['X']
+    u = np.stack([0.01 * X[:, 0] ** 2, 0.02 * X[:, 0] * X[:, 1]], axis=1).reshape(-1)
+    F = fe2.deformation_gradient(mesh, geo, u)
+    x, y = geo['Xg'][:, 0], geo['Xg'][:, 1]
+    ref = np.stack([np.stack([1 + 0.02 * x, 0 * x], -1), np.stack([0.02 * y, 1 + 0.02 * x], -1)], axis=1)
+    assert np.abs(F - ref).max() < 1e-14
+
+
+def test_traction_resultant_and_moment():
+    mesh = workloads.fe2_mesh(6, 2)
+    Tbar, W = 0.3, mesh['width']
+    f = fe2.external_force(mesh, Tbar).reshape(-1, 2)
+    assert np.abs(f[:, 0]).max() == 0.0
+    assert abs(f[:, 1].sum() + 2.0 / 3.0 * Tbar * W) < 1e-14              # -int T dx
+    assert abs(f[:, 1] @ mesh['X'][:, 0] + Tbar * W * W / 3.0) < 1e-14    # -int T x dx
+    u = np.zeros(2 * mesh['X'].shape[0])
+    u[1::2] = -0.5                                                          # rigid drop
+    assert abs(fe2.compliance(mesh, Tbar, u) - 0.5 * 2.0 / 3.0 * Tbar * W) < 1e-14
+
+
+def _boundary_dofs(mesh):
+    X = mesh['X']
+    on = (X[:, 0] == 0) | (X[:, 1] == 0) | np.isclose(X[:, 0], mesh['width']) | np.isclose(X[:, 1], mesh['height'])
+    nodes = np.flatnonzero(on)
+    return np.sort(np.concatenate([2 * nodes, 2 * nodes + 1]))
+
+
+def test_patch_test_through_the_rve_model():
+    rom = ROM(rom_path('onevoid_n20_m120'))
+    mesh = workloads.fe2_mesh(2, 2)
+    geo = fe2.geometry(mesh)
+    mu = np.tile(workloads.one_void_mu(7, 1), (geo['wJ'].size, 1))
+    F0 = np.array([[1.006, 0.002], [-0.001, 0.995]])
+    fixed = _boundary_dofs(mesh)
+    lin = ((F0 - np.eye(2)) @ mesh['X'].T).T.reshape(-1)
+    res = fe2.run(rom, mesh, mu, [0.0], fixed_dofs=fixed, fixed_values=[lin[fixed]], tol_abs=1e-13)
+    s = res[0]
+    assert s['status'] == 0
+    assert np.abs(s['u'] - lin).max() < 1e-11
+    F = fe2.deformation_gradient(mesh, geo, s['u'])
+    assert np.abs(F - F0).max() < 1e-11
+    ref = rom.step(np.zeros(rom.n), rom.virgin(), F0, *rom.transformation(mu[0]), tol=1e-10)
+    assert np.abs(s['Pbar'] - ref['Pbar']).max() < 1e-9 * np.abs(ref['Pbar']).max()
+
+
+def test_macro_tangent_matches_central_differences():
+    rom = ROM(rom_path('onevoid_n20_m120'))
+    mesh = workloads.fe2_mesh(2, 2)
+    geo = fe2.geometry(mesh)
+    mu = workloads.fe2_shape(geo['Xg'][:, 0], geo['Xg'][:, 1])
+    trans = [rom.transformation(m) for m in mu]
+    g = workloads.rng(8)
+    x, y = mesh['X'][:, 0], mesh['X'][:, 1]   # a smooth field, plastic at some points
+    u = np.stack([0.004 * x * y - 0.002 * y * y, -0.007 * y + 0.002 * x * y], axis=1).reshape(-1)
+
+    def solve(uu):
+        F = fe2.deformation_gradient(mesh, geo, uu)
+        return [rom.step(np.zeros(rom.n), rom.virgin(), F[p], *trans[p], tol=1e-13, max_iter=40)
+                for p in range(len(trans))]
+
+    steps = solve(u)
+    assert all(s['status'] == 0 for s in steps)
+    K = fe2.stiffness(mesh, geo, np.array([s['Abar'] for s in steps]))
+    assert np.abs(K - K.T).max() < 1e-8 * np.abs(K).max()   # Abar has the major symmetry
+    h = 1e-6
+    for d in g.choice(np.flatnonzero(np.abs(u) > 0), 4, replace=False):
+        fp, fm = [fe2.internal_force(mesh, geo, np.array([s['Pbar'] for s in solve(u + sg * h * np.eye(u.size)[d])]))
+                  for sg in (1, -1)]
+        fd = (fp - fm) / (2 * h)
+        assert np.abs(K[:, d] - fd).max() < 1e-6 * np.abs(K[:, d]).max(), d

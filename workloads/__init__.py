@@ -105,3 +105,67 @@ def uneven_cyclic_paths(seed, P, nsteps, rho=(0.02, 0.08)):
         beta = np.concatenate([beta, np.full(Kmax - K, beta[-1])])
         out[p] = np.eye(2)[None] + beta[:, None, None] * E[p][None]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Two-scale workload (Sec. 4.2 setting, rescaled to the ROMs' material):
+# a W x H block meshed with nx x ny eight-node quadrilaterals, fixed at the
+# bottom, loaded on the top edge by a downward parabolic traction of peak
+# Tbar_k; the void shape varies smoothly over the block.
+
+FE2_WIDTH, FE2_HEIGHT = 2.0, 1.0
+FE2_KAPPA = (1.4, 1.01)     # kappa(x, y) = KAPPA[0] - (KAPPA[0] - KAPPA[1]) y / H
+FE2_VOID = (0.12, 0.20)     # v(x, y) = VOID[0] + (VOID[1] - VOID[0]) (1 - x / (W / 2))^2
+
+
+def fe2_mesh(nx, ny, width=FE2_WIDTH, height=FE2_HEIGHT):
+    """Structured Q8 mesh of [0, width] x [0, height].
+
+    Nodes are numbered column by column in x (corner columns carry 2 ny + 1
+    nodes, the columns between them ny + 1), which keeps the bandwidth of
+    the stiffness small.  Element nodes: corners counterclockwise from
+    (-1, -1), then the midsides of the edges bottom, right, top, left.
+    Returns X (nodes, 2), conn (elements, 8), bottom (nodes on y = 0) and
+    top (elements, 3: nodes of each top edge from left to right)."""
+    dx, dy = width / nx, height / ny
+    X, full, mid = [], {}, {}
+    for c in range(2 * nx + 1):
+        x = 0.5 * c * dx
+        for j in range(2 * ny + 1):
+            if c % 2 == 1 and j % 2 == 1:
+                continue
+            (full if c % 2 == 0 else mid)[(c, j)] = len(X)
+            X.append((x, 0.5 * j * dy))
+    node = {**full, **mid}
+    conn, top = [], []
+    for i in range(nx):
+        for j in range(ny):
+            c0, c1, j0, j1 = 2 * i, 2 * i + 2, 2 * j, 2 * j + 2
+            e = [node[(c0, j0)], node[(c1, j0)], node[(c1, j1)], node[(c0, j1)],
+                 node[(c0 + 1, j0)], node[(c1, j0 + 1)], node[(c0 + 1, j1)], node[(c0, j0 + 1)]]
+            conn.append(e)
+            if j == ny - 1:
+                top.append((e[3], e[6], e[2]))
+    X = np.array(X)
+    bottom = np.flatnonzero(X[:, 1] == 0.0)
+    return dict(X=X, conn=np.array(conn, dtype=np.int32), bottom=bottom.astype(np.int32),
+                top=np.array(top, dtype=np.int32), width=width, height=height)
+
+
+def fe2_shape(x, y, width=FE2_WIDTH, height=FE2_HEIGHT):
+    """Semi-axes (a, b) of the one-void cell at reference position (x, y):
+    aspect ratio kappa = b / a and void fraction v = pi a b of the unit cell
+    vary linearly in y and quadratically in x."""
+    kappa = FE2_KAPPA[0] - (FE2_KAPPA[0] - FE2_KAPPA[1]) * np.asarray(y) / height
+    v = FE2_VOID[0] + (FE2_VOID[1] - FE2_VOID[0]) * (1.0 - np.asarray(x) / (0.5 * width)) ** 2
+    a = np.sqrt(v / (np.pi * kappa))
+    return np.stack([a, kappa * a], axis=-1)
+
+
+def fe2_loads(steps, peak):
+    """Peak traction per load step: up linearly to `peak` over steps / 2
+    steps, then back to zero."""
+    half = steps // 2
+    beta = np.concatenate([np.arange(1, half + 1) / half,
+                           1.0 - np.arange(1, steps - half + 1) / (steps - half)])
+    return peak * beta
