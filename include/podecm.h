@@ -286,6 +286,57 @@ int rom_path_advance(int32_t batch, const int32_t* active_dev, int32_t* step_dev
 int rom_timing_enable(rom_handle h, int enable);
 int rom_timing_read(rom_handle h, double* total_ms, int64_t* launches);
 
+/*
+ * Two-scale (FE^2) macro side (Sec. 4.2: a block of eight-node quadrilateral
+ * elements with four Gauss points each, fixed where the caller says,
+ * loaded on its top edge by the downward traction
+ * T(x) = Tbar (1 - (2 x / W - 1)^2) as a dead load).  Its quadrature points
+ * p = 4 e + g (g: Gauss points (-,-), (+,-), (+,+), (-,+) of the parent
+ * square) are the batch of rom_step: Fbar from the macro displacements,
+ * then Pbar and Abar of the RVE back into the macro Newton step.  Total
+ * Lagrangian, plane strain; dofs 2 n + i.
+ *
+ * rom_fe2_create copies the mesh (host arrays): X [nodes][2]; conn
+ * [elements][8], corners counterclockwise from the parent corner (-1, -1),
+ * then the midsides of the bottom, right, top and left edges; the fixed
+ * dofs; top [ntop][3] the nodes of each loaded edge (ends and middle, in
+ * order along the edge); width W of the traction profile.  It computes the
+ * point geometry on the device and sizes the banded solve from the
+ * numbering (half-bandwidth kl of the free dofs at most 255: number the
+ * nodes across the short side).  Returns ROM_EINVAL for out-of-range
+ * indices, repeated fixed dofs or no free dof, ROM_EUNSUPPORTED for a wider
+ * band.  The handle owns the band workspace: calls that overlap on one
+ * handle race.  All other buffers are caller-owned device memory; the calls
+ * enqueue on the stream and do not synchronise.
+ *
+ * rom_fe2_gradient:   Fbar[p][4] = I + sum_a u_a (x) dN_a/dX.
+ * rom_fe2_traction:   fext[dofs], the consistent nodal forces of T(x).
+ * rom_fe2_residual:   res[dofs] = fext - sum_p B_p^T Pbar_p w|J|; if norms is
+ *                     given, norms[0..1] = ||res||_2, ||fext||_2 over the
+ *                     free dofs.
+ * rom_fe2_solve:      assembles K_ff = sum_p B^T Abar_p B w|J| (free rows and
+ *                     columns) and solves K_ff du_f = res_f - K_fd du_d by
+ *                     banded LU with partial pivoting; u_f += du_f and
+ *                     u_d += du_d (du_d [nfixed] in the order of the fixed
+ *                     list, or NULL for zero).  info = 0, or k + 1 when
+ *                     column k has no nonzero pivot (u unchanged).
+ * rom_fe2_compliance: C = int_top T(x) (-u_y) dx, the work of the load.
+ */
+typedef struct rom_fe2* rom_fe2_handle;
+int rom_fe2_create(int32_t nodes, int32_t elements, const double* X_host, const int32_t* conn_host, int32_t nfixed,
+                   const int32_t* fixed_dofs_host, int32_t ntop, const int32_t* top_host, double width, int device,
+                   rom_fe2_handle* out);
+int rom_fe2_free(rom_fe2_handle h);
+int rom_fe2_info(rom_fe2_handle h, int32_t* dofs, int32_t* free_dofs, int32_t* points, int32_t* kl);
+int rom_fe2_points(rom_fe2_handle h, double* Xg_dev, hipStream_t stream);
+int rom_fe2_gradient(rom_fe2_handle h, const double* u_dev, double* Fbar_dev, hipStream_t stream);
+int rom_fe2_traction(rom_fe2_handle h, double Tbar, double* fext_dev, hipStream_t stream);
+int rom_fe2_residual(rom_fe2_handle h, const double* Pbar_dev, const double* fext_dev, double* res_dev,
+                     double* norms_dev, hipStream_t stream);
+int rom_fe2_solve(rom_fe2_handle h, const double* Abar_dev, const double* res_dev, const double* dud_dev,
+                  double* u_dev, int32_t* info_dev, hipStream_t stream);
+int rom_fe2_compliance(rom_fe2_handle h, double Tbar, const double* u_dev, double* C_dev, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

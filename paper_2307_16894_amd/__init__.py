@@ -41,7 +41,9 @@ EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_inf
            'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent', 'rom_shape_sensitivity',
            'rom_timing_enable', 'rom_timing_read', 'rom_mlp_create', 'rom_mlp_free', 'rom_mlp_param_count',
            'rom_mlp_set_params', 'rom_mlp_get_params', 'rom_mlp_set_scaling', 'rom_mlp_forward',
-           'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features', 'rom_path_gather', 'rom_path_advance']
+           'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features', 'rom_path_gather', 'rom_path_advance',
+           'rom_fe2_create', 'rom_fe2_free', 'rom_fe2_info', 'rom_fe2_points', 'rom_fe2_gradient', 'rom_fe2_traction',
+           'rom_fe2_residual', 'rom_fe2_solve', 'rom_fe2_compliance']
 
 
 class RomError(RuntimeError):
@@ -114,6 +116,16 @@ def lib():
         L.rom_features.argtypes = [vp, i32, vp, vp, vp, vp]
         L.rom_path_gather.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp]
         L.rom_path_advance.argtypes = [i32, vp, vp, vp]
+        dbl = ctypes.c_double
+        L.rom_fe2_create.argtypes = [i32, i32, vp, vp, i32, vp, i32, vp, dbl, ctypes.c_int, ctypes.POINTER(vp)]
+        L.rom_fe2_free.argtypes = [vp]
+        L.rom_fe2_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
+        L.rom_fe2_points.argtypes = [vp, vp, vp]
+        L.rom_fe2_gradient.argtypes = [vp, vp, vp, vp]
+        L.rom_fe2_traction.argtypes = [vp, dbl, vp, vp]
+        L.rom_fe2_residual.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.rom_fe2_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.rom_fe2_compliance.argtypes = [vp, dbl, vp, vp, vp]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -274,3 +286,51 @@ def rom_path_advance(batch, active_ptr, step_ptr, stream):
 def rom_fused_tiles(n):
     """16-column blocks of the fused contraction for n modes (f and C ride in columns n .. n+4)."""
     return (n + 5 + 15) // 16
+
+
+def rom_fe2_create(X, conn, fixed_dofs, top, width, device=0):
+    """Macro mesh on the device (host numpy inputs are copied)."""
+    import numpy as np
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    fixed = np.ascontiguousarray(fixed_dofs, dtype=np.int32)
+    top = np.ascontiguousarray(top, dtype=np.int32).reshape(-1, 3)
+    h = ctypes.c_void_p()
+    _check(lib().rom_fe2_create(X.shape[0], conn.shape[0], X.ctypes.data, conn.ctypes.data, fixed.size,
+                                fixed.ctypes.data, top.shape[0], top.ctypes.data, float(width), device,
+                                ctypes.byref(h)), 'rom_fe2_create')
+    return h
+
+
+def rom_fe2_free(h):
+    _check(lib().rom_fe2_free(h), 'rom_fe2_free')
+
+
+def rom_fe2_info(h):
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().rom_fe2_info(h, *[ctypes.byref(x) for x in v]), 'rom_fe2_info')
+    return dict(dofs=v[0].value, free_dofs=v[1].value, points=v[2].value, kl=v[3].value)
+
+
+def rom_fe2_points(h, Xg_ptr, stream):
+    _check(lib().rom_fe2_points(h, Xg_ptr, stream), 'rom_fe2_points')
+
+
+def rom_fe2_gradient(h, u_ptr, Fbar_ptr, stream):
+    _check(lib().rom_fe2_gradient(h, u_ptr, Fbar_ptr, stream), 'rom_fe2_gradient')
+
+
+def rom_fe2_traction(h, Tbar, fext_ptr, stream):
+    _check(lib().rom_fe2_traction(h, float(Tbar), fext_ptr, stream), 'rom_fe2_traction')
+
+
+def rom_fe2_residual(h, Pbar_ptr, fext_ptr, res_ptr, norms_ptr, stream):
+    _check(lib().rom_fe2_residual(h, Pbar_ptr, fext_ptr, res_ptr, norms_ptr, stream), 'rom_fe2_residual')
+
+
+def rom_fe2_solve(h, Abar_ptr, res_ptr, dud_ptr, u_ptr, info_ptr, stream):
+    _check(lib().rom_fe2_solve(h, Abar_ptr, res_ptr, dud_ptr, u_ptr, info_ptr, stream), 'rom_fe2_solve')
+
+
+def rom_fe2_compliance(h, Tbar, u_ptr, C_ptr, stream):
+    _check(lib().rom_fe2_compliance(h, float(Tbar), u_ptr, C_ptr, stream), 'rom_fe2_compliance')

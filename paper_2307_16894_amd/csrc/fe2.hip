@@ -1,0 +1,543 @@
+// Macro side of the two-scale problem (Sec. 4.2): a block of eight-node
+// quadrilaterals with 2 x 2 Gauss points, whose quadrature points are the
+// batch of the reduced RVE solve.  Total Lagrangian, plane strain: the macro
+// deformation gradient at a point is Fbar = I + sum_a u_a (x) dN_a/dX, the
+// internal force sum_p B_p^T Pbar_p w|J|, the tangent sum_p B_p^T Abar_p B_p
+// w|J| with Pbar and Abar of the RVE (eqs. eff_stress_1, eff_stiffness_1).
+// The top edge carries the downward traction T(x) = Tbar (1 - (2x/W - 1)^2)
+// as a dead load; the compliance is the work of that load.
+//
+// Layout: nodes numbered by the caller (a numbering with a small bandwidth
+// keeps the banded solve short), dofs 2 n + i, quadrature points p = 4 e + g.
+// The free-dof stiffness is held as a band of kl sub- and kl + kl super-
+// diagonals (room for the fill of row interchanges), row-major: row r keeps
+// columns r - kl .. r + 2 kl at offset c - r + kl.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "podecm.h"
+
+struct rom_fe2 {
+  int device;
+  int nodes, elements, points, dofs, nfixed, nfree, ntop, kl, ldab;
+  double width;
+  // device
+  double *X, *dNdX, *wJ, *Xg, *band, *rhs;
+  int *conn, *node_ptr, *node_ent, *dofmap, *fixed, *top;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// parent coordinates of the eight nodes: corners counterclockwise from
+// (-1, -1), then midsides of the bottom, right, top and left edges
+__constant__ double c_node_xi[8] = {-1, 1, 1, -1, 0, 1, 0, -1};
+__constant__ double c_node_eta[8] = {-1, -1, 1, 1, -1, 0, 1, 0};
+
+// serendipity shape function of node a and its parent derivatives
+__device__ void q8(int a, double xi, double eta, double& N, double& dxi, double& deta) {
+  const double xa = c_node_xi[a], ea = c_node_eta[a];
+  if (xa != 0.0 && ea != 0.0) {
+    const double sx = 1.0 + xi * xa, se = 1.0 + eta * ea, t = xi * xa + eta * ea - 1.0;
+    N = 0.25 * sx * se * t;
+    dxi = 0.25 * xa * se * (t + sx);
+    deta = 0.25 * ea * sx * (t + se);
+  } else if (xa == 0.0) {
+    const double se = 1.0 + eta * ea;
+    N = 0.5 * (1.0 - xi * xi) * se;
+    dxi = -xi * se;
+    deta = 0.5 * ea * (1.0 - xi * xi);
+  } else {
+    const double sx = 1.0 + xi * xa;
+    N = 0.5 * sx * (1.0 - eta * eta);
+    dxi = 0.5 * xa * (1.0 - eta * eta);
+    deta = -eta * sx;
+  }
+}
+
+// per point: dN/dX [p][8][2], weight x det J (unit Gauss weights), position
+__global__ void k_geometry(int points, const double* __restrict__ X, const int* __restrict__ conn,
+                           double* __restrict__ dNdX, double* __restrict__ wJ, double* __restrict__ Xg) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= points) return;
+  const int e = p >> 2, g = p & 3;
+  const double s = 1.0 / sqrt(3.0);
+  const double xi = (g == 0 || g == 3) ? -s : s, eta = (g < 2) ? -s : s;
+  double dxi[8], deta[8], J00 = 0, J01 = 0, J10 = 0, J11 = 0, x = 0, y = 0;
+  for (int a = 0; a < 8; ++a) {
+    double N;
+    q8(a, xi, eta, N, dxi[a], deta[a]);
+    const int n = conn[8 * e + a];
+    const double Xa = X[2 * n], Ya = X[2 * n + 1];
+    J00 += Xa * dxi[a];  // dX / dxi
+    J01 += Xa * deta[a];
+    J10 += Ya * dxi[a];
+    J11 += Ya * deta[a];
+    x += N * Xa;
+    y += N * Ya;
+  }
+  const double det = J00 * J11 - J01 * J10, inv = 1.0 / det;
+  // dN/dX_J = dN/dxi_j (J^-1)_jJ
+  for (int a = 0; a < 8; ++a) {
+    dNdX[(size_t)p * 16 + 2 * a] = (dxi[a] * J11 - deta[a] * J10) * inv;
+    dNdX[(size_t)p * 16 + 2 * a + 1] = (-dxi[a] * J01 + deta[a] * J00) * inv;
+  }
+  wJ[p] = det;
+  Xg[2 * p] = x;
+  Xg[2 * p + 1] = y;
+}
+
+__global__ void k_gradient(int points, const int* __restrict__ conn, const double* __restrict__ dNdX,
+                           const double* __restrict__ u, double* __restrict__ F) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= points) return;
+  const int e = p >> 2;
+  double f[4] = {1.0, 0.0, 0.0, 1.0};
+  for (int a = 0; a < 8; ++a) {
+    const int n = conn[8 * e + a];
+    const double gx = dNdX[(size_t)p * 16 + 2 * a], gy = dNdX[(size_t)p * 16 + 2 * a + 1];
+    const double ux = u[2 * n], uy = u[2 * n + 1];
+    f[0] = fma(ux, gx, f[0]);
+    f[1] = fma(ux, gy, f[1]);
+    f[2] = fma(uy, gx, f[2]);
+    f[3] = fma(uy, gy, f[3]);
+  }
+  for (int c = 0; c < 4; ++c) F[4 * (size_t)p + c] = f[c];
+}
+
+// three-point Gauss rule on a quadratic edge, nodes (left, middle, right)
+__device__ void edge_rule(int q, double& s, double& w) {
+  const double r = sqrt(0.6);
+  s = (q == 0) ? -r : (q == 1 ? 0.0 : r);
+  w = (q == 1) ? 8.0 / 9.0 : 5.0 / 9.0;
+}
+__device__ void edge_shape(double s, double N[3], double dN[3]) {
+  N[0] = 0.5 * s * (s - 1.0);
+  N[1] = 1.0 - s * s;
+  N[2] = 0.5 * s * (s + 1.0);
+  dN[0] = s - 0.5;
+  dN[1] = -2.0 * s;
+  dN[2] = s + 0.5;
+}
+
+// one workgroup: zero f_ext, then one lane adds the edges in order (the
+// corner nodes are shared by neighbouring edges)
+__global__ void k_traction(int dofs, int ntop, const int* __restrict__ top, const double* __restrict__ X,
+                           double Tbar, double width, double* __restrict__ fext) {
+  for (int d = threadIdx.x; d < dofs; d += blockDim.x) fext[d] = 0.0;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int t = 0; t < ntop; ++t) {
+    const int nd[3] = {top[3 * t], top[3 * t + 1], top[3 * t + 2]};
+    const double xs[3] = {X[2 * nd[0]], X[2 * nd[1]], X[2 * nd[2]]};
+    for (int q = 0; q < 3; ++q) {
+      double s, w, N[3], dN[3];
+      edge_rule(q, s, w);
+      edge_shape(s, N, dN);
+      const double x = N[0] * xs[0] + N[1] * xs[1] + N[2] * xs[2];
+      const double jac = fabs(dN[0] * xs[0] + dN[1] * xs[1] + dN[2] * xs[2]);
+      const double xr = 2.0 * x / width - 1.0, T = Tbar * (1.0 - xr * xr);
+      for (int a = 0; a < 3; ++a) fext[2 * nd[a] + 1] -= N[a] * T * jac * w;
+    }
+  }
+}
+
+__global__ void k_compliance(int ntop, const int* __restrict__ top, const double* __restrict__ X, double Tbar,
+                             double width, const double* __restrict__ u, double* __restrict__ C) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double c = 0.0;
+  for (int t = 0; t < ntop; ++t) {
+    const int nd[3] = {top[3 * t], top[3 * t + 1], top[3 * t + 2]};
+    const double xs[3] = {X[2 * nd[0]], X[2 * nd[1]], X[2 * nd[2]]};
+    const double uy[3] = {u[2 * nd[0] + 1], u[2 * nd[1] + 1], u[2 * nd[2] + 1]};
+    for (int q = 0; q < 3; ++q) {
+      double s, w, N[3], dN[3];
+      edge_rule(q, s, w);
+      edge_shape(s, N, dN);
+      const double x = N[0] * xs[0] + N[1] * xs[1] + N[2] * xs[2];
+      const double jac = fabs(dN[0] * xs[0] + dN[1] * xs[1] + dN[2] * xs[2]);
+      const double xr = 2.0 * x / width - 1.0, T = Tbar * (1.0 - xr * xr);
+      c -= T * (N[0] * uy[0] + N[1] * uy[1] + N[2] * uy[2]) * jac * w;
+    }
+  }
+  *C = c;
+}
+
+// res[d] = f_ext[d] - f_int[d]; lane per dof, gathering the (element, local
+// node) entries of its node in a fixed order
+__global__ void k_residual(int dofs, const int* __restrict__ node_ptr, const int* __restrict__ node_ent,
+                           const double* __restrict__ dNdX, const double* __restrict__ wJ,
+                           const double* __restrict__ Pbar, const double* __restrict__ fext, double* __restrict__ res) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= dofs) return;
+  const int n = d >> 1, i = d & 1;
+  double f = 0.0;
+  for (int k = node_ptr[n]; k < node_ptr[n + 1]; ++k) {
+    const int e = node_ent[k] >> 3, a = node_ent[k] & 7;
+    for (int g = 0; g < 4; ++g) {
+      const int p = 4 * e + g;
+      const double* G = dNdX + (size_t)p * 16 + 2 * a;
+      f = fma((Pbar[4 * (size_t)p + 2 * i] * G[0] + Pbar[4 * (size_t)p + 2 * i + 1] * G[1]), wJ[p], f);
+    }
+  }
+  res[d] = fext[d] - f;
+}
+
+// norms[0] = ||res||_2, norms[1] = ||f_ext||_2 over the free dofs (one
+// workgroup of 256, fixed-order tree)
+__global__ __launch_bounds__(256) void k_norms(int dofs, const int* __restrict__ dofmap,
+                                               const double* __restrict__ res, const double* __restrict__ fext,
+                                               double* __restrict__ norms) {
+  __shared__ double s0[256], s1[256];
+  double a = 0.0, b = 0.0;
+  for (int d = threadIdx.x; d < dofs; d += 256)
+    if (dofmap[d] >= 0) {
+      a = fma(res[d], res[d], a);
+      b = fma(fext[d], fext[d], b);
+    }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      s0[threadIdx.x] += s0[threadIdx.x + h];
+      s1[threadIdx.x] += s1[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    norms[0] = sqrt(s0[0]);
+    norms[1] = sqrt(s1[0]);
+  }
+}
+
+// Band of the free-dof tangent and right-hand side r_f - K_fd du_d: lane per
+// free row, its band row zeroed and then gathered from the points of the
+// elements that hold its node.
+__global__ void k_assemble(int dofs, int kl, int ldab, const int* __restrict__ node_ptr,
+                           const int* __restrict__ node_ent, const int* __restrict__ conn,
+                           const int* __restrict__ dofmap, const double* __restrict__ dNdX,
+                           const double* __restrict__ wJ, const double* __restrict__ Abar,
+                           const double* __restrict__ res, const double* __restrict__ dud, double* __restrict__ band,
+                           double* __restrict__ rhs) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= dofs) return;
+  const int r = dofmap[d];
+  if (r < 0) return;
+  double* row = band + (size_t)r * ldab;
+  for (int c = 0; c < ldab; ++c) row[c] = 0.0;
+  double b = res[d];
+  const int n = d >> 1, i = d & 1;
+  for (int k = node_ptr[n]; k < node_ptr[n + 1]; ++k) {
+    const int e = node_ent[k] >> 3, a = node_ent[k] & 7;
+    for (int g = 0; g < 4; ++g) {
+      const int p = 4 * e + g;
+      const double* G = dNdX + (size_t)p * 16;
+      const double* A = Abar + (size_t)p * 16;
+      // row of B^T Abar for (a, i): v_kL = sum_J dN_a/dX_J A[iJ, kL] w|J|
+      double v[4];
+      for (int kL = 0; kL < 4; ++kL) v[kL] = (G[2 * a] * A[(2 * i) * 4 + kL] + G[2 * a + 1] * A[(2 * i + 1) * 4 + kL]) * wJ[p];
+      for (int bn = 0; bn < 8; ++bn) {
+        const int col_node = conn[8 * e + bn];
+        for (int kk = 0; kk < 2; ++kk) {
+          const double kv = v[2 * kk] * G[2 * bn] + v[2 * kk + 1] * G[2 * bn + 1];
+          const int c = dofmap[2 * col_node + kk];
+          if (c >= 0)
+            row[c - r + kl] += kv;
+          else if (dud)
+            b -= kv * dud[-1 - c];
+        }
+      }
+    }
+  }
+  rhs[r] = b;
+}
+
+// Banded LU with partial pivoting of the free-dof tangent, the row
+// operations applied to the right-hand side as they are made, then back
+// substitution; u_f += x, u_d += du_d.  One workgroup; info = 0, or k + 1 at
+// a zero pivot in column k (u is then left unchanged).
+constexpr int LU_THREADS = 1024;
+__global__ __launch_bounds__(LU_THREADS) void k_band_solve(int nf, int kl, int ldab, double* __restrict__ band,
+                                                           double* __restrict__ rhs, int dofs,
+                                                           const int* __restrict__ dofmap, const int* __restrict__ fixed,
+                                                           int nfixed, const double* __restrict__ dud,
+                                                           double* __restrict__ u, int* __restrict__ info) {
+  __shared__ double s_mult[256];
+  __shared__ int s_piv;
+  __shared__ double s_pv;
+  const int tid = threadIdx.x, ku = 2 * kl;
+  auto at = [&](int rr, int c) -> double& { return band[(size_t)rr * ldab + (c - rr + kl)]; };
+  for (int k = 0; k < nf; ++k) {
+    const int last = min(nf - 1, k + kl);
+    // pivot: the largest |a_ik| over i = k .. last, first on ties (wave 0)
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i <= last; i += 64) {
+        const double v = fabs(at(i, k));
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) s_piv = bi;
+    }
+    __syncthreads();
+    const int pr = s_piv;
+    const int cend = min(nf - 1, k + ku);
+    if (pr != k) {
+      for (int c = k + tid; c <= cend; c += LU_THREADS) {
+        const double t = at(k, c);
+        at(k, c) = at(pr, c);
+        at(pr, c) = t;
+      }
+      if (tid == 0) {
+        const double t = rhs[k];
+        rhs[k] = rhs[pr];
+        rhs[pr] = t;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) s_pv = at(k, k);
+    __syncthreads();
+    const double pv = s_pv;
+    if (pv == 0.0) {
+      if (tid == 0) *info = k + 1;
+      return;
+    }
+    for (int i = k + 1 + tid; i <= last; i += LU_THREADS) s_mult[i - k - 1] = at(i, k) / pv;
+    __syncthreads();
+    const int rows = last - k, cols = cend - k;
+    for (int t = tid; t < rows * cols; t += LU_THREADS) {
+      const int i = k + 1 + t / cols, c = k + 1 + t % cols;
+      at(i, c) = fma(-s_mult[i - k - 1], at(k, c), at(i, c));
+    }
+    for (int i = k + 1 + tid; i <= last; i += LU_THREADS) rhs[i] = fma(-s_mult[i - k - 1], rhs[k], rhs[i]);
+    __syncthreads();
+  }
+  // back substitution on U (upper bandwidth 2 kl), one row at a time
+  __shared__ double s_red[LU_THREADS / 64];
+  for (int k = nf - 1; k >= 0; --k) {
+    const int cend = min(nf - 1, k + ku);
+    double s = 0.0;
+    for (int c = k + 1 + tid; c <= cend; c += LU_THREADS) s = fma(at(k, c), rhs[c], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((tid & 63) == 0) s_red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < LU_THREADS / 64; ++w) t += s_red[w];
+      rhs[k] = (rhs[k] - t) / at(k, k);
+    }
+    __syncthreads();
+  }
+  for (int d = tid; d < dofs; d += LU_THREADS) {
+    const int r = dofmap[d];
+    if (r >= 0) u[d] += rhs[r];
+  }
+  if (dud)
+    for (int j = tid; j < nfixed; j += LU_THREADS) u[fixed[j]] += dud[j];
+  if (tid == 0) *info = 0;
+}
+
+inline unsigned nblk(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+void release(rom_fe2* h) {
+  if (!h) return;
+  void* bufs[] = {h->X, h->dNdX, h->wJ, h->Xg, h->band, h->rhs, h->conn, h->node_ptr, h->node_ent,
+                  h->dofmap, h->fixed, h->top};
+  for (void* b : bufs) (void)hipFree(b);
+  delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rom_fe2_create(int32_t nodes, int32_t elements, const double* X_host, const int32_t* conn_host, int32_t nfixed,
+                   const int32_t* fixed_host, int32_t ntop, const int32_t* top_host, double width, int device,
+                   rom_fe2_handle* out) {
+  if (!out || nodes < 1 || elements < 1 || !X_host || !conn_host || nfixed < 0 || (nfixed > 0 && !fixed_host) ||
+      ntop < 0 || (ntop > 0 && !top_host) || !(width > 0) || elements > (1 << 24))
+    return ROM_EINVAL;
+  *out = nullptr;
+  const int dofs = 2 * nodes;
+  for (long k = 0; k < 8L * elements; ++k)
+    if (conn_host[k] < 0 || conn_host[k] >= nodes) return ROM_EINVAL;
+  for (long k = 0; k < 3L * ntop; ++k)
+    if (top_host[k] < 0 || top_host[k] >= nodes) return ROM_EINVAL;
+  // dof map: free index, or -1 - (index in the fixed list)
+  std::vector<int> dofmap(dofs, 0);
+  for (int j = 0; j < nfixed; ++j) {
+    const int d = fixed_host[j];
+    if (d < 0 || d >= dofs || dofmap[d] < 0) return ROM_EINVAL;
+    dofmap[d] = -1 - j;
+  }
+  int nfree = 0;
+  for (int d = 0; d < dofs; ++d)
+    if (dofmap[d] >= 0) dofmap[d] = nfree++;
+  if (nfree < 1) return ROM_EINVAL;
+  // node -> (element, local node) entries, elements ascending; bandwidth
+  std::vector<int> cnt(nodes + 1, 0), ent;
+  for (long k = 0; k < 8L * elements; ++k) ++cnt[conn_host[k] + 1];
+  for (int n = 0; n < nodes; ++n) cnt[n + 1] += cnt[n];
+  ent.resize(cnt[nodes]);
+  std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+  int kl = 0;
+  for (int e = 0; e < elements; ++e) {
+    int lo = nfree, hi = -1;
+    for (int a = 0; a < 8; ++a) {
+      const int n = conn_host[8 * e + a];
+      ent[fill[n]++] = 8 * e + a;
+      for (int i = 0; i < 2; ++i) {
+        const int r = dofmap[2 * n + i];
+        if (r >= 0) {
+          lo = std::min(lo, r);
+          hi = std::max(hi, r);
+        }
+      }
+    }
+    if (hi >= lo) kl = std::max(kl, hi - lo);
+  }
+  if (kl > 255) return ROM_EUNSUPPORTED;  // multipliers of a column held in LDS
+  DeviceGuard guard(device);
+  rom_fe2* h = new rom_fe2();
+  memset(h, 0, sizeof(*h));
+  h->device = device;
+  h->nodes = nodes;
+  h->elements = elements;
+  h->points = 4 * elements;
+  h->dofs = dofs;
+  h->nfixed = nfixed;
+  h->nfree = nfree;
+  h->ntop = ntop;
+  h->kl = kl;
+  h->ldab = 3 * kl + 1;
+  h->width = width;
+  bool ok = true;
+  auto al = [&](void** p, size_t bytes) {
+    if (ok && hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) ok = false;
+  };
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (ok && bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+  };
+  al((void**)&h->X, 8L * dofs);
+  al((void**)&h->dNdX, 8L * 16 * h->points);
+  al((void**)&h->wJ, 8L * h->points);
+  al((void**)&h->Xg, 16L * h->points);
+  al((void**)&h->band, 8L * nfree * h->ldab);
+  al((void**)&h->rhs, 8L * nfree);
+  al((void**)&h->conn, 32L * elements);
+  al((void**)&h->node_ptr, 4L * (nodes + 1));
+  al((void**)&h->node_ent, 4L * ent.size());
+  al((void**)&h->dofmap, 4L * dofs);
+  al((void**)&h->fixed, 4L * nfixed);
+  al((void**)&h->top, 12L * ntop);
+  up(h->X, X_host, 8L * dofs);
+  up(h->conn, conn_host, 32L * elements);
+  up(h->node_ptr, cnt.data(), 4L * (nodes + 1));
+  up(h->node_ent, ent.data(), 4L * ent.size());
+  up(h->dofmap, dofmap.data(), 4L * dofs);
+  up(h->fixed, fixed_host, 4L * nfixed);
+  up(h->top, top_host, 12L * ntop);
+  if (ok) {
+    k_geometry<<<nblk(h->points), 256>>>(h->points, h->X, h->conn, h->dNdX, h->wJ, h->Xg);
+    ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  }
+  if (!ok) {
+    release(h);
+    return ROM_EHIP;
+  }
+  *out = h;
+  return ROM_OK;
+}
+
+int rom_fe2_free(rom_fe2_handle h) {
+  if (!h) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  release(h);
+  return ROM_OK;
+}
+
+int rom_fe2_info(rom_fe2_handle h, int32_t* dofs, int32_t* free_dofs, int32_t* points, int32_t* kl) {
+  if (!h) return ROM_EINVAL;
+  if (dofs) *dofs = h->dofs;
+  if (free_dofs) *free_dofs = h->nfree;
+  if (points) *points = h->points;
+  if (kl) *kl = h->kl;
+  return ROM_OK;
+}
+
+int rom_fe2_points(rom_fe2_handle h, double* Xg_dev, hipStream_t s) {
+  if (!h || !Xg_dev) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  return hipMemcpyAsync(Xg_dev, h->Xg, 16L * h->points, hipMemcpyDeviceToDevice, s) == hipSuccess ? ROM_OK
+                                                                                                   : ROM_EHIP;
+}
+
+int rom_fe2_gradient(rom_fe2_handle h, const double* u_dev, double* Fbar_dev, hipStream_t s) {
+  if (!h || !u_dev || !Fbar_dev) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  k_gradient<<<nblk(h->points), 256, 0, s>>>(h->points, h->conn, h->dNdX, u_dev, Fbar_dev);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int rom_fe2_traction(rom_fe2_handle h, double Tbar, double* fext_dev, hipStream_t s) {
+  if (!h || !fext_dev || !std::isfinite(Tbar)) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  k_traction<<<1, 256, 0, s>>>(h->dofs, h->ntop, h->top, h->X, Tbar, h->width, fext_dev);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int rom_fe2_residual(rom_fe2_handle h, const double* Pbar_dev, const double* fext_dev, double* res_dev,
+                     double* norms_dev, hipStream_t s) {
+  if (!h || !Pbar_dev || !fext_dev || !res_dev) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  k_residual<<<nblk(h->dofs), 256, 0, s>>>(h->dofs, h->node_ptr, h->node_ent, h->dNdX, h->wJ, Pbar_dev, fext_dev,
+                                           res_dev);
+  if (norms_dev) k_norms<<<1, 256, 0, s>>>(h->dofs, h->dofmap, res_dev, fext_dev, norms_dev);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int rom_fe2_solve(rom_fe2_handle h, const double* Abar_dev, const double* res_dev, const double* dud_dev,
+                  double* u_dev, int32_t* info_dev, hipStream_t s) {
+  if (!h || !Abar_dev || !res_dev || !u_dev || !info_dev) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  k_assemble<<<nblk(h->dofs), 256, 0, s>>>(h->dofs, h->kl, h->ldab, h->node_ptr, h->node_ent, h->conn, h->dofmap,
+                                           h->dNdX, h->wJ, Abar_dev, res_dev, dud_dev, h->band, h->rhs);
+  k_band_solve<<<1, LU_THREADS, 0, s>>>(h->nfree, h->kl, h->ldab, h->band, h->rhs, h->dofs, h->dofmap, h->fixed,
+                                        h->nfixed, dud_dev, u_dev, info_dev);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int rom_fe2_compliance(rom_fe2_handle h, double Tbar, const double* u_dev, double* C_dev, hipStream_t s) {
+  if (!h || !u_dev || !C_dev || !std::isfinite(Tbar)) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  k_compliance<<<1, 64, 0, s>>>(h->ntop, h->top, h->X, Tbar, h->width, u_dev, C_dev);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+}  // extern "C"
