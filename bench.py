@@ -182,6 +182,39 @@ def sensitivity_rate(w, rom_file, at_step=5, reps=5):
                 after_steps=at_step, all_finite=finite)
 
 
+FE2_MESH, FE2_STEPS, FE2_PEAK = (20, 10), 50, 0.012
+
+
+def fe2_rate(rom_file, mode):
+    """The two-scale example: a 2 x 1 block of 20 x 10 eight-node elements
+    (800 RVE points, 1322 dofs), bottom fixed, parabolic top traction up to
+    FE2_PEAK over 25 steps and back to zero over 25; void shape fields over
+    the block.  Whole-run wall time of the macro Newton loop (trial and
+    commit RVE solves, assembly, banded solves, one host read-back per macro
+    iteration)."""
+    import torch
+    import workloads
+    from paper_2307_16894_amd.fe2 import Fe2Solver
+    mesh = workloads.fe2_mesh(*FE2_MESH)
+    sol = Fe2Solver(rom_file, mesh, lambda X: workloads.fe2_shape(X[:, 0], X[:, 1]), mode=mode)
+    loads = workloads.fe2_loads(FE2_STEPS, FE2_PEAK)
+    sol.load_step(0.0)  # warm-up: one converged step at zero load (the virgin state)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = sol.run(loads)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = sol.info
+    sol.close()
+    ok = sum(r['status'] == 0 for r in res)
+    C = [r['C'] for r in res]
+    return dict(workload=f"fe2_q8_{FE2_MESH[0]}x{FE2_MESH[1]}_P{info['points']}_K{FE2_STEPS}",
+                value=len(res) / dt, unit="macro load steps/s", seconds=dt, load_steps=len(res),
+                converged_steps=ok, macro_iters=sum(r['macro_iters'] for r in res),
+                rve_point_evals=sum(r['rve_evals'] for r in res), dofs=info['dofs'], points=info['points'],
+                band_kl=info['kl'], peak_traction=FE2_PEAK, max_compliance=max(C))
+
+
 def _oracle_worker(args):
     rom_file, mu, path = args
     from threadpoolctl import threadpool_limits
@@ -305,6 +338,7 @@ def main(argv=None):
     ap.add_argument('--workload', default=DEFAULT, choices=sorted(WORKLOADS) + sorted(UNEVEN))
     ap.add_argument('--variants', default=None, help='comma-separated forms (default: per workload)')
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-fe2', action='store_true', help='skip the two-scale example')
     ap.add_argument('--calibrate-copy', type=int, default=0, metavar='MIB',
                     help='first copy MIB MiB device to device (a known-size reference for HBM counters)')
     a = ap.parse_args(argv)
@@ -423,6 +457,9 @@ def main(argv=None):
         ws.close()
     log("[bench] shape sensitivities")
     out['shape_sensitivity'] = sensitivity_rate(w, rom_file)
+    if not a.no_fe2 and w['rom'] == 'onevoid_n40_m400':
+        log("[bench] two-scale example")
+        out['fe2'] = fe2_rate(rom_file, L.MODE_PHASED)
     if not a.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(w, rom_file)
     print(json.dumps(out), flush=True)

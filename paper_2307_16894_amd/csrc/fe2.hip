@@ -24,9 +24,10 @@
 struct rom_fe2 {
   int device;
   int nodes, elements, points, dofs, nfixed, nfree, ntop, kl, ldab;
+  int stage;  // rows per LDS staging block of the LDS-window solve (0: the global-memory solve)
   double width;
   // device
-  double *X, *dNdX, *wJ, *Xg, *band, *rhs;
+  double *X, *dNdX, *wJ, *Xg, *band, *rhs, *ubuf, *xbuf;  // ubuf, xbuf: the LDS-window solve
   int *conn, *node_ptr, *node_ent, *dofmap, *fixed, *top;
 };
 
@@ -363,12 +364,230 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_solve(int nf, int kl, int l
   if (tid == 0) *info = 0;
 }
 
+// The same factorisation with the active window in LDS: the rows k .. k +
+// kl + 1 of step k, each holding its columns c .. c + 2 kl (position c mod
+// Wc, Wc = 2 kl + 1) and its right-hand side (position Wc).  Row r lives in
+// slot map[r mod (kl + 2)]; a row interchange swaps two map entries, and the
+// row entering at step k takes the map entry (and the slot) of row k - 1,
+// which left the window the step before.  Step k: wave 0 picks the pivot and
+// swaps the map entries; the multipliers and slot offsets of the rows below;
+// then the update of those rows by 4 (2 kl + 2) threads, each holding one
+// column position (the right-hand side as one more) for every fourth row,
+// while row k of U is copied out, column k of the rows below is cleared and
+// row k + kl + 1 is copied in.  Rows in and out go through LDS staging blocks
+// of B rows, moved to and from HBM once per B steps, so that no step waits
+// on global memory.  Back substitution: blocks of kl + 2 rows of U and their
+// right-hand sides staged in LDS, then one wave walks them, lane l holding
+// x[k + 1 + l + 64 j] (j = 0, 1, 2) and the sum over the row by a wave
+// reduction.  Needs 2 kl + 1 <= 192 and B >= 1.
+constexpr int LDS_KL_MAX = 95;
+constexpr int LDS_THREADS_MAX = 1024;  // 4 (2 kl + 2) threads rounded up to whole waves
+constexpr int LDS_UNROLL = 4;
+constexpr int LDS_STAGE_MAX = 32;
+constexpr size_t LDS_BYTES_MAX = 160 * 1024;
+
+size_t band_lds_bytes(int kl, int B) {
+  const size_t S = kl + 2, RW = 2 * kl + 2;
+  return 8 * (S * RW + 2 * (size_t)B * RW + kl + 1) + 4 * (size_t)(2 * kl + 3);
+}
+int band_stage_rows(int kl) {
+  int B = LDS_STAGE_MAX;
+  while (B > 0 && band_lds_bytes(kl, B) > LDS_BYTES_MAX) --B;
+  return B;
+}
+
+__global__ __launch_bounds__(LDS_THREADS_MAX) void k_band_solve_lds(
+    int nf, int kl, int ldab, int B, const double* __restrict__ band, const double* __restrict__ rhs_in,
+    double* __restrict__ ubuf, double* __restrict__ x, int dofs, const int* __restrict__ dofmap,
+    const int* __restrict__ fixed, int nfixed, const double* __restrict__ dud, double* __restrict__ u,
+    int* __restrict__ info) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nt = blockDim.x;
+  const int Wc = 2 * kl + 1, S = kl + 2, RW = Wc + 1;
+  double* win = lds;                          // [S][RW]
+  double* sin = win + (size_t)S * RW;         // [B][RW] rows about to enter (band columns r - kl .. r + kl, rhs)
+  double* sout = sin + (size_t)B * RW;        // [B][RW] rows of U that left (columns k .. k + 2 kl, rhs)
+  double* s_mult = sout + (size_t)B * RW;     // [kl + 1]
+  int* s_off = (int*)(s_mult + kl + 1);       // [kl + 1] slot offsets of the rows below the pivot
+  int* map = s_off + kl + 1;                  // [S]
+  for (int t = tid; t < S * RW; t += nt) win[t] = 0.0;
+  for (int t = tid; t < S; t += nt) map[t] = t;
+  __syncthreads();
+  // rows 0 .. kl: columns max(0, r - kl) .. r + kl
+  for (int t = tid; t < (kl + 1) * RW; t += nt) {
+    const int r = t / RW, j = t % RW;
+    if (r >= nf) continue;
+    double* row = win + (size_t)map[r % S] * RW;
+    if (j == Wc) {
+      row[Wc] = rhs_in[r];
+    } else {
+      const int c = r - kl + j;
+      if (c >= 0) row[c % Wc] = band[(size_t)r * ldab + j];
+    }
+  }
+  int kw = 0;  // k mod Wc
+  for (int k = 0; k < nf; ++k) {
+    const int kb = k % B;
+    if (kb == 0) {
+      // rows of U of the last block out, rows k + kl + 1 .. k + kl + B in
+      for (int t = tid; t < B * RW && k > 0; t += nt) {
+        const int r = k - B + t / RW, j = t % RW;
+        if (j == Wc)
+          x[r] = sout[t];
+        else
+          ubuf[(size_t)r * Wc + j] = sout[t];
+      }
+      for (int t = tid; t < B * RW; t += nt) {
+        const int r = k + kl + 1 + t / RW, j = t % RW;
+        if (r < nf) sin[t] = (j == Wc) ? rhs_in[r] : band[(size_t)r * ldab + j];
+      }
+      __syncthreads();
+    }
+    const int last = min(nf - 1, k + kl), nr = last - k, cend = min(nf - 1, k + 2 * kl), ncol = cend - k;
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + lane; i <= last; i += 64) {
+        const double v = fabs(win[(size_t)map[i % S] * RW + kw]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0 && bi != k) {
+        const int a = map[k % S];
+        map[k % S] = map[bi % S];
+        map[bi % S] = a;
+      }
+    }
+    __syncthreads();
+    const int poff = map[k % S] * RW;
+    const double pv = win[poff + kw];
+    if (pv == 0.0) {
+      if (tid == 0) *info = k + 1;
+      return;
+    }
+    for (int i = tid; i < nr; i += nt) {
+      const int o = map[(k + 1 + i) % S] * RW;
+      s_off[i] = o;
+      s_mult[i] = win[o + kw] / pv;
+    }
+    __syncthreads();
+    // update: thread (g, p) takes position p of rows g, g + 4, ... below the
+    // pivot (position Wc the right-hand side), four rows in flight (loads
+    // before stores); a wave reads consecutive LDS words and broadcasts the
+    // row offsets and multipliers
+    {
+      const int g = tid / RW, p = tid - g * RW;
+      int q = p - kw - 1;
+      q = (q < 0) ? q + Wc : q;
+      if (g >= 4) {
+        // threads beyond 4 (2 kl + 2): the launch is rounded up to whole waves
+      } else if (p == Wc || q < ncol) {
+        const double a = win[poff + p];
+        for (int i0 = g; i0 < nr; i0 += 4 * LDS_UNROLL) {
+          int o[LDS_UNROLL];
+          double m[LDS_UNROLL], v[LDS_UNROLL];
+#pragma unroll
+          for (int w = 0; w < LDS_UNROLL; ++w) {
+            const int i = i0 + 4 * w;
+            o[w] = (i < nr) ? s_off[i] + p : -1;
+            m[w] = (i < nr) ? s_mult[i] : 0.0;
+          }
+#pragma unroll
+          for (int w = 0; w < LDS_UNROLL; ++w) v[w] = (o[w] >= 0) ? win[o[w]] : 0.0;
+#pragma unroll
+          for (int w = 0; w < LDS_UNROLL; ++w)
+            if (o[w] >= 0) win[o[w]] = fma(-m[w], a, v[w]);
+        }
+      } else if (p == kw) {
+        // column k of the rows below (never among the updated positions)
+        for (int i = g; i < nr; i += 4) win[s_off[i] + kw] = 0.0;
+      }
+    }
+    // row k of U (columns k .. k + 2 kl) and its right-hand side out; row
+    // k + kl + 1 in, to the slot of row k - 1 (it left the window last step;
+    // at k = 0 the spare slot), which no row k .. k + kl uses
+    for (int j = tid; j < RW; j += nt) {
+      int p = kw + j;
+      p = (p >= Wc) ? p - Wc : p;
+      sout[(size_t)kb * RW + j] = (j == Wc) ? win[poff + Wc] : ((k + j <= cend) ? win[poff + p] : 0.0);
+    }
+    const int rn = k + kl + 1;
+    if (rn < nf) {
+      double* row = win + (size_t)map[rn % S] * RW;
+      const double* src = sin + (size_t)kb * RW;
+      for (int j = tid; j < RW; j += nt) row[j == Wc ? Wc : (rn - kl + j) % Wc] = src[j];
+    }
+    __syncthreads();
+    kw = (kw + 1 == Wc) ? 0 : kw + 1;
+  }
+  {  // the last, partial block of U out
+    const int k0 = ((nf - 1) / B) * B, rows = nf - k0;
+    for (int t = tid; t < rows * RW; t += nt) {
+      const int r = k0 + t / RW, j = t % RW;
+      if (j == Wc)
+        x[r] = sout[t];
+      else
+        ubuf[(size_t)r * Wc + j] = sout[t];
+    }
+  }
+  __syncthreads();
+  // back substitution; x[] holds the forward-eliminated right-hand side
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;  // x[k + 1 + lane + 64 j]
+  double* yb = win + (size_t)S * Wc;      // [S] right-hand sides of the block
+  for (int kb = nf - 1; kb >= 0; kb -= S) {
+    const int k0 = max(0, kb - S + 1), rows = kb - k0 + 1;
+    for (int t = tid; t < rows * Wc; t += nt) win[t] = ubuf[(size_t)k0 * Wc + t];
+    for (int t = tid; t < rows; t += nt) yb[t] = x[k0 + t];
+    __syncthreads();
+    if (wave == 0) {
+      for (int k = kb; k >= k0; --k) {
+        const double* U = win + (size_t)(k - k0) * Wc;
+        const int jm = min(2 * kl, nf - 1 - k);
+        double s = 0.0;
+        if (lane + 1 <= jm) s = U[lane + 1] * r0;
+        if (lane + 65 <= jm) s = fma(U[lane + 65], r1, s);
+        if (lane + 129 <= jm) s = fma(U[lane + 129], r2, s);
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        const double xk = (yb[k - k0] - s) / U[0];
+        const double t0 = __shfl(r0, 63), t1 = __shfl(r1, 63);
+        r2 = __shfl_up(r2, 1);
+        r1 = __shfl_up(r1, 1);
+        r0 = __shfl_up(r0, 1);
+        if (lane == 0) {
+          r2 = t1;
+          r1 = t0;
+          r0 = xk;
+          x[k] = xk;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int d = tid; d < dofs; d += nt) {
+    const int r = dofmap[d];
+    if (r >= 0) u[d] += x[r];
+  }
+  if (dud)
+    for (int j = tid; j < nfixed; j += nt) u[fixed[j]] += dud[j];
+  if (tid == 0) *info = 0;
+}
+
 inline unsigned nblk(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 void release(rom_fe2* h) {
   if (!h) return;
-  void* bufs[] = {h->X, h->dNdX, h->wJ, h->Xg, h->band, h->rhs, h->conn, h->node_ptr, h->node_ent,
-                  h->dofmap, h->fixed, h->top};
+  void* bufs[] = {h->X, h->dNdX, h->wJ, h->Xg, h->band, h->rhs, h->ubuf, h->xbuf, h->conn, h->node_ptr,
+                  h->node_ent, h->dofmap, h->fixed, h->top};
   for (void* b : bufs) (void)hipFree(b);
   delete h;
 }
@@ -450,6 +669,14 @@ int rom_fe2_create(int32_t nodes, int32_t elements, const double* X_host, const 
   al((void**)&h->Xg, 16L * h->points);
   al((void**)&h->band, 8L * nfree * h->ldab);
   al((void**)&h->rhs, 8L * nfree);
+  h->stage = kl <= LDS_KL_MAX ? band_stage_rows(kl) : 0;
+  if (h->stage > 0) {
+    al((void**)&h->ubuf, 8L * nfree * (2 * kl + 1));
+    al((void**)&h->xbuf, 8L * nfree);
+    if (ok && hipFuncSetAttribute((const void*)k_band_solve_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)band_lds_bytes(kl, h->stage)) != hipSuccess)
+      ok = false;
+  }
   al((void**)&h->conn, 32L * elements);
   al((void**)&h->node_ptr, 4L * (nodes + 1));
   al((void**)&h->node_ent, 4L * ent.size());
@@ -528,8 +755,13 @@ int rom_fe2_solve(rom_fe2_handle h, const double* Abar_dev, const double* res_de
   DeviceGuard guard(h->device);
   k_assemble<<<nblk(h->dofs), 256, 0, s>>>(h->dofs, h->kl, h->ldab, h->node_ptr, h->node_ent, h->conn, h->dofmap,
                                            h->dNdX, h->wJ, Abar_dev, res_dev, dud_dev, h->band, h->rhs);
-  k_band_solve<<<1, LU_THREADS, 0, s>>>(h->nfree, h->kl, h->ldab, h->band, h->rhs, h->dofs, h->dofmap, h->fixed,
-                                        h->nfixed, dud_dev, u_dev, info_dev);
+  if (h->stage > 0)
+    k_band_solve_lds<<<1, (4 * (2 * h->kl + 2) + 63) / 64 * 64, band_lds_bytes(h->kl, h->stage), s>>>(
+        h->nfree, h->kl, h->ldab, h->stage, h->band, h->rhs, h->ubuf, h->xbuf, h->dofs, h->dofmap, h->fixed,
+        h->nfixed, dud_dev, u_dev, info_dev);
+  else
+    k_band_solve<<<1, LU_THREADS, 0, s>>>(h->nfree, h->kl, h->ldab, h->band, h->rhs, h->dofs, h->dofmap, h->fixed,
+                                          h->nfixed, dud_dev, u_dev, info_dev);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 

@@ -79,12 +79,21 @@ def full():
     return mesh, ofe2.geometry(mesh)
 
 
-def test_macro_kernels_full_size(gpu, full):
-    mesh, geo = full
+@pytest.mark.parametrize("dims", [(20, 10), (3, 30)])
+def test_macro_kernels_full_size(gpu, full, dims):
+    """(20, 10): the example (half-bandwidth 65, the LDS-window solve);
+    (3, 30): a tall block numbered across its long side (half-bandwidth
+    above 95, the global-memory solve)."""
+    mesh, geo = full if dims == (20, 10) else (lambda m: (m, ofe2.geometry(m)))(workloads.fe2_mesh(*dims))
     name = 'onevoid_n40_m400'
     sol = Fe2Solver(rom_path(name), mesh, shape)
     s = sol.stream.cuda_stream
-    assert sol.info['dofs'] == 1322 and sol.info['points'] == 800
+    print(f"[gpu] fe2 operators {dims}: {sol.info}", flush=True)
+    if dims == (20, 10):
+        assert sol.info['dofs'] == 1322 and sol.info['points'] == 800 and sol.info['kl'] <= 95
+    else:
+        assert 95 < sol.info['kl'] <= 255
+    ndof = sol.info['dofs']
     assert np.abs(sol.Xg.cpu().numpy() - geo['Xg']).max() < 1e-14
     x, y = mesh['X'][:, 0], mesh['X'][:, 1]
     u = np.stack([0.003 * x * y - 0.002 * y * y, -0.006 * y + 0.001 * x * y * (2 - x)], axis=1).reshape(-1)
@@ -106,7 +115,7 @@ def test_macro_kernels_full_size(gpu, full):
     res_o = fext_o - ofe2.internal_force(mesh, geo, Pbar)
     res = sol.res.cpu().numpy()
     assert np.abs(res - res_o).max() <= 1e-12 * np.abs(res_o).max()
-    free = np.setdiff1d(np.arange(1322), sol.fixed)
+    free = np.setdiff1d(np.arange(ndof), sol.fixed)
     nr, nf = sol.norms.cpu().numpy()
     assert abs(nr - np.linalg.norm(res_o[free])) <= 1e-12 * nr
     assert abs(nf - np.linalg.norm(fext_o[free])) <= 1e-12 * nf
