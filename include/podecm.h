@@ -337,6 +337,29 @@ int rom_fe2_solve(rom_fe2_handle h, const double* Abar_dev, const double* res_de
                   double* u_dev, int32_t* info_dev, hipStream_t stream);
 int rom_fe2_compliance(rom_fe2_handle h, double Tbar, const double* u_dev, double* C_dev, hipStream_t stream);
 
+/*
+ * Offline stage: POD by the method of snapshots (Sec. 3.1, the fluctuation
+ * modes of eq. pod_disp in the V^p inner product; Sec. 3.2, the weighted-
+ * stress modes in L^2 of the parent domain).  Snapshots S_dev [ns][nrow]
+ * (snapshot j contiguous); the weight M, symmetric positive definite, given
+ * either as a diagonal mdiag_dev [nrow] or as a CSR matrix (csr_ptr [nrow +
+ * 1], csr_col, csr_val), exactly one of the two.  Computes C = S^T M S, its
+ * eigenvalues lambda_dev [ns] (descending) and the n leading modes
+ * phi_k = S v_k / sqrt(lambda_k), re-orthonormalised once in the M product
+ * (phi <- phi L^-T, L L^T = phi^T M phi), into modes_dev [n][nrow] (mode k
+ * contiguous; the sign of each mode is that of the eigensolver's vector).
+ * work_dev: rom_pod_workspace(nrow, ns, n) bytes of device memory.  The
+ * call synchronises the stream (the rank test reads the eigenvalues) and
+ * the eigensolver and Cholesky steps may allocate their own scratch.
+ * Returns ROM_EINVAL when n exceeds the numerical rank (eigenvalues above
+ * 1e-13 of the largest) or the arguments are inconsistent, ROM_EHIP when
+ * a device step fails.
+ */
+int rom_pod_workspace(int32_t nrow, int32_t ns, int32_t n, size_t* bytes);
+int rom_pod(int32_t nrow, int32_t ns, const double* S_dev, const double* mdiag_dev, const int32_t* csr_ptr_dev,
+            const int32_t* csr_col_dev, const double* csr_val_dev, int32_t n, double* modes_dev, double* lambda_dev,
+            void* work_dev, size_t work_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

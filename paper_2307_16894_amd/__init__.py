@@ -43,7 +43,7 @@ EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_inf
            'rom_mlp_set_params', 'rom_mlp_get_params', 'rom_mlp_set_scaling', 'rom_mlp_forward',
            'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features', 'rom_path_gather', 'rom_path_advance',
            'rom_fe2_create', 'rom_fe2_free', 'rom_fe2_info', 'rom_fe2_points', 'rom_fe2_gradient', 'rom_fe2_traction',
-           'rom_fe2_residual', 'rom_fe2_solve', 'rom_fe2_compliance']
+           'rom_fe2_residual', 'rom_fe2_solve', 'rom_fe2_compliance', 'rom_pod_workspace', 'rom_pod']
 
 
 class RomError(RuntimeError):
@@ -126,6 +126,8 @@ def lib():
         L.rom_fe2_residual.argtypes = [vp, vp, vp, vp, vp, vp]
         L.rom_fe2_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.rom_fe2_compliance.argtypes = [vp, dbl, vp, vp, vp]
+        L.rom_pod_workspace.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
+        L.rom_pod.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -334,3 +336,15 @@ def rom_fe2_solve(h, Abar_ptr, res_ptr, dud_ptr, u_ptr, info_ptr, stream):
 
 def rom_fe2_compliance(h, Tbar, u_ptr, C_ptr, stream):
     _check(lib().rom_fe2_compliance(h, float(Tbar), u_ptr, C_ptr, stream), 'rom_fe2_compliance')
+
+
+def rom_pod_workspace(nrow, ns, n):
+    b = ctypes.c_size_t()
+    _check(lib().rom_pod_workspace(nrow, ns, n, ctypes.byref(b)), 'rom_pod_workspace')
+    return b.value
+
+
+def rom_pod(nrow, ns, S_ptr, mdiag_ptr, csr_ptr, csr_col, csr_val, n, modes_ptr, lambda_ptr, work_ptr, work_bytes,
+            stream):
+    _check(lib().rom_pod(nrow, ns, S_ptr, mdiag_ptr, csr_ptr, csr_col, csr_val, n, modes_ptr, lambda_ptr, work_ptr,
+                         work_bytes, stream), 'rom_pod')

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, 'csrc')
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, 'libpodecm.so')
-SOURCES = ['rom_api.hip', 'rom_staged.hip', 'rom_fused.hip', 'rom_phased.hip', 'rom_sens.hip', 'mlp.hip', 'fe2.hip'] + [f'rom_fused_t{t}.hip' for t in range(2, 9)]
+SOURCES = ['rom_api.hip', 'rom_staged.hip', 'rom_fused.hip', 'rom_phased.hip', 'rom_sens.hip', 'mlp.hip', 'fe2.hip', 'offline.hip'] + [f'rom_fused_t{t}.hip' for t in range(2, 9)]
 FLAGS = ['--offload-arch=gfx950', '-O3', '-std=c++17', '-fPIC',
          # packed FP32 instructions are left out of every kernel
          '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
@@ -36,7 +36,8 @@ def build(verbose=False, jobs=None):
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + '.tmp'
-    subprocess.run(['hipcc', '--offload-arch=gfx950', '-shared', '-fPIC', *objs, '-o', tmp], check=True)
+    subprocess.run(['hipcc', '--offload-arch=gfx950', '-shared', '-fPIC', *objs, '-o', tmp, '-L/opt/rocm/lib',
+                    '-lrocsolver', '-lrocblas', '-Wl,-rpath,/opt/rocm/lib'], check=True)
     os.replace(tmp, LIB)
     return LIB
 
