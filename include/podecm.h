@@ -360,6 +360,31 @@ int rom_pod(int32_t nrow, int32_t ns, const double* S_dev, const double* mdiag_d
             const int32_t* csr_col_dev, const double* csr_val_dev, int32_t n, double* modes_dev, double* lambda_dev,
             void* work_dev, size_t work_bytes, hipStream_t stream);
 
+/*
+ * Offline stage: empirical cubature (Sec. 3.2, eqs. integralsbasis and
+ * integral_ecm) by the greedy of the published method the paper defers to.
+ * Integrands J_dev [R][nq] (integrand i at quadrature point q) with full
+ * rule weights w_dev [nq] (positive).  J diag(sqrt(w)) = U Sigma V^T, rank r
+ * (singular values above 1e-12 of the largest), Z = V_r^T diag(1/sqrt(w)),
+ * b = Z w; from an empty set and res = b, repeatedly: the point of largest
+ * positive Z_q . res / |Z_q| (lowest index on ties) joins, least squares on
+ * the selected set (non-negative least squares when a weight is not
+ * positive), points of zero weight leave, res = b - Z_S w_S; until
+ * |res| <= eps |b|, m_max points or 10 m_max iterations, or no positive
+ * correlation is left.  Outputs: the selected points in selection order
+ * idx_dev [m_max] and their weights weights_dev [m_max], their count *m_out;
+ * optionally |res| / |b| after each iteration (hist_host, host memory,
+ * starting with 1, at most hist_cap entries, count *hist_len) and the rank r.
+ * m_max <= 1024.  work_dev: rom_ecm_workspace(R, nq, m_max) bytes.  The call
+ * synchronises the stream once per iteration (the stop test) and the SVD
+ * step may allocate its own scratch.  Returns ROM_EUNSUPPORTED (results so
+ * far written) if a chosen column is linearly dependent on the selected ones.
+ */
+int rom_ecm_workspace(int32_t R, int32_t nq, int32_t m_max, size_t* bytes);
+int rom_ecm(int32_t R, int32_t nq, const double* J_dev, const double* w_dev, double eps, int32_t m_max,
+            int32_t* idx_dev, double* weights_dev, int32_t* m_out, double* hist_host, int32_t hist_cap,
+            int32_t* hist_len, int32_t* rank_out, void* work_dev, size_t work_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

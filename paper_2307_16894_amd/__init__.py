@@ -43,7 +43,8 @@ EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_inf
            'rom_mlp_set_params', 'rom_mlp_get_params', 'rom_mlp_set_scaling', 'rom_mlp_forward',
            'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features', 'rom_path_gather', 'rom_path_advance',
            'rom_fe2_create', 'rom_fe2_free', 'rom_fe2_info', 'rom_fe2_points', 'rom_fe2_gradient', 'rom_fe2_traction',
-           'rom_fe2_residual', 'rom_fe2_solve', 'rom_fe2_compliance', 'rom_pod_workspace', 'rom_pod']
+           'rom_fe2_residual', 'rom_fe2_solve', 'rom_fe2_compliance', 'rom_pod_workspace', 'rom_pod',
+           'rom_ecm_workspace', 'rom_ecm']
 
 
 class RomError(RuntimeError):
@@ -128,6 +129,9 @@ def lib():
         L.rom_fe2_compliance.argtypes = [vp, dbl, vp, vp, vp]
         L.rom_pod_workspace.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
         L.rom_pod.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]
+        L.rom_ecm_workspace.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
+        L.rom_ecm.argtypes = [i32, i32, vp, vp, dbl, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), i32,
+                              ctypes.POINTER(i32), ctypes.POINTER(i32), vp, sz, vp]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -348,3 +352,22 @@ def rom_pod(nrow, ns, S_ptr, mdiag_ptr, csr_ptr, csr_col, csr_val, n, modes_ptr,
             stream):
     _check(lib().rom_pod(nrow, ns, S_ptr, mdiag_ptr, csr_ptr, csr_col, csr_val, n, modes_ptr, lambda_ptr, work_ptr,
                          work_bytes, stream), 'rom_pod')
+
+
+def rom_ecm_workspace(R, nq, m_max):
+    b = ctypes.c_size_t()
+    _check(lib().rom_ecm_workspace(R, nq, m_max, ctypes.byref(b)), 'rom_ecm_workspace')
+    return b.value
+
+
+def rom_ecm(R, nq, J_ptr, w_ptr, eps, m_max, idx_ptr, weights_ptr, work_ptr, work_bytes, stream, hist_cap=0):
+    """Returns (count, history list, rank, code); code ROM_EUNSUPPORTED is not raised (partial result)."""
+    m = ctypes.c_int32()
+    hl = ctypes.c_int32()
+    rk = ctypes.c_int32()
+    hist = (ctypes.c_double * max(hist_cap, 1))()
+    code = lib().rom_ecm(R, nq, J_ptr, w_ptr, float(eps), m_max, idx_ptr, weights_ptr, ctypes.byref(m), hist,
+                         hist_cap, ctypes.byref(hl), ctypes.byref(rk), work_ptr, work_bytes, stream)
+    if code not in (ROM_OK, ROM_EUNSUPPORTED):
+        _check(code, 'rom_ecm')
+    return m.value, list(hist[:hl.value]), rk.value, code

@@ -206,6 +206,496 @@ size_t pod_layout(long nrow, long ns, long n, PodWork* w, char* base) {
   return off;
 }
 
+
+// ---------------------------------------------------------------------------
+// Empirical cubature (Sec. 3.2, eqs. integralsbasis and integral_ecm): the
+// greedy of the published method the paper defers to.  The integrands J
+// (R x nq) weighted by the full rule: J diag(sqrt(w)) = U Sigma V^T, rank r
+// (singular values above 1e-12 of the largest); Z = V^T_r diag(1/sqrt(w)),
+// b = Z w.  From an empty set and res = b: add the point of largest positive
+// Z_q . res / |Z_q| (lowest index on ties), least squares on the selected
+// set, non-negative least squares when a weight comes out non-positive,
+// points of zero weight leave, res = b - Z_S w_S; until |res| <= eps |b|, the
+// point budget or no positive correlation.
+
+constexpr int ECM_THREADS = 1024;
+constexpr int ECM_SCORE_BLOCK = 256;
+
+// Jh (column-major R x nq) = J (row-major R x nq) diag(sqrt(w))
+__global__ void k_ecm_scale(int R, int nq, const double* __restrict__ J, const double* __restrict__ w,
+                            double* __restrict__ Jh) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= (long)R * nq) return;
+  const int q = (int)(t / R), i = (int)(t % R);
+  Jh[t] = J[(long)i * nq + q] * sqrt(w[q]);
+}
+
+// Zr[i][q] = V^T(i, q) / sqrt(w_q) for i < r (V^T column-major, ldv = R);
+// cn[q] = |Z_q|
+__global__ void k_ecm_z(int R, int r, int nq, const double* __restrict__ V, const double* __restrict__ w,
+                        double* __restrict__ Zr, double* __restrict__ cn) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const double is = 1.0 / sqrt(w[q]);
+  double s = 0.0;
+  for (int i = 0; i < r; ++i) {
+    const double z = V[i + (long)q * R] * is;
+    Zr[(long)i * nq + q] = z;
+    s = fma(z, z, s);
+  }
+  cn[q] = sqrt(s);
+}
+
+// b[i] = sum_q Zr[i][q] w[q]: a workgroup per i, fixed-order tree
+__global__ __launch_bounds__(256) void k_ecm_b(int nq, const double* __restrict__ Zr, const double* __restrict__ w,
+                                               double* __restrict__ b) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < nq; q += 256) s = fma(Zr[(long)i * nq + q], w[q], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) b[i] = red[0];
+}
+
+// score of every point, then the best of each workgroup (largest score,
+// lowest index on ties); selected points score -inf
+__global__ __launch_bounds__(ECM_SCORE_BLOCK) void k_ecm_score(int r, int nq, const double* __restrict__ Zr,
+                                                               const double* __restrict__ cn,
+                                                               const double* __restrict__ res,
+                                                               const int* __restrict__ sel_flag,
+                                                               double* __restrict__ best_v, int* __restrict__ best_i) {
+  extern __shared__ double sres[];
+  __shared__ double rv[ECM_SCORE_BLOCK];
+  __shared__ int ri[ECM_SCORE_BLOCK];
+  for (int i = threadIdx.x; i < r; i += ECM_SCORE_BLOCK) sres[i] = res[i];
+  __syncthreads();
+  const int q = blockIdx.x * ECM_SCORE_BLOCK + threadIdx.x;
+  double v = -INFINITY;
+  if (q < nq && !sel_flag[q]) {
+    double s = 0.0;
+    for (int i = 0; i < r; ++i) s = fma(Zr[(long)i * nq + q], sres[i], s);
+    v = s / cn[q];
+  }
+  rv[threadIdx.x] = v;
+  ri[threadIdx.x] = q;
+  __syncthreads();
+  for (int h = ECM_SCORE_BLOCK / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      const double ov = rv[threadIdx.x + h];
+      const int oi = ri[threadIdx.x + h];
+      if (ov > rv[threadIdx.x] || (ov == rv[threadIdx.x] && oi < ri[threadIdx.x])) {
+        rv[threadIdx.x] = ov;
+        ri[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    best_v[blockIdx.x] = rv[0];
+    best_i[blockIdx.x] = ri[0];
+  }
+}
+
+// Greedy state, device side
+struct EcmState {
+  int k;        // selected points
+  int status;   // 0 running, 1 no positive correlation, 2 dependent column
+  int qstar;    // last chosen point
+  int pad;
+  double sstar; // its score
+  double rn;    // |res|
+};
+
+// block-wide sum (fixed order), all threads receive it
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += red[w];
+  return t;
+}
+
+// Cholesky of the p x p matrix A (row-major, ld) into L (lower, row-major,
+// ld), in one workgroup; returns false if a pivot is not positive
+__device__ bool block_cholesky(int p, const double* __restrict__ A, double* __restrict__ Lm, int ld, double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (long t = tid; t < (long)p * p; t += nt) {
+    const int i = (int)(t / p), j = (int)(t % p);
+    Lm[(long)i * ld + j] = (j <= i) ? A[(long)i * ld + j] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < p; ++j) {
+    const double d = Lm[(long)j * ld + j];
+    __syncthreads();
+    if (!(d > 0.0)) return false;
+    const double sd = sqrt(d);
+    for (int i = j + tid; i < p; i += nt) Lm[(long)i * ld + j] = (i == j) ? sd : Lm[(long)i * ld + j] / sd;
+    __syncthreads();
+    const int rows = p - j - 1;
+    for (long t = tid; t < (long)rows * rows; t += nt) {
+      const int i = j + 1 + (int)(t / rows), c = j + 1 + (int)(t % rows);
+      if (c <= i) Lm[(long)i * ld + c] = fma(-Lm[(long)i * ld + j], Lm[(long)c * ld + j], Lm[(long)i * ld + c]);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// L L^T x = h (L lower row-major, ld) by one wave; x and h in LDS.  Lane 0
+// writes each x_i; the wave reads it in the next step (LDS operations of a
+// wave complete in order; the wave barrier only stops the compiler moving
+// code across it).  Called by wave 0 alone: no workgroup barrier inside.
+__device__ void chol_solve_wave(int p, const double* __restrict__ Lm, int ld, const double* h, double* x) {
+  const int lane = threadIdx.x & 63;
+  for (int i = 0; i < p; ++i) {
+    double s = 0.0;
+    for (int t = lane; t < i; t += 64) s = fma(Lm[(long)i * ld + t], x[t], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) x[i] = (h[i] - s) / Lm[(long)i * ld + i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  for (int i = p - 1; i >= 0; --i) {
+    double s = 0.0;
+    for (int t = i + 1 + lane; t < p; t += 64) s = fma(Lm[(long)t * ld + i], x[t], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) x[i] = (x[i] - s) / Lm[(long)i * ld + i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// One greedy iteration in one workgroup: pick the best point of the score
+// blocks, append it, extend the Cholesky factor of the selected set's Gram
+// matrix G = Z_S^T Z_S by one row, solve G w = Z_S^T b; if a weight is not
+// positive, Lawson-Hanson non-negative least squares on (G, h) started from
+// the previous (positive) weights with the new point at zero; drop points of
+// zero weight (refactoring G); res = b - Z_S w.  Every branch that reaches a
+// workgroup barrier is decided from shared values.
+__global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
+    int r, int nq, int mmax, int nblocks, const double* __restrict__ Zr, const double* __restrict__ b,
+    const double* __restrict__ best_v, const int* __restrict__ best_i, int* __restrict__ S, double* __restrict__ ZS,
+    double* __restrict__ G, double* __restrict__ Lm, double* __restrict__ Gp, double* __restrict__ Lp,
+    double* __restrict__ hv, double* __restrict__ w, double* __restrict__ res, int* __restrict__ sel_flag,
+    EcmState* __restrict__ st) {
+  extern __shared__ double sh[];
+  double* x = sh;               // [mmax + 1] current solution
+  double* z = x + mmax + 1;     // [mmax + 1] least-squares solution on the passive set
+  double* hp = z + mmax + 1;    // [mmax + 1] h gathered on the passive set
+  double* red = hp + mmax + 1;  // [32]
+  int* pas = (int*)(red + 32);  // [mmax + 1] passive flags
+  int* pidx = pas + mmax + 1;   // [mmax + 1] passive indices in order
+  __shared__ int s_q, s_k, s_flag, s_np, s_t;
+  __shared__ double s_v, s_alpha;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  if (tid == 0) {
+    double bv = -INFINITY;
+    int bi = nq;
+    for (int blk = 0; blk < nblocks; ++blk)
+      if (best_v[blk] > bv || (best_v[blk] == bv && best_i[blk] < bi)) {
+        bv = best_v[blk];
+        bi = best_i[blk];
+      }
+    s_v = bv;
+    s_q = bi;
+    s_k = st->k;
+  }
+  __syncthreads();
+  const int q = s_q, k = s_k;
+  if (!(s_v > 0.0)) {
+    if (tid == 0) {
+      st->status = 1;
+      st->sstar = s_v;
+      st->qstar = q;
+    }
+    return;
+  }
+  // append Z_q as row k of ZS
+  for (int i = tid; i < r; i += nt) ZS[(long)k * r + i] = Zr[(long)i * nq + q];
+  if (tid == 0) {
+    S[k] = q;
+    sel_flag[q] = 1;
+  }
+  __syncthreads();
+  // G[k][j] = G[j][k] = ZS[j] . ZS[k] (j <= k), h[k] = ZS[k] . b: a wave per product
+  for (int j = wave; j <= k + 1; j += nw) {
+    const double* zk = ZS + (long)k * r;
+    const double* o = (j <= k) ? ZS + (long)j * r : b;
+    double acc = 0.0;
+    for (int i = lane; i < r; i += 64) acc = fma(o[i], zk[i], acc);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) {
+      if (j <= k) {
+        G[(long)k * mmax + j] = acc;
+        G[(long)j * mmax + k] = acc;
+      } else {
+        hv[k] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  // new row of the Cholesky factor: L[k][0..k) = L^-1 g, L[k][k] = sqrt(G_kk - |y|^2)
+  for (int j = tid; j <= k; j += nt) hp[j] = G[(long)k * mmax + j];
+  __syncthreads();
+  if (wave == 0) {
+    for (int j = 0; j < k; ++j) {
+      double acc = 0.0;
+      for (int t = lane; t < j; t += 64) acc = fma(Lm[(long)j * mmax + t], z[t], acc);
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if (lane == 0) z[j] = (hp[j] - acc) / Lm[(long)j * mmax + j];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    double acc = 0.0;
+    for (int t = lane; t < k; t += 64) acc = fma(z[t], z[t], acc);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    const double d2 = hp[k] - acc;
+    if (lane == 0) s_flag = (d2 > 1e-14 * hp[k]) ? 0 : 1;
+    for (int t = lane; t < k; t += 64) Lm[(long)k * mmax + t] = z[t];
+    if (lane == 0) Lm[(long)k * mmax + k] = sqrt(fmax(d2, 0.0));
+  }
+  __syncthreads();
+  if (s_flag) {  // the new column depends on the selected ones
+    if (tid == 0) {
+      st->status = 2;
+      st->qstar = q;
+      sel_flag[q] = 0;
+    }
+    return;
+  }
+  const int p = k + 1;
+  // unconstrained least squares on all p points
+  for (int j = tid; j < p; j += nt) hp[j] = hv[j];
+  __syncthreads();
+  if (wave == 0) chol_solve_wave(p, Lm, mmax, hp, x);
+  __syncthreads();
+  if (tid == 0) {
+    int bad = 0;
+    for (int j = 0; j < p; ++j) bad |= !(x[j] > 0.0);
+    s_flag = bad;
+  }
+  __syncthreads();
+  int pnew = p;
+  if (s_flag) {
+    // Lawson-Hanson from x = (previous weights, 0), passive = previous points
+    double hmax = 0.0;
+    for (int j = 0; j < p; ++j) hmax = fmax(hmax, fabs(hv[j]));
+    const double tol = 1e-13 * hmax;
+    for (int j = tid; j < p; j += nt) {
+      x[j] = (j < k) ? w[j] : 0.0;
+      pas[j] = j < k;
+    }
+    __syncthreads();
+    for (int outer = 0; outer < 3 * p; ++outer) {
+      // gradient on the active points; the largest above tol joins the passive set
+      if (tid == 0) {
+        double gb = tol;
+        int tb = -1;
+        for (int i = 0; i < p; ++i) {
+          if (pas[i]) continue;
+          double gi = hv[i];
+          for (int j = 0; j < p; ++j) gi = fma(-G[(long)i * mmax + j], x[j], gi);
+          if (gi > gb) {
+            gb = gi;
+            tb = i;
+          }
+        }
+        s_t = tb;
+        if (tb >= 0) pas[tb] = 1;
+      }
+      __syncthreads();
+      if (s_t < 0) break;
+      for (int inner = 0; inner < p; ++inner) {
+        if (tid == 0) {
+          int np = 0;
+          for (int i = 0; i < p; ++i)
+            if (pas[i]) pidx[np++] = i;
+          s_np = np;
+        }
+        __syncthreads();
+        const int np = s_np;
+        for (long t = tid; t < (long)np * np; t += nt) {
+          const int a = (int)(t / np), c = (int)(t % np);
+          Gp[(long)a * mmax + c] = G[(long)pidx[a] * mmax + pidx[c]];
+        }
+        for (int a = tid; a < np; a += nt) hp[a] = hv[pidx[a]];
+        __syncthreads();
+        const bool ok = block_cholesky(np, Gp, Lp, mmax, red);
+        if (!ok) {
+          if (tid == 0) st->status = 2;
+          return;
+        }
+        if (wave == 0) chol_solve_wave(np, Lp, mmax, hp, z);
+        __syncthreads();
+        if (tid == 0) {
+          // step from x towards z as far as feasibility allows; the point
+          // that limits the step (and any other at zero) leaves the passive set
+          double alpha = 2.0;
+          int ia = -1;
+          for (int a = 0; a < np; ++a) {
+            const int i = pidx[a];
+            if (!(z[a] > 0.0)) {
+              const double al = x[i] / (x[i] - z[a]);
+              if (al < alpha) {
+                alpha = al;
+                ia = i;
+              }
+            }
+          }
+          s_alpha = alpha;
+          if (alpha > 1.0) {
+            for (int a = 0; a < np; ++a) x[pidx[a]] = z[a];
+          } else {
+            for (int a = 0; a < np; ++a) {
+              const int i = pidx[a];
+              x[i] = (i == ia) ? 0.0 : fma(alpha, z[a] - x[i], x[i]);
+              if (!(x[i] > 0.0)) {
+                x[i] = 0.0;
+                pas[i] = 0;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        if (s_alpha > 1.0) break;
+      }
+    }
+    // keep the points of positive weight (order kept), refactor
+    if (tid == 0) {
+      int c = 0;
+      for (int j = 0; j < p; ++j) {
+        if (x[j] > 0.0) {
+          pidx[c] = j;
+          ++c;
+        } else {
+          sel_flag[S[j]] = 0;
+        }
+      }
+      s_np = c;
+    }
+    __syncthreads();
+    pnew = s_np;
+    for (long t = tid; t < (long)pnew * pnew; t += nt) {
+      const int a = (int)(t / pnew), c = (int)(t % pnew);
+      Gp[(long)a * mmax + c] = G[(long)pidx[a] * mmax + pidx[c]];
+    }
+    for (int a = tid; a < pnew; a += nt) {
+      z[a] = x[pidx[a]];
+      hp[a] = hv[pidx[a]];
+    }
+    __syncthreads();
+    // rows of ZS and S compacted in order (a row only moves down)
+    for (int a = 0; a < pnew; ++a) {
+      const int from = pidx[a];
+      if (from != a)
+        for (int i = tid; i < r; i += nt) ZS[(long)a * r + i] = ZS[(long)from * r + i];
+      __syncthreads();
+    }
+    if (tid == 0)
+      for (int a = 0; a < pnew; ++a) S[a] = S[pidx[a]];
+    for (long t = tid; t < (long)pnew * pnew; t += nt) {
+      const int a = (int)(t / pnew), c = (int)(t % pnew);
+      G[(long)a * mmax + c] = Gp[(long)a * mmax + c];
+    }
+    for (int a = tid; a < pnew; a += nt) {
+      x[a] = z[a];
+      hv[a] = hp[a];
+    }
+    __syncthreads();
+    if (!block_cholesky(pnew, G, Lm, mmax, red)) {
+      if (tid == 0) st->status = 2;
+      return;
+    }
+  }
+  for (int j = tid; j < pnew; j += nt) w[j] = x[j];
+  __syncthreads();
+  // res = b - sum_j w_j ZS[j] (in order of j), |res|
+  double part = 0.0;
+  for (int i = tid; i < r; i += nt) {
+    double v = b[i];
+    for (int j = 0; j < pnew; ++j) v = fma(-w[j], ZS[(long)j * r + i], v);
+    res[i] = v;
+    part = fma(v, v, part);
+  }
+  const double rn2 = block_sum(part, red);
+  if (tid == 0) {
+    st->k = pnew;
+    st->status = 0;
+    st->qstar = q;
+    st->sstar = s_v;
+    st->rn = sqrt(rn2);
+  }
+}
+
+
+struct EcmWork {
+  double *Jh, *Sv, *V, *E, *Zr, *cn, *b, *res, *bv, *ZS, *G, *Lm, *Gp, *Lp, *hv, *w, *bn;
+  int *bi, *S, *sel, *info;
+  EcmState* st;
+};
+
+constexpr int ECM_MMAX = 1024;
+
+size_t ecm_layout(long R, long nq, long mmax, EcmWork* w, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  const long mn = std::min(R, nq), nblocks = (nq + ECM_SCORE_BLOCK - 1) / ECM_SCORE_BLOCK;
+  EcmWork e;
+  e.Jh = (double*)take(8 * (size_t)R * nq);
+  e.Sv = (double*)take(8 * (size_t)mn);
+  e.V = (double*)take(8 * (size_t)mn * nq);
+  e.E = (double*)take(8 * (size_t)mn);
+  e.Zr = (double*)take(8 * (size_t)mn * nq);
+  e.cn = (double*)take(8 * (size_t)nq);
+  e.b = (double*)take(8 * (size_t)mn);
+  e.res = (double*)take(8 * (size_t)mn);
+  e.bv = (double*)take(8 * (size_t)nblocks);
+  e.ZS = (double*)take(8 * (size_t)mmax * mn);
+  e.G = (double*)take(8 * (size_t)mmax * mmax);
+  e.Lm = (double*)take(8 * (size_t)mmax * mmax);
+  e.Gp = (double*)take(8 * (size_t)mmax * mmax);
+  e.Lp = (double*)take(8 * (size_t)mmax * mmax);
+  e.hv = (double*)take(8 * (size_t)mmax);
+  e.w = (double*)take(8 * (size_t)mmax);
+  e.bn = (double*)take(8);
+  e.bi = (int*)take(4 * (size_t)nblocks);
+  e.S = (int*)take(4 * (size_t)mmax);
+  e.sel = (int*)take(4 * (size_t)nq);
+  e.info = (int*)take(64);
+  e.st = (EcmState*)take(sizeof(EcmState));
+  if (w) *w = e;
+  return off;
+}
+
+// |b| in one workgroup
+__global__ __launch_bounds__(256) void k_norm(int n, const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s = fma(v[i], v[i], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -281,6 +771,86 @@ int rom_pod(int32_t nrow, int32_t ns, const double* S_dev, const double* mdiag_d
   }
   rocblas_destroy_handle(rb);
   return rc;
+}
+
+
+int rom_ecm_workspace(int32_t R, int32_t nq, int32_t m_max, size_t* bytes) {
+  if (!bytes || R < 1 || nq < 1 || m_max < 1 || m_max > ECM_MMAX) return ROM_EINVAL;
+  *bytes = ecm_layout(R, nq, m_max, nullptr, nullptr);
+  return ROM_OK;
+}
+
+int rom_ecm(int32_t R, int32_t nq, const double* J_dev, const double* w_dev, double eps, int32_t m_max,
+            int32_t* idx_dev, double* weights_dev, int32_t* m_out, double* hist_host, int32_t hist_cap,
+            int32_t* hist_len, int32_t* rank_out, void* work_dev, size_t work_bytes, hipStream_t stream) {
+  if (R < 1 || nq < 1 || !J_dev || !w_dev || !(eps >= 0) || m_max < 1 || m_max > ECM_MMAX || !idx_dev ||
+      !weights_dev || !m_out || !work_dev)
+    return ROM_EINVAL;
+  if (work_bytes < ecm_layout(R, nq, m_max, nullptr, nullptr)) return ROM_EINVAL;
+  EcmWork e;
+  ecm_layout(R, nq, m_max, &e, (char*)work_dev);
+  const int mn = std::min(R, nq), nblocks = (nq + ECM_SCORE_BLOCK - 1) / ECM_SCORE_BLOCK;
+  // Jh = J diag(sqrt(w)), its singular values and right singular vectors
+  k_ecm_scale<<<nblk((long)R * nq), 256, 0, stream>>>(R, nq, J_dev, w_dev, e.Jh);
+  if (hipGetLastError() != hipSuccess) return ROM_EHIP;
+  rocblas_handle rb;
+  if (rocblas_create_handle(&rb) != rocblas_status_success) return ROM_EHIP;
+  int rc = ROM_OK;
+  if (rocblas_set_stream(rb, stream) != rocblas_status_success ||
+      rocsolver_dgesvd(rb, rocblas_svect_none, rocblas_svect_singular, R, nq, e.Jh, R, e.Sv, nullptr, 1, e.V, mn,
+                       e.E, rocblas_outofplace, e.info) != rocblas_status_success)
+    rc = ROM_EHIP;
+  std::vector<double> sv(mn);
+  int info = 0;
+  if (rc == ROM_OK && (hipMemcpyAsync(sv.data(), e.Sv, 8L * mn, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                       hipMemcpyAsync(&info, e.info, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                       hipStreamSynchronize(stream) != hipSuccess))
+    rc = ROM_EHIP;
+  rocblas_destroy_handle(rb);
+  if (rc != ROM_OK) return rc;
+  if (info != 0) return ROM_EHIP;
+  int r = 0;
+  for (int i = 0; i < mn; ++i) r += sv[i] > 1e-12 * sv[0];
+  if (rank_out) *rank_out = r;
+  if (r < 1) return ROM_EINVAL;
+  // Z, column norms, b = Z w, |b|; empty selection, res = b
+  k_ecm_z<<<nblk(nq), 256, 0, stream>>>(mn, r, nq, e.V, w_dev, e.Zr, e.cn);
+  k_ecm_b<<<r, 256, 0, stream>>>(nq, e.Zr, w_dev, e.b);
+  k_norm<<<1, 256, 0, stream>>>(r, e.b, e.bn);
+  EcmState st0{0, 0, -1, 0, 0.0, 0.0};
+  if (hipMemsetAsync(e.sel, 0, 4L * nq, stream) != hipSuccess ||
+      hipMemcpyAsync(e.res, e.b, 8L * r, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(e.st, &st0, sizeof(st0), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return ROM_EHIP;
+  double bn = 0.0;
+  if (hipMemcpyAsync(&bn, e.bn, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return ROM_EHIP;
+  const size_t sh_update = 8 * (3 * (size_t)(m_max + 1) + 32) + 8 * (size_t)(m_max + 1);
+  int hl = 0;
+  if (hist_host && hist_cap > 0) hist_host[hl++] = 1.0;
+  EcmState st = st0;
+  st.rn = bn;
+  long n_iter = 0;
+  while (st.rn > eps * bn && st.k < m_max && n_iter < 10L * m_max) {
+    ++n_iter;
+    k_ecm_score<<<nblocks, ECM_SCORE_BLOCK, 8 * (size_t)r, stream>>>(r, nq, e.Zr, e.cn, e.res, e.sel, e.bv, e.bi);
+    k_ecm_update<<<1, ECM_THREADS, sh_update, stream>>>(r, nq, m_max, nblocks, e.Zr, e.b, e.bv, e.bi, e.S, e.ZS, e.G,
+                                                        e.Lm, e.Gp, e.Lp, e.hv, e.w, e.res, e.sel, e.st);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&st, e.st, sizeof(st), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return ROM_EHIP;
+    if (st.status != 0) break;
+    if (hist_host && hl < hist_cap) hist_host[hl++] = st.rn / bn;
+  }
+  if (hist_len) *hist_len = hl;
+  *m_out = st.k;
+  if (st.k > 0 && (hipMemcpyAsync(idx_dev, e.S, 4L * st.k, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+                   hipMemcpyAsync(weights_dev, e.w, 8L * st.k, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+                   hipStreamSynchronize(stream) != hipSuccess))
+    return ROM_EHIP;
+  return st.status == 2 ? ROM_EUNSUPPORTED : ROM_OK;
 }
 
 }  // extern "C"

@@ -36,3 +36,23 @@ def pod(S, M, n, device='cuda:0'):
     rom_pod(nrow, ns, St.data_ptr(), *weight, n, modes.data_ptr(), lam.data_ptr(), work.data_ptr(), wb,
             stream.cuda_stream)
     return modes.T, lam
+
+
+def ecm(J, w, eps, m_max, device='cuda:0'):
+    """Empirical cubature of the integrands J (R, nq) with full-rule weights w
+    (nq,): returns (selected points in selection order, their weights,
+    |res| / |b| after each iteration, rank of the integrand matrix, the
+    library's return code)."""
+    from . import rom_ecm, rom_ecm_workspace
+    dev = torch.device(device)
+    R, nq = J.shape
+    Jd = torch.as_tensor(np.ascontiguousarray(J, dtype=np.float64), device=dev)
+    wd = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64), device=dev)
+    idx = torch.zeros(m_max, dtype=torch.int32, device=dev)
+    wts = torch.zeros(m_max, dtype=torch.float64, device=dev)
+    wb = rom_ecm_workspace(R, nq, m_max)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    m, hist, rank, code = rom_ecm(R, nq, Jd.data_ptr(), wd.data_ptr(), eps, m_max, idx.data_ptr(), wts.data_ptr(),
+                                  work.data_ptr(), wb, stream.cuda_stream, hist_cap=10 * m_max + 1)
+    return idx[:m].cpu().numpy().astype(np.int64), wts[:m].cpu().numpy(), np.array(hist), rank, code
