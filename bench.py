@@ -215,6 +215,41 @@ def fe2_rate(rom_file, mode):
                 band_kl=info['kl'], peak_traction=FE2_PEAK, max_compliance=max(C))
 
 
+POD_SIZE = (32316, 960, 40)   # dofs of the n = 40 cell, snapshots (16 mu x 3 paths x 20 steps), modes
+ECM_SIZE = (441, 155, 154)    # integrands (n L + 1 for n = 40, L = 11), grid of about 24000 points
+
+
+def offline_rates():
+    """The offline stage on the GPU at the n = 40 ROM's sizes: POD of 960
+    snapshots of 32316 dofs with a sparse SPD weight (40 modes), and the
+    empirical cubature of 441 smooth integrands over 23870 points
+    (tolerance 1e-4).  Wall time of each call (inputs resident in HBM)."""
+    import torch
+    import workloads
+    from paper_2307_16894_amd.offline import ecm, pod
+    nrow, ns, n = POD_SIZE
+    S = workloads.pod_snapshots(7, nrow, ns, 200, 0.8, 1e-12)
+    M = workloads.banded_spd(8, nrow, 8)
+    pod(S[:, :64], M, 8)  # warm-up (library handles, code objects)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    modes, lam = pod(S, M, n)
+    torch.cuda.synchronize()
+    t_pod = time.perf_counter() - t0
+    R, nx, ny = ECM_SIZE
+    pts, w = workloads.grid_points(nx, ny)
+    J = workloads.cos_integrands(4, pts, R)
+    t0 = time.perf_counter()
+    idx, wq, hist, rank, code = ecm(J, w, 1e-4, 1024)
+    torch.cuda.synchronize()
+    t_ecm = time.perf_counter() - t0
+    gram_flops = 2.0 * ns * ns * nrow + 2.0 * n * ns * nrow + 2.0 * n * n * nrow
+    return dict(pod=dict(rows=nrow, snapshots=ns, modes=n, seconds=t_pod, gemm_gflop=gram_flops / 1e9,
+                         lambda_ratio=float(lam[n - 1] / lam[0])),
+                ecm=dict(integrands=R, points=nx * ny, rank=rank, selected=int(len(idx)), iterations=len(hist) - 1,
+                         final_residual=float(hist[-1]), seconds=t_ecm, code=code))
+
+
 def _oracle_worker(args):
     rom_file, mu, path = args
     from threadpoolctl import threadpool_limits
@@ -460,6 +495,8 @@ def main(argv=None):
     if not a.no_fe2 and w['rom'] == 'onevoid_n40_m400':
         log("[bench] two-scale example")
         out['fe2'] = fe2_rate(rom_file, L.MODE_PHASED)
+        log("[bench] offline stage")
+        out['offline'] = offline_rates()
     if not a.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline(w, rom_file)
     print(json.dumps(out), flush=True)

@@ -169,3 +169,46 @@ def fe2_loads(steps, peak):
     beta = np.concatenate([np.arange(1, half + 1) / half,
                            1.0 - np.arange(1, steps - half + 1) / (steps - half)])
     return peak * beta
+
+
+# ---------------------------------------------------------------------------
+# Offline-stage inputs: snapshot sets with a prescribed spectrum and sparse
+# SPD weights with the pattern of a mass-plus-stiffness matrix (POD), and
+# smooth integrands at the points of a uniform grid (cubature).
+
+def pod_snapshots(seed, nrow, ns, rank, decay, noise):
+    """(nrow, ns): rank-`rank` snapshots with singular values decay**k plus
+    Gaussian noise of size `noise`."""
+    g = rng(seed)
+    U = np.linalg.qr(g.standard_normal((nrow, rank)))[0]
+    V = np.linalg.qr(g.standard_normal((ns, rank)))[0]
+    return (U * decay ** np.arange(rank)) @ V.T + noise * g.standard_normal((nrow, ns))
+
+
+def banded_spd(seed, nrow, bw):
+    """Sparse symmetric positive definite (nrow, nrow) matrix with bw off-
+    diagonals on each side (diagonally dominant)."""
+    import scipy.sparse as sp
+    g = rng(seed)
+    diags = [g.uniform(-0.1, 0.1, nrow - k) for k in range(1, bw + 1)]
+    A = sp.diags(diags, list(range(1, bw + 1)), shape=(nrow, nrow))
+    return (A + A.T + sp.diags(np.full(nrow, 1.0 + 0.2 * bw))).tocsr()
+
+
+def grid_points(nx, ny):
+    """Cell centres of an nx x ny grid on the unit square and equal weights."""
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y, indexing='ij')
+    return np.stack([X.ravel(), Y.ravel()], axis=1), np.full(nx * ny, 1.0 / (nx * ny))
+
+
+def cos_integrands(seed, pts, R):
+    """(R, points): cos(pi k x + a_k) cos(pi l y + b_l) for the first R pairs
+    (k, l) of a K x K table, random phases."""
+    g = rng(seed)
+    K = int(np.ceil(np.sqrt(R)))
+    x, y = pts[:, 0], pts[:, 1]
+    ph, ps = g.uniform(0, 2 * np.pi, K), g.uniform(0, 2 * np.pi, K)
+    return np.array([np.cos(np.pi * k * x + ph[k]) * np.cos(np.pi * l * y + ps[l])
+                     for k in range(K) for l in range(K)][:R])
