@@ -396,12 +396,11 @@ int band_stage_rows(int kl) {
   return B;
 }
 
-__global__ __launch_bounds__(LDS_THREADS_MAX) void k_band_solve_lds(
-    int nf, int kl, int ldab, int B, const double* __restrict__ band, const double* __restrict__ rhs_in,
-    double* __restrict__ ubuf, double* __restrict__ x, int dofs, const int* __restrict__ dofmap,
-    const int* __restrict__ fixed, int nfixed, const double* __restrict__ dud, double* __restrict__ u,
-    int* __restrict__ info) {
-  extern __shared__ double lds[];
+__device__ void band_lu_lds(int nf, int kl, int ldab, int B, const double* __restrict__ band,
+                            const double* __restrict__ rhs_in, double* __restrict__ ubuf, double* __restrict__ x,
+                            int dofs, const int* __restrict__ dofmap, const int* __restrict__ fixed, int nfixed,
+                            const double* __restrict__ dud, double* __restrict__ u, int* __restrict__ info,
+                            double* lds) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nt = blockDim.x;
   const int Wc = 2 * kl + 1, S = kl + 2, RW = Wc + 1;
   double* win = lds;                          // [S][RW]
@@ -580,6 +579,183 @@ __global__ __launch_bounds__(LDS_THREADS_MAX) void k_band_solve_lds(
   if (dud)
     for (int j = tid; j < nfixed; j += nt) u[fixed[j]] += dud[j];
   if (tid == 0) *info = 0;
+}
+
+// Banded Cholesky L L^T of the free-dof tangent (symmetric; positive
+// definite while the material hardens), no row interchanges: the window
+// holds rows k .. k + kl with their columns k .. row (position c mod W,
+// W = kl + 1) and right-hand side (position W), row r in slot r mod W; the
+// row entering at step k takes the slot of row k, whose entries are in
+// s_mult by then.  Step k: the column of L and y_k; then the update of the
+// lower triangle of the rows below (thread (g, p): column k + 1 + p of every
+// fourth row at or below it; p = kl the right-hand side), while the column
+// goes out and row k + kl + 1 comes in through the staging blocks.  Back
+// substitution with L^T as in the LU form.  Returns false (u untouched) at a
+// pivot that is not positive.
+__device__ bool band_chol_lds(int nf, int kl, int ldab, int B, const double* __restrict__ band,
+                              const double* __restrict__ rhs_in, double* __restrict__ ubuf, double* __restrict__ x,
+                              double* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nt = blockDim.x;
+  const int W = kl + 1, S = kl + 1, RW = W + 1;
+  double* win = lds;                       // [S][RW]
+  double* sin = win + (size_t)S * RW;      // [B][RW] rows about to enter (columns r - kl .. r, rhs)
+  double* sout = sin + (size_t)B * RW;     // [B][RW] columns of L that left (L(k + j, k), j = 0 .. kl; y_k)
+  double* s_mult = sout + (size_t)B * RW;  // [kl + 1]
+  int* s_off = (int*)(s_mult + kl + 1);    // [kl + 1] slot offsets of the rows below
+  __shared__ double s_y, s_sd;
+  for (int t = tid; t < S * RW; t += nt) win[t] = 0.0;
+  __syncthreads();
+  for (int t = tid; t < (kl + 1) * RW; t += nt) {
+    const int r = t / RW, j = t % RW;
+    if (r >= nf) continue;
+    double* row = win + (size_t)(r % S) * RW;
+    if (j == W) {
+      row[W] = rhs_in[r];
+    } else {
+      const int c = r - kl + j;
+      if (c >= 0) row[c % W] = band[(size_t)r * ldab + j];
+    }
+  }
+  // k mod W (= k mod S) and k mod B kept as counters: no division in the loop
+  int kw = 0, kb = 0;
+  const int g = tid / W, p = tid - g * W;
+  for (int k = 0; k < nf; ++k) {
+    if (kb == 0) {
+      for (int t = tid; t < B * RW && k > 0; t += nt) {
+        const int r = k - B + t / RW, j = t % RW;
+        if (j == W)
+          x[r] = sout[t];
+        else
+          ubuf[(size_t)r * W + j] = sout[t];
+      }
+      for (int t = tid; t < B * RW; t += nt) {
+        const int r = k + kl + 1 + t / RW, j = t % RW;
+        if (r < nf) sin[t] = (j == W) ? rhs_in[r] : band[(size_t)r * ldab + j];
+      }
+      __syncthreads();
+    }
+    const int last = min(nf - 1, k + kl), nr = last - k;
+    const int koff = kw * RW;  // slot of row k (slots and positions share the modulus W = S)
+    const double d = win[koff + kw];
+    if (!(d > 0.0)) return false;  // every thread reads the same pivot
+    const double sd = sqrt(d);
+    const double isd = 1.0 / sd;
+    for (int a = tid; a < nr; a += nt) {
+      int sl = kw + 1 + a;
+      sl = (sl >= S) ? sl - S : sl;
+      const int o = sl * RW;
+      s_off[a] = o;
+      s_mult[a] = win[o + kw] * isd;
+    }
+    if (tid == 0) {
+      s_sd = sd;
+      s_y = win[koff + W] * isd;
+    }
+    __syncthreads();
+    {
+      // thread (g, p): column k + 1 + p (p = kl: the right-hand side) of the
+      // rows a = g, g + 4, ... at or below it, four rows in flight
+      if (g < 4) {
+        const bool rhs = p == kl;
+        int pos = kw + 1 + p;
+        pos = rhs ? W : (pos >= W ? pos - W : pos);
+        const double lp = rhs ? s_y : (p < nr ? s_mult[p] : 0.0);
+        for (int a0 = g; a0 < nr; a0 += 4 * LDS_UNROLL) {
+          int o[LDS_UNROLL];
+          double m[LDS_UNROLL], v[LDS_UNROLL];
+#pragma unroll
+          for (int w = 0; w < LDS_UNROLL; ++w) {
+            const int a = a0 + 4 * w;
+            const bool on = a < nr && (rhs || a >= p);
+            o[w] = on ? s_off[a] + pos : -1;
+            m[w] = on ? s_mult[a] : 0.0;
+          }
+#pragma unroll
+          for (int w = 0; w < LDS_UNROLL; ++w) v[w] = (o[w] >= 0) ? win[o[w]] : 0.0;
+#pragma unroll
+          for (int w = 0; w < LDS_UNROLL; ++w)
+            if (o[w] >= 0) win[o[w]] = fma(-m[w], lp, v[w]);
+        }
+      }
+    }
+    for (int j = tid; j < RW; j += nt)
+      sout[(size_t)kb * RW + j] = (j == 0) ? s_sd : (j == W ? s_y : (j <= nr ? s_mult[j - 1] : 0.0));
+    const int rn = k + kl + 1;
+    if (rn < nf) {
+      double* row = win + koff;  // row k + kl + 1 takes the slot of row k
+      const double* src = sin + (size_t)kb * RW;
+      for (int j = tid; j < RW; j += nt) {
+        int q = kw + 1 + j;  // column k + 1 + j
+        q = (q >= W) ? q - W : q;
+        row[j == W ? W : q] = src[j];
+      }
+    }
+    __syncthreads();
+    kw = (kw + 1 == W) ? 0 : kw + 1;
+    kb = (kb + 1 == B) ? 0 : kb + 1;
+  }
+  {
+    const int k0 = ((nf - 1) / B) * B, rows = nf - k0;
+    for (int t = tid; t < rows * RW; t += nt) {
+      const int r = k0 + t / RW, j = t % RW;
+      if (j == W)
+        x[r] = sout[t];
+      else
+        ubuf[(size_t)r * W + j] = sout[t];
+    }
+  }
+  __syncthreads();
+  // L^T x = y: x_k = (y_k - sum_j L(k + j, k) x_{k + j}) / L(k, k)
+  double r0 = 0.0, r1 = 0.0;  // x[k + 1 + lane + 64 j]
+  double* yb = win + (size_t)S * W;
+  for (int kb = nf - 1; kb >= 0; kb -= S) {
+    const int k0 = max(0, kb - S + 1), rows = kb - k0 + 1;
+    for (int t = tid; t < rows * W; t += nt) win[t] = ubuf[(size_t)k0 * W + t];
+    for (int t = tid; t < rows; t += nt) yb[t] = x[k0 + t];
+    __syncthreads();
+    if (wave == 0) {
+      for (int k = kb; k >= k0; --k) {
+        const double* Lc = win + (size_t)(k - k0) * W;
+        const int jm = min(kl, nf - 1 - k);
+        double sacc = 0.0;
+        if (lane + 1 <= jm) sacc = Lc[lane + 1] * r0;
+        if (lane + 65 <= jm) sacc = fma(Lc[lane + 65], r1, sacc);
+        for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off);
+        const double xk = (yb[k - k0] - sacc) / Lc[0];
+        const double t0 = __shfl(r0, 63);
+        r1 = __shfl_up(r1, 1);
+        r0 = __shfl_up(r0, 1);
+        if (lane == 0) {
+          r1 = t0;
+          r0 = xk;
+          x[k] = xk;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(LDS_THREADS_MAX) void k_band_solve_lds(
+    int nf, int kl, int ldab, int B, const double* __restrict__ band, const double* __restrict__ rhs_in,
+    double* __restrict__ ubuf, double* __restrict__ x, int dofs, const int* __restrict__ dofmap,
+    const int* __restrict__ fixed, int nfixed, const double* __restrict__ dud, double* __restrict__ u,
+    int* __restrict__ info) {
+  extern __shared__ double lds[];
+  if (band_chol_lds(nf, kl, ldab, B, band, rhs_in, ubuf, x, lds)) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int d = tid; d < dofs; d += nt) {
+      const int r = dofmap[d];
+      if (r >= 0) u[d] += x[r];
+    }
+    if (dud)
+      for (int j = tid; j < nfixed; j += nt) u[fixed[j]] += dud[j];
+    if (tid == 0) *info = 0;
+    return;
+  }
+  __syncthreads();
+  band_lu_lds(nf, kl, ldab, B, band, rhs_in, ubuf, x, dofs, dofmap, fixed, nfixed, dud, u, info, lds);
 }
 
 inline unsigned nblk(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }

@@ -128,6 +128,16 @@ def test_macro_kernels_full_size(gpu, full, dims):
     du = sol.u.cpu().numpy() - u
     assert np.abs(du[sol.fixed]).max() == 0.0
     assert np.abs(du[free] - du_o).max() <= 1e-9 * np.abs(du_o).max(), rel(du[free], du_o)
+    # -Abar: a negative definite tangent, so the Cholesky form gives way to
+    # the LU form with row interchanges (same launch); the step is -du
+    negA = (-sol.rb.Abar).contiguous()
+    sol.u.copy_(torch.from_numpy(u))
+    L.rom_fe2_solve(sol.h, negA.data_ptr(), sol.res.data_ptr(), None, sol.u.data_ptr(), sol.solve_info.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert int(sol.solve_info.item()) == 0
+    dn = sol.u.cpu().numpy() - u
+    assert np.abs(dn[free] + du_o).max() <= 1e-9 * np.abs(du_o).max(), rel(-dn[free], du_o)
+    sol.u.copy_(torch.from_numpy(u + du))
     L.rom_fe2_compliance(sol.h, T, sol.u.data_ptr(), sol.C.data_ptr(), s)
     torch.cuda.synchronize()
     Co = ofe2.compliance(mesh, T, sol.u.cpu().numpy())
