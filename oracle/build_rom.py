@@ -39,6 +39,11 @@ ROMS = {
                              seed=2000),
 }
 
+# two phases: the one-void cell whose void is lined with a stiff elastic
+# coating (every point of the parent cell within `coating` of the void
+# boundary), ten times the matrix modulus and no yield in range
+ROMS['coatvoid_n20_m120'] = dict(ROMS['onevoid_n20_m120'], coating=0.06, mat2=(10.0, 0.3, 1.0e3, 0.0), seed=1500)
+
 # four elliptical voids of fixed area 0.075 each (porosity 0.3), parent circles
 # of equal area; mu = (kappa_i, theta_i) per void; ~30k T6.  The three ROMs
 # share mesh and training data (so they can share a snapshot cache).
@@ -62,6 +67,23 @@ def _geometry(spec):
     return m, space, grad_modes
 
 
+def phases(spec, m):
+    """Phase of every quadrature point of the parent mesh: 1 in the coating
+    around the (centred) void, 0 in the matrix."""
+    if 'coating' not in spec:
+        return np.zeros(m.nq, dtype=np.int64)
+    d = np.hypot(m.qX[:, 0] - 0.5, m.qX[:, 1] - 0.5)
+    return (d < spec['r0'] + spec['coating']).astype(np.int64)
+
+
+def material(spec, m):
+    """Material constants at every quadrature point (scalars for one phase)."""
+    ph = phases(spec, m)
+    if not ph.any():
+        return MAT
+    return tuple(np.where(ph == 1, b, a) for a, b in zip(MAT, spec['mat2']))
+
+
 def _mu_coeff(spec, mu):
     return auxiliary.coefficients(spec['kind'], mu, spec['r0'], spec.get('void_area'))
 
@@ -70,7 +92,7 @@ def _fom_job(args):
     spec, mu, path = args
     m, space, grad_modes = _G['geom']
     Fmu = auxiliary.transformation(grad_modes, _mu_coeff(spec, mu))
-    pr = fem.Problem(m, space, Fmu, MAT)
+    pr = fem.Problem(m, space, Fmu, material(spec, m))
     res = fom.solve_path(pr, path, tol=1e-10 * max(1.0, 1.0), want_W=True)
     return np.array(res.w), np.array(res.W), np.array(res.Pbar), res.iters
 
@@ -127,8 +149,11 @@ def build(name, outdir, workers, snapshot_cache=None, overrides=None):
     Gd = np.stack([g.reshape(m.nq, 4)[idx] for g in grad_modes], axis=-1)  # (m, 4, c)
     path = os.path.join(outdir, name + '.rom')
     n_mu = 2 if spec['kind'] == 0 else 8
+    ph = phases(spec, m)
+    two = bool(ph.any())
     artifact.write(path, spec['n'], idx.size, grad_modes.shape[0], spec['kind'], n_mu, MAT,
-                   spec['r0'], spec.get('void_area', 0.0), 1.0, wq, Gfull[idx], Gd, idx)
+                   spec['r0'], spec.get('void_area', 0.0), 1.0, wq, Gfull[idx], Gd, idx,
+                   mat2=spec['mat2'] if two else None, phase=ph[idx] if two else None)
     # ROM quality on held-out paths (not a parity check)
     rom = ROM(path)
     test_mu = (workloads.one_void_mu if spec['kind'] == 0 else workloads.four_void_mu)(spec['seed'] + 7, 4)

@@ -150,12 +150,14 @@ def j2_update(F, Fp, Fp33, xi, mat):
     Fp    : (..., 2, 2) committed in-plane plastic deformation gradient F^pl_n.
     Fp33  : (...)       committed F^pl_33.
     xi    : (...)       committed equivalent plastic strain xi_n.
-    mat   : (E, nu, sigma_y0, H).
+    mat   : (E, nu, sigma_y0, H), scalars or arrays of the batch shape (...)
+            (a material per point: several phases).
 
     Returns (P, Fp_new, Fp33_new, xi_new, gamma), P the in-plane 1PK stress.
     """
-    E, nu, sy0, H = mat
+    E, nu, sy0, H = (np.asarray(v, dtype=np.float64) for v in mat)
     lam, G = lame(E, nu)
+    G2 = G[..., None, None]  # G against (..., 2, 2) tensors
     # trial elastic state, eq. j2_7 with eps = 1/2 ln C^el
     Fe_tr = F @ inv2(Fp)
     Ce_tr = tr2(Fe_tr) @ Fe_tr
@@ -163,7 +165,7 @@ def j2_update(F, Fp, Fp33, xi, mat):
     eps33 = -np.log(Fp33)  # F^el_33 = 1 / F^pl_33 because F_33 = 1
     treps = eps[..., 0, 0] + eps[..., 1, 1] + eps33
     # eq. j2_1 (trial: eps^pl carried by F^pl)
-    sig = 2.0 * G * eps
+    sig = 2.0 * G2 * eps
     sig[..., 0, 0] += lam * treps
     sig[..., 1, 1] += lam * treps
     sig33 = 2.0 * G * eps33 + lam * treps
@@ -183,7 +185,7 @@ def j2_update(F, Fp, Fp33, xi, mat):
     # eq. j2_3: flow direction
     r = SQRT32 * dev / nds[..., None, None]
     r33 = SQRT32 * dev33 / nds
-    sig_new = sig - 2.0 * G * gam[..., None, None] * r
+    sig_new = sig - 2.0 * G2 * gam[..., None, None] * r
     xi_new = xi + gam
     # eq. j2_10: exponential update of F^pl
     Fp_new = expm_sym2(gam[..., None, None] * r) @ Fp

@@ -45,6 +45,12 @@ class ROM:
     def __init__(self, path=None, data=None):
         d = artifact.read(path) if data is None else data
         self.__dict__.update(d)
+        # material per ECM point (a second phase where phase == 1)
+        phase = np.asarray(d.get('phase', np.zeros(self.m, dtype=np.int64)))
+        if d.get('mat2') is not None and np.any(phase == 1):
+            self.mat_q = tuple(np.where(phase == 1, b, a) for a, b in zip(self.mat, d['mat2']))
+        else:
+            self.mat_q = self.mat
 
     # -- step 1 -------------------------------------------------------------
     def transformation(self, mu):
@@ -59,7 +65,7 @@ class ROM:
     def evaluate(self, r, Fbar, hist, Finv, J):
         H = (self.G @ r).reshape(self.m, 2, 2)  # sum_n r_n grad phi_n at the points
         F = Fbar[None] + H @ Finv
-        P, A, Fp, Fp33, xi, gam = material.j2_point(F, *hist, self.mat)
+        P, A, Fp, Fp33, xi, gam = material.j2_point(F, *hist, self.mat_q)
         wJ = self.w * np.abs(J)
         T = right_map(Finv)  # vec(Hp F_mu^-1) = T vec(Hp)
         B = T @ self.G  # mapped mode gradients (m, 4, n)
