@@ -55,6 +55,7 @@ void release(rom_model* h) {
   (void)hipFree(h->Gd);
   (void)hipFree(h->Gq32);
   (void)hipFree(h->Gq16);
+  (void)hipFree(h->phase);
   delete h;
 }
 
@@ -128,18 +129,35 @@ int rom_load(const void* blob, size_t bytes, int device, rom_handle* out) {
   if (bytes < 256 || memcmp(b, "PODECMR1", 8) != 0) return ROM_EFORMAT;
   uint32_t hdr[6];
   memcpy(hdr, b + 8, sizeof(hdr));
-  if (hdr[0] != 1) return ROM_EVERSION;
+  if (hdr[0] != 1 && hdr[0] != 2) return ROM_EVERSION;
+  const bool two = hdr[0] == 2;  // version 2: a second phase and the phase of every point
   const int n = (int)hdr[1], m = (int)hdr[2], c = (int)hdr[3], kind = (int)hdr[4], n_mu = (int)hdr[5];
   if (n < 1 || n > ROM_NMAX - 5 || m < 1 || m > (1 << 24) || c < 1 || c > 12) return ROM_EFORMAT;
   if (!((kind == 0 && c == 2 && n_mu == 2) || (kind == 1 && c == 12 && n_mu == 8))) return ROM_EFORMAT;
   double par[7];
   memcpy(par, b + 32, sizeof(par));
-  const size_t need = 256 + 8 * ((size_t)m + (size_t)m * 4 * n + (size_t)m * 4 * c + (size_t)m);
+  const size_t need = 256 + 8 * ((size_t)m + (size_t)m * 4 * n + (size_t)m * 4 * c + (size_t)m + (two ? (size_t)m : 0));
   if (bytes < need) return ROM_EFORMAT;
   for (int i = 0; i < 7; ++i)
     if (!isfinite(par[i])) return ROM_EFORMAT;
   const double E = par[0], nu = par[1];
   if (!(E > 0 && nu > -1 && nu < 0.5 && par[2] > 0 && par[3] >= 0 && par[4] > 0 && par[6] > 0)) return ROM_EFORMAT;
+  double par2[4] = {E, nu, par[2], par[3]};
+  std::vector<int> phase;
+  if (two) {
+    memcpy(par2, b + 88, sizeof(par2));
+    for (int i = 0; i < 4; ++i)
+      if (!isfinite(par2[i])) return ROM_EFORMAT;
+    if (!(par2[0] > 0 && par2[1] > -1 && par2[1] < 0.5 && par2[2] > 0 && par2[3] >= 0)) return ROM_EFORMAT;
+    const unsigned char* pp = b + 256 + 8 * ((size_t)m + (size_t)m * 4 * n + (size_t)m * 4 * c + (size_t)m);
+    phase.resize(m);
+    for (int q = 0; q < m; ++q) {
+      int64_t v;
+      memcpy(&v, pp + 8 * (size_t)q, 8);
+      if (v != 0 && v != 1) return ROM_EFORMAT;
+      phase[q] = (int)v;
+    }
+  }
   std::vector<double> w(m), G((size_t)m * 4 * n), Gd((size_t)m * 4 * c);
   const unsigned char* p = b + 256;
   memcpy(w.data(), p, 8 * w.size());
@@ -191,8 +209,15 @@ int rom_load(const void* blob, size_t bytes, int device, rom_handle* out) {
   h->mp.K = h->mp.lam + 2.0 * h->mp.G / 3.0;
   h->mp.sy0 = par[2];
   h->mp.H = par[3];
+  h->mp2.G = par2[0] / (2.0 * (1.0 + par2[1]));
+  h->mp2.lam = par2[0] * par2[1] / ((1.0 + par2[1]) * (1.0 - 2.0 * par2[1]));
+  h->mp2.K = h->mp2.lam + 2.0 * h->mp2.G / 3.0;
+  h->mp2.sy0 = par2[2];
+  h->mp2.H = par2[3];
   int rc = ROM_OK;
-  if (hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) rc = ROM_EHIP;
+  if (two) rc = upload(&h->phase, phase);
+  if (rc == ROM_OK && hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    rc = ROM_EHIP;
   if (rc == ROM_OK) rc = upload(&h->w, w);
   if (rc == ROM_OK) rc = upload(&h->Gt, Gt);
   if (rc == ROM_OK) rc = upload(&h->Gq, Gq);

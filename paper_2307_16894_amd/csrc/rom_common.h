@@ -21,6 +21,8 @@ struct rom_model {
   int ncu;               // compute units of the device
   double E, nu, sy0, H, r0, void_area, cell_area;
   J2Params mp;
+  J2Params mp2;  // second phase (two-phase cells)
+  int* phase;    // [m] phase of every ECM point (0: mp, 1: mp2), null for a single-phase cell
   double* w;    // [m] ECM weights
   double* Gt;   // [n][4][m] mode gradients, point fastest (per-lane kinematics)
   double* Gq;   // [m][4][npad] mode gradients, mode fastest, zero padded (contractions)
@@ -37,6 +39,20 @@ struct rom_model {
   int cap;                 // event pairs allocated
   hipEvent_t* ev;          // [2 * cap]
 };
+
+// Material of ECM point q: the second phase where the cell has one and the
+// point lies in it.  By value: a reference into a kernel's argument struct
+// would make the compiler copy the whole struct to private memory.
+__host__ __device__ inline J2Params point_params(J2Params mp, J2Params mp2, const int* phase, int q) {
+  const bool two = phase && phase[q];
+  J2Params r;
+  r.G = two ? mp2.G : mp.G;
+  r.lam = two ? mp2.lam : mp.lam;
+  r.K = two ? mp2.K : mp.K;
+  r.sy0 = two ? mp2.sy0 : mp.sy0;
+  r.H = two ? mp2.H : mp.H;
+  return r;
+}
 
 // Record the start / stop event of a timed launch; no-ops unless enabled.
 int rom_timing_mark(rom_model* h, int stop, hipStream_t s);

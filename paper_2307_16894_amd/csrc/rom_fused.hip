@@ -60,6 +60,8 @@ int rom_fused_prepare(rom_model* h, int P, const double* Fbar, void* state, cons
   a.tol = o.tol;
   a.inv_area = 1.0 / h->cell_area;
   a.mp = h->mp;
+  a.mp2 = h->mp2;
+  a.phase = h->phase;
   a.Gt = h->Gt;
   a.Gq = h->Gq;
   a.Fbar = Fbar;

@@ -8,6 +8,8 @@ struct FusedArgs {
   int max_sub;  // load-step cutting depth (0: plain step)
   double tol, inv_area;
   J2Params mp;
+  J2Params mp2;       // second phase of a two-phase cell
+  const int* phase;   // [m] phase of every ECM point, or null
   const double* Gt;
   const double* Gq;
   const double* Fbar;

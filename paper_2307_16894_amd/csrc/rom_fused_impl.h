@@ -968,7 +968,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) Fi[k] = tmu[k * m + q];
           kinematics(n, m, q, a.Gt, sR, Fb, Fi, F);
-          point_material(F, m, q, tmu, hc, ht, a.mp, D, P, Fi, wJ);
+          point_material(F, m, q, tmu, hc, ht, point_params(a.mp, a.mp2, a.phase, q), D, P, Fi, wJ);
           put_record_d<PREC>(sQ + tid * QS, 1, D);
           put_record_wf(sQ + tid * QS, P, Fi, wJ);
           if constexpr (PREC != PREC_F64) {

@@ -133,7 +133,8 @@ __global__ __launch_bounds__(256) void k_ph_mat(const FusedArgs a) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) Fi[k] = tmu[k * m + q];
   kin_F(Fb, H[0], H[m], H[2 * m], H[3 * m], Fi, F);
-  point_material(F, m, q, tmu, a.hc + (size_t)p * 6 * m, a.ht + (size_t)p * 6 * m, a.mp, D, P, Fi, wJ);
+  point_material(F, m, q, tmu, a.hc + (size_t)p * 6 * m, a.ht + (size_t)p * 6 * m, point_params(a.mp, a.mp2, a.phase, q),
+                 D, P, Fi, wJ);
   put_record_d<PREC>(rec, m, D);
 #pragma unroll
   for (int k = 0; k < 4; ++k) rec[(size_t)(rec_p_row<PREC>() + k) * m] = P[k];

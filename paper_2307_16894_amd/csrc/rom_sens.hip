@@ -49,7 +49,8 @@ __device__ void mu_to_dc(int kind, const double* mu, double r0, double void_area
 // and the per-parameter b, d); then df/dmu = sum_q G_q^T b over the chunk on
 // MFMA, the waves splitting its points.
 __global__ __launch_bounds__(256) void k_sens(int n, int npad, int m, int c, int kind, int n_mu, double r0,
-                                              double void_area, double inv_area, J2Params mp,
+                                              double void_area, double inv_area, J2Params mp, J2Params mp2,
+                                              const int* __restrict__ phase,
                                               const double* __restrict__ Gt, const double* __restrict__ Gq,
                                               const double* __restrict__ Gd, const double* __restrict__ Fbar,
                                               const double* __restrict__ rt, const double* __restrict__ hc,
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(256) void k_sens(int n, int npad, int m, int c, int
       kin_F(Fb, H[0], H[1], H[2], H[3], Fi, F);
       const double Fp[4] = {hq[q], hq[m + q], hq[2 * m + q], hq[3 * m + q]};
       double P[4], A[16], Fpn[4], Fp33n, xin;
-      j2_point<true>(F, Fp, hq[4 * m + q], hq[5 * m + q], mp, P, A, Fpn, Fp33n, xin);
+      j2_point<true>(F, Fp, hq[4 * m + q], hq[5 * m + q], point_params(mp, mp2, phase, q), P, A, Fpn, Fp33n, xin);
 #pragma unroll
       for (int k = 0; k < SENS_MU; ++k) {
         if (k >= n_mu) break;
@@ -200,7 +201,7 @@ int rom_launch_shape_sensitivity(rom_model* h, int P, const double* Fbar, const 
   const StateLayout L = rom_state_layout(h, P);
   void* st = const_cast<void*>(state);
   k_sens<<<P, 256, 0, s>>>(h->n, h->npad, h->m, h->c, h->kind, h->n_mu, h->r0, h->void_area, 1.0 / h->cell_area,
-                           h->mp, h->Gt, h->Gq, h->Gd, Fbar, field<double>(st, L, F_RT), field<double>(st, L, F_HC),
+                           h->mp, h->mp2, h->phase, h->Gt, h->Gq, h->Gd, Fbar, field<double>(st, L, F_RT), field<double>(st, L, F_HC),
                            field<double>(st, L, F_TMU), field<double>(st, L, F_MU), field<int>(st, L, F_MUOK),
                            field<double>(st, L, F_ZK), out);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;

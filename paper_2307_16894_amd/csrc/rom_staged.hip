@@ -122,7 +122,8 @@ __device__ __forceinline__ void point_kinematics(int n, int m, int q, const doub
   F[3] = Fb[3] + H2 * Fi[1] + H3 * Fi[3];
 }
 
-__global__ __launch_bounds__(64) void k_eval(int n, int m, J2Params mp, const double* __restrict__ Gt,
+__global__ __launch_bounds__(64) void k_eval(int n, int m, J2Params mp, J2Params mp2, const int* __restrict__ phase,
+                                             const double* __restrict__ Gt,
                                              const double* __restrict__ Fbar, const double* __restrict__ rt,
                                              const double* __restrict__ hc, double* __restrict__ ht,
                                              const double* __restrict__ tmu, const int* __restrict__ done,
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(64) void k_eval(int n, int m, J2Params mp, const do
   const double* h = hc + (size_t)p * 6 * m + q;
   const double Fp[4] = {h[0], h[m], h[2 * m], h[3 * m]};
   double P[4], A[16], Fpn[4], Fp33n, xin;
-  j2_point<true>(F, Fp, h[4 * m], h[5 * m], mp, P, A, Fpn, Fp33n, xin);
+  j2_point<true>(F, Fp, h[4 * m], h[5 * m], point_params(mp, mp2, phase, q), P, A, Fpn, Fp33n, xin);
   double* ho = ht + (size_t)p * 6 * m + q;
   ho[0] = Fpn[0];
   ho[m] = Fpn[1];
@@ -406,6 +407,7 @@ __global__ __launch_bounds__(256) void k_solve(int n, int it, int max_iter, int 
 
 // Effective stress and stiffness at the returned state (Sec. 3.3).
 __global__ __launch_bounds__(128) void k_effective(int n, int npad, int m, double inv_area, J2Params mp,
+                                                   J2Params mp2, const int* __restrict__ phase,
                                                    const double* __restrict__ Gt, const double* __restrict__ Gq,
                                                    const double* __restrict__ Fbar, const double* __restrict__ rt,
                                                    const double* __restrict__ hc, const double* __restrict__ tmu,
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(128) void k_effective(int n, int npad, int m, doubl
       const double* h = hc + (size_t)p * 6 * m + q;
       const double Fp[4] = {h[0], h[m], h[2 * m], h[3 * m]};
       double P[4], A[16], Fpn[4], Fp33n, xin;
-      j2_point<true>(F, Fp, h[4 * m], h[5 * m], mp, P, A, Fpn, Fp33n, xin);
+      j2_point<true>(F, Fp, h[4 * m], h[5 * m], point_params(mp, mp2, phase, q), P, A, Fpn, Fp33n, xin);
 #pragma unroll
       for (int k = 0; k < 4; ++k) accP[k] += wJ * P[k];
 #pragma unroll
@@ -700,14 +702,15 @@ int rom_launch_step_staged(rom_model* h, int P, const double* Fbar, void* state,
   k_step_begin<<<(tot + 255) / 256, 256, 0, s>>>(P, n, rc, rt, muok, done, status, iters, res);
   const size_t solve_lds = (size_t)(n * n + n + 8) * 8 + (size_t)n * 4;
   for (int it = 0; it < o.max_iter; ++it) {
-    k_eval<<<dim3((m + 63) / 64, P), 64, 0, s>>>(n, m, h->mp, h->Gt, Fbar, rt, hc, ht, tmu, done, D, W);
+    k_eval<<<dim3((m + 63) / 64, P), 64, 0, s>>>(n, m, h->mp, h->mp2, h->phase, h->Gt, Fbar, rt, hc, ht, tmu, done,
+                                                 D, W);
     if (rom_timing_mark(h, 0, s) != ROM_OK) return ROM_EHIP;
     k_assemble<<<P, 256, 0, s>>>(n, h->npad, m, h->Gq, D, W, done, K, f);
     if (rom_timing_mark(h, 1, s) != ROM_OK) return ROM_EHIP;
     k_solve<<<P, 256, solve_lds, s>>>(n, it, o.max_iter, o.fixed_iters, o.tol, K, f, piv, rt, done, status,
                                       iters, res);
   }
-  k_effective<<<P, 128, 0, s>>>(n, h->npad, m, 1.0 / h->cell_area, h->mp, h->Gt, h->Gq, Fbar, rt, hc, tmu, muok,
+  k_effective<<<P, 128, 0, s>>>(n, h->npad, m, 1.0 / h->cell_area, h->mp, h->mp2, h->phase, h->Gt, h->Gq, Fbar, rt, hc, tmu, muok,
                                 K, piv, field<double>(state, L, F_PBAR), field<double>(state, L, F_ABAR),
                                 field<double>(state, L, F_ZK));
   k_finish<<<P, 256, 0, s>>>(n, m, o.commit, Fbar, field<double>(state, L, F_FBC), status, iters, res, rt, rc, ht,

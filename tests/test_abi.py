@@ -51,8 +51,10 @@ def test_rom_load_rejects_malformed_artifacts():
     assert _load_code(b'NOTAROM!' + good[8:]) == L.ROM_EFORMAT
     assert _load_code(good[:-8]) == L.ROM_EFORMAT  # truncated
     bad = bytearray(good)
-    bad[8:12] = np.array([2], dtype='<u4').tobytes()
+    bad[8:12] = np.array([3], dtype='<u4').tobytes()
     assert _load_code(bad) == L.ROM_EVERSION
+    bad[8:12] = np.array([2], dtype='<u4').tobytes()  # two phases: the phase array is missing
+    assert _load_code(bad) == L.ROM_EFORMAT
     bad = bytearray(good)
     bad[256:264] = np.array([-1.0]).tobytes()  # a non-positive ECM weight
     assert _load_code(bad) == L.ROM_EFORMAT
@@ -70,3 +72,18 @@ def test_null_arguments():
     assert lib.rom_state_bytes(None, 4, None) == L.ROM_EINVAL
     assert lib.rom_step(None, 4, None, None, None, None, None, None, None) == L.ROM_EINVAL
     assert lib.rom_free(None) == L.ROM_EINVAL
+
+
+def test_rom_load_two_phase_artifacts():
+    """Version 2 (a second phase and the phase of every ECM point): the
+    loader rejects a phase other than 0 or 1 and an invalid second material
+    before touching a device."""
+    good = open(rom_path('coatvoid_n20_m120'), 'rb').read()
+    assert np.frombuffer(good[8:12], dtype='<u4')[0] == 2
+    bad = bytearray(good)
+    bad[-8:] = np.array([2], dtype='<i8').tobytes()  # phase of the last point
+    assert _load_code(bad) == L.ROM_EFORMAT
+    bad = bytearray(good)
+    bad[88:96] = np.array([-1.0]).tobytes()  # E of the second phase
+    assert _load_code(bad) == L.ROM_EFORMAT
+    assert _load_code(good[:-8]) == L.ROM_EFORMAT  # phases truncated
