@@ -51,6 +51,15 @@ WORKLOADS = {
     'fourvoid_n100_m1500_P16384_cyclic20': dict(rom='fourvoid_n100_m1500', cell='fourvoid', P=16384, steps=20,
                                                 path='cyclic', rho=(0.02, 0.08), seed=0, timed=3, warm=1,
                                                 variants=['fp64', 'fp32', 'bf16']),
+    # two phases: the n = 20 one-void cell lined with a stiff elastic coating,
+    # 16384 points, 10-step monotone paths; beside it the single-phase cell
+    # at the same size (the cost of a material per ECM point)
+    'coatvoid_n20_m120_P16384_monotone10': dict(rom='coatvoid_n20_m120', cell='onevoid', P=16384, steps=10,
+                                                path='monotone', rho=(0.02, 0.05), seed=0, timed=10, warm=10,
+                                                variants=['fp64', 'fp64_phased', 'bf16_phased']),
+    'onevoid_n20_m120_P16384_monotone10': dict(rom='onevoid_n20_m120', cell='onevoid', P=16384, steps=10,
+                                               path='monotone', rho=(0.02, 0.05), seed=0, timed=10, warm=10,
+                                               variants=['fp64', 'fp64_phased', 'bf16_phased']),
 }
 # uneven persistent batch: several ROMs in one captured step, per-point step
 # counts U[5, 40], Newton cap 15 per step; the points are shared out by cost
