@@ -582,140 +582,193 @@ __device__ void band_lu_lds(int nf, int kl, int ldab, int B, const double* __res
 }
 
 // Banded Cholesky L L^T of the free-dof tangent (symmetric; positive
-// definite while the material hardens), no row interchanges: the window
-// holds rows k .. k + kl with their columns k .. row (position c mod W,
-// W = kl + 1) and right-hand side (position W), row r in slot r mod W; the
-// row entering at step k takes the slot of row k, whose entries are in
-// s_mult by then.  Step k: the column of L and y_k; then the update of the
-// lower triangle of the rows below (thread (g, p): column k + 1 + p of every
-// fourth row at or below it; p = kl the right-hand side), while the column
-// goes out and row k + kl + 1 comes in through the staging blocks.  Back
-// substitution with L^T as in the LU form.  Returns false (u untouched) at a
-// pivot that is not positive.
-__device__ bool band_chol_lds(int nf, int kl, int ldab, int B, const double* __restrict__ band,
+// definite while the material hardens), no row interchanges, blocked by
+// panels of CH_NB columns.  The window holds rows k .. k + kl + CH_NB - 1
+// with their columns from k up to the row (position c mod W, W = kl + CH_NB)
+// and right-hand side (position W), row r in slot r mod W.  Panel k .. ke-1:
+// one wave factors its columns (pivot, column of L, forward substitution of
+// the right-hand side, update of the panel's later columns), with no
+// workgroup barrier; then all threads apply the rank-CH_NB update to the
+// rows and columns below the panel (a lane per column, all lanes of a wave
+// on the same row, so the row's panel entries are broadcast and its column
+// entries come from registers); the panel's columns of L go out and the next
+// CH_NB rows come in through the staging blocks.  Back substitution with L^T
+// as in the LU form.  Returns false (u untouched) at a pivot that is not
+// positive.
+constexpr int CH_NB = 8;
+constexpr int CH_STAGE = 32;  // staging block, a multiple of CH_NB
+
+size_t chol_lds_bytes(int kl) {
+  const size_t W = kl + CH_NB, RW = W + 1, RB = kl + 2;
+  return 8 * (W * RW + 2 * (size_t)CH_STAGE * RB) + 64;
+}
+
+__device__ bool band_chol_lds(int nf, int kl, int ldab, const double* __restrict__ band,
                               const double* __restrict__ rhs_in, double* __restrict__ ubuf, double* __restrict__ x,
                               double* lds) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nt = blockDim.x;
-  const int W = kl + 1, S = kl + 1, RW = W + 1;
-  double* win = lds;                       // [S][RW]
-  double* sin = win + (size_t)S * RW;      // [B][RW] rows about to enter (columns r - kl .. r, rhs)
-  double* sout = sin + (size_t)B * RW;     // [B][RW] columns of L that left (L(k + j, k), j = 0 .. kl; y_k)
-  double* s_mult = sout + (size_t)B * RW;  // [kl + 1]
-  int* s_off = (int*)(s_mult + kl + 1);    // [kl + 1] slot offsets of the rows below
-  __shared__ double s_y, s_sd;
+  const int W = kl + CH_NB, S = W, RW = W + 1, RB = kl + 2;
+  double* win = lds;                                  // [S][RW]
+  double* sin = win + (size_t)S * RW;                 // [CH_STAGE][RB] rows about to enter: columns r - kl .. r, rhs
+  double* sout = sin + (size_t)CH_STAGE * RB;         // [CH_STAGE][RB] columns of L that left: L(j + t, j), t = 0 .. kl; y_j
+  __shared__ int s_fail;
   for (int t = tid; t < S * RW; t += nt) win[t] = 0.0;
+  if (tid == 0) s_fail = 0;
   __syncthreads();
-  for (int t = tid; t < (kl + 1) * RW; t += nt) {
-    const int r = t / RW, j = t % RW;
+  for (int t = tid; t < W * (kl + 2); t += nt) {  // rows 0 .. W - 1
+    const int r = t / (kl + 2), j = t % (kl + 2);
     if (r >= nf) continue;
     double* row = win + (size_t)(r % S) * RW;
-    if (j == W) {
+    if (j == kl + 1) {
       row[W] = rhs_in[r];
     } else {
       const int c = r - kl + j;
       if (c >= 0) row[c % W] = band[(size_t)r * ldab + j];
     }
   }
-  // k mod W (= k mod S) and k mod B kept as counters: no division in the loop
-  int kw = 0, kb = 0;
-  const int g = tid / W, p = tid - g * W;
-  for (int k = 0; k < nf; ++k) {
+  for (int k = 0; k < nf; k += CH_NB) {
+    const int ke = min(k + CH_NB, nf), kb = k % CH_STAGE;
     if (kb == 0) {
-      for (int t = tid; t < B * RW && k > 0; t += nt) {
-        const int r = k - B + t / RW, j = t % RW;
-        if (j == W)
-          x[r] = sout[t];
+      // the columns of the last block out; the rows entering during this block in
+      for (int t = tid; t < CH_STAGE * RB && k > 0; t += nt) {
+        const int j = k - CH_STAGE + t / RB, q = t % RB;
+        if (q == kl + 1)
+          x[j] = sout[t];
         else
-          ubuf[(size_t)r * W + j] = sout[t];
+          ubuf[(size_t)j * (kl + 1) + q] = sout[t];
       }
-      for (int t = tid; t < B * RW; t += nt) {
-        const int r = k + kl + 1 + t / RW, j = t % RW;
-        if (r < nf) sin[t] = (j == W) ? rhs_in[r] : band[(size_t)r * ldab + j];
+      for (int t = tid; t < CH_STAGE * RB; t += nt) {
+        const int r = k + W + t / RB, q = t % RB;
+        if (r < nf) sin[t] = (q == kl + 1) ? rhs_in[r] : band[(size_t)r * ldab + q];
       }
-      __syncthreads();
-    }
-    const int last = min(nf - 1, k + kl), nr = last - k;
-    const int koff = kw * RW;  // slot of row k (slots and positions share the modulus W = S)
-    const double d = win[koff + kw];
-    if (!(d > 0.0)) return false;  // every thread reads the same pivot
-    const double sd = sqrt(d);
-    const double isd = 1.0 / sd;
-    for (int a = tid; a < nr; a += nt) {
-      int sl = kw + 1 + a;
-      sl = (sl >= S) ? sl - S : sl;
-      const int o = sl * RW;
-      s_off[a] = o;
-      s_mult[a] = win[o + kw] * isd;
-    }
-    if (tid == 0) {
-      s_sd = sd;
-      s_y = win[koff + W] * isd;
     }
     __syncthreads();
-    {
-      // thread (g, p): column k + 1 + p (p = kl: the right-hand side) of the
-      // rows a = g, g + 4, ... at or below it, four rows in flight
-      if (g < 4) {
-        const bool rhs = p == kl;
-        int pos = kw + 1 + p;
-        pos = rhs ? W : (pos >= W ? pos - W : pos);
-        const double lp = rhs ? s_y : (p < nr ? s_mult[p] : 0.0);
-        for (int a0 = g; a0 < nr; a0 += 4 * LDS_UNROLL) {
-          int o[LDS_UNROLL];
-          double m[LDS_UNROLL], v[LDS_UNROLL];
-#pragma unroll
-          for (int w = 0; w < LDS_UNROLL; ++w) {
-            const int a = a0 + 4 * w;
-            const bool on = a < nr && (rhs || a >= p);
-            o[w] = on ? s_off[a] + pos : -1;
-            m[w] = on ? s_mult[a] : 0.0;
+    if (wave == 0) {
+      for (int j = k; j < ke; ++j) {
+        const int sj = (j % S) * RW, pj = j % W, last = min(nf - 1, j + kl);
+        const double d = win[sj + pj];
+        if (!(d > 0.0)) {
+          if (lane == 0) s_fail = 1;
+          break;
+        }
+        const double sd = sqrt(d), isd = 1.0 / sd, yj = win[sj + W] * isd;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+          win[sj + pj] = sd;
+          win[sj + W] = yj;
+        }
+        for (int i = j + 1 + lane; i <= last; i += 64) {  // column j of L, forward substitution
+          const int si = (i % S) * RW;
+          const double l = win[si + pj] * isd;
+          win[si + pj] = l;
+          win[si + W] = fma(-l, yj, win[si + W]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int i = j + 1 + lane; i <= last; i += 64) {  // the panel's later columns c <= i
+          const int si = (i % S) * RW;
+          const double l = win[si + pj];
+          // column c at position (= slot, S = W) pj + 1 + (c - j - 1), wrapped once
+          int pc = pj + 1;
+          for (int c = j + 1; c < ke && c <= i; ++c) {
+            pc = (pc >= W) ? pc - W : pc;
+            win[si + pc] = fma(-l, win[pc * RW + pj], win[si + pc]);
+            ++pc;
           }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();
+    if (s_fail) return false;
+    {
+      // rank-CH_NB update: column c = ke + p, rows i = ke + g, ke + g + 4, ... with i >= c
+      const int iend = min(nf - 1, k + kl + CH_NB - 1), ncols = iend - ke + 1;
+      const int g = tid / W, p = tid - g * W;
+      if (g < 4 && p < ncols) {
+        // positions of the panel's columns (= slots, S = W), of column c and of row ke + g
+        const int pk = k % W;
+        int pp[CH_NB];
 #pragma unroll
-          for (int w = 0; w < LDS_UNROLL; ++w) v[w] = (o[w] >= 0) ? win[o[w]] : 0.0;
+        for (int t = 0; t < CH_NB; ++t) pp[t] = (pk + t >= W) ? pk + t - W : pk + t;
+        const int c = ke + p;
+        int pc = pp[0] + (ke - k) + p;
+        while (pc >= W) pc -= W;
+        double lc[CH_NB];
 #pragma unroll
-          for (int w = 0; w < LDS_UNROLL; ++w)
-            if (o[w] >= 0) win[o[w]] = fma(-m[w], lp, v[w]);
+        for (int t = 0; t < CH_NB; ++t) {
+          const int j = k + t;
+          lc[t] = (j < ke && c <= j + kl) ? win[pc * RW + pp[t]] : 0.0;
+        }
+        int sl = pp[0] + (ke - k) + g;  // slot of row i = ke + g, advanced by 4
+        while (sl >= W) sl -= W;
+        for (int i = ke + g; i <= iend; i += 4) {
+          if (i >= c) {
+            const int si = sl * RW;
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < CH_NB; ++t) {
+              const int j = k + t;
+              const double li = (j < ke && i <= j + kl) ? win[si + pp[t]] : 0.0;
+              acc = fma(li, lc[t], acc);
+            }
+            win[si + pc] -= acc;
+          }
+          sl += 4;
+          sl = (sl >= W) ? sl - W : sl;
         }
       }
+      // the right-hand side of the rows below the panel was updated column by column in the panel
     }
-    for (int j = tid; j < RW; j += nt)
-      sout[(size_t)kb * RW + j] = (j == 0) ? s_sd : (j == W ? s_y : (j <= nr ? s_mult[j - 1] : 0.0));
-    const int rn = k + kl + 1;
-    if (rn < nf) {
-      double* row = win + koff;  // row k + kl + 1 takes the slot of row k
-      const double* src = sin + (size_t)kb * RW;
-      for (int j = tid; j < RW; j += nt) {
-        int q = kw + 1 + j;  // column k + 1 + j
-        q = (q >= W) ? q - W : q;
-        row[j == W ? W : q] = src[j];
-      }
+    // the panel's columns of L and y out; rows ke + kl + CH_NB - ... : the next rows in
+    for (int t = tid; t < (ke - k) * RB; t += nt) {
+      const int j = k + t / RB, q = t % RB;
+      sout[(size_t)(kb + t / RB) * RB + q] =
+          (q == kl + 1) ? win[(j % S) * RW + W] : ((j + q < nf) ? win[((j + q) % S) * RW + j % W] : 0.0);
     }
     __syncthreads();
-    kw = (kw + 1 == W) ? 0 : kw + 1;
-    kb = (kb + 1 == B) ? 0 : kb + 1;
+    for (int t = tid; t < (ke - k) * RB; t += nt) {
+      const int r = k + W + t / RB, q = t % RB;
+      if (r >= nf) continue;
+      double* row = win + (size_t)(r % S) * RW;
+      const double v = sin[(size_t)(kb + t / RB) * RB + q];
+      if (q == kl + 1) {
+        row[W] = v;
+      } else {
+        row[(r - kl + q) % W] = v;
+      }
+      if (q == 0)
+        for (int z = r + 1; z < r + CH_NB; ++z) row[z % W] = 0.0;  // positions of columns beyond the row
+    }
+    __syncthreads();
   }
   {
-    const int k0 = ((nf - 1) / B) * B, rows = nf - k0;
-    for (int t = tid; t < rows * RW; t += nt) {
-      const int r = k0 + t / RW, j = t % RW;
-      if (j == W)
-        x[r] = sout[t];
+    const int k0 = ((nf - 1) / CH_STAGE) * CH_STAGE, rows = nf - k0;
+    for (int t = tid; t < rows * RB; t += nt) {
+      const int j = k0 + t / RB, q = t % RB;
+      if (q == kl + 1)
+        x[j] = sout[t];
       else
-        ubuf[(size_t)r * W + j] = sout[t];
+        ubuf[(size_t)j * (kl + 1) + q] = sout[t];
     }
   }
   __syncthreads();
   // L^T x = y: x_k = (y_k - sum_j L(k + j, k) x_{k + j}) / L(k, k)
+  const int Wl = kl + 1;
   double r0 = 0.0, r1 = 0.0;  // x[k + 1 + lane + 64 j]
-  double* yb = win + (size_t)S * W;
-  for (int kb = nf - 1; kb >= 0; kb -= S) {
-    const int k0 = max(0, kb - S + 1), rows = kb - k0 + 1;
-    for (int t = tid; t < rows * W; t += nt) win[t] = ubuf[(size_t)k0 * W + t];
+  const int SB = (S * RW - 64) / (Wl + 1);  // rows of L^T per staged block
+  double* yb = win + (size_t)SB * Wl;
+  for (int kb = nf - 1; kb >= 0; kb -= SB) {
+    const int k0 = max(0, kb - SB + 1), rows = kb - k0 + 1;
+    for (int t = tid; t < rows * Wl; t += nt) win[t] = ubuf[(size_t)k0 * Wl + t];
     for (int t = tid; t < rows; t += nt) yb[t] = x[k0 + t];
     __syncthreads();
     if (wave == 0) {
       for (int k = kb; k >= k0; --k) {
-        const double* Lc = win + (size_t)(k - k0) * W;
+        const double* Lc = win + (size_t)(k - k0) * Wl;
         const int jm = min(kl, nf - 1 - k);
         double sacc = 0.0;
         if (lane + 1 <= jm) sacc = Lc[lane + 1] * r0;
@@ -737,13 +790,16 @@ __device__ bool band_chol_lds(int nf, int kl, int ldab, int B, const double* __r
   return true;
 }
 
+// LDS of the solve: the Cholesky form's or the LU form's, whichever is larger
+size_t solve_lds_bytes(int kl, int B) { return std::max(band_lds_bytes(kl, B), chol_lds_bytes(kl)); }
+
 __global__ __launch_bounds__(LDS_THREADS_MAX) void k_band_solve_lds(
     int nf, int kl, int ldab, int B, const double* __restrict__ band, const double* __restrict__ rhs_in,
     double* __restrict__ ubuf, double* __restrict__ x, int dofs, const int* __restrict__ dofmap,
     const int* __restrict__ fixed, int nfixed, const double* __restrict__ dud, double* __restrict__ u,
     int* __restrict__ info) {
   extern __shared__ double lds[];
-  if (band_chol_lds(nf, kl, ldab, B, band, rhs_in, ubuf, x, lds)) {
+  if (band_chol_lds(nf, kl, ldab, band, rhs_in, ubuf, x, lds)) {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int d = tid; d < dofs; d += nt) {
       const int r = dofmap[d];
@@ -850,7 +906,7 @@ int rom_fe2_create(int32_t nodes, int32_t elements, const double* X_host, const 
     al((void**)&h->ubuf, 8L * nfree * (2 * kl + 1));
     al((void**)&h->xbuf, 8L * nfree);
     if (ok && hipFuncSetAttribute((const void*)k_band_solve_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)band_lds_bytes(kl, h->stage)) != hipSuccess)
+                                  (int)solve_lds_bytes(kl, h->stage)) != hipSuccess)
       ok = false;
   }
   al((void**)&h->conn, 32L * elements);
@@ -932,7 +988,7 @@ int rom_fe2_solve(rom_fe2_handle h, const double* Abar_dev, const double* res_de
   k_assemble<<<nblk(h->dofs), 256, 0, s>>>(h->dofs, h->kl, h->ldab, h->node_ptr, h->node_ent, h->conn, h->dofmap,
                                            h->dNdX, h->wJ, Abar_dev, res_dev, dud_dev, h->band, h->rhs);
   if (h->stage > 0)
-    k_band_solve_lds<<<1, (4 * (2 * h->kl + 2) + 63) / 64 * 64, band_lds_bytes(h->kl, h->stage), s>>>(
+    k_band_solve_lds<<<1, (4 * (2 * h->kl + 2) + 63) / 64 * 64, solve_lds_bytes(h->kl, h->stage), s>>>(
         h->nfree, h->kl, h->ldab, h->stage, h->band, h->rhs, h->ubuf, h->xbuf, h->dofs, h->dofmap, h->fixed,
         h->nfixed, dud_dev, u_dev, info_dev);
   else
