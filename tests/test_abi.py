@@ -87,3 +87,33 @@ def test_rom_load_two_phase_artifacts():
     bad[88:96] = np.array([-1.0]).tobytes()  # E of the second phase
     assert _load_code(bad) == L.ROM_EFORMAT
     assert _load_code(good[:-8]) == L.ROM_EFORMAT  # phases truncated
+
+
+def test_offline_and_two_scale_argument_checks():
+    """Argument validation of the two-scale and offline entry points happens
+    on the host, before any device memory is touched."""
+    import ctypes
+    lib = L.lib()
+    X = np.zeros((4, 2))
+    conn = np.array([[0, 1, 2, 3, 0, 1, 2, 3]], dtype=np.int32)
+    top = np.array([[3, 2, 2]], dtype=np.int32)
+    h = ctypes.c_void_p()
+
+    def create(conn_, fixed_, top_=top):
+        return lib.rom_fe2_create(4, conn_.shape[0], X.ctypes.data, conn_.ctypes.data, fixed_.size,
+                                  fixed_.ctypes.data, top_.shape[0], top_.ctypes.data, 2.0, 0, ctypes.byref(h))
+    bad_conn = conn.copy()
+    bad_conn[0, 5] = 9                                   # node index out of range
+    assert create(bad_conn, np.array([0, 1], dtype=np.int32)) == L.ROM_EINVAL
+    assert create(conn, np.array([0, 0], dtype=np.int32)) == L.ROM_EINVAL       # a dof fixed twice
+    assert create(conn, np.arange(8, dtype=np.int32)) == L.ROM_EINVAL           # no free dof
+    assert create(conn, np.array([0, 9], dtype=np.int32)) == L.ROM_EINVAL       # dof out of range
+    assert create(conn, np.array([0], dtype=np.int32), np.array([[3, 2, 7]], dtype=np.int32)) == L.ROM_EINVAL
+    b = ctypes.c_size_t()
+    assert lib.rom_pod_workspace(10, 4, 5, ctypes.byref(b)) == L.ROM_EINVAL     # more modes than snapshots
+    assert lib.rom_pod_workspace(10, 4, 2, ctypes.byref(b)) == L.ROM_OK and b.value > 0
+    assert lib.rom_ecm_workspace(5, 100, 2000, ctypes.byref(b)) == L.ROM_EINVAL  # point budget above 1024
+    assert lib.rom_ecm_workspace(5, 100, 50, ctypes.byref(b)) == L.ROM_OK and b.value > 0
+    dummy = ctypes.c_void_p(1)
+    # neither or both weights given
+    assert lib.rom_pod(10, 4, dummy, None, None, None, None, 2, dummy, dummy, dummy, 1 << 30, None) == L.ROM_EINVAL
