@@ -69,10 +69,10 @@ UNEVEN = {'uneven_mixed_P32768': dict(
     steps=(5, 40), rho=(0.01, 0.04), seed=0, max_iter=15, tune_points=1024)}
 DEFAULT = 'onevoid_n40_m400_P4096_cyclic20'
 VARIANTS = WORKLOADS[DEFAULT]['variants']
-# warm-start training: 40 epochs of minibatch Adam, cosine-decayed from 4e-3
-# (measured on the n = 40 workload: 3.29 Newton evaluations per point-step
-# against 3.51 after 12 epochs at 2e-3; training is set-up, not timed)
-WS_EPOCHS = 80
+# warm-start training: 160 epochs of minibatch Adam, cosine-decayed from 4e-3
+# (measured on the n = 40 workload: 3.20 Newton evaluations per point-step,
+# 3.24 after 80 epochs, 3.29 after 40; training is set-up, not timed)
+WS_EPOCHS = 160
 PBAR_TOL = 1e-5  # reduced-precision forms: largest admitted |Pbar - Pbar_FP64| / max |Pbar_FP64|
 SUBSTEPS = 4  # load-step cutting depth of the fused forms: a failed step is retried in up to 1/16 strides
 
