@@ -226,8 +226,8 @@ int rom_shape_sensitivity(rom_handle h, int32_t batch, const double* Fbar_dev, c
  * backward (FP32) and Adam kernels.  With opts.warm_start = ROM_WARM_MLP,
  * rom_step starts Newton from r_committed + dr and falls back to the plain
  * guess when ||f|| has not dropped tenfold after two Newton updates
- * (status ROM_ST_FALLBACK when it then converges).  Plain Newton is the judge
- * of the prediction: the converged state does not depend on the guess.
+ * (status ROM_ST_FALLBACK when it then converges).  Plain Newton decides the
+ * result: the converged state does not depend on the guess.
  *
  * Parameter layout (FP32, host): W1 [n_in][width], b1 [width], W2 [width][width],
  * b2, W3 [width][width], b3, W4 [width][n_out], b4 [n_out].

@@ -1,6 +1,6 @@
 """Warm-start network kernels against the FP64 oracle network, the feature
 kernel against the oracle's statistics, and what the trained network gains
-over plain Newton (with plain Newton as the judge)."""
+over plain Newton (plain Newton deciding the converged state)."""
 import numpy as np
 import pytest
 import torch

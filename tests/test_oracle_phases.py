@@ -1,4 +1,4 @@
-"""Two-phase cells (the survey's multi-phase RVE; here a one-void cell whose
+"""Two-phase cells (multi-phase RVEs; here a one-void cell whose
 void is lined with a stiff elastic coating) in the oracle, pinned by what
 fixes them independently: the material routine with per-point constants
 equals point-by-point calls with scalars (the tangent to rounding); a second phase with the matrix's
