@@ -248,6 +248,8 @@ def offline_rates():
     R, nx, ny = ECM_SIZE
     pts, w = workloads.grid_points(nx, ny)
     J = workloads.cos_integrands(4, pts, R)
+    ecm(J[:16, :512], w[:512], 1e-4, 64)  # warm-up
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     idx, wq, hist, rank, code = ecm(J, w, 1e-4, 1024)
     torch.cuda.synchronize()

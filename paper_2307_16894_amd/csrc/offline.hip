@@ -230,6 +230,15 @@ __global__ void k_ecm_scale(int R, int nq, const double* __restrict__ J, const d
   Jh[t] = J[(long)i * nq + q] * sqrt(w[q]);
 }
 
+// Jt (column-major nq x R: the transpose of the scaled J) = J diag(sqrt(w)),
+// which has the layout of J itself
+__global__ void k_ecm_scale_t(int R, int nq, const double* __restrict__ J, const double* __restrict__ w,
+                              double* __restrict__ Jt) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= (long)R * nq) return;
+  Jt[t] = J[t] * sqrt(w[t % nq]);
+}
+
 // Zr[i][q] = V^T(i, q) / sqrt(w_q) for i < r (V^T column-major, ldv = R);
 // cn[q] = |Z_q|
 __global__ void k_ecm_z(int R, int r, int nq, const double* __restrict__ V, const double* __restrict__ w,
@@ -244,6 +253,30 @@ __global__ void k_ecm_z(int R, int r, int nq, const double* __restrict__ V, cons
     s = fma(z, z, s);
   }
   cn[q] = sqrt(s);
+}
+
+// R (column-major R x R, upper) from the QR factorisation left in Jt
+// (column-major nq x R)
+__global__ void k_copy_r(int R, int nq, const double* __restrict__ Jt, double* __restrict__ Rm) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= (long)R * R) return;
+  const int i = (int)(t % R), j = (int)(t / R);
+  Rm[t] = (i <= j) ? Jt[i + (long)j * nq] : 0.0;
+}
+
+// Zr[i][q] = Vt[i][q] / sqrt(w_q) (Vt row-major r x nq); cn[q] = |Z_q|
+__global__ void k_ecm_z_rows(int r, int nq, const double* __restrict__ Vt, const double* __restrict__ w,
+                             double* __restrict__ Zr, double* __restrict__ cn) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const double is = 1.0 / sqrt(w[q]);
+  double sacc = 0.0;
+  for (int i = 0; i < r; ++i) {
+    const double z = Vt[(long)i * nq + q] * is;
+    Zr[(long)i * nq + q] = z;
+    sacc = fma(z, z, sacc);
+  }
+  cn[q] = sqrt(sacc);
 }
 
 // b[i] = sum_q Zr[i][q] w[q]: a workgroup per i, fixed-order tree
@@ -640,7 +673,7 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
 
 
 struct EcmWork {
-  double *Jh, *Sv, *V, *E, *Zr, *cn, *b, *res, *bv, *ZS, *G, *Lm, *Gp, *Lp, *hv, *w, *bn;
+  double *Jh, *Sv, *V, *E, *tau, *Rm, *U, *Zr, *cn, *b, *res, *bv, *ZS, *G, *Lm, *Gp, *Lp, *hv, *w, *bn;
   int *bi, *S, *sel, *info;
   EcmState* st;
 };
@@ -660,6 +693,9 @@ size_t ecm_layout(long R, long nq, long mmax, EcmWork* w, char* base) {
   e.Sv = (double*)take(8 * (size_t)mn);
   e.V = (double*)take(8 * (size_t)mn * nq);
   e.E = (double*)take(8 * (size_t)mn);
+  e.tau = (double*)take(8 * (size_t)mn);
+  e.Rm = (double*)take(8 * (size_t)mn * mn);
+  e.U = (double*)take(8 * (size_t)mn * mn);
   e.Zr = (double*)take(8 * (size_t)mn * nq);
   e.cn = (double*)take(8 * (size_t)nq);
   e.b = (double*)take(8 * (size_t)mn);
@@ -790,16 +826,36 @@ int rom_ecm(int32_t R, int32_t nq, const double* J_dev, const double* w_dev, dou
   EcmWork e;
   ecm_layout(R, nq, m_max, &e, (char*)work_dev);
   const int mn = std::min(R, nq), nblocks = (nq + ECM_SCORE_BLOCK - 1) / ECM_SCORE_BLOCK;
-  // Jh = J diag(sqrt(w)), its singular values and right singular vectors
-  k_ecm_scale<<<nblk((long)R * nq), 256, 0, stream>>>(R, nq, J_dev, w_dev, e.Jh);
+  // singular values and right singular vectors of Jh = J diag(sqrt(w)).
+  // With no more integrands than points (the usual case) the tall transpose
+  // is reduced first: Jh^T = Q Rm (Householder QR), Rm = U_R S V_R^T, so
+  // that Jh = V_R S (Q U_R)^T and the right singular vectors are the columns
+  // of Q U_R; only the R x R factor goes through the SVD.
+  const bool tall = R <= nq;
+  if (tall)
+    k_ecm_scale_t<<<nblk((long)R * nq), 256, 0, stream>>>(R, nq, J_dev, w_dev, e.Jh);
+  else
+    k_ecm_scale<<<nblk((long)R * nq), 256, 0, stream>>>(R, nq, J_dev, w_dev, e.Jh);
   if (hipGetLastError() != hipSuccess) return ROM_EHIP;
   rocblas_handle rb;
   if (rocblas_create_handle(&rb) != rocblas_status_success) return ROM_EHIP;
   int rc = ROM_OK;
-  if (rocblas_set_stream(rb, stream) != rocblas_status_success ||
-      rocsolver_dgesvd(rb, rocblas_svect_none, rocblas_svect_singular, R, nq, e.Jh, R, e.Sv, nullptr, 1, e.V, mn,
-                       e.E, rocblas_outofplace, e.info) != rocblas_status_success)
+  if (rocblas_set_stream(rb, stream) != rocblas_status_success) rc = ROM_EHIP;
+  if (rc == ROM_OK && tall) {
+    if (rocsolver_dgeqrf(rb, nq, R, e.Jh, nq, e.tau) != rocblas_status_success) rc = ROM_EHIP;
+    if (rc == ROM_OK) {
+      k_copy_r<<<nblk((long)R * R), 256, 0, stream>>>(R, nq, e.Jh, e.Rm);
+      if (hipGetLastError() != hipSuccess ||
+          rocsolver_dorgqr(rb, nq, R, R, e.Jh, nq, e.tau) != rocblas_status_success ||
+          rocsolver_dgesdd(rb, rocblas_svect_singular, rocblas_svect_none, R, R, e.Rm, R, e.Sv, e.U, R, nullptr, 1,
+                           e.info) != rocblas_status_success)
+        rc = ROM_EHIP;
+    }
+  } else if (rc == ROM_OK &&
+             rocsolver_dgesvd(rb, rocblas_svect_none, rocblas_svect_singular, R, nq, e.Jh, R, e.Sv, nullptr, 1, e.V,
+                              mn, e.E, rocblas_outofplace, e.info) != rocblas_status_success) {
     rc = ROM_EHIP;
+  }
   std::vector<double> sv(mn);
   int info = 0;
   if (rc == ROM_OK && (hipMemcpyAsync(sv.data(), e.Sv, 8L * mn, hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -814,7 +870,14 @@ int rom_ecm(int32_t R, int32_t nq, const double* J_dev, const double* w_dev, dou
   if (rank_out) *rank_out = r;
   if (r < 1) return ROM_EINVAL;
   // Z, column norms, b = Z w, |b|; empty selection, res = b
-  k_ecm_z<<<nblk(nq), 256, 0, stream>>>(mn, r, nq, e.V, w_dev, e.Zr, e.cn);
+  if (tall) {
+    // V^T (row-major r x nq) = U_R(:, :r)^T Q^T: one MFMA pass over Q
+    dim3 grid((nq + 63) / 64, (r + 63) / 64, 1);
+    k_gemm_f64<false><<<grid, 256, 0, stream>>>(r, nq, R, e.U, R, e.Jh, nq, e.V, nq, (R + 15) / 16 * 16, 0);
+    k_ecm_z_rows<<<nblk(nq), 256, 0, stream>>>(r, nq, e.V, w_dev, e.Zr, e.cn);
+  } else {
+    k_ecm_z<<<nblk(nq), 256, 0, stream>>>(mn, r, nq, e.V, w_dev, e.Zr, e.cn);
+  }
   k_ecm_b<<<r, 256, 0, stream>>>(nq, e.Zr, w_dev, e.b);
   k_norm<<<1, 256, 0, stream>>>(r, e.b, e.bn);
   EcmState st0{0, 0, -1, 0, 0.0, 0.0};
