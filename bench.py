@@ -387,6 +387,8 @@ def main(argv=None):
     ap.add_argument('--no-fe2', action='store_true', help='skip the two-scale example')
     ap.add_argument('--calibrate-copy', type=int, default=0, metavar='MIB',
                     help='first copy MIB MiB device to device (a known-size reference for HBM counters)')
+    ap.add_argument('--offline-only', action='store_true',
+                    help='time only the offline stage (POD and cubature) at the n = 40 sizes and print it')
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(json.dumps(dict(error="this benchmark runs on one GPU: the macro points of a batch are "
@@ -405,6 +407,9 @@ def main(argv=None):
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {a.calibrate_copy} MiB done")
         del src, dst
+    if a.offline_only:
+        print(json.dumps(dict(offline=offline_rates())), flush=True)
+        return 0
     if a.workload in UNEVEN:
         return uneven_main(a, log)
     w = WORKLOADS[a.workload]

@@ -382,29 +382,85 @@ __device__ bool block_cholesky(int p, const double* __restrict__ A, double* __re
   return true;
 }
 
-// L L^T x = h (L lower row-major, ld) by one wave; x and h in LDS.  Lane 0
-// writes each x_i; the wave reads it in the next step (LDS operations of a
-// wave complete in order; the wave barrier only stops the compiler moving
-// code across it).  Called by wave 0 alone: no workgroup barrier inside.
-__device__ void chol_solve_wave(int p, const double* __restrict__ Lm, int ld, const double* h, double* x) {
-  const int lane = threadIdx.x & 63;
-  for (int i = 0; i < p; ++i) {
-    double s = 0.0;
-    for (int t = lane; t < i; t += 64) s = fma(Lm[(long)i * ld + t], x[t], s);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) x[i] = (h[i] - s) / Lm[(long)i * ld + i];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Triangular solves with the Cholesky factor (L lower, row-major, ld), in
+// place on a vector in LDS, by the whole workgroup (every thread calls them).
+// Blocks of TRI_NB unknowns: the diagonal block is staged in LDS (T, row
+// stride TRI_LD against bank conflicts) and solved by wave 0 with one unknown
+// per lane, column by column (the solved value is read from its lane, so no
+// reduction sits on the sequential chain); the rest of the vector is then
+// updated by all threads.
+constexpr int TRI_NB = 64, TRI_LD = 65;
+
+__device__ inline double readlane_d(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ void tri_stage(int kb, int nb, const double* __restrict__ Lm, int ld, double* T) {
+  for (int t = threadIdx.x; t < nb * TRI_NB; t += blockDim.x) {
+    const int a = t / TRI_NB, c = t % TRI_NB;
+    if (c <= a) T[a * TRI_LD + c] = Lm[(long)(kb + a) * ld + kb + c];
   }
-  for (int i = p - 1; i >= 0; --i) {
-    double s = 0.0;
-    for (int t = i + 1 + lane; t < p; t += 64) s = fma(Lm[(long)t * ld + i], x[t], s);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) x[i] = (x[i] - s) / Lm[(long)i * ld + i];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __syncthreads();
+}
+
+// y <- L^-1 y (L is p x p)
+__device__ void lower_solve(int p, const double* __restrict__ Lm, int ld, double* y, double* T) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  for (int kb = 0; kb < p; kb += TRI_NB) {
+    const int nb = min(TRI_NB, p - kb);
+    tri_stage(kb, nb, Lm, ld, T);
+    if (tid < 64) {
+      double v = (lane < nb) ? y[kb + lane] : 0.0;
+      const double inv = (lane < nb) ? 1.0 / T[lane * TRI_LD + lane] : 0.0;
+      for (int l = 0; l < nb; ++l) {
+        const double xl = readlane_d(v, l) * readlane_d(inv, l);
+        if (lane == l)
+          v = xl;
+        else if (lane > l && lane < nb)
+          v = fma(-T[lane * TRI_LD + l], xl, v);
+      }
+      if (lane < nb) y[kb + lane] = v;
+    }
+    __syncthreads();
+    for (int j = kb + nb + tid; j < p; j += nt) {
+      const double* row = Lm + (long)j * ld + kb;
+      double acc = y[j];
+      for (int t = 0; t < nb; ++t) acc = fma(-row[t], y[kb + t], acc);
+      y[j] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// y <- L^-T y
+__device__ void upper_solve(int p, const double* __restrict__ Lm, int ld, double* y, double* T) {
+  if (p <= 0) return;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  for (int kb = ((p - 1) / TRI_NB) * TRI_NB; kb >= 0; kb -= TRI_NB) {
+    const int nb = min(TRI_NB, p - kb);
+    tri_stage(kb, nb, Lm, ld, T);
+    if (tid < 64) {
+      double v = (lane < nb) ? y[kb + lane] : 0.0;
+      const double inv = (lane < nb) ? 1.0 / T[lane * TRI_LD + lane] : 0.0;
+      for (int l = nb - 1; l >= 0; --l) {
+        const double xl = readlane_d(v, l) * readlane_d(inv, l);
+        if (lane == l)
+          v = xl;
+        else if (lane < l)
+          v = fma(-T[l * TRI_LD + lane], xl, v);
+      }
+      if (lane < nb) y[kb + lane] = v;
+    }
+    __syncthreads();
+    for (int j = tid; j < kb; j += nt) {
+      double acc = y[j];
+      for (int t = 0; t < nb; ++t) acc = fma(-Lm[(long)(kb + t) * ld + j], y[kb + t], acc);
+      y[j] = acc;
+    }
+    __syncthreads();
   }
 }
 
@@ -426,7 +482,8 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
   double* z = x + mmax + 1;     // [mmax + 1] least-squares solution on the passive set
   double* hp = z + mmax + 1;    // [mmax + 1] h gathered on the passive set
   double* red = hp + mmax + 1;  // [32]
-  int* pas = (int*)(red + 32);  // [mmax + 1] passive flags
+  double* T = red + 32;         // [TRI_NB * TRI_LD] diagonal block of a triangular solve
+  int* pas = (int*)(T + TRI_NB * TRI_LD);  // [mmax + 1] passive flags
   int* pidx = pas + mmax + 1;   // [mmax + 1] passive indices in order
   __shared__ int s_q, s_k, s_flag, s_np, s_t;
   __shared__ double s_v, s_alpha;
@@ -478,18 +535,10 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
   }
   __syncthreads();
   // new row of the Cholesky factor: L[k][0..k) = L^-1 g, L[k][k] = sqrt(G_kk - |y|^2)
-  for (int j = tid; j <= k; j += nt) hp[j] = G[(long)k * mmax + j];
+  for (int j = tid; j <= k; j += nt) hp[j] = z[j] = G[(long)k * mmax + j];
   __syncthreads();
+  lower_solve(k, Lm, mmax, z, T);
   if (wave == 0) {
-    for (int j = 0; j < k; ++j) {
-      double acc = 0.0;
-      for (int t = lane; t < j; t += 64) acc = fma(Lm[(long)j * mmax + t], z[t], acc);
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-      if (lane == 0) z[j] = (hp[j] - acc) / Lm[(long)j * mmax + j];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
     double acc = 0.0;
     for (int t = lane; t < k; t += 64) acc = fma(z[t], z[t], acc);
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
@@ -509,10 +558,10 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
   }
   const int p = k + 1;
   // unconstrained least squares on all p points
-  for (int j = tid; j < p; j += nt) hp[j] = hv[j];
+  for (int j = tid; j < p; j += nt) x[j] = hv[j];
   __syncthreads();
-  if (wave == 0) chol_solve_wave(p, Lm, mmax, hp, x);
-  __syncthreads();
+  lower_solve(p, Lm, mmax, x, T);
+  upper_solve(p, Lm, mmax, x, T);
   if (tid == 0) {
     int bad = 0;
     for (int j = 0; j < p; ++j) bad |= !(x[j] > 0.0);
@@ -562,15 +611,15 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
           const int a = (int)(t / np), c = (int)(t % np);
           Gp[(long)a * mmax + c] = G[(long)pidx[a] * mmax + pidx[c]];
         }
-        for (int a = tid; a < np; a += nt) hp[a] = hv[pidx[a]];
+        for (int a = tid; a < np; a += nt) z[a] = hv[pidx[a]];
         __syncthreads();
         const bool ok = block_cholesky(np, Gp, Lp, mmax, red);
         if (!ok) {
           if (tid == 0) st->status = 2;
           return;
         }
-        if (wave == 0) chol_solve_wave(np, Lp, mmax, hp, z);
-        __syncthreads();
+        lower_solve(np, Lp, mmax, z, T);
+        upper_solve(np, Lp, mmax, z, T);
         if (tid == 0) {
           // step from x towards z as far as feasibility allows; the point
           // that limits the step (and any other at zero) leaves the passive set
@@ -889,7 +938,10 @@ int rom_ecm(int32_t R, int32_t nq, const double* J_dev, const double* w_dev, dou
   if (hipMemcpyAsync(&bn, e.bn, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess)
     return ROM_EHIP;
-  const size_t sh_update = 8 * (3 * (size_t)(m_max + 1) + 32) + 8 * (size_t)(m_max + 1);
+  const size_t sh_update = 8 * (3 * (size_t)(m_max + 1) + 32 + TRI_NB * TRI_LD) + 8 * (size_t)(m_max + 1);
+  if (hipFuncSetAttribute((const void*)k_ecm_update, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_update) !=
+      hipSuccess)
+    return ROM_EHIP;
   int hl = 0;
   if (hist_host && hist_cap > 0) hist_host[hl++] = 1.0;
   EcmState st = st0;
