@@ -310,8 +310,17 @@ __global__ __launch_bounds__(ECM_SCORE_BLOCK) void k_ecm_score(int r, int nq, co
   const int q = blockIdx.x * ECM_SCORE_BLOCK + threadIdx.x;
   double v = -INFINITY;
   if (q < nq && !sel_flag[q]) {
+    // in order of i, 16 loads of Z in flight per lane
     double s = 0.0;
-    for (int i = 0; i < r; ++i) s = fma(Zr[(long)i * nq + q], sres[i], s);
+    int i = 0;
+    for (; i + 16 <= r; i += 16) {
+      double zz[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) zz[u] = Zr[(long)(i + u) * nq + q];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s = fma(zz[u], sres[i + u], s);
+    }
+    for (; i < r; ++i) s = fma(Zr[(long)i * nq + q], sres[i], s);
     v = s / cn[q];
   }
   rv[threadIdx.x] = v;
@@ -428,6 +437,7 @@ __device__ void lower_solve(int p, const double* __restrict__ Lm, int ld, double
     for (int j = kb + nb + tid; j < p; j += nt) {
       const double* row = Lm + (long)j * ld + kb;
       double acc = y[j];
+#pragma unroll 8
       for (int t = 0; t < nb; ++t) acc = fma(-row[t], y[kb + t], acc);
       y[j] = acc;
     }
@@ -457,6 +467,7 @@ __device__ void upper_solve(int p, const double* __restrict__ Lm, int ld, double
     __syncthreads();
     for (int j = tid; j < kb; j += nt) {
       double acc = y[j];
+#pragma unroll 8
       for (int t = 0; t < nb; ++t) acc = fma(-Lm[(long)(kb + t) * ld + j], y[kb + t], acc);
       y[j] = acc;
     }
@@ -517,19 +528,33 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
     sel_flag[q] = 1;
   }
   __syncthreads();
-  // G[k][j] = G[j][k] = ZS[j] . ZS[k] (j <= k), h[k] = ZS[k] . b: a wave per product
-  for (int j = wave; j <= k + 1; j += nw) {
+  // G[k][j] = G[j][k] = ZS[j] . ZS[k] (j <= k), h[k] = ZS[k] . b: a wave per
+  // product, four products interleaved so that their loads and reductions overlap
+  for (int j0 = 4 * wave; j0 <= k + 1; j0 += 4 * nw) {
     const double* zk = ZS + (long)k * r;
-    const double* o = (j <= k) ? ZS + (long)j * r : b;
-    double acc = 0.0;
-    for (int i = lane; i < r; i += 64) acc = fma(o[i], zk[i], acc);
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    const double* o[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) o[u] = (j0 + u <= k) ? ZS + (long)(j0 + u) * r : b;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = lane; i < r; i += 64) {
+      const double zi = zk[i];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j0 + u <= k + 1) acc[u] = fma(o[u][i], zi, acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      for (int off = 32; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off);
     if (lane == 0) {
-      if (j <= k) {
-        G[(long)k * mmax + j] = acc;
-        G[(long)j * mmax + k] = acc;
-      } else {
-        hv[k] = acc;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + u;
+        if (j <= k) {
+          G[(long)k * mmax + j] = acc[u];
+          G[(long)j * mmax + k] = acc[u];
+        } else if (j == k + 1) {
+          hv[k] = acc[u];
+        }
       }
     }
   }
@@ -702,11 +727,20 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
   }
   for (int j = tid; j < pnew; j += nt) w[j] = x[j];
   __syncthreads();
-  // res = b - sum_j w_j ZS[j] (in order of j), |res|
+  // res = b - sum_j w_j ZS[j] (in order of j), |res|; the weights are read
+  // from LDS and the rows of ZS in batches of 8 loads in flight
   double part = 0.0;
   for (int i = tid; i < r; i += nt) {
     double v = b[i];
-    for (int j = 0; j < pnew; ++j) v = fma(-w[j], ZS[(long)j * r + i], v);
+    int j = 0;
+    for (; j + 8 <= pnew; j += 8) {
+      double zz[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) zz[u] = ZS[(long)(j + u) * r + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v = fma(-x[j + u], zz[u], v);
+    }
+    for (; j < pnew; ++j) v = fma(-x[j], ZS[(long)j * r + i], v);
     res[i] = v;
     part = fma(v, v, part);
   }

@@ -7,7 +7,8 @@ six points; random integrands (the oracle test's), run to exactness with
 every point available; random integrands for which the unconstrained least
 squares gives a non-positive weight, so that the non-negative least squares
 and the removal of points are taken (one and two times); smooth integrands
-at the size of the n = 40 ROM's cubature (441 integrands, 23814 points)."""
+at the size of the n = 40 ROM's cubature (441 integrands, 23814 points);
+more integrands than points, at full rank and at rank 10."""
 import numpy as np
 import pytest
 
@@ -79,6 +80,27 @@ def test_ecm_non_negative_branch(gpu, case):
         J = g.normal(size=(60, m.nq)) * g.uniform(0.1, 10, size=(1, m.nq))
     idx, wq, _ = compare(J, m.qw, eps, m.nq)
     assert np.all(wq > 0)
+
+
+def test_ecm_more_integrands_than_points(gpu):
+    """More integrands than points (the wide SVD branch).  At full rank every
+    point is needed; Z is then an orthogonal matrix times diag(1/sqrt(w)) and
+    every score equals sqrt(w_q), equal on this uniform mesh, so the order
+    is decided by rounding: compared is what is unique (all points, the full
+    rule's weights).  At rank 10 the rank cut leaves ten points, compared
+    in order with the oracle."""
+    m = M.mesh_square(2)
+    g = workloads.rng(5)
+    J1 = g.normal(size=(30, m.nq))
+    J2 = g.normal(size=(30, 10)) @ g.normal(size=(10, m.nq))
+    idx, wq, hist, rank, code = gecm(J1, m.qw, 1e-3, m.nq)
+    assert code == L.ROM_OK and rank == m.nq
+    assert sorted(idx) == list(range(m.nq)) and hist[-1] < 1e-12
+    assert np.abs(wq - m.qw[idx]).max() <= 1e-9 * m.qw.max()
+    for eps in (1e-3, 1e-10):
+        idx, wq, hist = compare(J2, m.qw, eps, m.nq)
+        assert len(idx) == 10 and np.all(wq > 0)
+    assert gecm(J2, m.qw, 1e-10, m.nq)[3] == 10
 
 
 def test_ecm_full_size(gpu):
