@@ -480,14 +480,17 @@ __device__ void upper_solve(int p, const double* __restrict__ Lm, int ld, double
 // matrix G = Z_S^T Z_S by one row, solve G w = Z_S^T b; if a weight is not
 // positive, Lawson-Hanson non-negative least squares on (G, h) started from
 // the previous (positive) weights with the new point at zero; drop points of
-// zero weight (refactoring G); res = b - Z_S w.  Every branch that reaches a
-// workgroup barrier is decided from shared values.
+// zero weight (refactoring G); res = b - Z_S w.  yv = L^-1 h is kept from
+// one iteration to the next: appending a point leaves its first k entries
+// unchanged, so only the new one is computed; after points leave it is
+// recomputed from the new factor.  Every branch that reaches a workgroup
+// barrier is decided from shared values.
 __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
     int r, int nq, int mmax, int nblocks, const double* __restrict__ Zr, const double* __restrict__ b,
     const double* __restrict__ best_v, const int* __restrict__ best_i, int* __restrict__ S, double* __restrict__ ZS,
     double* __restrict__ G, double* __restrict__ Lm, double* __restrict__ Gp, double* __restrict__ Lp,
-    double* __restrict__ hv, double* __restrict__ w, double* __restrict__ res, int* __restrict__ sel_flag,
-    EcmState* __restrict__ st) {
+    double* __restrict__ hv, double* __restrict__ yv, double* __restrict__ w, double* __restrict__ res,
+    int* __restrict__ sel_flag, EcmState* __restrict__ st) {
   extern __shared__ double sh[];
   double* x = sh;               // [mmax + 1] current solution
   double* z = x + mmax + 1;     // [mmax + 1] least-squares solution on the passive set
@@ -568,9 +571,17 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
     for (int t = lane; t < k; t += 64) acc = fma(z[t], z[t], acc);
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     const double d2 = hp[k] - acc;
+    // new entry of L^-1 h: (h_k - L[k][0..k) . yv[0..k)) / L[k][k]
+    double ay = 0.0;
+    for (int t = lane; t < k; t += 64) ay = fma(z[t], yv[t], ay);
+    for (int off = 32; off > 0; off >>= 1) ay += __shfl_xor(ay, off);
+    const double lkk = sqrt(fmax(d2, 0.0));
     if (lane == 0) s_flag = (d2 > 1e-14 * hp[k]) ? 0 : 1;
     for (int t = lane; t < k; t += 64) Lm[(long)k * mmax + t] = z[t];
-    if (lane == 0) Lm[(long)k * mmax + k] = sqrt(fmax(d2, 0.0));
+    if (lane == 0) {
+      Lm[(long)k * mmax + k] = lkk;
+      yv[k] = (hv[k] - ay) / lkk;
+    }
   }
   __syncthreads();
   if (s_flag) {  // the new column depends on the selected ones
@@ -583,9 +594,8 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
   }
   const int p = k + 1;
   // unconstrained least squares on all p points
-  for (int j = tid; j < p; j += nt) x[j] = hv[j];
+  for (int j = tid; j < p; j += nt) x[j] = yv[j];
   __syncthreads();
-  lower_solve(p, Lm, mmax, x, T);
   upper_solve(p, Lm, mmax, x, T);
   if (tid == 0) {
     int bad = 0;
@@ -724,6 +734,10 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
       if (tid == 0) st->status = 2;
       return;
     }
+    for (int a = tid; a < pnew; a += nt) z[a] = hv[a];
+    __syncthreads();
+    lower_solve(pnew, Lm, mmax, z, T);
+    for (int a = tid; a < pnew; a += nt) yv[a] = z[a];
   }
   for (int j = tid; j < pnew; j += nt) w[j] = x[j];
   __syncthreads();
@@ -756,7 +770,7 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
 
 
 struct EcmWork {
-  double *Jh, *Sv, *V, *E, *tau, *Rm, *U, *Zr, *cn, *b, *res, *bv, *ZS, *G, *Lm, *Gp, *Lp, *hv, *w, *bn;
+  double *Jh, *Sv, *V, *E, *tau, *Rm, *U, *Zr, *cn, *b, *res, *bv, *ZS, *G, *Lm, *Gp, *Lp, *hv, *yv, *w, *bn;
   int *bi, *S, *sel, *info;
   EcmState* st;
 };
@@ -790,6 +804,7 @@ size_t ecm_layout(long R, long nq, long mmax, EcmWork* w, char* base) {
   e.Gp = (double*)take(8 * (size_t)mmax * mmax);
   e.Lp = (double*)take(8 * (size_t)mmax * mmax);
   e.hv = (double*)take(8 * (size_t)mmax);
+  e.yv = (double*)take(8 * (size_t)mmax);
   e.w = (double*)take(8 * (size_t)mmax);
   e.bn = (double*)take(8);
   e.bi = (int*)take(4 * (size_t)nblocks);
@@ -985,7 +1000,8 @@ int rom_ecm(int32_t R, int32_t nq, const double* J_dev, const double* w_dev, dou
     ++n_iter;
     k_ecm_score<<<nblocks, ECM_SCORE_BLOCK, 8 * (size_t)r, stream>>>(r, nq, e.Zr, e.cn, e.res, e.sel, e.bv, e.bi);
     k_ecm_update<<<1, ECM_THREADS, sh_update, stream>>>(r, nq, m_max, nblocks, e.Zr, e.b, e.bv, e.bi, e.S, e.ZS, e.G,
-                                                        e.Lm, e.Gp, e.Lp, e.hv, e.w, e.res, e.sel, e.st);
+                                                        e.Lm, e.Gp, e.Lp, e.hv, e.yv, e.w, e.res, e.sel,
+                                                        e.st);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&st, e.st, sizeof(st), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
