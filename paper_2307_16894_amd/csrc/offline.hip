@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_ecm_b(int nq, const double* __restrict_
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
   if (threadIdx.x == 0) b[i] = red[0];
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(ECM_SCORE_BLOCK) void k_ecm_score(int r, int nq, co
   ri[threadIdx.x] = q;
   __syncthreads();
   for (int h = ECM_SCORE_BLOCK / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) {
+    if ((int)threadIdx.x < h) {
       const double ov = rv[threadIdx.x + h];
       const int oi = ri[threadIdx.x + h];
       if (ov > rv[threadIdx.x] || (ov == rv[threadIdx.x] && oi < ri[threadIdx.x])) {
@@ -367,7 +367,7 @@ __device__ double block_sum(double v, double* red) {
 
 // Cholesky of the p x p matrix A (row-major, ld) into L (lower, row-major,
 // ld), in one workgroup; returns false if a pivot is not positive
-__device__ bool block_cholesky(int p, const double* __restrict__ A, double* __restrict__ Lm, int ld, double* red) {
+__device__ bool block_cholesky(int p, const double* __restrict__ A, double* __restrict__ Lm, int ld) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (long t = tid; t < (long)p * p; t += nt) {
     const int i = (int)(t / p), j = (int)(t % p);
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
         }
         for (int a = tid; a < np; a += nt) z[a] = hv[pidx[a]];
         __syncthreads();
-        const bool ok = block_cholesky(np, Gp, Lp, mmax, red);
+        const bool ok = block_cholesky(np, Gp, Lp, mmax);
         if (!ok) {
           if (tid == 0) st->status = 2;
           return;
@@ -730,7 +730,7 @@ __global__ __launch_bounds__(ECM_THREADS) void k_ecm_update(
       hv[a] = hp[a];
     }
     __syncthreads();
-    if (!block_cholesky(pnew, G, Lm, mmax, red)) {
+    if (!block_cholesky(pnew, G, Lm, mmax)) {
       if (tid == 0) st->status = 2;
       return;
     }
@@ -824,7 +824,7 @@ __global__ __launch_bounds__(256) void k_norm(int n, const double* __restrict__ 
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = sqrt(red[0]);
