@@ -8,7 +8,8 @@ every point available; random integrands for which the unconstrained least
 squares gives a non-positive weight, so that the non-negative least squares
 and the removal of points are taken (one and two times); smooth integrands
 at the size of the n = 40 ROM's cubature (441 integrands, 23814 points);
-more integrands than points, at full rank and at rank 10."""
+more integrands than points, at full rank and at rank 10; a point budget
+that ends the greedy before the tolerance."""
 import numpy as np
 import pytest
 
@@ -80,6 +81,16 @@ def test_ecm_non_negative_branch(gpu, case):
         J = g.normal(size=(60, m.nq)) * g.uniform(0.1, 10, size=(1, m.nq))
     idx, wq, _ = compare(J, m.qw, eps, m.nq)
     assert np.all(wq > 0)
+
+
+@pytest.mark.parametrize("m_max", [1, 5, 12])
+def test_ecm_point_budget(gpu, m_max):
+    """The point budget ends the greedy before the tolerance (1e-12) is met:
+    the same m_max points, weights and history as the oracle."""
+    m = M.mesh_square(3)
+    J = workloads.rng(1).normal(size=(30, m.nq))
+    idx, wq, hist = compare(J, m.qw, 1e-12, m_max)
+    assert len(idx) == m_max and hist[-1] > 1e-3
 
 
 def test_ecm_more_integrands_than_points(gpu):
