@@ -166,3 +166,92 @@ def test_load_step_cutting_equals_plain_steps_along_its_targets():
     # a path through run_path with cutting commits the same state
     via = rom.run_path(mu, [Fb], max_iter=15, max_substeps=D)[-1]
     assert np.array_equal(via['r'], cut['r'])
+
+
+def _graded_square(v):
+    """Void-free unit cell on the vertex lines v (both directions), two T6 per
+    quad: elements of unequal size, so a misplaced quadrature weight shows."""
+    v = np.asarray(v, dtype=np.float64)
+    s = np.empty(2 * v.size - 1)
+    s[0::2] = v
+    s[1::2] = 0.5 * (v[1:] + v[:-1])
+    P = np.zeros((s.size, s.size, 2))
+    P[..., 0] = s[:, None]
+    P[..., 1] = s[None, :]
+    merger = M._NodeMerger()
+    elems = []
+    M._add_quad_grid(merger, elems, P, -1)
+    return M.Mesh(np.array(merger.pts), np.array(elems), np.array(merger.void), [])
+
+
+def _square_problem(v):
+    m = _graded_square(v)
+    sp = fem.PeriodicSpace(m)
+    pr = fem.Problem(m, sp, np.tile(np.eye(2), (m.nq, 1, 1)), MAT)
+    return m, sp, pr
+
+
+def _nodal_dofs(m, sp, fx, fy):
+    """DOF vector of the periodic field (fx, fy) sampled at the master nodes."""
+    w = np.zeros(sp.ndof)
+    for a in sp.free_nodes:
+        k = sp.node_dof[a]
+        x, y = m.X[a]
+        w[2 * k], w[2 * k + 1] = fx(x, y), fy(x, y)
+    return w
+
+
+def test_v_gram_exact_on_piecewise_linear_periodic_fields():
+    """eq. Vdotproduct on the parent cell: (u, v)_V = int u.v + grad u : grad v.
+    The triangle wave t(s) = 1 - |2 s - 1| is periodic, vanishes at the fixed
+    corner and is linear on every element of a grid with a line at s = 1/2,
+    so the degree-2 rule integrates both terms exactly:
+    int t^2 = 1/3, int t'^2 = 4, int t(x) t(y) = 1/4, grad t(x) . grad t(y) = 0."""
+    m, sp, pr = _square_problem([0.0, 0.12, 0.3, 0.5, 0.55, 0.8, 1.0])
+    assert np.ptp(m.qw) > 0.1 * m.qw.max()  # unequal elements
+    MV = pod.v_gram(pr)
+    t = lambda s: 1.0 - abs(2.0 * s - 1.0)  # noqa: E731
+    z = lambda x, y: 0.0  # noqa: E731
+    ux = _nodal_dofs(m, sp, lambda x, y: t(x), z)      # (t(x), 0)
+    uy = _nodal_dofs(m, sp, z, lambda x, y: t(y))      # (0, t(y))
+    vx = _nodal_dofs(m, sp, lambda x, y: t(y), z)      # (t(y), 0): d/dy of the first component
+    cx = _nodal_dofs(m, sp, z, lambda x, y: t(x))      # (0, t(x))
+    s = _nodal_dofs(m, sp, lambda x, y: t(x) + t(y), z)
+    ip = lambda a, b: float(a @ (MV @ b))  # noqa: E731
+    assert abs(ip(ux, ux) - (1 / 3 + 4)) < 1e-12
+    assert abs(ip(uy, uy) - (1 / 3 + 4)) < 1e-12
+    assert abs(ip(vx, vx) - (1 / 3 + 4)) < 1e-12
+    assert abs(ip(ux, vx) - 0.25) < 1e-12       # mass term only: the gradients are orthogonal
+    assert abs(ip(ux, cx)) < 1e-12              # different components never couple
+    assert abs(ip(s, s) - (2 * (1 / 3 + 4) + 2 * 0.25)) < 1e-12
+    # symmetric, and positive on every non-zero field
+    assert abs(MV - MV.T).max() < 1e-14
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        v = rng.standard_normal(sp.ndof)
+        assert ip(v, v) > 0
+
+
+def test_integrand_matrix_integrals_of_affine_fields():
+    """eq. integralsbasis: J[(i, l), q] = grad phi_i(X_q) : B_l(X_q), and
+    J w_hat = int grad phi_i : B_l.  With affine fields
+    G_i[a] = al + be x + ga y and B_l[a] = de + ep x + ze y the integrand is
+    quadratic, integrated exactly by the degree-2 rule over the unit square:
+    int = al de + (al ep + be de + al ze + ga de) / 2 + (be ep + ga ze) / 3 + (be ze + ga ep) / 4,
+    summed over the four components a.  Random coefficients make a transposed
+    contraction or a (l, i) row order fail."""
+    m = _graded_square([0.0, 0.2, 0.45, 0.5, 0.9, 1.0])
+    rng = np.random.default_rng(11)
+    n, L = 3, 4
+    cg = rng.standard_normal((3, n, 4))   # al, be, ga of G_i[a]
+    cb = rng.standard_normal((3, L, 4))   # de, ep, ze of B_l[a]
+    x, y = m.qX[:, 0], m.qX[:, 1]
+    G = (cg[0][None] + cg[1][None] * x[:, None, None] + cg[2][None] * y[:, None, None]).transpose(0, 2, 1)
+    B = (cb[0][None] + cb[1][None] * x[:, None, None] + cb[2][None] * y[:, None, None]).transpose(0, 2, 1)
+    J = ecm.integrand_matrix(G, B, n, L)
+    assert J.shape == (n * L, m.nq)
+    al, be, ga = cg[:, :, None, :]
+    de, ep, ze = cb[:, None, :, :]
+    exact = (al * de + (al * ep + be * de + al * ze + ga * de) / 2 + (be * ep + ga * ze) / 3
+             + (be * ze + ga * ep) / 4).sum(axis=-1).reshape(n * L)
+    assert np.abs(J @ m.qw - exact).max() < 1e-12
