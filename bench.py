@@ -75,6 +75,7 @@ VARIANTS = WORKLOADS[DEFAULT]['variants']
 WS_EPOCHS = 160
 PBAR_TOL = 1e-5  # reduced-precision forms: largest admitted |Pbar - Pbar_FP64| / max |Pbar_FP64|
 SUBSTEPS = 4  # load-step cutting depth of the fused forms: a failed step is retried in up to 1/16 strides
+MAX_ITER = 15  # Newton evaluations per attempt (the library's default cap)
 
 
 def inputs(w, seed=None, P=None):
@@ -133,7 +134,8 @@ def gpu_run(w, steps, warmup, opts, rom_file):
                 k = 0
             rb.step(Fb[k], opts)
             if record:  # device-side copies, no synchronisation
-                rec.append((rb.iters.clone(), (rb.status == 0).sum() + (rb.status == 3).sum(), rb.Pbar.clone()))
+                rec.append((rb.iters.clone(), (rb.status == 0).sum() + (rb.status == 3).sum(), rb.Pbar.clone(),
+                            rb.substeps().clone()))
             k += 1
         return rec
 
@@ -151,13 +153,26 @@ def gpu_run(w, steps, warmup, opts, rom_file):
     t1 = time.perf_counter()
     kern_ms, launches = L.rom_timing_read(rb.h)
     L.rom_timing_enable(rb.h, False)
-    evals = int(sum(int(it.sum()) for it, _, _ in rec))
-    conv = int(sum(int(c) for _, c, _ in rec))
-    max_it = int(max(int(it.max()) for it, _, _ in rec))
-    Pbars = torch.stack([p for _, _, p in rec]).cpu().numpy()
+    evals = int(sum(int(r[0].sum()) for r in rec))
+    conv = int(sum(int(r[1]) for r in rec))
+    max_it = int(max(int(r[0].max()) for r in rec))
+    Pbars = torch.stack([r[2] for r in rec]).cpu().numpy()
+    subs = torch.stack([r[3] for r in rec]).cpu().numpy()
     rb.close()
     return dict(elapsed=t1 - t0, evals=evals, converged=conv, max_iter=max_it, kern_ms=kern_ms,
-                launches=launches, n=n, m=m, Pbar=Pbars)
+                launches=launches, n=n, m=m, Pbar=Pbars, sub=subs, K=K)
+
+
+def same_path(g, ref):
+    """[steps][P] mask of the point-steps whose loading path so far equals the
+    reference run's: every (sub-)step of the point since the start of its path
+    ended at the same fractions of its load steps (the sub-step records agree),
+    so both runs solved the same sequence of discrete problems."""
+    agree = g['sub'] == ref['sub']
+    same = np.empty_like(agree)
+    for k in range(agree.shape[0]):
+        same[k] = agree[k] if k % g['K'] == 0 else (same[k - 1] & agree[k])
+    return same
 
 
 def sensitivity_rate(w, rom_file, at_step=5, reps=5):
@@ -263,37 +278,62 @@ def offline_rates():
                          final_residual=float(hist[-1]), seconds=t_ecm, code=code))
 
 
-def _oracle_worker(args):
-    rom_file, mu, path = args
+_ORACLE = {}
+
+
+def _oracle_init(rom_file):
+    """Pool worker set-up, outside the timed map: one BLAS thread, the ROM loaded once."""
     from threadpoolctl import threadpool_limits
-    with threadpool_limits(1):
-        from oracle.rom import ROM
-        rom = ROM(rom_file)
-        out = rom.run_path(mu, path)
+    from oracle.rom import ROM
+    _ORACLE['limit'] = threadpool_limits(1)
+    _ORACLE['rom'] = ROM(rom_file)
+
+
+def _oracle_worker(args):
+    mu, path = args
+    out = _ORACLE['rom'].run_path(mu, path, max_iter=MAX_ITER, max_substeps=SUBSTEPS)
     return sum(o['iters'] for o in out), sum(o['status'] == 0 for o in out)
 
 
+def cpu_model():
+    try:
+        with open('/proc/cpuinfo') as fh:
+            for line in fh:
+                if line.startswith('model name'):
+                    return line.split(':', 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, rom_file, budget_s=20.0):
-    """The FP64 oracle on a bounded sample of the workload, one process per core."""
+    """The FP64 oracle on a bounded sample of the workload, one process per
+    core, with the GPU forms' options (Newton cap MAX_ITER, load-step cutting
+    depth SUBSTEPS); the rate counts converged point-steps only."""
     import multiprocessing as mp
     mu, paths = inputs(w)
     cores = min(len(os.sched_getaffinity(0)), 16)
+    _oracle_init(rom_file)
     t0 = time.perf_counter()
-    _oracle_worker((rom_file, mu[0], paths[0]))
+    _oracle_worker((mu[0], paths[0]))
     t1 = time.perf_counter() - t0
     S = int(np.clip(budget_s * cores / max(t1, 1e-3), cores, w['P']))
     S = max(cores, (S // cores) * cores)
-    jobs = [(rom_file, mu[i], paths[i]) for i in range(S)]
-    with mp.get_context('fork').Pool(cores) as pool:
+    jobs = [(mu[i], paths[i]) for i in range(S)]
+    with mp.get_context('fork').Pool(cores, initializer=_oracle_init, initargs=(rom_file,)) as pool:
+        pool.map(_oracle_worker, jobs[:cores], chunksize=1)  # every worker has loaded the ROM
         t0 = time.perf_counter()
         res = pool.map(_oracle_worker, jobs, chunksize=1)
         wall = time.perf_counter() - t0
     steps = S * w['steps']
-    return dict(value=steps / wall, unit='macro-point load steps/s', cores=cores, kind='oracle',
-                sample=f"first {S} of {w['P']} macro points, all {w['steps']} load steps "
-                       f"({steps} point-steps, {wall:.1f}s wall)",
+    conv = int(sum(r[1] for r in res))
+    return dict(value=conv / wall, unit='macro-point load steps/s', cores=cores, kind='oracle',
+                cpu=cpu_model(),
+                sample=f"first {S} of {w['P']} macro points, all {w['steps']} load steps ({steps} point-steps, "
+                       f"{conv} converged, {wall:.1f}s wall); Newton cap {MAX_ITER}, cutting depth {SUBSTEPS} "
+                       f"as on the GPU; the rate counts converged point-steps",
                 mean_iters=float(sum(r[0] for r in res) / steps),
-                converged_fraction=float(sum(r[1] for r in res) / steps))
+                converged_fraction=float(conv / steps))
 
 
 def uneven_main(a, log):
@@ -453,18 +493,32 @@ def main(argv=None):
                  converged_fraction=g['converged'] / (P * a.steps),
                  kernel_ms_per_step=g['kern_ms'] / a.steps)
         if ref is not None and v != 'fp64':
-            # first load step (same virgin state on both sides: the precision and
-            # warm-start effect alone) and all steps (also path effects: a point that
-            # is cut into sub-steps on one side follows another loading path)
+            # Deviation from plain FP64 over every timed point-step that followed the
+            # same loading path (the same converged sub-steps since the start of the
+            # path), where both runs solve the same discrete problems and differ by
+            # precision and Newton's stopping point alone.  A point whose steps are
+            # cut differently (the warm start or a reduced-precision tangent changes
+            # whether the full step converges) integrates the plastic flow over other
+            # increments from then on: those point-steps are counted, and their
+            # deviation is reported apart.
             scale = np.abs(ref['Pbar']).max()
-            d['max_rel_diff_Pbar_vs_fp64_step1'] = float(np.abs(g['Pbar'][0] - ref['Pbar'][0]).max() / scale)
-            d['max_rel_diff_Pbar_vs_fp64'] = float(np.abs(g['Pbar'] - ref['Pbar']).max() / scale)
-            d['median_rel_diff_Pbar_vs_fp64'] = float(np.median(np.abs(g['Pbar'] - ref['Pbar']).max(axis=-1)) / scale)
+            dev = np.abs(g['Pbar'] - ref['Pbar']).max(axis=-1) / scale  # [steps][P]
+            same = same_path(g, ref)
+            d['max_rel_diff_Pbar_vs_fp64_step1'] = float(dev[0].max())
+            d['max_rel_diff_Pbar_vs_fp64_same_path'] = float(dev[same].max()) if same.any() else None
+            d['median_rel_diff_Pbar_vs_fp64_same_path'] = float(np.median(dev[same])) if same.any() else None
+            d['other_path_fraction'] = float(1.0 - same.mean())
+            d['other_path_points'] = int((~same).any(axis=0).sum())
+            d['max_rel_diff_Pbar_vs_fp64_other_path'] = float(dev[~same].max()) if (~same).any() else None
+            d['max_rel_diff_Pbar_vs_fp64'] = float(dev.max())
         out_var[v] = d
     # head: the learned + reduced-precision form (else the reduced-precision
     # form) of highest throughput whose Pbar stays within PBAR_TOL of plain FP64
+    # on every timed point-step of the same loading path, all of them converged
     def admitted(v):
-        return v in out_var and out_var[v].get('max_rel_diff_Pbar_vs_fp64_step1', 1.0) <= PBAR_TOL
+        d = out_var.get(v, {})
+        dm = d.get('max_rel_diff_Pbar_vs_fp64_same_path')
+        return dm is not None and dm <= PBAR_TOL and d['converged_fraction'] == 1.0
     reduced = [v for v in out_var if v.split('_')[0] in ('fp32', 'bf16')]
     cands = [v for v in reduced if '_mlp' in v and admitted(v)] or [v for v in reduced if admitted(v)]
     head = max(cands, key=lambda v: out_var[v]['value']) if cands else ('fp64' if 'fp64' in out_var else variants[0])
@@ -490,11 +544,13 @@ def main(argv=None):
         dtype={'bf16': 'bf16+f64', 'fp32': 'f32+f64'}.get(head.split('_')[0], 'f64'),
         data="synthetic",
         config=dict(workload=a.workload, rom=w['rom'], n=n, m=m, batch=P, load_steps=w['steps'], tol=1e-8,
-                    form=head, contraction=head.split('_')[0], warm_start=head.endswith('_mlp')),
+                    form=head, contraction=head.split('_')[0], warm_start='_mlp' in head),
         plain_fp64=dict(out_var[plain_best], form=plain_best) if plain_best else None,
         speedup_vs_plain_fp64=(out_var[head]['value'] / out_var[plain_best]['value']) if plain_best else None,
-        head_rule=f"learned+reduced-precision form (else reduced-precision form) of highest throughput with "
-                  f"max |Pbar - Pbar_fp64| / max |Pbar_fp64| <= {PBAR_TOL:g} on the first load step",
+        head_rule=f"learned+reduced-precision form (else reduced-precision form) of highest throughput with every "
+                  f"timed point-step converged and max |Pbar - Pbar_fp64| / max |Pbar_fp64| <= {PBAR_TOL:g} over all "
+                  f"timed point-steps that followed the plain FP64 loading path (same converged sub-steps); the "
+                  f"fraction on another path is reported per form (other_path_fraction)",
         variants=out_var,
         warm_start=wsinfo,
         roofline=dict(bound="mfma",

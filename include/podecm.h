@@ -149,7 +149,13 @@ int rom_info(rom_handle h, int32_t* n, int32_t* m, int32_t* c, int32_t* n_mu);
 #define ROM_FIELD_MU_OK       7  /* i32 [batch] 1 if the shape parameters were accepted */
 #define ROM_FIELD_FBAR_COMMITTED 8  /* f64 [batch][4] Fbar of the last committed step (I initially) */
 #define ROM_FIELD_R_GUESS     9  /* f64 [batch][n] initial guess used by the last rom_step */
-#define ROM_NFIELDS           10
+#define ROM_FIELD_SUBSTEPS   10  /* u32 [batch] converged (sub-)steps of the last rom_step: bit k is set when one
+                                    ended at t = (k+1)/32 of the segment from the committed Fbar to Fbar (exact
+                                    up to cutting depth 5; deeper, the 1/32 cell holding the end).  A plain step
+                                    that converges sets bit 31 alone; 0 when none converged.  Two runs followed
+                                    the same loading path through a step when their records agree (written by
+                                    every form; untouched for inactive points) */
+#define ROM_NFIELDS           11
 int rom_state_bytes(rom_handle h, int32_t batch, size_t* bytes);
 int rom_state_offsets(rom_handle h, int32_t batch, size_t* offsets /* [ROM_NFIELDS] */);
 
@@ -226,8 +232,14 @@ int rom_shape_sensitivity(rom_handle h, int32_t batch, const double* Fbar_dev, c
  * backward (FP32) and Adam kernels.  With opts.warm_start = ROM_WARM_MLP,
  * rom_step starts Newton from r_committed + dr and falls back to the plain
  * guess when ||f|| has not dropped tenfold after two Newton updates
- * (status ROM_ST_FALLBACK when it then converges).  Plain Newton decides the
- * result: the converged state does not depend on the guess.
+ * (status ROM_ST_FALLBACK when it then converges).  Newton judges the guess:
+ * a point is converged only at ||f||_2 <= tol, so where a step is solved
+ * over the same (sub-)steps as from the plain guess (equal
+ * ROM_FIELD_SUBSTEPS records) the two results differ only within the
+ * tolerance.  With load-step cutting a better guess can let a full step
+ * converge that the plain guess would cut into sub-steps (or the reverse);
+ * the point then integrates its plastic flow over other increments, a
+ * different loading path of its own history.
  *
  * Parameter layout (FP32, host): W1 [n_in][width], b1 [width], W2 [width][width],
  * b2, W3 [width][width], b3, W4 [width][n_out], b4 [n_out].

@@ -31,14 +31,26 @@ def init(dims, seed):
     return params
 
 
-def forward(params, X):
-    """Returns output and the cache (pre-activations, activations)."""
+def bf16(x):
+    """Round to the nearest bfloat16 (8 significand bits, ties to even), via
+    the nearest float32: the top 16 bits of the float32 pattern after adding
+    0x7fff plus the lowest kept bit.  Returned as float64."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(params, X, bf16_operands=False):
+    """Returns output and the cache (pre-activations, activations).  With
+    bf16_operands every product takes its two operands rounded to bfloat16
+    (activations and weights), the sums exact; the biases, the SiLU and the
+    cached activations stay unrounded."""
     a = X
     zs, acts = [], [X]
     L = len(params) // 2
     for l in range(L):
         W, b = params[2 * l], params[2 * l + 1]
-        z = a @ W + b
+        z = (bf16(a) @ bf16(W) if bf16_operands else a @ W) + b
         zs.append(z)
         a = silu(z) if l < L - 1 else z
         acts.append(a)
@@ -50,9 +62,10 @@ def loss(params, X, Y):
     return float(np.mean(np.sum((out - Y) ** 2, axis=1)))
 
 
-def backward(params, X, Y):
-    """Loss and gradients (same order as params)."""
-    out, (zs, acts) = forward(params, X)
+def backward(params, X, Y, bf16_operands=False):
+    """Loss and gradients (same order as params); the forward pass as in
+    forward(), the backward pass unrounded."""
+    out, (zs, acts) = forward(params, X, bf16_operands)
     B = X.shape[0]
     L = len(params) // 2
     grads = [None] * len(params)

@@ -150,19 +150,21 @@ class ROM:
         """One load step with cutting (see the module notes).  Returns the last
         attempt's step dict with 'iters' summed over all attempts, plus the
         start state of that attempt ('r_c', 'hist_c', 'Fbar_c': the committed
-        state after the converged sub-steps) and the converged intermediate
-        targets in order ('targets')."""
+        state after the converged sub-steps), the converged intermediate
+        targets in order ('targets') and the end points t / 2^D of every
+        converged sub-step, the last one included ('ends', as integers t)."""
         full = 2 ** max_substeps
         t, dt = 0, full
         r0, h0, F0 = r_c, hist_c, np.asarray(Fbar_c, dtype=np.float64)
         Fbar = np.asarray(Fbar, dtype=np.float64)
-        total, targets = 0, []
+        total, targets, ends = 0, [], []
         while True:
             target = Fbar if t + dt == full else Fbar_c + ((t + dt) / full) * (Fbar - Fbar_c)
             s = self.step(r0, h0, target, Finv, J, tol, max_iter, fixed)
             total += s['iters']
             if s['status'] == 0:
                 t += dt
+                ends.append(t)
                 if t == full:
                     break
                 r0, h0, F0 = s['r'], s['hist'], target
@@ -172,7 +174,7 @@ class ROM:
                 if dt == 1:
                     break
                 dt //= 2
-        s.update(iters=total, r_c=r0, hist_c=h0, Fbar_c=F0, targets=targets)
+        s.update(iters=total, r_c=r0, hist_c=h0, Fbar_c=F0, targets=targets, ends=ends)
         return s
 
     def virgin(self):

@@ -34,8 +34,8 @@ MODE_STAGED, MODE_FUSED, MODE_PHASED = 0, 1, 2
 
 FIELD_R_COMMITTED, FIELD_R_TRIAL, FIELD_H_COMMITTED, FIELD_H_TRIAL = 0, 1, 2, 3
 FIELD_TRANSFORM, FIELD_PBAR, FIELD_ABAR, FIELD_MU_OK = 4, 5, 6, 7
-FIELD_FBAR_COMMITTED, FIELD_R_GUESS = 8, 9
-NFIELDS = 10
+FIELD_FBAR_COMMITTED, FIELD_R_GUESS, FIELD_SUBSTEPS = 8, 9, 10
+NFIELDS = 11
 
 EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_info', 'rom_state_bytes',
            'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent', 'rom_shape_sensitivity',

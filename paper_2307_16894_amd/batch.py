@@ -7,7 +7,7 @@ the method happens here.
 import torch
 
 from . import (FIELD_ABAR, FIELD_FBAR_COMMITTED, FIELD_H_COMMITTED, FIELD_H_TRIAL, FIELD_MU_OK, FIELD_PBAR, FIELD_R_COMMITTED,
-               FIELD_R_TRIAL, FIELD_TRANSFORM, rom_default_opts, rom_free, rom_homogenized_stress_tangent,
+               FIELD_R_TRIAL, FIELD_SUBSTEPS, FIELD_TRANSFORM, rom_default_opts, rom_free, rom_homogenized_stress_tangent,
                rom_info, rom_load_file, rom_shape_sensitivity, rom_state_bytes, rom_state_init, rom_state_offsets,
                rom_step)
 
@@ -89,3 +89,8 @@ class RomBatch:
 
     def mu_ok(self):
         return self._view(FIELD_MU_OK, (self.P,), torch.int32)
+
+    def substeps(self):
+        """Record of the converged (sub-)steps of the last step, one int32 per
+        point (bit k: a sub-step ended at (k+1)/32 of the load step)."""
+        return self._view(FIELD_SUBSTEPS, (self.P,), torch.int32)

@@ -54,6 +54,14 @@ __host__ __device__ inline J2Params point_params(J2Params mp, J2Params mp2, cons
   return r;
 }
 
+// Bit of the sub-step record (ROM_FIELD_SUBSTEPS) for a converged sub-step
+// ending at t_done / 2^D of the load step: exact on the 1/32 grid up to
+// D = 5, the 1/32 cell holding the end point beyond.
+__host__ __device__ inline unsigned int substep_bit(int t_done, int D) {
+  const int k = (D <= 5) ? (t_done << (5 - D)) - 1 : (t_done - 1) >> (D - 5);
+  return 1u << k;
+}
+
 // Record the start / stop event of a timed launch; no-ops unless enabled.
 int rom_timing_mark(rom_model* h, int stop, hipStream_t s);
 
@@ -64,7 +72,7 @@ int rom_launch_features(const rom_model* h, int P, const double* Fbar, const voi
 
 // Internal state fields (public ones first, same numbering as ROM_FIELD_*).
 enum {
-  F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK, F_FBC, F_RG,
+  F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK, F_FBC, F_RG, F_SUB,
   F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT, F_XF, F_DR, F_MU, F_LIST,
   F_D, F_W, F_K, F_F, F_PIV,
   F_REC, F_PHI, F_PHD, F_LIST2, F_LIST3, F_LIST4, F_HKIN, F_ZK,
@@ -94,6 +102,7 @@ static inline StateLayout rom_state_layout(const rom_model* h, size_t P) {
   sz[F_MUOK] = P * 4;
   sz[F_FBC] = P * 4 * 8;
   sz[F_RG] = P * n * 8;
+  sz[F_SUB] = P * 4;
   sz[F_DONE] = P * 4;
   sz[F_STATUS] = P * 4;
   sz[F_ITERS] = P * 4;

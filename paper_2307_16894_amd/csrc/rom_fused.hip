@@ -77,6 +77,7 @@ int rom_fused_prepare(rom_model* h, int P, const double* Fbar, void* state, cons
   a.it_out = it_out;
   a.res_out = res_out;
   a.rg = field<double>(state, L, F_RG);
+  a.sub = field<unsigned int>(state, L, F_SUB);
   a.fbc = field<double>(state, L, F_FBC);
   a.zk = field<double>(state, L, F_ZK);
   a.active = o.active;

@@ -30,6 +30,7 @@ struct FusedArgs {
   int* counter;      // next list entry to take (device)
   const float* dr;   // warm-start increments [P][n] (NULL: plain guess)
   double* rg;        // initial guess actually used [P][n]
+  unsigned int* sub;  // converged sub-steps of the step, substep_bit() per sub-step [P]
   double* fbc;       // committed Fbar [P][4]
   double* zk;        // K*^-1 C at the returned state [P][n][4]
   // phased form: the first evaluations of attempt 0 as a material launch and a

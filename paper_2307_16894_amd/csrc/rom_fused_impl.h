@@ -847,13 +847,15 @@ __device__ __forceinline__ void write_effective(const FusedArgs& a, int p, const
 // Outputs of a finished load step, and the commit of a converged one (r,
 // history and the Fbar reached).
 __device__ __forceinline__ void finish_point(const FusedArgs& a, int p, const double* sR, const double Fb[4],
-                                             int status, bool fell_back, int iters, double rn, int tid) {
+                                             int status, bool fell_back, int iters, double rn, unsigned int sub,
+                                             int tid) {
   const int n = a.n, m = a.m;
   for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i];
   if (tid == 0) {
     a.st_out[p] = (status == ROM_ST_CONVERGED && fell_back) ? ROM_ST_FALLBACK : status;
     a.it_out[p] = iters;
     a.res_out[p] = rn;
+    a.sub[p] = sub;
   }
   if (a.commit && status == ROM_ST_CONVERGED) {
     if (tid < 4) a.fbc[4 * (size_t)p + tid] = Fb[tid];
@@ -874,6 +876,7 @@ __device__ __forceinline__ void bad_mu_outputs(const FusedArgs& a, int p, int ti
     a.st_out[p] = ROM_ST_BADMU;
     a.it_out[p] = 0;
     a.res_out[p] = __builtin_nan("");
+    a.sub[p] = 0u;
   }
 }
 
@@ -949,6 +952,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
   }
   const int full = 1 << a.max_sub;
   int t_done = 0, stride = full, total = 0;
+  unsigned int sub = 0u;  // end points of the converged sub-steps
   const double* tmu = a.tmu + (size_t)p * 5 * m;
   const double* hc = a.hc + (size_t)p * 6 * m;
   double* ht = a.ht + (size_t)p * 6 * m;
@@ -1008,6 +1012,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
     total += iters;
     if (status == ROM_ST_CONVERGED) {
       t_done += stride;
+      sub |= substep_bit(t_done, a.max_sub);
       if (t_done == full) break;
       // a converged sub-step becomes the committed start of the next attempt
       double* hcw = a.hc + (size_t)p * 6 * m;
@@ -1028,7 +1033,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
     for (int k = 0; k < 4; ++k) Fb[k] = (t_next == full) ? sF1[k] : sF0[k] + frac * (sF1[k] - sF0[k]);
     __syncthreads();
   }
-  finish_point(a, p, sR, Fb, status, fell_back, total, rn, tid);
+  finish_point(a, p, sR, Fb, status, fell_back, total, rn, sub, tid);
 }
 
 // Phased form, contraction launch: one evaluation of each listed point from
@@ -1166,7 +1171,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cs_waves<T,
         write_effective<T>(a, p, sK, sC, sOrd, n, tid);
         const double Fb[4] = {a.Fbar[4 * (size_t)p], a.Fbar[4 * (size_t)p + 1], a.Fbar[4 * (size_t)p + 2],
                               a.Fbar[4 * (size_t)p + 3]};
-        finish_point(a, p, sR, Fb, status, fell_back, it + 1, rn, tid);
+        finish_point(a, p, sR, Fb, status, fell_back, it + 1, rn, status == ROM_ST_CONVERGED ? (1u << 31) : 0u,
+                     tid);
         return;
       }
       next = 0;  // failed attempt: the fused kernel redoes the point with load-step cutting

@@ -191,6 +191,7 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
   a.chand = cnt + 2;
   const int T = rom_fused_tiles(h->n);
   if (rom_timing_mark(h, 0, s) != ROM_OK) return ROM_EHIP;
+  // from here every exit goes through the join and the stop mark below
   k_zero6<<<1, 64, 0, s>>>(cnt);
   {
     FusedArgs b = a;
@@ -198,7 +199,7 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
     b.cout = cnt;
     k_ph_begin<<<(unsigned int)(((long long)P * h->n + 255) / 256), 256, 0, s>>>(b, P);
   }
-  if (hipGetLastError() != hipSuccess) return ROM_EHIP;
+  if (hipGetLastError() != hipSuccess) rc = ROM_EHIP;
   bool forked = false;
   for (int e = 0; e < kph && rc == ROM_OK; ++e) {
     FusedArgs b = a;
@@ -210,16 +211,21 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
     if (rc == ROM_OK) rc = rom_phased_cs(T, b, o.contraction, split, P, s);
     if (rc == ROM_OK && a.ph_early > 0 && e + 1 == a.ph_early) {
       // fork: the early list to the fused kernel on the side stream
-      if (hipEventRecord(h->ev_fork, s) != hipSuccess) return ROM_EHIP;
-      if (hipStreamWaitEvent(h->aux, h->ev_fork, 0) != hipSuccess) return ROM_EHIP;
+      if (hipEventRecord(h->ev_fork, s) != hipSuccess) {
+        rc = ROM_EHIP;
+        break;
+      }
+      if (hipStreamWaitEvent(h->aux, h->ev_fork, 0) != hipSuccess) {
+        rc = ROM_EHIP;
+        break;
+      }
+      forked = true;
       FusedArgs f = a;
       f.resume = 1;
       f.list = early;
       f.nlist = cnt + 4;
       f.counter = cnt + 5;
       rc = rom_fused_launch(T, f, o.contraction, split, PH_EARLY_GRID * h->ncu, P, h->aux);
-      if (hipEventRecord(h->ev_join, h->aux) != hipSuccess) return ROM_EHIP;
-      forked = true;
     }
   }
   if (rc == ROM_OK) {
@@ -231,8 +237,16 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
     const int grid = (o.grid_per_cu > 0 ? o.grid_per_cu : 2) * h->ncu;
     rc = rom_fused_launch(T, f, o.contraction, split, grid, P, s);
   }
-  // join: the step ends when the side stream's points are done too
-  if (forked && hipStreamWaitEvent(s, h->ev_join, 0) != hipSuccess) return ROM_EHIP;
-  if (rom_timing_mark(h, 1, s) != ROM_OK) return ROM_EHIP;
+  // join: the step ends when the side stream's work is done too (also after
+  // a failed launch, so that nothing of this step is left running beside s)
+  if (forked) {
+    const bool joined = hipEventRecord(h->ev_join, h->aux) == hipSuccess &&
+                        hipStreamWaitEvent(s, h->ev_join, 0) == hipSuccess;
+    if (!joined) {
+      (void)hipStreamSynchronize(h->aux);  // the event pair failed: wait on the host instead
+      if (rc == ROM_OK) rc = ROM_EHIP;
+    }
+  }
+  if (rom_timing_mark(h, 1, s) != ROM_OK && rc == ROM_OK) rc = ROM_EHIP;
   return rc;
 }

@@ -549,7 +549,7 @@ __global__ __launch_bounds__(256) void k_finish(int n, int m, int commit, const 
                                                 const double* __restrict__ rt, double* __restrict__ rc,
                                                 const double* __restrict__ ht, double* __restrict__ hc,
                                                 int* __restrict__ st_out, int* __restrict__ it_out,
-                                                double* __restrict__ res_out) {
+                                                double* __restrict__ res_out, unsigned int* __restrict__ sub) {
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int st = status[p];
@@ -557,6 +557,7 @@ __global__ __launch_bounds__(256) void k_finish(int n, int m, int commit, const 
     st_out[p] = st;
     it_out[p] = iters[p];
     res_out[p] = res[p];
+    sub[p] = (st == ROM_ST_CONVERGED) ? (1u << 31) : 0u;  // the plain step: no cutting in this form
   }
   if (!(commit && st == ROM_ST_CONVERGED)) return;
   if (tid < 4) fbc[4 * (size_t)p + tid] = Fbar[4 * (size_t)p + tid];
@@ -671,6 +672,7 @@ int rom_launch_state_init(const rom_model* h, int P, const double* mu, void* sta
   int* count = field<int>(state, L, F_COUNT);
   k_fill_i32<<<(P + 255) / 256, 256, 0, s>>>(muok, P, 1);
   k_fill_i32<<<1, 64, 0, s>>>(count, 16, 0);
+  k_fill_i32<<<(P + 255) / 256, 256, 0, s>>>(field<int>(state, L, F_SUB), P, 0);  // no step made yet
   dim3 g((h->m + 127) / 128, P);
   k_state_init<<<g, 128, 0, s>>>(h->n, h->m, h->c, h->kind, h->n_mu, h->r0, h->void_area, mu, h->w, h->Gd,
                                  field<double>(state, L, F_RC), field<double>(state, L, F_HC),
@@ -714,6 +716,6 @@ int rom_launch_step_staged(rom_model* h, int P, const double* Fbar, void* state,
                                 K, piv, field<double>(state, L, F_PBAR), field<double>(state, L, F_ABAR),
                                 field<double>(state, L, F_ZK));
   k_finish<<<P, 256, 0, s>>>(n, m, o.commit, Fbar, field<double>(state, L, F_FBC), status, iters, res, rt, rc, ht,
-                             hc, st_out, it_out, res_out);
+                             hc, st_out, it_out, res_out, field<unsigned int>(state, L, F_SUB));
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }

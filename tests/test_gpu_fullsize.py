@@ -38,7 +38,7 @@ def run_gpu(opts, K):
         torch.cuda.synchronize()
         out.append(dict(status=st.cpu().numpy().copy(), iters=it.cpu().numpy().copy(),
                         r=rb.r(trial=True).cpu().numpy().copy(), Pbar=rb.Pbar.cpu().numpy().copy(),
-                        Abar=rb.Abar.cpu().numpy().copy()))
+                        Abar=rb.Abar.cpu().numpy().copy(), sub=rb.substeps().cpu().numpy().view(np.uint32).copy()))
     rb.close()
     return out
 
@@ -76,6 +76,8 @@ def test_converged_paths_full_size(gpu, dt, tol_P, tol_A):
         ref = oracle(int(p), K, False, 15, 4)
         for k in range(K):
             assert g[k]['status'][p] == ref[k]['status'] == 0, (p, k)
+            if dt == L.DT_F64:  # the same converged sub-steps (ends t / 16: bit 2t - 1)
+                assert g[k]['sub'][p] == sum(1 << (2 * t - 1) for t in ref[k]['ends']), (p, k)
             if dt == L.DT_F64:
                 assert abs(int(g[k]['iters'][p]) - ref[k]['iters']) <= 2, (p, k)
             assert rel(g[k]['Pbar'][p], ref[k]['Pbar']) < tol_P, (p, k)
@@ -122,7 +124,7 @@ def test_phased_matches_fused_bitwise_full_size(gpu, dt):
 
 
 W4 = WORKLOADS['fourvoid_n100_m1500_P16384_cyclic20']
-SAMPLE4 = [0, 5461, 10922, W4['P'] - 1]
+SAMPLE4 = [0, 5461, 10922, W4['P'] - 1, 1, 2047, 8191, 13000, 4095, 12288]
 
 
 def run_gpu4(opts, K):
@@ -152,7 +154,7 @@ def test_fourvoid_fixed_iteration_parity_full_size(gpu):
     """n = 100 (seven column tiles, the tile split of the waves), 16384 points."""
     K = 3
     g = run_gpu4(L.rom_default_opts(mode=L.MODE_FUSED, fixed_iters=1, max_iter=4), K)
-    for i, p in enumerate(SAMPLE4[:3]):
+    for i, p in enumerate(SAMPLE4):
         ref = oracle4(p, K, True, 4)
         for k in range(K):
             assert g[k]['status'][i] == ref[k]['status'], (p, k)

@@ -47,21 +47,32 @@ def test_param_count(net):
     assert ws.param_count == 155944 == sum(fi * fo + fo for fi, fo in zip(dims[:-1], dims[1:]))
 
 
-def test_fp32_gradients_match_oracle(net):
+@pytest.mark.parametrize("prec,rtol,atol", [(L.DT_F32, 1e-4, 1e-5), (L.DT_BF16, 1e-3, 1e-4)])
+def test_gradients_match_oracle_elementwise(net, prec, rtol, atol):
+    """Every weight and bias gradient against the FP64 oracle, entry by entry:
+    |g - g_ref| <= rtol |g_ref| + atol max |g_ref of the array|.  The BF16
+    forward is compared with the oracle's forward on bfloat16-rounded
+    operands (the backward pass is FP32 on both), so the tolerance covers FP32
+    accumulation and the rare activation whose rounding to bfloat16 goes the
+    other way."""
     ws, dims, X, Y = net
     L.rom_mlp_set_scaling(ws.h, np.zeros(54), np.ones(54), np.zeros(40), np.ones(40))
     p = ws.params()
     Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
     grads = torch.zeros(p.size, dtype=torch.float32, device='cuda')
     loss = torch.zeros(1, dtype=torch.float32, device='cuda')
-    L.rom_mlp_gradients(ws.h, 300, Xd.data_ptr(), Yd.data_ptr(), L.DT_F32, grads.data_ptr(), loss.data_ptr(),
+    L.rom_mlp_gradients(ws.h, 300, Xd.data_ptr(), Yd.data_ptr(), prec, grads.data_ptr(), loss.data_ptr(),
                         torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
-    ref_loss, ref = OM.backward(unflatten(p, dims), X.astype(np.float64), Y.astype(np.float64))
+    ref_loss, ref = OM.backward(unflatten(p, dims), X.astype(np.float64), Y.astype(np.float64),
+                                bf16_operands=(prec == L.DT_BF16))
     got = unflatten(grads.cpu().numpy(), dims)
     assert abs(loss.item() - ref_loss) < 1e-5 * ref_loss
-    for a, b in zip(got, ref):
-        assert np.linalg.norm(a - b) < 1e-4 * max(np.linalg.norm(b), 1e-12)
+    for i, (a, b) in enumerate(zip(got, ref)):
+        err = np.abs(a - b)
+        bound = rtol * np.abs(b) + atol * np.abs(b).max()
+        print(f"array {i}: max err / bound {np.max(err / bound):.3f}")
+        assert (err <= bound).all(), (i, np.argmax(err - bound))
 
 
 def test_bf16_forward_matches_oracle(net):
@@ -98,8 +109,17 @@ def test_adam_step_matches_oracle(net):
     torch.cuda.synchronize()
     got = ws.params()
     ref = flatten(P)
-    moved = np.abs(ref - p0).max()
-    assert np.abs(got - ref).max() < 2e-2 * moved  # Adam normalises steps: compare against the step size
+    # Adam moves every parameter by at most about lr per step, whatever its
+    # gradient; where the gradient is far above FP32 rounding the three steps
+    # agree entry by entry, elsewhere (the direction of a near-zero gradient is
+    # rounding noise) only the bound on the step holds
+    g1 = np.abs(flatten(OM.backward(unflatten(p0, dims), X.astype(np.float64), Y.astype(np.float64))[1]))
+    big = g1 > 1e-2 * g1.max()
+    assert big.mean() > 0.4
+    err = np.abs(got - ref)
+    print(f"Adam: max err {err[big].max():.2e} on {big.mean():.2f} of the entries, {err.max():.2e} overall")
+    assert err[big].max() < 1e-3 * 1e-3
+    assert np.abs(got - p0).max() <= 3 * 1e-3 * (1 + 1e-6)
 
 
 def test_features_match_oracle_statistics(gpu):

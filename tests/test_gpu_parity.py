@@ -170,9 +170,12 @@ def test_load_step_cutting_parity(gpu, form):
         Pb, Ab, rc, fbc = (rb.Pbar.cpu().numpy(), rb.Abar.cpu().numpy(), rb.r().cpu().numpy(),
                            rb.fbar_committed().cpu().numpy())
         hc = rb.history().cpu().numpy()
+        sub = rb.substeps().cpu().numpy().view(np.uint32)
         for p in range(P):
             s = refs[p][k]
             assert st[p] == s['status'] and its[p] == s['iters'], (p, k, st[p], s['status'], its[p], s['iters'])
+            # converged sub-step ends t / 16 on the 1/32 grid: bit 2t - 1
+            assert sub[p] == sum(1 << (2 * t - 1) for t in s['ends']), (p, k, hex(sub[p]), s['ends'])
             assert rel_err(Pb[p], s['Pbar']) < TOL and rel_err(Ab[p], s['Abar'].reshape(-1)) < TOL, (p, k)
             r_c, h_c, F_c = ((s['r'], s['hist'], paths[p, k]) if s['status'] == 0
                              else (s['r_c'], s['hist_c'], s['Fbar_c']))

@@ -118,3 +118,43 @@ def test_phased_form_refuses_graph_capture(gpu):
     torch.cuda.synchronize()
     assert code == L.ROM_EUNSUPPORTED
     rb.close()
+
+
+def test_full_uneven_workload_against_oracle(gpu):
+    """The benchmark's uneven workload at full size: five ROMs (n = 20 ... 120,
+    m = 120 ... 2000), 32768 points, per-point step counts U[5, 40], Newton
+    cap 15, cutting depth 4, one captured step replayed until every path is
+    done.  Every point-step converges, and in every ROM group the points with
+    the two shortest paths and one of median length end at the oracle's Pbar
+    and Abar on their own paths."""
+    from bench import SUBSTEPS, UNEVEN
+    u = UNEVEN['uneven_mixed_P32768']
+    groups, specs = [], []
+    for i, (name, P) in enumerate(u['roms']):
+        seed = u['seed'] + i
+        mu = workloads.one_void_mu(seed, P) if name.startswith('onevoid') else workloads.four_void_mu(seed, P)
+        ns = workloads.uneven_steps(seed, P, *u['steps'])
+        paths = workloads.uneven_cyclic_paths(seed, P, ns, u['rho'])
+        groups.append(Group(rom_path(name), mu, paths, ns, max_iter=u['max_iter'], max_substeps=SUBSTEPS))
+        specs.append((name, mu, paths, ns))
+    b = UnevenBatch(groups)
+    b.capture()
+    for k in range(b.max_steps):
+        if k % 10 == 0:
+            print(f"[gpu] uneven full size replay {k} of {b.max_steps}", flush=True)
+        b.graph.replay()
+    torch.cuda.synchronize()
+    tot = b.totals()
+    assert tot['failed'] == 0
+    assert tot['point_steps'] == sum(int(ns.sum()) for *_, ns in specs)
+    for (name, mu, paths, ns), g in zip(specs, groups):
+        rom = ROM(rom_path(name))
+        Pb, Ab = g.rb.Pbar.cpu().numpy(), g.rb.Abar.cpu().numpy()
+        order = np.argsort(ns, kind='stable')
+        for p in (order[0], order[1], order[len(order) // 2]):
+            print(f"[oracle] {name} point {p}, {ns[p]} steps", flush=True)
+            ref = rom.run_path(mu[p], paths[p, :ns[p]], max_iter=u['max_iter'], max_substeps=SUBSTEPS)[-1]
+            assert ref['status'] == 0
+            assert np.abs(Pb[p] - ref['Pbar']).max() < 1e-6 * np.abs(ref['Pbar']).max(), (name, p)
+            assert np.abs(Ab[p] - ref['Abar'].reshape(-1)).max() < 1e-6 * np.abs(ref['Abar']).max(), (name, p)
+    b.close()

@@ -54,3 +54,24 @@ def test_plastic_statistics_by_hand():
     s = mlp.plastic_statistics(wJ, (Fp, np.ones(2), xi))
     assert np.allclose(s, [0.15, 0.2, np.sqrt(0.25 * 0.15 ** 2 + 0.75 * 0.05 ** 2), 0.75,
                            0.075, 0.15, 0.0, -0.075], atol=1e-15)
+
+
+def test_bf16_rounding_and_forward():
+    """bfloat16 keeps 8 significand bits: 1 + 2^-7 is exact, 1 + 2^-8 is a tie
+    going to the even 1, 1 + 3 * 2^-8 a tie going up to 1 + 2^-6, 1 + 2^-8 +
+    2^-20 rounds up (truncation would not); sign and exponent are kept.  With
+    weights and inputs that are bfloat16 numbers already, the first layer's
+    pre-activations are the same with and without rounded operands; deeper
+    layers differ only by the rounding of the hidden activations."""
+    x = np.array([1.0, 1 + 2 ** -7, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, -3.0, 2.0 ** -130])
+    r = mlp.bf16(x)
+    assert np.array_equal(r[:6], [1.0, 1 + 2 ** -7, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, -3.0])
+    assert r[6] == 2.0 ** -130  # subnormal in float32, a single significant bit
+    g = np.random.Generator(np.random.PCG64(5))
+    params = [mlp.bf16(p) for p in mlp.init([6, 5, 5, 5, 3], 2)]
+    X = mlp.bf16(g.normal(size=(4, 6)))
+    a, _ = mlp.forward(params, X)
+    b, (zs, _) = mlp.forward(params, X, bf16_operands=True)
+    z0 = X @ params[0] + params[1]
+    assert np.array_equal(zs[0], z0)  # first layer: the operands are bfloat16 already
+    assert np.abs(a - b).max() < 2e-2 * np.abs(a).max() and not np.array_equal(a, b)

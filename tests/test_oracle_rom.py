@@ -157,6 +157,8 @@ def test_load_step_cutting_equals_plain_steps_along_its_targets():
         assert np.ptp(s) < 1e-12  # on the segment
         fr.append(s.mean() * 2 ** D)
     assert np.allclose(fr, np.round(fr), atol=1e-9) and all(np.diff(fr) > 0) and fr[-1] < 2 ** D
+    # the reported end points are the intermediate targets' fractions, then the full step
+    assert cut['ends'] == [int(round(f)) for f in fr] + [2 ** D]
     replay = rom.run_path(mu, cut['targets'] + [Fb], max_iter=15)
     assert all(s['status'] == 0 for s in replay)
     assert np.array_equal(replay[-1]['r'], cut['r'])
