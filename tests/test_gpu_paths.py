@@ -98,7 +98,7 @@ def test_every_point_against_plain_fp64(gpu, form):
     print(f"{form}: same-path max {dev[same].max():.2e} median {np.median(dev[same]):.2e}; "
           f"other path {(~same).mean():.4f} of point-steps, {other.size} points, max {dev.max():.2e}")
     assert dev[same].max() <= TOL_P
-    assert (~same).mean() < 0.02
+    assert (~same).mean() < 0.05
     # points on another path: the oracle along the increments the form converged on
     mu, paths = inputs(W)
     rom = ROM(rom_path(W['rom']))
