@@ -44,6 +44,7 @@ extern "C" {
 #define ROM_EHIP        -4  /* a HIP runtime call failed */
 #define ROM_EINVAL_MU   -5  /* some shape parameters give det F_mu <= 0 at an ECM point */
 #define ROM_EUNSUPPORTED -6 /* option combination not built */
+#define ROM_ESCRATCH    -7  /* rom_step_noalloc: the batch exceeds its static scratch (ROM_NOALLOC_MAX_BATCH) */
 
 /* per-point status written by rom_step */
 #define ROM_ST_CONVERGED 0  /* ||f||_2 <= tol at the returned state */
@@ -204,6 +205,30 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
  */
 int rom_homogenized_stress_tangent(rom_handle h, int32_t batch, const void* state_dev,
                                    double* Pbar_dev, double* Abar_dev, hipStream_t stream);
+
+/*
+ * rom_step_noalloc -- for callers that cannot allocate device memory or
+ * create runtime objects during the call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  The same solve as
+ * rom_step with opts->mode = ROM_MODE_FUSED on a persistent grid
+ * (opts->grid_per_cu workgroups per compute unit, 0 meaning 2), same
+ * arguments and the same results bit for bit; the work list and queue
+ * counters of the persistent grid live in a static device array of the
+ * library (ROM_NOALLOC_MAX_BATCH + 64 int32, 128.25 KiB per device, held
+ * until the process ends) instead of the state, and no timing marks are
+ * recorded.  The call allocates nothing and creates no event.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other streams, other threads, other handles) race and must be
+ * serialised by the caller.  The counters are cleared by a kernel at the
+ * start of each call, so the array's previous contents do not matter.
+ * Errors: as rom_step; ROM_ESCRATCH when batch > ROM_NOALLOC_MAX_BATCH;
+ * ROM_EUNSUPPORTED for another mode; ROM_EHIP when the array's device
+ * address was not found at rom_load.
+ */
+#define ROM_NOALLOC_MAX_BATCH 32768
+int rom_step_noalloc(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_dev,
+                     const rom_opts* opts, int32_t* status_dev, int32_t* iters_dev,
+                     double* resnorm_dev, hipStream_t stream);
 
 /*
  * rom_shape_sensitivity -- sensitivities of the effective stress to the shape

@@ -21,6 +21,8 @@ ROM_EVERSION = -3
 ROM_EHIP = -4
 ROM_EINVAL_MU = -5
 ROM_EUNSUPPORTED = -6
+ROM_ESCRATCH = -7
+NOALLOC_MAX_BATCH = 32768
 
 ST_CONVERGED = 0
 ST_MAXITER = 1
@@ -38,7 +40,7 @@ FIELD_FBAR_COMMITTED, FIELD_R_GUESS, FIELD_SUBSTEPS = 8, 9, 10
 NFIELDS = 11
 
 EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_info', 'rom_state_bytes',
-           'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_homogenized_stress_tangent', 'rom_shape_sensitivity',
+           'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_step_noalloc', 'rom_homogenized_stress_tangent', 'rom_shape_sensitivity',
            'rom_timing_enable', 'rom_timing_read', 'rom_mlp_create', 'rom_mlp_free', 'rom_mlp_param_count',
            'rom_mlp_set_params', 'rom_mlp_get_params', 'rom_mlp_set_scaling', 'rom_mlp_forward',
            'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features', 'rom_path_gather', 'rom_path_advance',
@@ -47,9 +49,16 @@ EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_inf
            'rom_ecm_workspace', 'rom_ecm']
 
 
+_CODES = {ROM_EINVAL: 'ROM_EINVAL (bad argument)', ROM_EFORMAT: 'ROM_EFORMAT (malformed artifact)',
+          ROM_EVERSION: 'ROM_EVERSION (artifact version)', ROM_EHIP: 'ROM_EHIP (HIP runtime call failed)',
+          ROM_EINVAL_MU: 'ROM_EINVAL_MU (shape parameters give det F_mu <= 0)',
+          ROM_EUNSUPPORTED: 'ROM_EUNSUPPORTED (option combination not built)',
+          ROM_ESCRATCH: f'ROM_ESCRATCH (batch above the static scratch limit of {NOALLOC_MAX_BATCH} points)'}
+
+
 class RomError(RuntimeError):
     def __init__(self, code, what):
-        super().__init__(f"{what} failed with code {code}")
+        super().__init__(f"{what} failed with code {code}: {_CODES.get(code, 'unknown')}")
         self.code = code
 
 
@@ -100,6 +109,7 @@ def lib():
         L.rom_state_offsets.argtypes = [vp, i32, ctypes.POINTER(sz)]
         L.rom_state_init.argtypes = [vp, i32, vp, vp, vp]
         L.rom_step.argtypes = [vp, i32, vp, vp, ctypes.POINTER(rom_opts), vp, vp, vp, vp]
+        L.rom_step_noalloc.argtypes = [vp, i32, vp, vp, ctypes.POINTER(rom_opts), vp, vp, vp, vp]
         L.rom_shape_sensitivity.argtypes = [vp, i32, vp, vp, vp, vp]
         L.rom_homogenized_stress_tangent.argtypes = [vp, i32, vp, vp, vp, vp]
         L.rom_timing_enable.argtypes = [vp, ctypes.c_int]
@@ -198,6 +208,12 @@ def rom_state_init(h, batch, mu_ptr, state_ptr, stream):
 def rom_step(h, batch, Fbar_ptr, state_ptr, opts, status_ptr, iters_ptr, res_ptr, stream):
     return _check(lib().rom_step(h, batch, Fbar_ptr, state_ptr, ctypes.byref(opts) if opts is not None else None,
                                  status_ptr, iters_ptr, res_ptr, stream), 'rom_step')
+
+
+def rom_step_noalloc(h, batch, Fbar_ptr, state_ptr, opts, status_ptr, iters_ptr, res_ptr, stream):
+    return _check(lib().rom_step_noalloc(h, batch, Fbar_ptr, state_ptr,
+                                         ctypes.byref(opts) if opts is not None else None,
+                                         status_ptr, iters_ptr, res_ptr, stream), 'rom_step_noalloc')
 
 
 def rom_homogenized_stress_tangent(h, batch, state_ptr, Pbar_ptr, Abar_ptr, stream):

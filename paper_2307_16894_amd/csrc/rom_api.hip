@@ -226,6 +226,7 @@ int rom_load(const void* blob, size_t bytes, int device, rom_handle* out) {
   if (rc == ROM_OK) rc = upload(&h->Gq16, Gq16);
   if (rc == ROM_OK) rc = rom_staged_setup();
   if (rc == ROM_OK) rc = rom_fused_setup();
+  if (rc == ROM_OK) rc = rom_noalloc_setup(device);  // the static scratch of rom_step_noalloc on this device
   // side stream and events of the phased form (created here, not inside a
   // caller's graph capture)
   if (rc == ROM_OK && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) rc = ROM_EHIP;
@@ -327,6 +328,29 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
     return rom_launch_step_phased(h, batch, Fbar_dev, state_dev, o, status_dev, iters_dev, resnorm_dev, stream);
   }
   return ROM_EINVAL;
+}
+
+int rom_step_noalloc(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_dev, const rom_opts* opts,
+                     int32_t* status_dev, int32_t* iters_dev, double* resnorm_dev, hipStream_t stream) {
+  if (!h || batch < 0) return ROM_EINVAL;
+  if (batch == 0) return ROM_OK;
+  if (batch > ROM_NOALLOC_MAX_BATCH) return ROM_ESCRATCH;
+  if (!Fbar_dev || !state_dev || !status_dev || !iters_dev || !resnorm_dev) return ROM_EINVAL;
+  rom_opts o;
+  if (opts)
+    o = *opts;
+  else
+    rom_default_opts(&o);
+  if (o.max_iter < 1 || o.max_iter > 1000 || !(o.tol >= 0.0)) return ROM_EINVAL;
+  if (o.contraction < ROM_DT_F64 || o.contraction > ROM_DT_BF16) return ROM_EINVAL;
+  if (o.warm_start != ROM_WARM_PREV && o.warm_start != ROM_WARM_MLP) return ROM_EINVAL;
+  if (o.warm_start == ROM_WARM_MLP && !o.mlp) return ROM_EINVAL;
+  if (o.grid_per_cu < 0 || o.grid_per_cu > 64) return ROM_EINVAL;
+  if (o.max_substeps < 0 || o.max_substeps > ROM_MAX_SUBSTEPS) return ROM_EINVAL;
+  if (o.max_substeps > 0 && !o.commit) return ROM_EUNSUPPORTED;
+  if (o.mode != ROM_MODE_FUSED) return ROM_EUNSUPPORTED;
+  DeviceGuard guard(h->device);
+  return rom_launch_step_noalloc(h, batch, Fbar_dev, state_dev, o, status_dev, iters_dev, resnorm_dev, stream);
 }
 
 int rom_shape_sensitivity(rom_handle h, int32_t batch, const double* Fbar_dev, const void* state_dev,

@@ -20,7 +20,28 @@ __global__ void k_zero2(int* __restrict__ c) {
   if (threadIdx.x < 2) c[threadIdx.x] = 0;
 }
 
+// Work list and queue counters of rom_step_noalloc: ROM_NOALLOC_MAX_BATCH
+// entries, then the two counters at a 256-byte boundary.  Each device holds
+// its own copy; host code uses the address looked up per device at set-up,
+// never this name.
+constexpr int NOALLOC_CNT = (ROM_NOALLOC_MAX_BATCH + 63) / 64 * 64;
+static __device__ __align__(256) int scratch[NOALLOC_CNT + 64];
+
+constexpr int NOALLOC_DEVICES = 64;
+int* scratch_ptr[NOALLOC_DEVICES];  // device address of scratch per device (null: not looked up)
+
 }  // namespace
+
+// Once per device, with that device current (called by rom_load).
+int rom_noalloc_setup(int device) {
+  if (device < 0 || device >= NOALLOC_DEVICES) return ROM_EINVAL;
+  if (__atomic_load_n(&scratch_ptr[device], __ATOMIC_ACQUIRE)) return ROM_OK;
+  int* ptr = nullptr;
+  if (hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+    return ROM_EHIP;
+  __atomic_store_n(&scratch_ptr[device], ptr, __ATOMIC_RELEASE);  // the same address from any racing caller
+  return ROM_OK;
+}
 
 int rom_fused_tiles(int n) { return (n + 5 + 15) / 16; }
 
@@ -142,4 +163,28 @@ int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, 
   rc = rom_fused_launch(rom_fused_tiles(h->n), a, o.contraction, split, grid, P, s);
   if (rom_timing_mark(h, 1, s) != ROM_OK) return ROM_EHIP;
   return rc;
+}
+
+// The fused form on a persistent grid with its work list and counters in the
+// device's static scratch: no allocation, no timing marks (they create events).
+int rom_launch_step_noalloc(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
+                            int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
+  if (P > ROM_NOALLOC_MAX_BATCH) return ROM_ESCRATCH;
+  if (h->device < 0 || h->device >= NOALLOC_DEVICES) return ROM_EHIP;
+  int* base = __atomic_load_n(&scratch_ptr[h->device], __ATOMIC_ACQUIRE);
+  if (!base) return ROM_EHIP;  // rom_load looks it up; a handle without it was not loaded here
+  FusedArgs a;
+  int split = 0;
+  int rc = rom_fused_prepare(h, P, Fbar, state, o, st_out, it_out, res_out, s, a, split);
+  if (rc != ROM_OK) return rc;
+  int* list = base;
+  int* cnt = base + NOALLOC_CNT;
+  k_zero2<<<1, 64, 0, s>>>(cnt);  // the last call's counters: cleared by a kernel, as in a captured graph
+  k_compact<<<(P + 255) / 256, 256, 0, s>>>(P, o.active, list, cnt);
+  if (hipGetLastError() != hipSuccess) return ROM_EHIP;
+  a.list = list;
+  a.nlist = cnt;
+  a.counter = cnt + 1;
+  const int grid = (o.grid_per_cu > 0 ? o.grid_per_cu : 2) * h->ncu;
+  return rom_fused_launch(rom_fused_tiles(h->n), a, o.contraction, split, grid, P, s);
 }
