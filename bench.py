@@ -29,7 +29,6 @@ sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
 
-PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (vector and matrix)
 
 WORKLOADS = {
     # one elliptical void, n = 40 modes, m ~ 400 ECM points, 4096 points,
@@ -68,12 +67,20 @@ UNEVEN = {'uneven_mixed_P32768': dict(
           ('fourvoid_n100_m1500', 2048), ('fourvoid_n120_m2000', 2048)],
     steps=(5, 40), rho=(0.01, 0.04), seed=0, max_iter=15, tune_points=1024)}
 DEFAULT = 'onevoid_n40_m400_P4096_cyclic20'
+EXTRA_N100, EXTRA_UNEVEN = 'fourvoid_n100_m1500_P16384_cyclic20', 'uneven_mixed_P32768'
 VARIANTS = WORKLOADS[DEFAULT]['variants']
 # warm-start training: 160 epochs of minibatch Adam, cosine-decayed from 4e-3
 # (measured on the n = 40 workload: 3.20 Newton evaluations per point-step,
 # 3.24 after 80 epochs, 3.29 after 40; training is set-up, not timed)
 WS_EPOCHS = 160
 PBAR_TOL = 1e-5  # reduced-precision forms: largest admitted |Pbar - Pbar_FP64| / max |Pbar_FP64|
+# counted floating-point operations per ECM point and evaluation
+# (paper_2307_16894_amd/flop_count.py, the smallest over the return map's
+# branches; each transcendental call counted once): the return map with its
+# consistent tangent, and the weighting D = w|J| T^T A T, W = w|J| P F_mu^-T
+C_CM, C_W = 559, 144
+PEAK = {'f64': 78.6, 'f32': 157.3, 'bf16': 2500.0}  # MI355X dense TFLOP/s: FP64 (vector = matrix), FP32 MFMA, BF16
+HBM_TBS = 8.0
 SUBSTEPS = 4  # load-step cutting depth of the fused forms: a failed step is retried in up to 1/16 strides
 MAX_ITER = 15  # Newton evaluations per attempt (the library's default cap)
 
@@ -209,6 +216,30 @@ def sensitivity_rate(w, rom_file, at_step=5, reps=5):
 FE2_MESH, FE2_STEPS, FE2_PEAK = (20, 10), 50, 0.012
 
 
+def fe2_compliance_error(mode):
+    """The compliance error of the GPU two-scale loop with the n = 20 ROM
+    against the full-order two-scale reference stored in
+    tests/golden/fe2_fom_4x2.json (4 x 2 block, eight load steps up to the
+    peak and back; Sec. 4.2): eps_C,k = |C_k - C_k^ref| / |C_k^ref| per
+    loaded step and its mean."""
+    from paper_2307_16894_amd.fe2 import Fe2Solver
+    with open(os.path.join(ROOT, 'tests', 'golden', 'fe2_fom_4x2.json')) as fh:
+        ref = json.load(fh)
+    mesh = workloads.fe2_mesh(*ref['macro_mesh'])
+    loads = workloads.fe2_loads(ref['load_steps'], ref['peak_traction'])
+    sol = Fe2Solver(os.path.join(ROOT, 'roms', ref['cell'] + '.rom'), mesh,
+                    lambda X: workloads.fe2_shape(X[:, 0], X[:, 1]), mode=mode)
+    out = sol.run(loads)
+    sol.close()
+    C, Cr = np.array([o['C'] for o in out]), np.array(ref['compliance'])
+    loaded = np.asarray(loads) > 0
+    eps = np.abs(C[loaded] - Cr[loaded]) / np.abs(Cr[loaded])
+    return dict(workload=f"fe2_q8_{ref['macro_mesh'][0]}x{ref['macro_mesh'][1]}_K{ref['load_steps']}",
+                rom=ref['cell'], reference="full-order RVE at every macro point (oracle, stored)",
+                converged_steps=int(sum(o['status'] == 0 for o in out)), eps_C=[float(e) for e in eps],
+                eps_C_mean=float(eps.mean()))
+
+
 def fe2_rate(rom_file, mode):
     """The two-scale example: a 2 x 1 block of 20 x 10 eight-node elements
     (800 RVE points, 1322 dofs), bottom fixed, parabolic top traction up to
@@ -336,7 +367,7 @@ def cpu_baseline(w, rom_file, budget_s=20.0):
                 converged_fraction=float(conv / steps))
 
 
-def uneven_main(a, log):
+def uneven_run(workload, log):
     """The uneven persistent batch: autotuned launch per ROM, one load step of
     every ROM captured as a graph (a branch per ROM), replayed until every
     point has finished its own path; the timed run starts from the virgin
@@ -345,7 +376,7 @@ def uneven_main(a, log):
     import paper_2307_16894_amd as L
     from paper_2307_16894_amd import autotune
     from paper_2307_16894_amd.uneven import Group, UnevenBatch
-    u = UNEVEN[a.workload]
+    u = UNEVEN[workload]
     groups, tuned = [], {}
     for i, (name, P) in enumerate(u['roms']):
         seed = u['seed'] + i
@@ -379,14 +410,42 @@ def uneven_main(a, log):
                value=tot['point_steps'] / elapsed, unit="macro-point load steps/s", n_gpus=1, steps=K, warmup=K,
                ms_per_step=1e3 * elapsed / K, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
                data="synthetic",
-               config=dict(workload=a.workload, roms=[dict(rom=n, points=p) for n, p in u['roms']], batch=P,
+               config=dict(workload=workload, roms=[dict(rom=n, points=p) for n, p in u['roms']], batch=P,
                            steps_per_point=list(u['steps']), newton_cap=u['max_iter'], tol=1e-8, form='fp64',
                            graph=True, tuned=tuned),
                point_steps=tot['point_steps'], evaluations=tot['evaluations'],
                mean_evaluations=tot['evaluations'] / max(tot['point_steps'], 1),
                failed_point_steps=tot['failed'], replays=K, elapsed_s=elapsed)
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
+
+
+def flops_per_eval(n, m):
+    """Algorithmic flops of one Newton evaluation of one macro point: per ECM
+    point the contraction K = sum_q G_q^T (D_q G_q) (8 n^2 + 32 n), the
+    residual f (8 n), the tangent right-hand sides C (32 n), the kinematics
+    (8 n), the return map with tangent (C_CM) and the weighting (C_W); per
+    point the elimination (2/3 n^3) and five right-hand sides (forward and
+    back substitution, 2 n^2 each)."""
+    return m * (8.0 * n * n + 80.0 * n + C_CM + C_W) + 2.0 / 3.0 * n ** 3 + 10.0 * n * n
+
+
+def stage_roofline(n, m, evals, point_steps, contraction, kern_ms):
+    """Sum over the stages of max(flops / peak of the stage's unit, bytes /
+    HBM bandwidth) for a run of `evals` point-evaluations, against its kernel
+    time: the contraction of K and C (8 n^2 + 32 n per ECM point) at the peak
+    of its precision, everything else at the FP64 peak; the history read and
+    committed once per point-step (2 x 48 m bytes) is the algorithmic HBM
+    traffic."""
+    c_flops = evals * m * (8.0 * n * n + 32.0 * n)
+    r_flops = evals * flops_per_eval(n, m) - c_flops
+    t_c = c_flops / (PEAK[contraction] * 1e12)
+    t_r = r_flops / (PEAK['f64'] * 1e12)
+    t_b = point_steps * 2 * 48.0 * m / (HBM_TBS * 1e12)
+    t_roof = t_c + max(t_r, t_b)
+    return dict(t_roofline_ms=1e3 * t_roof, t_kernels_ms=kern_ms, frac=1e3 * t_roof / kern_ms if kern_ms > 0 else 0.0,
+                stages=dict(contraction=dict(flops=c_flops, peak_tflops=PEAK[contraction], ms=1e3 * t_c),
+                            fp64_rest=dict(flops=r_flops, peak_tflops=PEAK['f64'], ms=1e3 * t_r),
+                            history_bytes=dict(bytes=point_steps * 2 * 48.0 * m, ms=1e3 * t_b)))
 
 
 def kernel_source_digest():
@@ -427,6 +486,8 @@ def main(argv=None):
     ap.add_argument('--variants', default=None, help='comma-separated forms (default: per workload)')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-fe2', action='store_true', help='skip the two-scale example')
+    ap.add_argument('--no-extra', action='store_true',
+                    help='skip the four-void n = 100 and uneven workloads reported beside the default one')
     ap.add_argument('--calibrate-copy', type=int, default=0, metavar='MIB',
                     help='first copy MIB MiB device to device (a known-size reference for HBM counters)')
     ap.add_argument('--offline-only', action='store_true',
@@ -453,45 +514,120 @@ def main(argv=None):
         print(json.dumps(dict(offline=offline_rates())), flush=True)
         return 0
     if a.workload in UNEVEN:
-        return uneven_main(a, log)
+        print(json.dumps(uneven_run(a.workload, log)), flush=True)
+        return 0
     w = WORKLOADS[a.workload]
-    a.steps = w['timed'] if a.steps is None else a.steps
-    a.warmup = w['warm'] if a.warmup is None else a.warmup
-    rom_file = os.path.join(ROOT, 'roms', w['rom'] + '.rom')
+    steps = w['timed'] if a.steps is None else a.steps
+    warmup = w['warm'] if a.warmup is None else a.warmup
     variants = [v for v in (a.variants or ','.join(w['variants'])).split(',') if v]
+    r = run_forms(a.workload, variants, steps, warmup, log)
+    out_var, head, plain_best, n, m = r['variants'], r['head'], r['plain'], r['n'], r['m']
+    rf = r['res'][plain_best] if plain_best else r['res'][head]
+    rf_form = 'phased' if (plain_best or '').endswith('_phased') else 'fused'
+    fpe = flops_per_eval(n, m)
+    achieved = fpe * rf['evals'] / (rf['kern_ms'] * 1e-3) / 1e12 if rf['kern_ms'] > 0 else 0.0
+    P = w['P']
+    out = dict(
+        metric="ROM macro-point load steps/s at 1e-8 residual; learned+mixed vs plain FP64",
+        value=out_var[head]['value'], unit="macro-point load steps/s", n_gpus=1, steps=steps, warmup=warmup,
+        ms_per_step=out_var[head]['ms_per_step'], higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype={'bf16': 'bf16+f64', 'fp32': 'f32+f64'}.get(head.split('_')[0], 'f64'),
+        data="synthetic",
+        config=dict(workload=a.workload, rom=w['rom'], n=n, m=m, batch=P, load_steps=w['steps'], tol=1e-8,
+                    form=head, contraction=head.split('_')[0], warm_start='_mlp' in head),
+        plain_fp64=dict(out_var[plain_best], form=plain_best) if plain_best else None,
+        speedup_vs_plain_fp64=(out_var[head]['value'] / out_var[plain_best]['value']) if plain_best else None,
+        head_rule=f"learned+reduced-precision form (else reduced-precision form) of highest throughput with every "
+                  f"timed point-step converged and max |Pbar - Pbar_fp64| / max |Pbar_fp64| <= {PBAR_TOL:g} over all "
+                  f"timed point-steps that followed the plain FP64 loading path (same converged sub-steps); the "
+                  f"fraction on another path is reported per form (other_path_fraction)",
+        variants=out_var,
+        warm_start=r['warm_start'],
+        # the plain FP64 step against the FP64 peak (its kernels: the fused
+        # kernel, or the phased step's material, contraction and finishing
+        # launches on both streams); algorithmic flops per point-evaluation as
+        # in flops_per_eval
+        roofline=dict(bound="mfma",
+                      kernel=("k_fused<fp64>" if rf_form == 'fused' else
+                              "phased step <fp64>: k_ph_mat + k_ph_cs + k_fused_queue"),
+                      achieved=achieved, peak=PEAK['f64'],
+                      unit="TFLOP/s", frac=achieved / PEAK['f64'],
+                      traffic=measured_traffic(a.workload, rf_form),
+                      launches=rf['launches'], avg_launch_ms=rf['kern_ms'] / max(rf['launches'], 1),
+                      flops_per_point_eval=fpe, point_evals=rf['evals'], c_cm=C_CM, c_w=C_W),
+        roofline_head=dict(form=head, **out_var[head]['stage_roofline']),
+    )
+    rom_file = os.path.join(ROOT, 'roms', w['rom'] + '.rom')
+    log("[bench] shape sensitivities")
+    out['shape_sensitivity'] = sensitivity_rate(w, rom_file)
+    if not a.no_fe2 and w['rom'] == 'onevoid_n40_m400':
+        log("[bench] two-scale example")
+        out['fe2'] = fe2_rate(rom_file, L.MODE_PHASED)
+        out['fe2']['compliance_error'] = fe2_compliance_error(L.MODE_PHASED)
+        log("[bench] offline stage")
+        out['offline'] = offline_rates()
+    if not a.no_extra and a.workload == DEFAULT:
+        # the four-void n = 100 workload (reduced-precision contraction at a
+        # large n) and the uneven batch over five ROMs, each with its own rates
+        log("[bench] four-void n = 100")
+        r4 = run_forms(EXTRA_N100, WORKLOADS[EXTRA_N100]['variants'], WORKLOADS[EXTRA_N100]['timed'],
+                       WORKLOADS[EXTRA_N100]['warm'], log)
+        out[EXTRA_N100] = dict(head=r4['head'], n=r4['n'], m=r4['m'], batch=WORKLOADS[EXTRA_N100]['P'],
+                               variants=r4['variants'])
+        log("[bench] uneven batch")
+        out[EXTRA_UNEVEN] = uneven_run(EXTRA_UNEVEN, log)
+    if not a.no_cpu_baseline:
+        out['cpu_baseline'] = cpu_baseline(w, os.path.join(ROOT, 'roms', w['rom'] + '.rom'))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_forms(workload, variants, steps, warmup, log):
+    """Every form of `variants` on a standard workload (warm-up steps, then
+    the timed steps), compared with plain FP64; returns the per-form rates
+    and accuracy, the head form and the plain FP64 form of highest rate."""
+    import paper_2307_16894_amd as L
+    w = WORKLOADS[workload]
+    rom_file = os.path.join(ROOT, 'roms', w['rom'] + '.rom')
     ws, wsinfo = (None, None)
     if any('_mlp' in v for v in variants):
         ws, wsinfo = train_warm_start(w, rom_file, log)
     P = w['P']
     res = {}
+    n = m = 0
     for v in variants:
         # <precision>[_mlp][_phased[K[eE]] | _staged]  (K: phased evaluations, E: early hand-over,
         # -1 none; library defaults when left out)
-        dt = {'fp64': L.DT_F64, 'fp32': L.DT_F32, 'bf16': L.DT_BF16}[v.split('_')[0]]
-        last = v.split('_')[-1]
+        vb = v
+        dt = {'fp64': L.DT_F64, 'fp32': L.DT_F32, 'bf16': L.DT_BF16}[vb.split('_')[0]]
+        last = vb.split('_')[-1]
         mode = L.MODE_PHASED if last.startswith('phased') else L.MODE_FUSED
         kph, kearly = 0, 0
         if mode == L.MODE_PHASED and last[6:]:
             ks, _, es = last[6:].partition('e')
             kph, kearly = int(ks or 0), int(es or 0)
         ph = dict(mode=mode, phased_evals=kph, phased_early=kearly)
-        if '_mlp' in v:
+        if '_mlp' in vb:
             opts = ws.opts(contraction=dt, max_substeps=SUBSTEPS, **ph)
-        elif v.endswith('_staged'):  # the staged form has no load-step cutting
+        elif vb.endswith('_staged'):  # the staged form has no load-step cutting
             opts = L.rom_default_opts(mode=L.MODE_STAGED, contraction=dt)
         else:
             opts = L.rom_default_opts(contraction=dt, max_substeps=SUBSTEPS, **ph)
-        log(f"[bench] {v}")
-        g = gpu_run(w, a.steps, a.warmup, opts, rom_file)
+        log(f"[bench] {workload}: {v}")
+        g = gpu_run(w, steps, warmup, opts, rom_file)
         n, m = g['n'], g['m']
         res[v] = g
+    if ws is not None:
+        ws.close()
     ref = res.get('fp64')
     out_var = {}
     for v, g in res.items():
-        d = dict(value=P * a.steps / g['elapsed'], ms_per_step=1e3 * g['elapsed'] / a.steps,
-                 mean_iters=g['evals'] / (P * a.steps), max_iters=g['max_iter'],
-                 converged_fraction=g['converged'] / (P * a.steps),
-                 kernel_ms_per_step=g['kern_ms'] / a.steps)
+        d = dict(value=P * steps / g['elapsed'], ms_per_step=1e3 * g['elapsed'] / steps,
+                 mean_iters=g['evals'] / (P * steps), max_iters=g['max_iter'],
+                 converged_fraction=g['converged'] / (P * steps),
+                 kernel_ms_per_step=g['kern_ms'] / steps)
+        prec = {'fp64': 'f64', 'fp32': 'f32', 'bf16': 'bf16'}[v.split('_')[0]]
+        d['stage_roofline'] = stage_roofline(n, m, g['evals'], P * steps, prec, g['kern_ms'])
         if ref is not None and v != 'fp64':
             # Deviation from plain FP64 over every timed point-step that followed the
             # same loading path (the same converged sub-steps since the start of the
@@ -512,6 +648,7 @@ def main(argv=None):
             d['max_rel_diff_Pbar_vs_fp64_other_path'] = float(dev[~same].max()) if (~same).any() else None
             d['max_rel_diff_Pbar_vs_fp64'] = float(dev.max())
         out_var[v] = d
+
     # head: the learned + reduced-precision form (else the reduced-precision
     # form) of highest throughput whose Pbar stays within PBAR_TOL of plain FP64
     # on every timed point-step of the same loading path, all of them converged
@@ -526,55 +663,7 @@ def main(argv=None):
     # arithmetic, the same results bit for bit)
     plain = [v for v in ('fp64', 'fp64_phased') if v in out_var]
     plain_best = max(plain, key=lambda v: out_var[v]['value']) if plain else None
-    # dominant work, per point-evaluation and ECM point: the reduced tangent
-    # K = sum_q G_q^T (D_q G_q) (8 n^2 + 32 n), the residual f = sum_q G_q^T W_q
-    # (8 n), the tangent right-hand sides C = sum_q G_q^T E_q (32 n) and the
-    # kinematics sum_i r_i G_i(q) (8 n): m (8 n^2 + 80 n) flops.  The return map
-    # and the n x n solve are not counted.  Measured on the plain FP64 run over
-    # all kernels of its steps (fused form: the one kernel; phased form: the
-    # material, contraction and fused-finish launches).
-    rf = res[plain_best] if plain_best else res[head]
-    rf_form = 'phased' if (plain_best or '').endswith('_phased') else 'fused'
-    flops_per_eval = m * (8.0 * n * n + 80.0 * n)
-    achieved = flops_per_eval * rf['evals'] / (rf['kern_ms'] * 1e-3) / 1e12 if rf['kern_ms'] > 0 else 0.0
-    out = dict(
-        metric="ROM macro-point load steps/s at 1e-8 residual; learned+mixed vs plain FP64",
-        value=out_var[head]['value'], unit="macro-point load steps/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
-        ms_per_step=out_var[head]['ms_per_step'], higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype={'bf16': 'bf16+f64', 'fp32': 'f32+f64'}.get(head.split('_')[0], 'f64'),
-        data="synthetic",
-        config=dict(workload=a.workload, rom=w['rom'], n=n, m=m, batch=P, load_steps=w['steps'], tol=1e-8,
-                    form=head, contraction=head.split('_')[0], warm_start='_mlp' in head),
-        plain_fp64=dict(out_var[plain_best], form=plain_best) if plain_best else None,
-        speedup_vs_plain_fp64=(out_var[head]['value'] / out_var[plain_best]['value']) if plain_best else None,
-        head_rule=f"learned+reduced-precision form (else reduced-precision form) of highest throughput with every "
-                  f"timed point-step converged and max |Pbar - Pbar_fp64| / max |Pbar_fp64| <= {PBAR_TOL:g} over all "
-                  f"timed point-steps that followed the plain FP64 loading path (same converged sub-steps); the "
-                  f"fraction on another path is reported per form (other_path_fraction)",
-        variants=out_var,
-        warm_start=wsinfo,
-        roofline=dict(bound="mfma",
-                      kernel=("k_fused<fp64>" if rf_form == 'fused' else
-                              "phased step <fp64>: k_ph_mat + k_ph_cs + k_fused_queue"),
-                      achieved=achieved, peak=PEAK_FP64_TFLOPS,
-                      unit="TFLOP/s", frac=achieved / PEAK_FP64_TFLOPS,
-                      traffic=measured_traffic(a.workload, rf_form),
-                      launches=rf['launches'], avg_launch_ms=rf['kern_ms'] / max(rf['launches'], 1),
-                      flops_per_point_eval=flops_per_eval, point_evals=rf['evals']),
-    )
-    if ws is not None:
-        ws.close()
-    log("[bench] shape sensitivities")
-    out['shape_sensitivity'] = sensitivity_rate(w, rom_file)
-    if not a.no_fe2 and w['rom'] == 'onevoid_n40_m400':
-        log("[bench] two-scale example")
-        out['fe2'] = fe2_rate(rom_file, L.MODE_PHASED)
-        log("[bench] offline stage")
-        out['offline'] = offline_rates()
-    if not a.no_cpu_baseline:
-        out['cpu_baseline'] = cpu_baseline(w, rom_file)
-    print(json.dumps(out), flush=True)
-    return 0
+    return dict(variants=out_var, head=head, plain=plain_best, res=res, n=n, m=m, warm_start=wsinfo)
 
 
 if __name__ == '__main__':

@@ -117,7 +117,12 @@ int rom_default_opts(rom_opts* o);
  * rom_load -- parse a ROM artifact (the output of the offline stage of
  * Algorithm 1: ECM weights and points, parent gradients of the POD modes and
  * of the auxiliary transformation modes at those points, material constants,
- * mu -> c map) and upload it to `device`.
+ * mu -> c map) and upload it to `device`.  The maps from the shape
+ * parameters mu to the affine coefficients c of the transformation
+ * (Sec. 3.4, the auxiliary problem with affine boundary data): kind 0, one
+ * axis-aligned elliptical void, mu = (a, b), c = mu / r0 - 1; kind 1, four
+ * rotated voids of fixed area, mu = (kappa_i, theta_i); kind 2, inclusions
+ * all scaled about their centres (Sec. 4.1), mu = (zeta), c = zeta - 1.
  *   blob/bytes : host memory holding the artifact file; read only, not retained.
  *   device     : HIP device ordinal; made current during the call.
  *   out        : receives the handle; release with rom_free.
@@ -288,6 +293,26 @@ int rom_mlp_gradients(rom_mlp_handle m, int32_t batch, const float* X_dev, const
 /* gradients as above, then one Adam update (beta1 0.9, beta2 0.999, eps 1e-8, step counter kept inside) */
 int rom_mlp_train_step(rom_mlp_handle m, int32_t batch, const float* X_dev, const float* Y_dev, float lr,
                        int32_t precision, float* loss_dev, hipStream_t stream);
+/* rom_mlp_infer: the network's inference on raw features (the same call as rom_mlp_forward) */
+int rom_mlp_infer(rom_mlp_handle m, int32_t batch, const float* X_dev, float* Y_dev, int32_t precision,
+                  hipStream_t stream);
+/* One epoch of minibatch Adam over N samples X [N][n_in], Y [N][n_out] (device): minibatch j takes the
+   rows order[j * batch .. (j + 1) * batch - 1] (device i32 [N], a permutation chosen by the caller),
+   floor(N / batch) updates at learning rate lr; loss_sum_dev (device f32) receives the sum of the
+   minibatch losses.  batch <= max_batch. */
+int rom_mlp_train_epoch(rom_mlp_handle m, int32_t N, const float* X_dev, const float* Y_dev, const int32_t* order_dev,
+                        int32_t batch, float lr, int32_t precision, float* loss_sum_dev, hipStream_t stream);
+/* Scaling from N >= 2 samples (device): the column means and standard deviations (N - 1 in the
+   denominator, 1 for a column whose deviation is below 1e-12) of X and Y become x_mean, x_std,
+   y_mean, y_std.  FP64 accumulation, enqueued on `stream`. */
+int rom_mlp_fit_scaling(rom_mlp_handle m, int32_t N, const float* X_dev, const float* Y_dev, hipStream_t stream);
+/* Network artifact (host memory): "PODECMN1", u32 version 1, n_in, width, n_out, u32 0, then f32
+   x_mean, x_std, y_mean, y_std and the parameters in the layout above.  rom_mlp_save writes it when
+   blob is non-NULL and capacity suffices (*bytes: its size; synchronises the device); rom_mlp_load
+   creates a network from it (errors as rom_load: ROM_EFORMAT for a bad magic, size, non-finite value
+   or a deviation <= 0, ROM_EVERSION). */
+int rom_mlp_save(rom_mlp_handle m, void* blob, size_t capacity, size_t* bytes);
+int rom_mlp_load(const void* blob, size_t bytes, int32_t max_batch, int device, rom_mlp_handle* out);
 
 /*
  * rom_features -- per-point inputs of the warm-start network for the step
@@ -298,6 +323,21 @@ int rom_mlp_train_step(rom_mlp_handle m, int32_t batch, const float* X_dev, cons
  */
 int rom_features(rom_handle h, int32_t batch, const double* Fbar_dev, const void* state_dev, float* X_dev,
                  hipStream_t stream);
+
+/*
+ * rom_warm_samples -- training samples of the warm-start network from the
+ * load step just solved on this state: for every point whose status_dev
+ * entry is ROM_ST_CONVERGED, in point order, its features X_feat_dev
+ * [batch][n_in] (rom_features before the step) and its increment
+ * dr = r_committed - r_before_dev (r_before_dev: f64 [batch][n], the
+ * committed r before the step) in FP32, written at rows *count_dev,
+ * *count_dev + 1, ... of X_out_dev [.][n_in] and Y_out_dev [.][n]; *count_dev
+ * (device i32) is advanced.  The caller sizes the outputs for every sample
+ * it collects.  Asynchronous on `stream`.
+ */
+int rom_warm_samples(rom_handle h, int32_t batch, const void* state_dev, const float* X_feat_dev,
+                     const double* r_before_dev, const int32_t* status_dev, float* X_out_dev, float* Y_out_dev,
+                     int32_t* count_dev, hipStream_t stream);
 
 /*
  * Uneven batches: every point p follows its own path of nsteps[p] load steps

@@ -14,7 +14,7 @@ Layout (little-endian), 256-byte header then FP64 / int64 arrays:
    12  uint32     n        reduced displacement modes
    16  uint32     m        ECM points
    20  uint32     c        affine transformation coefficients
-   24  uint32     kind     mu -> c map (0: one void (a, b); 1: four voids)
+   24  uint32     kind     mu -> c map (0: one void (a, b); 1: four voids; 2: inclusions scaled by zeta)
    28  uint32     n_mu     shape parameters per macro point
    32  f64[4]     E, nu, sigma_y0, H
    64  f64        r0        parent void radius

@@ -24,6 +24,12 @@ Parameter maps (kind):
      theta_4): a = sqrt(A_v / (pi kappa)), b = kappa a (as in the paper's
      second example), S = R(theta) diag(a, b) R(theta)^T / r0,
      c = (S_xx - 1, S_yy - 1, S_xy) per void.
+  2  inclusions all scaled about their centres by one factor, mu = (zeta)
+     (the paper's first example): S = zeta I for every inclusion, one
+     coefficient c = zeta - 1 and one mode, the response to
+     d = X - X_c,i on the nodes of every inclusion i at once.  The
+     inclusion meshes do not fit the ellipses; the data are prescribed on
+     all nodes inside an inclusion, so the map is exactly the scaling there.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -54,7 +60,7 @@ def _plane_strain_D(E, nu):
 
 
 def n_coeff(kind):
-    return {0: 2, 1: 12}[kind]
+    return {0: 2, 1: 12, 2: 1}[kind]
 
 
 def unit_patterns(kind):
@@ -68,6 +74,8 @@ def unit_patterns(kind):
             out.append((np.array([[0.0, 0.0], [0.0, 1.0]]), v))
             out.append((np.array([[0.0, 1.0], [1.0, 0.0]]), v))
         return out
+    if kind == 2:
+        return [(np.eye(2), -1)]  # every inclusion (void index -1: all of them)
     raise ValueError(kind)
 
 
@@ -86,6 +94,8 @@ def coefficients(kind, mu, r0, void_area=None):
             S = R @ np.diag([a, b]) @ R.T / r0
             c += [S[0, 0] - 1.0, S[1, 1] - 1.0, S[0, 1]]
         return np.array(c)
+    if kind == 2:
+        return np.array([mu[0] - 1.0])
     raise ValueError(kind)
 
 
@@ -113,6 +123,8 @@ def coefficient_jacobian(kind, mu, r0, void_area=None):
             Jc[3 * v + 1, 2 * v + 1] = 2.0 * sn * cs * (a - b) / r0
             Jc[3 * v + 2, 2 * v + 1] = (a - b) * (cs * cs - sn * sn) / r0
         return Jc
+    if kind == 2:
+        return np.ones((1, 1))
     raise ValueError(kind)
 
 
@@ -150,10 +162,11 @@ class AuxiliaryProblem:
         mesh = self.mesh
         dB = np.zeros((mesh.nn, 2))
         for Ev, v in patterns:
-            nodes = self.inner[mesh.void_of_node[self.inner] == v]
-            cx, cy, _ = mesh.voids[v]
-            dX = mesh.X[nodes] - np.array([cx, cy])
-            dB[nodes] += dX @ Ev.T
+            for u in (range(len(mesh.voids)) if v < 0 else (v,)):
+                nodes = self.inner[mesh.void_of_node[self.inner] == u]
+                cx, cy, _ = mesh.voids[u]
+                dX = mesh.X[nodes] - np.array([cx, cy])
+                dB[nodes] += dX @ Ev.T
         return dB
 
     def modes(self):

@@ -53,14 +53,25 @@ ROMS['fourvoid_n100_m1500'] = dict(_FOUR, n=100, L=16, m=1500)
 ROMS['fourvoid_n60_m800'] = dict(_FOUR, n=60, L=15, m=800)
 ROMS['fourvoid_n120_m2000'] = dict(_FOUR, n=120, L=19, m=2000)
 
+# the composite cell of Sec. 4.1: 23 random elliptical inclusions (23.4 % of
+# the cell at zeta = 1) ten times stiffer than the matrix and elastic in
+# range, mu = (zeta) in [0.5, 1.2] scaling every inclusion about its centre;
+# structured 40 x 40 mesh (3200 T6), inclusions resolved to the element size;
+# 16 training zeta x 3 cyclic paths
+ROMS['inclusions_n30_m250'] = dict(kind=2, nx=40, layout_seed=5, r0=0.0, n=30, L=12, m=250, eps=1e-4, n_mu=16,
+                                   per_mu=3, path='cyclic', steps=20, rho=(0.02, 0.05), seed=4100,
+                                   mat2=(10.0, 0.3, 1.0e3, 0.0))
+
 _G = {}
 
 
 def _geometry(spec):
     if spec['kind'] == 0:
         m = meshmod.one_void_cell(spec['r0'], spec['nt'], spec['nr'])
-    else:
+    elif spec['kind'] == 1:
         m = meshmod.four_void_cell(spec['r0'], spec['nt'], spec['nr'])
+    else:
+        m = meshmod.inclusion_cell(spec['nx'], workloads.inclusion_layout(spec['layout_seed']))
     space = fem.PeriodicSpace(m)
     ax = auxiliary.AuxiliaryProblem(m, spec['kind'])
     grad_modes = ax.gradients(ax.modes())  # (c, nq, 2, 2)
@@ -69,7 +80,9 @@ def _geometry(spec):
 
 def phases(spec, m):
     """Phase of every quadrature point of the parent mesh: 1 in the coating
-    around the (centred) void, 0 in the matrix."""
+    around the (centred) void or in an inclusion, 0 in the matrix."""
+    if spec['kind'] == 2:
+        return m.qphase.copy()
     if 'coating' not in spec:
         return np.zeros(m.nq, dtype=np.int64)
     d = np.hypot(m.qX[:, 0] - 0.5, m.qX[:, 1] - 0.5)
@@ -106,7 +119,13 @@ def _paths(spec, seed, count):
 def _training_mu(spec, seed, count):
     if spec['kind'] == 0:
         return workloads.one_void_training_mu(seed, count)
+    if spec['kind'] == 2:
+        return workloads.inclusion_training_mu(seed, count)
     return workloads.four_void_training_mu(seed, count)
+
+
+def _test_mu(spec, seed, count):
+    return {0: workloads.one_void_mu, 1: workloads.four_void_mu, 2: workloads.inclusion_mu}[spec['kind']](seed, count)
 
 
 def build(name, outdir, workers, snapshot_cache=None, overrides=None):
@@ -148,7 +167,7 @@ def build(name, outdir, workers, snapshot_cache=None, overrides=None):
     idx, wq = idx[order], wq[order]
     Gd = np.stack([g.reshape(m.nq, 4)[idx] for g in grad_modes], axis=-1)  # (m, 4, c)
     path = os.path.join(outdir, name + '.rom')
-    n_mu = 2 if spec['kind'] == 0 else 8
+    n_mu = {0: 2, 1: 8, 2: 1}[spec['kind']]
     ph = phases(spec, m)
     two = bool(ph.any())
     artifact.write(path, spec['n'], idx.size, grad_modes.shape[0], spec['kind'], n_mu, MAT,
@@ -156,7 +175,7 @@ def build(name, outdir, workers, snapshot_cache=None, overrides=None):
                    mat2=spec['mat2'] if two else None, phase=ph[idx] if two else None)
     # ROM quality on held-out paths (not a parity check)
     rom = ROM(path)
-    test_mu = (workloads.one_void_mu if spec['kind'] == 0 else workloads.four_void_mu)(spec['seed'] + 7, 4)
+    test_mu = _test_mu(spec, spec['seed'] + 7, 4)
     test_paths = _paths(spec, spec['seed'] + 8, 4)
     with mp.get_context('fork').Pool(workers) as pool:
         ref = pool.map(_fom_job, [(spec, test_mu[i], test_paths[i]) for i in range(4)])

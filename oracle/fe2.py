@@ -171,8 +171,11 @@ def run(rom, mesh, mu, Tbars, fixed_dofs=None, fixed_values=None, tol_rel=1e-9, 
         status, evals, steps = 1, 0, None
         for it in range(max_macro):
             F = deformation_gradient(mesh, geo, u)
-            steps = [rom.step(r_c[p], h_c[p], F[p], *trans[p], tol=rve_tol, max_iter=rve_max_iter)
-                     for p in range(P)]
+            if hasattr(rom, 'step_all'):  # RVE models that solve the points side by side
+                steps = rom.step_all([(r_c[p], h_c[p], F[p], trans[p]) for p in range(P)], rve_tol, rve_max_iter)
+            else:
+                steps = [rom.step(r_c[p], h_c[p], F[p], *trans[p], tol=rve_tol, max_iter=rve_max_iter)
+                         for p in range(P)]
             evals += sum(s['iters'] for s in steps)
             if any(s['status'] != 0 for s in steps):
                 status = 2
@@ -196,3 +199,103 @@ def run(rom, mesh, mu, Tbars, fixed_dofs=None, fixed_values=None, tol_rel=1e-9, 
         if status != 0:
             break
     return out
+
+
+_FOM = {}
+
+
+def damped_newton(problem, w0, Fbar, hist, tol, max_iter=200):
+    """Newton with backtracking on ||f||: the step -K^-1 f is halved until the
+    residual norm drops (at most 30 halvings).  The same equations as plain
+    Newton, reached from starts where the full step overshoots; used for the
+    reference solution only when plain Newton fails."""
+    from . import fom, material
+    w = w0.copy()
+    ev = problem.evaluate(w, Fbar, hist, material.j2_point)
+    res = np.linalg.norm(ev['f'])
+    for it in range(max_iter):
+        if not np.isfinite(res):
+            return None
+        if res <= tol:
+            return w, ev, it + 1
+        d = fom._solve(ev['K'], ev['f'])
+        a = 1.0
+        for _ in range(30):
+            wn = w - a * d
+            evn = problem.evaluate(wn, Fbar, hist, material.j2_point)
+            rn = np.linalg.norm(evn['f'])
+            if np.isfinite(rn) and rn < res:
+                break
+            a *= 0.5
+        else:
+            return None
+        w, ev, res = wn, evn, rn
+    return None
+
+
+def _fom_step(args):
+    r0, hist, Fbar, mu, tol, max_iter = args
+    return _FOM['rve'].step(r0, hist, Fbar, mu, tol=tol, max_iter=max_iter)
+
+
+class FomRve:
+    """The full-order RVE (Sec. 2: the periodic fluctuation on the mapped
+    parent cell, Newton on the full system, eq. full_newton; effective stress
+    and stiffness of eqs. eff_stress_full and eff_stiffness_full) with the
+    interface run() uses for the reduced model, so the same macro loop gives
+    the reference two-scale solution of the compliance error (Sec. 4.2).
+    `spec` is the offline stage's description of the cell (its mesh,
+    transformation modes and materials); the 'coordinates' are the
+    fluctuation dofs.  With `workers` > 1 the points of a macro iteration are
+    solved in a process pool."""
+
+    def __init__(self, spec, workers=1):
+        from . import build_rom
+        self._br = build_rom
+        self.spec = dict(spec)
+        self.mesh, self.space, self.grad_modes = build_rom._geometry(self.spec)
+        self.mat = build_rom.material(self.spec, self.mesh)
+        self.n = self.space.ndof
+        self.workers = workers
+        self._pool = None
+
+    def close(self):
+        if self._pool is not None:
+            self._pool.close()
+            self._pool = None
+
+    def transformation(self, mu):
+        return (np.asarray(mu, dtype=np.float64),)
+
+    def _problem(self, mu):
+        from . import auxiliary, fem
+        Fmu = auxiliary.transformation(self.grad_modes, self._br._mu_coeff(self.spec, mu))
+        return fem.Problem(self.mesh, self.space, Fmu, self.mat)
+
+    def virgin(self):
+        from . import material
+        return material.virgin_history((self.mesh.nq,))
+
+    def step(self, r0, hist, Fbar, mu, tol=1e-10, max_iter=25):
+        from . import fom
+        pr = self._problem(mu)
+        Fbar = np.asarray(Fbar, dtype=np.float64)
+        sol = fom.newton(pr, r0, Fbar, hist, tol, max_iter)
+        if sol is None:
+            sol = damped_newton(pr, r0, Fbar, hist, tol)
+        if sol is None:
+            nan = np.full((2, 2), np.nan)
+            return dict(r=r0, hist=hist, status=1, iters=max_iter, Pbar=nan, Abar=np.full((2, 2, 2, 2), np.nan))
+        w, ev, its = sol
+        return dict(r=w, hist=ev['hist'], status=0, iters=its, Pbar=pr.effective_stress(ev),
+                    Abar=pr.effective_stiffness(ev, fom._solve))
+
+    def step_all(self, jobs, tol, max_iter):
+        args = [(r, h, F, t[0], tol, max_iter) for r, h, F, t in jobs]
+        if self.workers <= 1:
+            return [self.step(*a[:4], tol=tol, max_iter=max_iter) for a in args]
+        if self._pool is None:
+            import multiprocessing as mp
+            _FOM['rve'] = self
+            self._pool = mp.get_context('fork').Pool(self.workers)
+        return self._pool.map(_fom_step, args, chunksize=1)

@@ -13,6 +13,13 @@ join one side of the sub-cell to a quarter of the circle.  Opposite cell sides
 carry the same node distribution, so boundary nodes pair periodically.
 Mid-side nodes are placed by the block map, so edges on a void follow the
 circle.
+
+The composite cell (Sec. 4.1: stiff elliptical inclusions in a plastic
+matrix) is meshed without fitting the inclusions: a structured mesh of the
+cell, the phase of every quadrature point decided by whether it lies in an
+ellipse, and the nodes inside an ellipse marked as carrying that inclusion's
+transformation data (the auxiliary problem prescribes them; see
+auxiliary.py).  The interface is thus resolved to the element size.
 """
 import numpy as np
 
@@ -229,3 +236,30 @@ def one_void_cell(r0, nt, nr, grading=1.0):
 def four_void_cell(r0, nt, nr, grading=1.0):
     c = [0.25, 0.75]
     return mesh_voids([(c[i], c[j], r0) for j in range(2) for i in range(2)], nt, nr, grading)
+
+
+def in_ellipses(P, inclusions):
+    """Index of the ellipse (cx, cy, a, b, theta) containing each point of
+    P (k, 2) (boundary included), -1 outside all."""
+    P = np.asarray(P, dtype=np.float64)
+    out = np.full(P.shape[0], -1, dtype=np.int64)
+    for i, (cx, cy, a, b, th) in enumerate(np.asarray(inclusions, dtype=np.float64)):
+        c, sn = np.cos(th), np.sin(th)
+        dx, dy = P[:, 0] - cx, P[:, 1] - cy
+        u = c * dx + sn * dy    # coordinates in the ellipse's axes
+        v = -sn * dx + c * dy
+        out[(u / a) ** 2 + (v / b) ** 2 <= 1.0] = i
+    return out
+
+
+def inclusion_cell(nx, inclusions):
+    """Structured nx x nx cell with elliptical inclusions (cx, cy, a, b,
+    theta): nodes inside inclusion i carry void_of_node = i and voids[i] =
+    (cx, cy, 0) holds its centre (the point its transformation scales about);
+    qphase gives 1 at the quadrature points inside an inclusion."""
+    m = mesh_square(nx)
+    m.inclusions = np.asarray(inclusions, dtype=np.float64)
+    m.void_of_node = in_ellipses(m.X, m.inclusions)
+    m.voids = [(float(c[0]), float(c[1]), 0.0) for c in m.inclusions]
+    m.qphase = (in_ellipses(m.qX, m.inclusions) >= 0).astype(np.int64)
+    return m

@@ -43,7 +43,8 @@ EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_inf
            'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_step_noalloc', 'rom_homogenized_stress_tangent', 'rom_shape_sensitivity',
            'rom_timing_enable', 'rom_timing_read', 'rom_mlp_create', 'rom_mlp_free', 'rom_mlp_param_count',
            'rom_mlp_set_params', 'rom_mlp_get_params', 'rom_mlp_set_scaling', 'rom_mlp_forward',
-           'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_features', 'rom_path_gather', 'rom_path_advance',
+           'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_mlp_infer', 'rom_mlp_train_epoch', 'rom_mlp_fit_scaling',
+           'rom_mlp_save', 'rom_mlp_load', 'rom_features', 'rom_warm_samples', 'rom_path_gather', 'rom_path_advance',
            'rom_fe2_create', 'rom_fe2_free', 'rom_fe2_info', 'rom_fe2_points', 'rom_fe2_gradient', 'rom_fe2_traction',
            'rom_fe2_residual', 'rom_fe2_solve', 'rom_fe2_compliance', 'rom_pod_workspace', 'rom_pod',
            'rom_ecm_workspace', 'rom_ecm']
@@ -125,6 +126,12 @@ def lib():
         L.rom_mlp_gradients.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp]
         L.rom_mlp_train_step.argtypes = [vp, i32, vp, vp, ctypes.c_float, i32, vp, vp]
         L.rom_features.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.rom_mlp_infer.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.rom_mlp_train_epoch.argtypes = [vp, i32, vp, vp, vp, i32, ctypes.c_float, i32, vp, vp]
+        L.rom_mlp_fit_scaling.argtypes = [vp, i32, vp, vp, vp]
+        L.rom_mlp_save.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.rom_mlp_load.argtypes = [vp, ctypes.c_size_t, i32, ctypes.c_int, ctypes.POINTER(vp)]
+        L.rom_warm_samples.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rom_path_gather.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp]
         L.rom_path_advance.argtypes = [i32, vp, vp, vp]
         dbl = ctypes.c_double
@@ -294,6 +301,40 @@ def rom_mlp_train_step(m, batch, X_ptr, Y_ptr, lr, precision, loss_ptr, stream):
 
 def rom_features(h, batch, Fbar_ptr, state_ptr, X_ptr, stream):
     _check(lib().rom_features(h, batch, Fbar_ptr, state_ptr, X_ptr, stream), 'rom_features')
+
+
+def rom_mlp_infer(m, batch, X_ptr, Y_ptr, precision, stream):
+    _check(lib().rom_mlp_infer(m, batch, X_ptr, Y_ptr, precision, stream), 'rom_mlp_infer')
+
+
+def rom_mlp_train_epoch(m, N, X_ptr, Y_ptr, order_ptr, batch, lr, precision, loss_sum_ptr, stream):
+    _check(lib().rom_mlp_train_epoch(m, N, X_ptr, Y_ptr, order_ptr, batch, ctypes.c_float(lr), precision,
+                                     loss_sum_ptr, stream), 'rom_mlp_train_epoch')
+
+
+def rom_mlp_fit_scaling(m, N, X_ptr, Y_ptr, stream):
+    _check(lib().rom_mlp_fit_scaling(m, N, X_ptr, Y_ptr, stream), 'rom_mlp_fit_scaling')
+
+
+def rom_mlp_save(m):
+    need = ctypes.c_size_t()
+    _check(lib().rom_mlp_save(m, None, 0, ctypes.byref(need)), 'rom_mlp_save')
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib().rom_mlp_save(m, buf, need.value, ctypes.byref(need)), 'rom_mlp_save')
+    return buf.raw
+
+
+def rom_mlp_load(blob, max_batch, device=0):
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    _check(lib().rom_mlp_load(buf, len(blob), max_batch, device, ctypes.byref(h)), 'rom_mlp_load')
+    return h
+
+
+def rom_warm_samples(h, batch, state_ptr, X_feat_ptr, r_before_ptr, status_ptr, X_out_ptr, Y_out_ptr, count_ptr,
+                     stream):
+    _check(lib().rom_warm_samples(h, batch, state_ptr, X_feat_ptr, r_before_ptr, status_ptr, X_out_ptr, Y_out_ptr,
+                                  count_ptr, stream), 'rom_warm_samples')
 
 
 def rom_path_gather(batch, paths_ptr, max_steps, nsteps_ptr, step_ptr, Fbar_ptr, active_ptr, stream):

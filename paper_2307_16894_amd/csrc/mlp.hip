@@ -37,12 +37,15 @@ struct rom_mlp {
   float* loss_part;        // [grid] partial losses
   float* kpart;            // [MLP_KSPLIT][max K][max N] partial products of a split inner dimension
   float* cpart;            // [MLP_CSPLIT][max N] partial column sums
+  double* spart;           // [MLP_SSPLIT][n_in + n_out] partial sample moments
+  float* loss_one;         // loss of one minibatch (epoch training)
 };
 
 namespace {
 
 constexpr int MLP_KSPLIT = 16;  // most slices of a split inner dimension
 constexpr int MLP_CSPLIT = 32;  // row slices of the bias-gradient column sum
+constexpr int MLP_SSPLIT = 64;  // row slices of the sample moments (input / output scaling)
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
 __device__ __forceinline__ float dsilu_f(float z) {
@@ -141,13 +144,16 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* _
       }
 }
 
-// layer input: x_hat = (x - mean) / std, zero padded to K0 columns
-__global__ void k_scale_in(int B, int n_in, int K0, const float* __restrict__ X, const float* __restrict__ xm,
-                           const float* __restrict__ xs, float* __restrict__ A32, uint16_t* __restrict__ A16) {
+// layer input: x_hat = (x - mean) / std, zero padded to K0 columns; row b of
+// the batch is row idx[b] of X (idx null: row b)
+__global__ void k_scale_in(int B, int n_in, int K0, const float* __restrict__ X, const int* __restrict__ idx,
+                           const float* __restrict__ xm, const float* __restrict__ xs, float* __restrict__ A32,
+                           uint16_t* __restrict__ A16) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= (long)B * K0) return;
   const int b = (int)(i / K0), k = (int)(i % K0);
-  const float v = (k < n_in) ? (X[(long)b * n_in + k] - xm[k]) / xs[k] : 0.f;
+  const long row = idx ? idx[b] : b;
+  const float v = (k < n_in) ? (X[row * n_in + k] - xm[k]) / xs[k] : 0.f;
   A32[i] = v;
   A16[i] = bf16_bits(v);
 }
@@ -172,17 +178,18 @@ __global__ void k_scale_out(int B, int n_out, int Np, const float* __restrict__ 
 
 // dLoss/dout = 2 (out - y_hat) / B on the real outputs, 0 on padding; partial losses per block
 __global__ __launch_bounds__(256) void k_loss(int B, int n_out, int Np, const float* __restrict__ Z,
-                                              const float* __restrict__ Y, const float* __restrict__ ym,
-                                              const float* __restrict__ ys, float* __restrict__ dZ,
-                                              float* __restrict__ part) {
+                                              const float* __restrict__ Y, const int* __restrict__ idx,
+                                              const float* __restrict__ ym, const float* __restrict__ ys,
+                                              float* __restrict__ dZ, float* __restrict__ part) {
   __shared__ float red[256];
   const long i = blockIdx.x * 256L + threadIdx.x;
   float l = 0.f;
   if (i < (long)B * Np) {
     const int b = (int)(i / Np), k = (int)(i % Np);
+    const long row = idx ? idx[b] : b;
     float d = 0.f;
     if (k < n_out) {
-      const float e = Z[i] - (Y[(long)b * n_out + k] - ym[k]) / ys[k];
+      const float e = Z[i] - (Y[row * n_out + k] - ym[k]) / ys[k];
       l = e * e;
       d = 2.f * e / (float)B;
     }
@@ -195,6 +202,67 @@ __global__ __launch_bounds__(256) void k_loss(int B, int n_out, int Np, const fl
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_zero_f32(float* __restrict__ x) {
+  if (threadIdx.x == 0) x[0] = 0.f;
+}
+__global__ void k_add_f32(float* __restrict__ sum, const float* __restrict__ x) {
+  if (threadIdx.x == 0) sum[0] += x[0];
+}
+
+// Column moments of the samples (columns 0 .. n_in - 1 of X, then n_out of
+// Y), lane = column, the waves and the grid's y dimension slicing the rows:
+// pass 0 the sum, pass 1 the sum of squared deviations from the mean, as
+// FP64 partials [slice][column] added in slice order by k_col_finish.
+__global__ __launch_bounds__(256) void k_col_moments(int N, int n_in, int n_out, const float* __restrict__ X,
+                                                     const float* __restrict__ Y, int pass,
+                                                     const float* __restrict__ xm, const float* __restrict__ ym,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane, nc = n_in + n_out;
+  const int S = gridDim.y, y = blockIdx.y;
+  const long r0 = (long)N * y / S, r1 = (long)N * (y + 1) / S;
+  double acc = 0.0;
+  if (c < nc) {
+    const bool isx = c < n_in;
+    const float* src = isx ? X + c : Y + (c - n_in);
+    const long ld = isx ? n_in : n_out;
+    const double mean = pass ? (double)(isx ? xm[c] : ym[c - n_in]) : 0.0;
+    for (long r = r0 + wave; r < r1; r += 4) {
+      const double v = (double)src[r * ld] - mean;
+      acc += pass ? v * v : v;
+    }
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && c < nc) part[(long)y * nc + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// pass 0: mean = sum / N; pass 1: std = sqrt(sum of squares / (N - 1)), 1
+// where it is below 1e-12 (a constant column)
+__global__ void k_col_finish(int N, int n_in, int n_out, int pass, const double* __restrict__ part,
+                             float* __restrict__ xm, float* __restrict__ xs, float* __restrict__ ym,
+                             float* __restrict__ ys) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, nc = n_in + n_out;
+  if (c >= nc) return;
+  double t = 0.0;
+  for (int y = 0; y < MLP_SSPLIT; ++y) t += part[(long)y * nc + c];
+  if (pass == 0) {
+    const float mean = (float)(t / N);
+    if (c < n_in)
+      xm[c] = mean;
+    else
+      ym[c - n_in] = mean;
+  } else {
+    const double sd = sqrt(t / (N - 1));
+    const float v = sd > 1e-12 ? (float)sd : 1.0f;
+    if (c < n_in)
+      xs[c] = v;
+    else
+      ys[c - n_in] = v;
+  }
 }
 
 // one workgroup of 256: strided partial sums, then a fixed-order tree
@@ -308,7 +376,7 @@ struct DeviceGuard {
 void mlp_release(rom_mlp* m) {
   if (!m) return;
   void* bufs[] = {m->P, m->Pb, m->Mo, m->Vo, m->G, m->xm, m->xs, m->ym, m->ys, m->dZ, m->dA, m->loss_part,
-                  m->kpart, m->cpart};
+                  m->kpart, m->cpart, m->spart, m->loss_one};
   for (void* b : bufs) (void)hipFree(b);
   for (int l = 0; l < 4; ++l) {
     (void)hipFree(m->A32[l]);
@@ -331,13 +399,15 @@ int mlp_forward_scaled(rom_mlp* m, int B, int prec, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 
-int mlp_gradients(rom_mlp* m, int B, const float* X, const float* Y, int prec, float* loss, hipStream_t s) {
-  k_scale_in<<<nblk((long)B * m->K[0]), 256, 0, s>>>(B, m->n_in, m->K[0], X, m->xm, m->xs, m->A32[0], m->A16[0]);
+int mlp_gradients(rom_mlp* m, int B, const float* X, const float* Y, const int* idx, int prec, float* loss,
+                  hipStream_t s) {
+  k_scale_in<<<nblk((long)B * m->K[0]), 256, 0, s>>>(B, m->n_in, m->K[0], X, idx, m->xm, m->xs, m->A32[0],
+                                                     m->A16[0]);
   int rc = mlp_forward_scaled(m, B, prec, s);
   if (rc != ROM_OK) return rc;
   const int Np = m->N[3];
   const unsigned nb = nblk((long)B * Np);
-  k_loss<<<nb, 256, 0, s>>>(B, m->n_out, Np, m->Z[3], Y, m->ym, m->ys, m->dZ, m->loss_part);
+  k_loss<<<nb, 256, 0, s>>>(B, m->n_out, Np, m->Z[3], Y, idx, m->ym, m->ys, m->dZ, m->loss_part);
   if (loss) k_loss_final<<<1, 256, 0, s>>>((int)nb, B, m->loss_part, loss);
   for (int l = 3; l >= 0; --l) {
     const int K = m->K[l], N = m->N[l];
@@ -350,6 +420,16 @@ int mlp_gradients(rom_mlp* m, int B, const float* X, const float* Y, int prec, f
     // dA_prev = dZ W^T  (M = B, N = K, inner = N)
     if (l > 0) gemm<false>(B, K, N, m->dZ, N, 1, m->P + m->off_w[l], 1, N, m->dA, K, nullptr, s);
   }
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int mlp_train_step(rom_mlp* m, int B, const float* X, const float* Y, const int* idx, float lr, int prec,
+                   float* loss, hipStream_t s) {
+  int rc = mlp_gradients(m, B, X, Y, idx, prec, loss, s);
+  if (rc != ROM_OK) return rc;
+  m->t += 1;
+  const float c1 = 1.0f - powf(0.9f, (float)m->t), c2 = 1.0f - powf(0.999f, (float)m->t);
+  k_adam<<<nblk(m->npad), 256, 0, s>>>(m->npad, m->P, m->Pb, m->Mo, m->Vo, m->G, lr, c1, c2);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 
@@ -410,6 +490,8 @@ int rom_mlp_create(int32_t n_in, int32_t width, int32_t n_out, int32_t max_batch
   for (int l = 0; l < 4; ++l) maxKxN = maxKxN > (long)Ks[l] * Ns[l] ? maxKxN : (long)Ks[l] * Ns[l];
   al((void**)&m->kpart, 4L * MLP_KSPLIT * maxKxN);
   al((void**)&m->cpart, 4L * MLP_CSPLIT * maxKN);
+  al((void**)&m->spart, 8L * MLP_SSPLIT * (n_in + n_out));
+  al((void**)&m->loss_one, 4L);
   if (!ok) {
     mlp_release(m);
     return ROM_EHIP;
@@ -489,18 +571,84 @@ int rom_mlp_forward(rom_mlp_handle m, int32_t B, const float* X, float* Y, int32
   if (B == 0) return ROM_OK;
   if (!X || !Y) return ROM_EINVAL;
   DeviceGuard guard(m->device);
-  k_scale_in<<<nblk((long)B * m->K[0]), 256, 0, s>>>(B, m->n_in, m->K[0], X, m->xm, m->xs, m->A32[0], m->A16[0]);
+  k_scale_in<<<nblk((long)B * m->K[0]), 256, 0, s>>>(B, m->n_in, m->K[0], X, nullptr, m->xm, m->xs, m->A32[0],
+                                                     m->A16[0]);
   int rc = mlp_forward_scaled(m, B, prec, s);
   if (rc != ROM_OK) return rc;
   k_scale_out<<<nblk((long)B * m->n_out), 256, 0, s>>>(B, m->n_out, m->N[3], m->Z[3], m->ym, m->ys, Y);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 
+int rom_mlp_infer(rom_mlp_handle m, int32_t B, const float* X, float* Y, int32_t prec, hipStream_t s) {
+  return rom_mlp_forward(m, B, X, Y, prec, s);
+}
+
+// Network artifact: "PODECMN1", u32 version 1, n_in, width, n_out, u32 pad,
+// then f32 x_mean [n_in], x_std [n_in], y_mean [n_out], y_std [n_out] and the
+// parameters in the host layout of rom_mlp_set_params.
+static size_t mlp_blob_bytes(int n_in, int width, int n_out, int64_t nparam) {
+  return 32 + 4 * (2 * (size_t)n_in + 2 * (size_t)n_out + (size_t)nparam);
+}
+
+int rom_mlp_save(rom_mlp_handle m, void* blob, size_t capacity, size_t* bytes) {
+  if (!m || !bytes) return ROM_EINVAL;
+  const size_t need = mlp_blob_bytes(m->n_in, m->width, m->n_out, m->nparam);
+  *bytes = need;
+  if (!blob) return ROM_OK;
+  if (capacity < need) return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  unsigned char* b = static_cast<unsigned char*>(blob);
+  memset(b, 0, 32);
+  memcpy(b, "PODECMN1", 8);
+  const uint32_t hdr[4] = {1u, (uint32_t)m->n_in, (uint32_t)m->width, (uint32_t)m->n_out};
+  memcpy(b + 8, hdr, sizeof(hdr));
+  float* f = reinterpret_cast<float*>(b + 32);
+  if (hipDeviceSynchronize() != hipSuccess) return ROM_EHIP;
+  bool ok = hipMemcpy(f, m->xm, 4 * m->n_in, hipMemcpyDeviceToHost) == hipSuccess;
+  ok = ok && hipMemcpy(f + m->n_in, m->xs, 4 * m->n_in, hipMemcpyDeviceToHost) == hipSuccess;
+  ok = ok && hipMemcpy(f + 2 * m->n_in, m->ym, 4 * m->n_out, hipMemcpyDeviceToHost) == hipSuccess;
+  ok = ok && hipMemcpy(f + 2 * m->n_in + m->n_out, m->ys, 4 * m->n_out, hipMemcpyDeviceToHost) == hipSuccess;
+  if (!ok) return ROM_EHIP;
+  return rom_mlp_get_params(m, f + 2 * m->n_in + 2 * m->n_out, m->nparam);
+}
+
+int rom_mlp_load(const void* blob, size_t bytes, int32_t max_batch, int device, rom_mlp_handle* out) {
+  if (!blob || !out) return ROM_EINVAL;
+  *out = nullptr;
+  const unsigned char* b = static_cast<const unsigned char*>(blob);
+  if (bytes < 32 || memcmp(b, "PODECMN1", 8) != 0) return ROM_EFORMAT;
+  uint32_t hdr[4];
+  memcpy(hdr, b + 8, sizeof(hdr));
+  if (hdr[0] != 1) return ROM_EVERSION;
+  const int n_in = (int)hdr[1], width = (int)hdr[2], n_out = (int)hdr[3];
+  if (n_in < 1 || n_in > 1024 || width < 16 || width > 1024 || width % 32 || n_out < 1 || n_out > 1024)
+    return ROM_EFORMAT;
+  const int64_t nparam =
+      (int64_t)n_in * width + width + 2 * ((int64_t)width * width + width) + (int64_t)width * n_out + n_out;
+  if (bytes < mlp_blob_bytes(n_in, width, n_out, nparam)) return ROM_EFORMAT;
+  std::vector<float> f((size_t)(2 * n_in + 2 * n_out + nparam));
+  memcpy(f.data(), b + 32, 4 * f.size());
+  for (float v : f)
+    if (!isfinite(v)) return ROM_EFORMAT;
+  rom_mlp_handle m = nullptr;
+  int rc = rom_mlp_create(n_in, width, n_out, max_batch, device, &m);
+  if (rc != ROM_OK) return rc;
+  rc = rom_mlp_set_scaling(m, f.data(), f.data() + n_in, f.data() + 2 * n_in, f.data() + 2 * n_in + n_out);
+  if (rc == ROM_EINVAL) rc = ROM_EFORMAT;  // a non-positive deviation in the file
+  if (rc == ROM_OK) rc = rom_mlp_set_params(m, f.data() + 2 * n_in + 2 * n_out, nparam);
+  if (rc != ROM_OK) {
+    rom_mlp_free(m);
+    return rc;
+  }
+  *out = m;
+  return ROM_OK;
+}
+
 int rom_mlp_gradients(rom_mlp_handle m, int32_t B, const float* X, const float* Y, int32_t prec, float* grads,
                       float* loss, hipStream_t s) {
   if (!m || B < 1 || B > m->max_batch || !X || !Y || (prec != ROM_DT_F32 && prec != ROM_DT_BF16)) return ROM_EINVAL;
   DeviceGuard guard(m->device);
-  int rc = mlp_gradients(m, B, X, Y, prec, loss, s);
+  int rc = mlp_gradients(m, B, X, Y, nullptr, prec, loss, s);
   if (rc != ROM_OK || !grads) return rc;
   // unpad into the host parameter layout
   const int fi[4] = {m->n_in, m->width, m->width, m->width}, fo[4] = {m->width, m->width, m->width, m->n_out};
@@ -522,11 +670,35 @@ int rom_mlp_train_step(rom_mlp_handle m, int32_t B, const float* X, const float*
   if (!m || B < 1 || B > m->max_batch || !X || !Y || !(lr > 0) || (prec != ROM_DT_F32 && prec != ROM_DT_BF16))
     return ROM_EINVAL;
   DeviceGuard guard(m->device);
-  int rc = mlp_gradients(m, B, X, Y, prec, loss, s);
-  if (rc != ROM_OK) return rc;
-  m->t += 1;
-  const float c1 = 1.0f - powf(0.9f, (float)m->t), c2 = 1.0f - powf(0.999f, (float)m->t);
-  k_adam<<<nblk(m->npad), 256, 0, s>>>(m->npad, m->P, m->Pb, m->Mo, m->Vo, m->G, lr, c1, c2);
+  return mlp_train_step(m, B, X, Y, nullptr, lr, prec, loss, s);
+}
+
+int rom_mlp_train_epoch(rom_mlp_handle m, int32_t N, const float* X, const float* Y, const int32_t* order,
+                        int32_t batch, float lr, int32_t prec, float* loss_sum, hipStream_t s) {
+  if (!m || N < 1 || batch < 1 || batch > m->max_batch || batch > N || !X || !Y || !order || !loss_sum ||
+      !(lr > 0) || (prec != ROM_DT_F32 && prec != ROM_DT_BF16))
+    return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  k_zero_f32<<<1, 64, 0, s>>>(loss_sum);
+  for (int32_t b0 = 0; b0 + batch <= N; b0 += batch) {
+    const int rc = mlp_train_step(m, batch, X, Y, order + b0, lr, prec, m->loss_one, s);
+    if (rc != ROM_OK) return rc;
+    k_add_f32<<<1, 64, 0, s>>>(loss_sum, m->loss_one);
+  }
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int rom_mlp_fit_scaling(rom_mlp_handle m, int32_t N, const float* X, const float* Y, hipStream_t s) {
+  if (!m || N < 2 || !X || !Y) return ROM_EINVAL;
+  DeviceGuard guard(m->device);
+  const int nc = m->n_in + m->n_out;
+  const dim3 grid((unsigned)((nc + 63) / 64), MLP_SSPLIT);
+  // mean, then the sum of squared deviations from it (two passes, FP64 partials over row slices)
+  for (int pass = 0; pass < 2; ++pass) {
+    k_col_moments<<<grid, 256, 0, s>>>(N, m->n_in, m->n_out, X, Y, pass, m->xm, m->ym, m->spart);
+    k_col_finish<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(N, m->n_in, m->n_out, pass, m->spart, m->xm, m->xs,
+                                                              m->ym, m->ys);
+  }
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 

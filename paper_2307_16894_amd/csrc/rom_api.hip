@@ -133,7 +133,8 @@ int rom_load(const void* blob, size_t bytes, int device, rom_handle* out) {
   const bool two = hdr[0] == 2;  // version 2: a second phase and the phase of every point
   const int n = (int)hdr[1], m = (int)hdr[2], c = (int)hdr[3], kind = (int)hdr[4], n_mu = (int)hdr[5];
   if (n < 1 || n > ROM_NMAX - 5 || m < 1 || m > (1 << 24) || c < 1 || c > 12) return ROM_EFORMAT;
-  if (!((kind == 0 && c == 2 && n_mu == 2) || (kind == 1 && c == 12 && n_mu == 8))) return ROM_EFORMAT;
+  if (!((kind == 0 && c == 2 && n_mu == 2) || (kind == 1 && c == 12 && n_mu == 8) || (kind == 2 && c == 1 && n_mu == 1)))
+    return ROM_EFORMAT;
   double par[7];
   memcpy(par, b + 32, sizeof(par));
   const size_t need = 256 + 8 * ((size_t)m + (size_t)m * 4 * n + (size_t)m * 4 * c + (size_t)m + (two ? (size_t)m : 0));
@@ -141,7 +142,9 @@ int rom_load(const void* blob, size_t bytes, int device, rom_handle* out) {
   for (int i = 0; i < 7; ++i)
     if (!isfinite(par[i])) return ROM_EFORMAT;
   const double E = par[0], nu = par[1];
-  if (!(E > 0 && nu > -1 && nu < 0.5 && par[2] > 0 && par[3] >= 0 && par[4] > 0 && par[6] > 0)) return ROM_EFORMAT;
+  // the parent void radius r0 enters the voids' maps only (kinds 0 and 1)
+  if (!(E > 0 && nu > -1 && nu < 0.5 && par[2] > 0 && par[3] >= 0 && (kind == 2 || par[4] > 0) && par[6] > 0))
+    return ROM_EFORMAT;
   double par2[4] = {E, nu, par[2], par[3]};
   std::vector<int> phase;
   if (two) {
@@ -369,6 +372,19 @@ int rom_features(rom_handle h, int32_t batch, const double* Fbar_dev, const void
   if (!Fbar_dev || !state_dev || !X_dev || batch > 65535) return ROM_EINVAL;
   DeviceGuard guard(h->device);
   return rom_launch_features(h, batch, Fbar_dev, state_dev, X_dev, stream);
+}
+
+int rom_warm_samples(rom_handle h, int32_t batch, const void* state_dev, const float* X_feat_dev,
+                     const double* r_before_dev, const int32_t* status_dev, float* X_out_dev, float* Y_out_dev,
+                     int32_t* count_dev, hipStream_t stream) {
+  if (!h || batch < 0) return ROM_EINVAL;
+  if (batch == 0) return ROM_OK;
+  if (!state_dev || !X_feat_dev || !r_before_dev || !status_dev || !X_out_dev || !Y_out_dev || !count_dev ||
+      batch > 65535)
+    return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  return rom_launch_warm_samples(h, batch, state_dev, X_feat_dev, r_before_dev, status_dev, X_out_dev, Y_out_dev,
+                                 count_dev, stream);
 }
 
 int rom_path_gather(int32_t batch, const double* paths, int32_t max_steps, const int32_t* nsteps,

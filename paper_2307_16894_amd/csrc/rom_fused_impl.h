@@ -25,8 +25,11 @@
 // components (i, .) of W and E, which undoes the F_mu^-T of W and of T^T)
 //   sum_q w|J| P  and  sum_q w|J| A        (eqs. eff_stress_1, eff_stiffness_1).
 // Only the tiles I <= J are contracted (K and the padding blocks are symmetric
-// or above the diagonal); the rest of K is mirrored.
-//   FP64  v_mfma_f64_16x16x4f64;
+// or above the diagonal); the rest of K is mirrored.  The padding block
+// starts at pad_base(n): n, or the next tile boundary when the rows n .. n + 3
+// would cross one (n mod 16 >= 13), since an entry of those rows against the
+// columns n .. n + 4 would then fall in a tile below the diagonal.
+//   FP64  v_mfma_f64_16x16x4f64 (H = D [G | V] on v_mfma_f64_4x4x4f64);
 //   FP32  v_mfma_f32_16x16x4f32 on FP32 operands, FP32 accumulation;
 //   BF16  v_mfma_f32_16x16x32_bf16, eight ECM points per instruction, FP32
 //         accumulation;
@@ -187,8 +190,14 @@ constexpr bool owns(int J) {
 //     n + 1 + (k, l) feed the H MFMA with V[(k', s)][(k, l)] = delta(k', k)
 //     F_mu[l][s] (the entries of T^-1, right multiplication by F_mu) in place
 //     of G, so that H = D V = E there.
+// First row / column of the padding block: n, or the next tile boundary when
+// the four padding rows would cross one (n mod 16 >= 13), so that every
+// padding entry lies in tiles I <= J; the columns in between are zero.
+__host__ __device__ __forceinline__ int pad_base(int n) { return (n & 15) <= 12 ? n : (n + 15) & ~15; }
+
 struct Pad {
-  int In;       // tile row / column of index n
+  int nb;       // pad_base(n)
+  int In;       // tile row / column of index nb
   bool a_use;   // this lane's A value in tile In comes from the record
   int a_off;    // its record offset
   int w_use;    // bit t: this lane's B value in tile In + t is W[k_row]
@@ -199,15 +208,16 @@ struct Pad {
 
 __device__ __forceinline__ Pad make_pad(int n, int k_row, int c_col) {
   Pad d;
-  d.In = n >> 4;
-  const int row = 16 * d.In + c_col, ar = row - n;
+  d.nb = pad_base(n);
+  d.In = d.nb >> 4;
+  const int row = 16 * d.In + c_col, ar = row - d.nb;
   d.a_use = (ar >= 0 && ar < 4 && (ar >> 1) == (k_row >> 1));
   d.a_off = d.a_use ? R_FM + 2 * (ar & 1) + (k_row & 1) : R_FM;
   d.w_use = d.v_use = d.v_zero = 0;
   int off[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const int dc = 16 * (d.In + t) + c_col - n;
+    const int dc = 16 * (d.In + t) + c_col - d.nb;
     off[t] = R_FM;
     if (dc == 0) d.w_use |= 1 << t;
     if (dc >= 1 && dc <= 4) {
@@ -244,18 +254,21 @@ struct Ops {
 
 // Operands of the point with record rq and loads L (and, in the
 // reduced-precision forms, its FP64 residual partial G_q[k_row][col] W_q[k_row]).
-// H = D [G | V] comes from an MFMA per column tile: A = D, B = the lane's G
-// component, and row k_row of the result is in the first output register of
-// lane (k_row, c_col).  The output rows of the FP64 instruction are
-// k_row + 4 j, those of the FP32 one 4 k_row + j, so D goes into A rows 0..3
-// (lane c_col < 4 holds D[c_col][k_row]) or rows 0, 4, 8, 12.
+// H = D [G | V] comes from an MFMA per column tile, B = the lane's G
+// component, and H[k_row][col] lands in lane (k_row, c_col), where the
+// contraction wants it as its B operand.  FP64: v_mfma_f64_4x4x4f64, whose
+// four blocks b take the columns 4b .. 4b + 3 of the tile (block b: A[i][k]
+// from lane 16 k + 4 b + i, B[k][j] from lane 16 k + 4 b + j, C[i][j] to lane
+// 16 i + 4 b + j), so every lane holds D[c_col mod 4][k_row]: a quarter of the
+// issue cycles of the 16 x 16 x 4 form.  FP32: v_mfma_f32_16x16x4f32, output
+// rows 4 k_row + j, D in A rows 0, 4, 8, 12.
 template <int T, int PREC, int W, int TW>
 __device__ __forceinline__ void make_ops(Ops<T>& O, double (&fpart)[T], bool do_f, const GLoad<T>& L,
                                          const double* rq, const Pad& pd, int k_row, int n, int c_col) {
   constexpr bool F64 = (PREC == PREC_F64);
   const int drow = F64 ? (c_col & 3) : (c_col >> 2);
   const double dv = rq[R_D + 4 * drow + k_row];
-  const double dop = (F64 ? c_col < 4 : (c_col & 3) == 0) ? dv : 0.0;
+  const double dop = (F64 || (c_col & 3) == 0) ? dv : 0.0;
   const double xa = rq[pd.a_off], xw = rq[R_W + k_row], xv0 = rq[pd.v_off0], xv1 = rq[pd.v_off1];
 #pragma unroll
   for (int J = 0; J < T; ++J) {
@@ -273,8 +286,7 @@ __device__ __forceinline__ void make_ops(Ops<T>& O, double (&fpart)[T], bool do_
     if (!owns<T, W, TW>(J)) {
       // not this wave's column: B unused
     } else if constexpr (PREC == PREC_F64) {
-      const d4 hz = __builtin_amdgcn_mfma_f64_16x16x4f64(dop, g, (d4){0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
-      h = hz[0];
+      h = __builtin_amdgcn_mfma_f64_4x4x4f64(dop, g, 0.0, 0, 0, 0);
     } else {
       const f4 hz = __builtin_amdgcn_mfma_f32_16x16x4f32((float)dop, (float)g, (f4){0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
       h = (double)hz[0];
@@ -377,7 +389,7 @@ __device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T],
   constexpr int NPAD = 16 * T;
   if (qa >= qb) return;
   const double* Gb = Gq + (size_t)q0 * 4 * NPAD;
-  const int arow = 16 * pd.In + c_col - n;  // padding-row offset of this lane in tile In
+  const int arow = 16 * pd.In + c_col - pd.nb;  // padding-row offset of this lane in tile In
   const bool apad = arow >= 0 && arow < 4, aodd = arow & 1;
   // E columns: B = D V with V[(k', s)][(k, l)] = delta(k', k) F_mu[l][s] in place of G
   G8 cur, nxt;
@@ -407,7 +419,7 @@ __device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T],
         load_g8<T>(nxt, Gb, qs, J + 1, qa, qb, k_row, c_col);
       else
         load_g8<T>(nxt, Gb, min(qs + 8, qb - 1), 0, qa, qb, k_row, c_col);
-      const int col = 16 * J + c_col, dc = col - n;
+      const int col = 16 * J + c_col, dc = col - pd.nb;
       const bool ecol = dc >= 1 && dc <= 4, wcol = dc == 0;
       const int ek = (dc - 1) >> 1, el = (dc - 1) & 1;
       if (do_f) {
@@ -466,7 +478,7 @@ __device__ __forceinline__ void contract_any(typename Acc<PREC>::type* acc, doub
 // the transposed tile below the diagonal.
 template <int T, int PREC, int W, int TW>
 __device__ __forceinline__ void store_acc(const typename Acc<PREC>::type* acc, double* sK, bool accum, bool mirror,
-                                          int k_row, int c_col) {
+                                          int n, int k_row, int c_col) {
   constexpr int LD = ldk<T>();
   int u = 0;
 #pragma unroll
@@ -478,10 +490,15 @@ __device__ __forceinline__ void store_acc(const typename Acc<PREC>::type* acc, d
         for (int j = 0; j < 4; ++j) {
           // output layouts: FP64 row = k_row + 4 j, FP32 accumulators row = 4 k_row + j
           const int row = 16 * I + (PREC == PREC_F64 ? k_row + 4 * j : 4 * k_row + j), col = 16 * J + c_col;
+          // K is kept exactly symmetric: in the diagonal tiles its entries
+          // below the diagonal are the mirror of those above (the padding rows
+          // and columns are not symmetric quantities and stay as computed)
+          const bool upper_k = row < col && col < n;
+          if (I == J && row > col && row < n) continue;
           double x = (double)acc[u][j];
           if (accum) x += sK[row * LD + col];
           sK[row * LD + col] = x;
-          if (mirror && I < J) sK[col * LD + row] = x;
+          if (mirror && (I < J || upper_k)) sK[col * LD + row] = x;
         }
         ++u;
       }
@@ -519,14 +536,14 @@ __device__ __forceinline__ unsigned int pivot_key(double v, bool cand) {
 // multipliers a[r][k] / a[pr][k] of all other rows; every wave then
 // eliminates column k from those rows with the unscaled pivot row (pivot rows
 // stay unscaled and are divided by their pivot at the end).  One barrier per
-// step.  On return sK[ord[k]][n + y] holds unknown k of right-hand side y
+// step.  On return sK[ord[k]][pad_base(n) + y] holds unknown k of right-hand side y
 // (y = 0: f, 1..4: C) with ord[k] = sOrd[k].
 template <int T>
 __device__ void gauss_jordan(double* sK, int n, double* sL, double* sPv, int* sOrd, int* sPiv) {
   constexpr int NPAD = 16 * T, LD = ldk<T>();
   constexpr int ROWS = NPAD > 64 ? 2 : 1, COLS = NPAD / 4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ncol = n + 5;
+  const int ncol = pad_base(n) + 5;  // K, zero columns up to the padding base, then [f | C]
   double a[ROWS][COLS];
 #pragma unroll
   for (int s = 0; s < ROWS; ++s) {
@@ -750,17 +767,18 @@ template <int T, int PREC, int SPLIT>
 __device__ __forceinline__ double assemble(const EvalAcc<T, PREC, SPLIT>& E, double* sK, double* sC, double* sX,
                                            int n, int tid, int lane, int wave, int k_row, int c_col) {
   constexpr int NPAD = 16 * T, LD = ldk<T>();
+  const int nb = pad_base(n);
   if constexpr (SPLIT == 0) {
     for (int w = 0; w < 4; ++w) {
-      if (wave == w) store_acc<T, PREC, 0, 1>(E.acc, sK, w > 0, w == 3, k_row, c_col);
+      if (wave == w) store_acc<T, PREC, 0, 1>(E.acc, sK, w > 0, w == 3, n, k_row, c_col);
       __syncthreads();
     }
   } else {
     switch (wave) {
-      case 0: store_acc<T, PREC, 0, 4>(E.acc, sK, false, true, k_row, c_col); break;
-      case 1: store_acc<T, PREC, 1, 4>(E.acc, sK, false, true, k_row, c_col); break;
-      case 2: store_acc<T, PREC, 2, 4>(E.acc, sK, false, true, k_row, c_col); break;
-      default: store_acc<T, PREC, 3, 4>(E.acc, sK, false, true, k_row, c_col); break;
+      case 0: store_acc<T, PREC, 0, 4>(E.acc, sK, false, true, n, k_row, c_col); break;
+      case 1: store_acc<T, PREC, 1, 4>(E.acc, sK, false, true, n, k_row, c_col); break;
+      case 2: store_acc<T, PREC, 2, 4>(E.acc, sK, false, true, n, k_row, c_col); break;
+      default: store_acc<T, PREC, 3, 4>(E.acc, sK, false, true, n, k_row, c_col); break;
     }
     __syncthreads();
   }
@@ -783,15 +801,15 @@ __device__ __forceinline__ double assemble(const EvalAcc<T, PREC, SPLIT>& E, dou
     if (tid < n) {
       const double v = (SPLIT == 0) ? ((sFp[tid] + sFp[NPAD + tid]) + sFp[2 * NPAD + tid]) + sFp[3 * NPAD + tid]
                                     : sFp[tid];
-      sK[tid * LD + n] = v;
+      sK[tid * LD + nb] = v;
     }
-    if (tid < 4) sK[(n + tid) * LD + n] = ((sX[4 * tid] + sX[4 * tid + 1]) + sX[4 * tid + 2]) + sX[4 * tid + 3];
+    if (tid < 4) sK[(nb + tid) * LD + nb] = ((sX[4 * tid] + sX[4 * tid + 1]) + sX[4 * tid + 2]) + sX[4 * tid + 3];
     __syncthreads();
   }
-  for (int idx = tid; idx < 4 * n; idx += 256) sC[idx] = sK[(idx >> 2) * LD + n + 1 + (idx & 3)];
+  for (int idx = tid; idx < 4 * n; idx += 256) sC[idx] = sK[(idx >> 2) * LD + nb + 1 + (idx & 3)];
   double part = 0.0;
   if (tid < n) {
-    const double fv = sK[tid * LD + n];
+    const double fv = sK[tid * LD + nb];
     part = fv * fv;
   }
   for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
@@ -827,20 +845,21 @@ template <int T>
 __device__ __forceinline__ void write_effective(const FusedArgs& a, int p, const double* sK, const double* sC,
                                                 const int* sOrd, int n, int tid) {
   constexpr int LD = ldk<T>();
+  const int nb = pad_base(n);
   if (tid < 20) {
     const double inv_area = a.inv_area;
     if (tid < 4) {
-      a.Pbar[4 * (size_t)p + tid] = sK[(n + tid) * LD + n] * inv_area;
+      a.Pbar[4 * (size_t)p + tid] = sK[(nb + tid) * LD + nb] * inv_area;
     } else {
       const int e = tid - 4, x = e >> 2, y = e & 3;
-      double acc2 = sK[(n + x) * LD + n + 1 + y];
-      for (int i = 0; i < n; ++i) acc2 = fma(-sC[4 * i + x], sK[sOrd[i] * LD + n + 1 + y], acc2);
+      double acc2 = sK[(nb + x) * LD + nb + 1 + y];
+      for (int i = 0; i < n; ++i) acc2 = fma(-sC[4 * i + x], sK[sOrd[i] * LD + nb + 1 + y], acc2);
       a.Abar[16 * (size_t)p + e] = acc2 * inv_area;
     }
   }
   // K*^-1 C, kept for the shape sensitivities of the returned state
   for (int idx = tid; idx < 4 * n; idx += 256)
-    a.zk[(size_t)p * 4 * n + idx] = sK[sOrd[idx >> 2] * LD + n + 1 + (idx & 3)];
+    a.zk[(size_t)p * 4 * n + idx] = sK[sOrd[idx >> 2] * LD + nb + 1 + (idx & 3)];
   __syncthreads();
 }
 
@@ -1006,7 +1025,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
         write_effective<T>(a, p, sK, sC, sOrd, n, tid);
         break;
       }
-      if (tid < n) sR[tid] -= sK[sOrd[tid] * LD + n];
+      if (tid < n) sR[tid] -= sK[sOrd[tid] * LD + pad_base(n)];
       __syncthreads();
     }
     total += iters;
@@ -1178,7 +1197,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cs_waves<T,
       next = 0;  // failed attempt: the fused kernel redoes the point with load-step cutting
       fell_back = false;
     } else {
-      for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i] - sK[sOrd[i] * LD + n];
+      for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i] - sK[sOrd[i] * LD + pad_base(n)];
     }
   }
   if (tid == 0) {

@@ -22,12 +22,17 @@ constexpr int SCH = 128;    // ECM points per chunk
 // d c / d mu of the shape-to-coefficient maps, [c][n_mu] (row c_index, column
 // shape parameter): kind 0 c = (a, b) / r0 - 1; kind 1 per void
 // S = R(theta) diag(a, b) R(theta)^T / r0 with a = sqrt(A_v / (pi kappa)),
-// b = kappa a (da/dkappa = -a / (2 kappa), db/dkappa = a / 2).
+// b = kappa a (da/dkappa = -a / (2 kappa), db/dkappa = a / 2); kind 2
+// c = zeta - 1.
 __device__ void mu_to_dc(int kind, const double* mu, double r0, double void_area, int n_mu, double* dc) {
   for (int i = 0; i < 12 * n_mu; ++i) dc[i] = 0.0;
   if (kind == 0) {
     dc[0 * n_mu + 0] = 1.0 / r0;
     dc[1 * n_mu + 1] = 1.0 / r0;
+    return;
+  }
+  if (kind == 2) {
+    dc[0] = 1.0;
     return;
   }
   for (int v = 0; v < 4; ++v) {

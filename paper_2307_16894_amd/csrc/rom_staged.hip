@@ -24,6 +24,8 @@ __device__ __forceinline__ void mu_to_c(int kind, const double* __restrict__ mu,
   if (kind == 0) {
     cc[0] = mu[0] / r0 - 1.0;
     cc[1] = mu[1] / r0 - 1.0;
+  } else if (kind == 2) {
+    cc[0] = mu[0] - 1.0;  // every inclusion scaled by zeta about its centre
   } else {
     for (int v = 0; v < 4; ++v) {
       const double kappa = mu[2 * v], theta = mu[2 * v + 1];
@@ -655,6 +657,57 @@ int rom_launch_features(const rom_model* h, int P, const double* Fbar, const voi
   void* st = const_cast<void*>(state);
   k_features<<<P, 256, 0, s>>>(h->n, h->m, h->n_mu, field<double>(st, L, F_MU), Fbar, field<double>(st, L, F_FBC),
                                field<double>(st, L, F_RC), field<double>(st, L, F_HC), field<double>(st, L, F_TMU), X);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+namespace {
+
+// Training samples of the warm-start network from a solved load step, in
+// point order: for every converged point, its features X_feat[p] (taken
+// before the step) and dr = r_committed - r_before in FP32, appended at
+// *count (device counter, advanced).  One workgroup walks the batch in blocks
+// of 1024 points, ranking the converged ones with a ballot per wave.
+__global__ __launch_bounds__(1024) void k_warm_samples(int P, int n, int nf, const float* __restrict__ X_feat,
+                                                        const double* __restrict__ rc,
+                                                        const double* __restrict__ r_before,
+                                                        const int* __restrict__ status, float* __restrict__ X_out,
+                                                        float* __restrict__ Y_out, int* __restrict__ count) {
+  __shared__ int wsum[16];
+  __shared__ int base0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base0 = *count;
+  __syncthreads();
+  int base = base0;
+  for (int p0 = 0; p0 < P; p0 += 1024) {
+    const int p = p0 + threadIdx.x;
+    const bool ok = p < P && status[p] == ROM_ST_CONVERGED;
+    const unsigned long long bal = __ballot(ok);
+    if (lane == 0) wsum[wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      off += (w < wave) ? wsum[w] : 0;
+      tot += wsum[w];
+    }
+    if (ok) {
+      const long d = base + off + __popcll(bal & ((1ull << lane) - 1ull));
+      for (int j = 0; j < nf; ++j) X_out[d * nf + j] = X_feat[(long)p * nf + j];
+      for (int i = 0; i < n; ++i) Y_out[d * n + i] = (float)(rc[(long)p * n + i] - r_before[(long)p * n + i]);
+    }
+    base += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = base;
+}
+
+}  // namespace
+
+int rom_launch_warm_samples(const rom_model* h, int P, const void* state, const float* X_feat, const double* r_before,
+                            const int* status, float* X_out, float* Y_out, int* count, hipStream_t s) {
+  const StateLayout L = rom_state_layout(h, P);
+  void* st = const_cast<void*>(state);
+  k_warm_samples<<<1, 1024, 0, s>>>(P, h->n, rom_n_features(h), X_feat, field<double>(st, L, F_RC), r_before, status,
+                                    X_out, Y_out, count);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 

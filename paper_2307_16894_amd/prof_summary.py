@@ -1,11 +1,14 @@
 """Summaries of rocprofv3 CSV output for the profiles directory.
 
     python -m paper_2307_16894_amd.prof_summary stats KERNEL_STATS_CSV OUT.md --command "..."
+    python -m paper_2307_16894_amd.prof_summary counters OUT.md PMC_CSV [PMC_CSV ...] --command "..." [--command ...]
     python -m paper_2307_16894_amd.prof_summary traffic FETCH_CSV WRITE_CSV OUT_PREFIX \\
         --workload W --copy-mib N --command-fetch "..." --command-write "..."
 
 `stats` keeps the kernel table of a --kernel-trace --stats run (with
 --unit-kernel K also the summed duration per call of K, e.g. per phased step).
+`counters` adds up the counters of --pmc runs per kernel and derives the
+MFMA-busy fraction and per-wave instruction counts.
 `traffic` takes the FETCH_SIZE and WRITE_SIZE counter runs (KiB per
 dispatch), scales each by the reading of the same counter for the calibration
 copy of known size (bench.py --calibrate-copy), and writes the HBM bytes per
@@ -106,6 +109,48 @@ def traffic(args):
         fh.write('\n'.join(lines) + '\n')
 
 
+def counters(args):
+    """Per-kernel sums of the counters of one or more --pmc runs (every
+    dispatch of a kernel added), with the derived ratios: MFMA-busy fraction
+    SQ_VALU_MFMA_BUSY_CYCLES / (4 SQ_BUSY_CU_CYCLES) (four SIMDs per compute
+    unit), instructions per wave, LDS bank-conflict cycles per LDS
+    instruction."""
+    tot = {}
+    for path in args.csvs:
+        for r in _rows(path):
+            name = r['Kernel_Name']
+            if args.kernels and not any(k in name for k in args.kernels.split(',')):
+                continue
+            d = tot.setdefault(name, {})
+            key = r['Counter_Name']
+            d[key] = d.get(key, 0.0) + float(r['Counter_Value'])
+            d.setdefault('_dispatches_' + os.path.basename(path), set()).add(r['Dispatch_Id'])
+    lines = [f"# rocprofv3 counters: {args.title}", "", "Commands:", "", "```"] + args.command + ["```", ""]
+    for name, d in sorted(tot.items(), key=lambda kv: -kv[1].get('SQ_BUSY_CU_CYCLES', kv[1].get('SQ_WAVES', 0))):
+        disp = max(len(v) for k, v in d.items() if k.startswith('_dispatches_'))
+        lines.append(f"## `{name[:110]}` ({disp} dispatches)")
+        lines.append("")
+        lines.append("| counter | sum over dispatches |")
+        lines.append("|---|---|")
+        for k in sorted(k for k in d if not k.startswith('_')):
+            lines.append(f"| {k} | {d[k]:.6g} |")
+        derived = []
+        if 'SQ_VALU_MFMA_BUSY_CYCLES' in d and d.get('SQ_BUSY_CU_CYCLES'):
+            derived.append(f"MFMA busy: {d['SQ_VALU_MFMA_BUSY_CYCLES'] / (4.0 * d['SQ_BUSY_CU_CYCLES']):.3f} "
+                           f"of the SIMD cycles while the compute units were busy")
+        if d.get('SQ_WAVES'):
+            for k in ('SQ_INSTS_VALU', 'SQ_INSTS_MFMA', 'SQ_INSTS_LDS', 'SQ_INSTS_SALU', 'SQ_INSTS_VMEM_RD'):
+                if k in d:
+                    derived.append(f"{k} per wave: {d[k] / d['SQ_WAVES']:.1f}")
+        if d.get('SQ_INSTS_LDS') and 'SQ_LDS_BANK_CONFLICT' in d:
+            derived.append(f"LDS bank-conflict cycles per LDS instruction: {d['SQ_LDS_BANK_CONFLICT'] / d['SQ_INSTS_LDS']:.3f}")
+        if derived:
+            lines += [""] + [f"- {x}" for x in derived]
+        lines.append("")
+    with open(args.out, 'w') as fh:
+        fh.write('\n'.join(lines) + '\n')
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest='what', required=True)
@@ -128,8 +173,14 @@ def main(argv=None):
     t.add_argument('--unit-kernel', default='')
     t.add_argument('--command-fetch', required=True)
     t.add_argument('--command-write', required=True)
+    c = sub.add_parser('counters')
+    c.add_argument('out')
+    c.add_argument('csvs', nargs='+')
+    c.add_argument('--command', action='append', required=True)
+    c.add_argument('--title', default='')
+    c.add_argument('--kernels', default='')
     a = ap.parse_args(argv)
-    stats(a) if a.what == 'stats' else traffic(a)
+    {'stats': stats, 'traffic': traffic, 'counters': counters}[a.what](a)
 
 
 if __name__ == '__main__':

@@ -3,16 +3,19 @@ solve and training with the library's own network kernels.
 
 Samples are (features, dr) pairs of converged load steps: rom_features gives
 the inputs for the step (mu, Fbar - Fbar_committed, r_committed, eight plastic
-statistics) and dr = r_converged - r_committed is the target.  Python only
-marshals arguments and shuffles sample indices; the network's forward,
-backward and Adam updates run in libpodecm.
+statistics), and rom_warm_samples appends the converged points' features and
+dr = r_converged - r_committed.  The scaling is fitted by rom_mlp_fit_scaling,
+and rom_mlp_train_epoch runs the minibatches (gathering their rows itself).
+Python only allocates buffers, draws the per-epoch permutation of the sample
+indices (a seeded generator) and the learning-rate schedule, and marshals
+arguments: the arithmetic runs in libpodecm.
 """
 import numpy as np
 import torch
 
 from . import (DT_BF16, DT_F64, MODE_FUSED, WARM_MLP, rom_default_opts, rom_features, rom_mlp_create,
-               rom_mlp_free, rom_mlp_get_params, rom_mlp_param_count, rom_mlp_set_params, rom_mlp_set_scaling,
-               rom_mlp_train_step, rom_state_init)
+               rom_mlp_fit_scaling, rom_mlp_free, rom_mlp_get_params, rom_mlp_param_count, rom_mlp_set_params,
+               rom_mlp_train_epoch, rom_state_init, rom_warm_samples)
 
 WIDTH = 256
 
@@ -40,16 +43,20 @@ def generate(rb, paths, opts=None):
     o = opts if opts is not None else rom_default_opts(mode=MODE_FUSED, contraction=DT_F64)
     rom_state_init(rb.h, P, rb.mu.data_ptr(), rb.state.data_ptr(), rb.stream.cuda_stream)
     Fb = torch.from_numpy(np.ascontiguousarray(paths.reshape(P, K, 4).transpose(1, 0, 2))).to(dev)
-    Xs, Ys = [], []
     X = torch.empty(P, nf, dtype=torch.float32, device=dev)
+    r0 = torch.empty(P, n, dtype=torch.float64, device=dev)
+    Xs = torch.empty(P * K, nf, dtype=torch.float32, device=dev)
+    Ys = torch.empty(P * K, n, dtype=torch.float32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    s = rb.stream.cuda_stream
     for k in range(K):
-        rom_features(rb.h, P, Fb[k].data_ptr(), rb.state.data_ptr(), X.data_ptr(), rb.stream.cuda_stream)
-        r0 = rb.r().clone()
+        rom_features(rb.h, P, Fb[k].data_ptr(), rb.state.data_ptr(), X.data_ptr(), s)
+        r0.copy_(rb.r())
         rb.step(Fb[k], o)
-        ok = rb.status == 0
-        Xs.append(X[ok].clone())
-        Ys.append((rb.r() - r0)[ok].float())
-    return torch.cat(Xs), torch.cat(Ys)
+        rom_warm_samples(rb.h, P, rb.state.data_ptr(), X.data_ptr(), r0.data_ptr(), rb.status.data_ptr(),
+                         Xs.data_ptr(), Ys.data_ptr(), count.data_ptr(), s)
+    N = int(count.item())
+    return Xs[:N], Ys[:N]
 
 
 class WarmStart:
@@ -80,41 +87,30 @@ class WarmStart:
         return rom_mlp_get_params(self.h)
 
     def fit_scaling(self, X, Y):
-        xm = X.mean(0).cpu().numpy()
-        xs = X.std(0).cpu().numpy()
-        ym = Y.mean(0).cpu().numpy()
-        ys = Y.std(0).cpu().numpy()
-        xs = np.where(xs > 1e-12, xs, 1.0)
-        ys = np.where(ys > 1e-12, ys, 1.0)
-        rom_mlp_set_scaling(self.h, xm, xs, ym, ys)
+        rom_mlp_fit_scaling(self.h, X.shape[0], X.contiguous().data_ptr(), Y.contiguous().data_ptr(),
+                            torch.cuda.current_stream(X.device).cuda_stream)
 
     def train(self, X, Y, epochs=10, batch=1024, lr=1e-3, precision=DT_BF16, seed=0, stream=None, log=None):
-        """Minibatch Adam; returns the mean loss of each epoch."""
+        """Minibatch Adam with a cosine-decayed learning rate; the samples are
+        visited in a fresh seeded permutation each epoch.  Returns the mean
+        loss of each epoch."""
         s = stream if stream is not None else torch.cuda.current_stream(X.device)
-        g = torch.Generator(device=X.device)
-        g.manual_seed(seed)
+        g = np.random.Generator(np.random.PCG64(seed))
         N = X.shape[0]
-        loss = torch.zeros(1, dtype=torch.float32, device=X.device)
-        hist = []
         batch = min(batch, self.max_batch)
+        nb = N // batch
+        X, Y = X.contiguous(), Y.contiguous()
+        order = torch.empty(N, dtype=torch.int32, device=X.device)
+        sums = torch.zeros(epochs, dtype=torch.float32, device=X.device)
         for e in range(epochs):
-            perm = torch.randperm(N, generator=g, device=X.device)
-            tot = torch.zeros((), dtype=torch.float32, device=X.device)
-            nb = 0
-            # cosine decay of the learning rate over the epochs
+            with torch.cuda.stream(s):  # ordered after the previous epoch's reads of `order`
+                order.copy_(torch.from_numpy(g.permutation(N).astype(np.int32)))
             lr_e = lr * 0.5 * (1.0 + np.cos(np.pi * e / max(epochs, 1)))
-            for b0 in range(0, N - batch + 1, batch):
-                idx = perm[b0:b0 + batch]
-                xb = X[idx].contiguous()
-                yb = Y[idx].contiguous()
-                rom_mlp_train_step(self.h, batch, xb.data_ptr(), yb.data_ptr(), max(lr_e, 1e-6), precision,
-                                   loss.data_ptr(), s.cuda_stream)
-                tot += loss[0]
-                nb += 1
-            hist.append(float(tot) / max(nb, 1))
+            rom_mlp_train_epoch(self.h, N, X.data_ptr(), Y.data_ptr(), order.data_ptr(), batch, max(lr_e, 1e-6),
+                                precision, sums[e:e + 1].data_ptr(), s.cuda_stream)
             if log:
-                log(f"epoch {e}: loss {hist[-1]:.4e}")
-        return hist
+                log(f"epoch {e}: loss {float(sums[e]) / max(nb, 1):.4e}")
+        return [float(v) / max(nb, 1) for v in sums.cpu().numpy()]
 
     def opts(self, **kw):
         kw.setdefault('mode', MODE_FUSED)

@@ -171,3 +171,32 @@ def test_full_size_load_steps(gpu, full):
     C = [r['C'] for r in out]
     assert all(c > 0 for c in C) and all(b > a for a, b in zip(C, C[1:]))
     print(f"full size: macro iterations {[r['macro_iters'] for r in out]}, compliance {C}")
+
+
+def test_compliance_error_against_full_order_two_scale(gpu):
+    """The GPU two-scale loop with the n = 20 ROM against the full-order
+    two-scale reference of tests/golden/fe2_fom_4x2.json (Sec. 4.2): the
+    compliance error per loaded step equals the oracle ROM's (the GPU loop
+    reproduces the oracle's), and its mean lies in the paper's band."""
+    import json
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    ref = json.load(open(os.path.join(here, 'golden', 'fe2_fom_4x2.json')))
+    mesh = workloads.fe2_mesh(*ref['macro_mesh'])
+    loads = workloads.fe2_loads(ref['load_steps'], ref['peak_traction'])
+    rom_file = rom_path(ref['cell'])
+    orc = ofe2.run(ROM(rom_file), mesh, shape(ofe2.geometry(mesh)['Xg']), loads)
+    print("[gpu] fe2 compliance error", flush=True)
+    sol = Fe2Solver(rom_file, mesh, shape, mode=L.MODE_PHASED)
+    out = sol.run(loads)
+    sol.close()
+    Cr = np.array(ref['compliance'])
+    loaded = np.asarray(loads) > 0
+    C = np.array([o['C'] for o in out])
+    Co = np.array([o['C'] for o in orc])
+    assert all(o['status'] == 0 for o in out)
+    eps = np.abs(C[loaded] - Cr[loaded]) / np.abs(Cr[loaded])
+    eps_o = np.abs(Co[loaded] - Cr[loaded]) / np.abs(Cr[loaded])
+    print("eps_C per loaded step", np.round(eps, 4), "mean", eps.mean())
+    assert np.abs(eps - eps_o).max() < 1e-7
+    assert eps.mean() < 0.06

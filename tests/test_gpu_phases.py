@@ -1,11 +1,11 @@
-"""Two-phase cell on the GPU (the one-void cell lined with a stiff elastic
-coating; 57 of its 120 ECM points in the coating) against the oracle: the
-material of every ECM point chosen by its phase in each execution form.
-Fixed-iteration parity (the same Newton map on both sides) of the status,
-reduced coordinates, effective stress and tangent within 2e-9 (the
-conditioning of the two-phase tangent, see TOL) in the staged, fused and
-phased forms, fused and phased bit for bit; converged
-steps with load-step cutting within 1e-8 of the oracle's; shape
+"""Two-phase cells on the GPU against the oracle: the one-void cell lined
+with a stiff elastic coating (57 of its 120 ECM points in the coating) and
+the composite cell with 23 stiff elliptical inclusions scaled by one
+parameter (Sec. 4.1; mu = zeta), the material of every ECM point chosen by
+its phase in each execution form.  Fixed-iteration parity (the same Newton
+map on both sides) of the status, reduced coordinates, effective stress and
+tangent in the staged, fused and phased forms, fused and phased bit for bit;
+converged steps with load-step cutting within 1e-8 of the oracle's; shape
 sensitivities within 1e-9."""
 import numpy as np
 import pytest
@@ -20,28 +20,30 @@ from paper_2307_16894_amd.batch import RomBatch
 
 pytestmark = pytest.mark.gpu
 
-NAME = 'coatvoid_n20_m120'
+ROMS = {'coatvoid_n20_m120': workloads.one_void_mu, 'inclusions_n30_m250': workloads.inclusion_mu}
 P, K, IT = 8, 3, 4
-# The stiff coating raises the condition number of the reduced tangent about
-# twelvefold over the single-phase n = 20 ROM (190-350 against 21-29 at these
-# states), and rounding in each Newton solve grows with it: the single-phase
-# fixed-iteration bound of 1e-10 becomes about 1.2e-9 here.
-TOL = 2e-9
+# Where the fixed evaluations end converged (status 0) the FP64 bound holds.
+# Where they do not, the iterate is far from the solution (the stiff phase
+# slows Newton down: ||f|| = 0.16 after four evaluations at one point-step of
+# the coated cell) and the Newton map there amplifies rounding: the oracle's
+# own answer moves by 1.2e-10 when Fbar changes by one ulp.  GPU and oracle
+# eliminate in different orders at every evaluation, hence the wider bound.
+TOL, TOL_FREE = 1e-10, 2e-9
 
 
 def rel(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
 
 
-def inputs(seed):
-    return workloads.one_void_mu(seed, P), workloads.monotone_paths(seed, P, K, (0.02, 0.04))
+def inputs(name, seed):
+    return ROMS[name](seed, P), workloads.monotone_paths(seed, P, K, (0.02, 0.04))
 
 
-def run_gpu(mu, paths, **kw):
-    rb = RomBatch(rom_path(NAME), mu)
+def run_gpu(name, mu, paths, **kw):
+    rb = RomBatch(rom_path(name), mu)
     out = []
     for k in range(K):
-        print(f"[gpu] two-phase {kw} step {k}", flush=True)
+        print(f"[gpu] two-phase {name} {kw} step {k}", flush=True)
         st, it, _ = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), L.rom_default_opts(**kw))
         torch.cuda.synchronize()
         out.append(dict(st=st.cpu().numpy().copy(), r=rb.r(trial=True).cpu().numpy().copy(),
@@ -50,41 +52,47 @@ def run_gpu(mu, paths, **kw):
     return out
 
 
-def test_fixed_iteration_parity_every_form(gpu):
-    mu, paths = inputs(81)
-    rom = ROM(rom_path(NAME))
-    assert rom.phase.sum() == 57
+@pytest.mark.parametrize("name", sorted(ROMS))
+def test_fixed_iteration_parity_every_form(gpu, name):
+    mu, paths = inputs(name, 81)
+    rom = ROM(rom_path(name))
+    assert 0 < rom.phase.sum() < rom.m
+    if name.startswith('coatvoid'):
+        assert rom.phase.sum() == 57
     refs = [rom.run_path(mu[p], paths[p], max_iter=IT, fixed=True) for p in range(P)]
     res = {}
     for form, kw in (('staged', dict(mode=L.MODE_STAGED)), ('fused', dict(mode=L.MODE_FUSED)),
                      ('phased', dict(mode=L.MODE_PHASED, phased_evals=2))):
-        res[form] = out = run_gpu(mu, paths, fixed_iters=1, max_iter=IT, **kw)
+        res[form] = out = run_gpu(name, mu, paths, fixed_iters=1, max_iter=IT, **kw)
         for k in range(K):
             for p in range(P):
                 s = refs[p][k]
+                tol = TOL if s['status'] == 0 else TOL_FREE
                 assert out[k]['st'][p] == s['status'], (form, k, p)
-                assert rel(out[k]['r'][p], s['r']) < TOL, (form, k, p)
-                assert rel(out[k]['Pbar'][p], s['Pbar']) < TOL, (form, k, p)
-                assert rel(out[k]['Abar'][p], s['Abar'].reshape(-1)) < TOL, (form, k, p)
+                assert rel(out[k]['r'][p], s['r']) < tol, (form, k, p)
+                assert rel(out[k]['Pbar'][p], s['Pbar']) < tol, (form, k, p)
+                assert rel(out[k]['Abar'][p], s['Abar'].reshape(-1)) < tol, (form, k, p)
     for k in range(K):
         for key in ('st', 'r', 'Pbar', 'Abar'):
             assert np.array_equal(res['fused'][k][key], res['phased'][k][key]), (k, key)
 
 
-def test_converged_with_cutting(gpu):
-    mu, paths = inputs(82)
-    rom = ROM(rom_path(NAME))
+@pytest.mark.parametrize("name", sorted(ROMS))
+def test_converged_with_cutting(gpu, name):
+    mu, paths = inputs(name, 82)
+    rom = ROM(rom_path(name))
     refs = [rom.run_path(mu[p], paths[p], tol=1e-8, max_iter=15, max_substeps=2) for p in range(P)]
-    out = run_gpu(mu, paths, mode=L.MODE_FUSED, tol=1e-8, max_iter=15, max_substeps=2)
+    out = run_gpu(name, mu, paths, mode=L.MODE_FUSED, tol=1e-8, max_iter=15, max_substeps=2)
     for k in range(K):
         for p in range(P):
             assert out[k]['st'][p] == refs[p][k]['status'], (k, p)
             assert rel(out[k]['Pbar'][p], refs[p][k]['Pbar']) < 1e-8, (k, p)
 
 
-def test_shape_sensitivity(gpu):
-    mu, paths = inputs(83)
-    rom = ROM(rom_path(NAME))
+@pytest.mark.parametrize("name", sorted(ROMS))
+def test_shape_sensitivity(gpu, name):
+    mu, paths = inputs(name, 83)
+    rom = ROM(rom_path(name))
     ref = []
     for p in range(P):
         Finv, J = rom.transformation(mu[p])
@@ -96,7 +104,7 @@ def test_shape_sensitivity(gpu):
         s = rom.step(r, hist, paths[p, K - 1], Finv, J, max_iter=IT, fixed=True)
         ref.append(rom.shape_sensitivity(mu[p], s['r'], paths[p, K - 1], hist))
     ref = np.array(ref)
-    rb = RomBatch(rom_path(NAME), mu)
+    rb = RomBatch(rom_path(name), mu)
     for k in range(K):
         o = L.rom_default_opts(mode=L.MODE_FUSED, max_iter=IT, fixed_iters=1, commit=int(k < K - 1))
         rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(), o)

@@ -120,3 +120,36 @@ def test_macro_tangent_matches_central_differences():
                   for sg in (1, -1)]
         fd = (fp - fm) / (2 * h)
         assert np.abs(K[:, d] - fd).max() < 1e-6 * np.abs(K[:, d]).max(), d
+
+
+def test_rom_compliance_error_against_full_order_two_scale():
+    """The reduced model's two-scale compliance against the full-order
+    two-scale reference (tests/golden/fe2_fom_4x2.json, written by
+    make_fe2_fom.py from the oracle's FOM): eps_C,k = |C_k - C_k^ref| /
+    |C_k^ref| over the loaded steps (Sec. 4.2), whose mean the paper reports
+    between 0.4 % and 4.7 % for its ROMs (Table 1).  Here n = 20 modes and
+    120 cubature points."""
+    import json
+    import os
+    from oracle import fe2
+    from oracle.rom import ROM
+    import workloads
+    here = os.path.dirname(os.path.abspath(__file__))
+    ref = json.load(open(os.path.join(here, 'golden', 'fe2_fom_4x2.json')))
+    assert all(s == 0 for s in ref['status'])
+    mesh = workloads.fe2_mesh(*ref['macro_mesh'])
+    Xg = fe2.geometry(mesh)['Xg']
+    mu = workloads.fe2_shape(Xg[:, 0], Xg[:, 1])
+    loads = workloads.fe2_loads(ref['load_steps'], ref['peak_traction'])
+    assert np.allclose(loads, ref['loads'], rtol=0, atol=1e-15)
+    rom = ROM(os.path.join(os.path.dirname(here), 'roms', ref['cell'] + '.rom'))
+    out = fe2.run(rom, mesh, mu, loads)
+    assert all(o['status'] == 0 for o in out)
+    C = np.array([o['C'] for o in out])
+    Cr = np.array(ref['compliance'])
+    loaded = np.asarray(loads) > 0
+    eps = np.abs(C[loaded] - Cr[loaded]) / np.abs(Cr[loaded])
+    print("eps_C per loaded step", np.round(eps, 4), "mean", eps.mean())
+    assert eps.mean() < 0.06 and eps.max() < 0.15
+    # the unloaded end has no compliance on either side
+    assert np.all(C[~loaded] == 0.0) and np.all(Cr[~loaded] == 0.0)

@@ -92,3 +92,86 @@ def test_artifact_keeps_phases():
     assert one['mat2'] is None and not one['phase'].any()
     assert two['mat2'] == MAT2 and np.array_equal(two['phase'], ph)
     assert np.array_equal(two['G'], data['G'])
+
+
+# the composite cell with stiff elliptical inclusions (Sec. 4.1)
+def _small_inclusions():
+    inc = np.array([[0.3, 0.3, 0.12, 0.08, 0.4], [0.7, 0.65, 0.1, 0.1, 0.0], [0.28, 0.74, 0.09, 0.06, 2.0]])
+    return M.inclusion_cell(12, inc), inc
+
+
+def test_inclusion_layout_and_phases():
+    """The seeded layout holds the requested area fraction exactly, its
+    ellipses grown by the largest scale (1.2) stay apart and inside the cell;
+    the quadrature points' phases cover the inclusion area to the mesh
+    resolution; the point-in-ellipse test at known points."""
+    L = workloads.inclusion_layout(5)
+    assert L.shape == (23, 5) and abs(np.sum(np.pi * L[:, 2] * L[:, 3]) - 0.234) < 1e-12
+    t = np.linspace(0, 2 * np.pi, 400, endpoint=False)
+    pts = []
+    for cx, cy, a, b, th in L:
+        R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        B = np.array([cx, cy]) + (R @ np.stack([1.2 * a * np.cos(t), 1.2 * b * np.sin(t)])).T
+        assert B.min() > 0 and B.max() < 1
+        pts.append(B)
+    for i, B in enumerate(pts):
+        grown = L.copy()
+        grown[:, 2:4] *= 1.2
+        hit = M.in_ellipses(B, np.delete(grown, i, axis=0))
+        assert (hit < 0).all(), i
+    m = M.inclusion_cell(40, L)
+    assert abs(np.sum(m.qw * m.qphase) - 0.234) < 3e-3
+    inc = np.array([[0.5, 0.5, 0.2, 0.1, np.pi / 2]])  # long axis along y
+    assert list(M.in_ellipses(np.array([[0.5, 0.5], [0.5, 0.69], [0.69, 0.5], [0.5, 0.71]]), inc)) == [0, 0, -1, -1]
+
+
+def test_inclusion_transformation_scales_every_inclusion():
+    """kind 2: c = zeta - 1 with one mode; F_mu = I at zeta = 1, F_mu affine
+    in zeta, exactly zeta I on the elements whose nodes all lie in one
+    inclusion, zero displacement on the cell boundary, det F_mu > 0 over
+    zeta in [0.5, 1.2]; dc/dzeta = 1."""
+    m, inc = _small_inclusions()
+    ax = aux.AuxiliaryProblem(m, 2)
+    modes = ax.modes()
+    assert modes.shape[0] == aux.n_coeff(2) == 1
+    assert np.abs(modes[0][m.outer_boundary_nodes()]).max() == 0.0
+    gm = ax.gradients(modes)
+    assert np.array_equal(aux.transformation(gm, aux.coefficients(2, [1.0], 0.0)), np.broadcast_to(np.eye(2), (m.nq, 2, 2)))
+    F07 = aux.transformation(gm, aux.coefficients(2, [0.7], 0.0))
+    F12 = aux.transformation(gm, aux.coefficients(2, [1.2], 0.0))
+    assert np.abs((F07 - np.eye(2)) / -0.3 - (F12 - np.eye(2)) / 0.2).max() < 1e-12
+    idx = m.void_of_node[m.T]
+    inside = np.repeat((idx.min(axis=1) >= 0) & (idx.max(axis=1) == idx.min(axis=1)), 3)
+    assert inside.sum() > 0
+    assert np.abs(F07[inside] - 0.7 * np.eye(2)).max() < 1e-12
+    for z in (0.5, 1.2):
+        assert np.linalg.det(aux.transformation(gm, aux.coefficients(2, [z], 0.0))).min() > 0
+    h = 1e-6
+    fd = (aux.coefficients(2, [0.9 + h], 0.0) - aux.coefficients(2, [0.9 - h], 0.0)) / (2 * h)
+    assert np.allclose(aux.coefficient_jacobian(2, [0.9], 0.0), fd[:, None], atol=1e-9)
+
+
+def test_full_basis_inclusion_rom_reproduces_fom():
+    """With the full FE basis and the full rule, the reduced solve of the
+    inclusion cell (kind 2, two phases; one inclusion on a 6 x 6 mesh, so
+    that the dense full-basis reduced operators stay small) equals its
+    full-order solve."""
+    m = M.inclusion_cell(6, np.array([[0.45, 0.5, 0.22, 0.15, 0.3]]))
+    assert 0 < m.qphase.sum() < m.nq
+    sp = fem.PeriodicSpace(m)
+    ax = aux.AuxiliaryProblem(m, 2)
+    gm = ax.gradients(ax.modes())
+    Gop = fem.gradient_operator(m, sp.node_dof, sp.ndof).toarray().reshape(m.nq, 4, sp.ndof)
+    Gd = np.stack([g.reshape(m.nq, 4) for g in gm], axis=-1)
+    data = dict(n=sp.ndof, m=m.nq, c=1, kind=2, n_mu=1, mat=MAT, r0=0.0, void_area=0.0, cell_area=1.0,
+                w=m.qw.copy(), G=Gop, Gd=Gd, src=np.arange(m.nq), mat2=MAT2, phase=m.qphase)
+    rom = ROM(data=data)
+    mu = np.array([0.8])
+    Fmu = aux.transformation(gm, aux.coefficients(2, mu, 0.0))
+    mats = tuple(np.where(m.qphase == 1, b, a) for a, b in zip(MAT, MAT2))
+    ref = fom.solve_path(fem.Problem(m, sp, Fmu, mats), _path(), tol=1e-11, want_tangent=True)
+    out = rom.run_path(mu, _path(), tol=1e-11)
+    for k in range(len(_path())):
+        assert out[k]['status'] == 0
+        assert np.abs(out[k]['Pbar'] - ref.Pbar[k].reshape(-1)).max() < 1e-12
+        assert np.abs(out[k]['Abar'] - ref.Abar[k].reshape(4, 4)).max() < 1e-10 * np.abs(ref.Abar[k]).max()

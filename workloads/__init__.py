@@ -85,6 +85,65 @@ def four_void_training_mu(seed, count):
     return sobol_points(seed, count, lo, hi)
 
 
+def inclusion_layout(seed, count=23, fraction=0.234, grow=1.2, gap=0.012, aspect=(0.6, 1.0), spread=(0.75, 1.25),
+                     tries=20000):
+    """Random non-overlapping elliptical inclusions in the unit cell (the
+    composite cell of Sec. 4.1): `count` ellipses of total area `fraction`,
+    semi-axis ratio U[aspect], orientation U[0, pi), sizes spread by U[spread]
+    around the mean, placed one after another (largest first) at uniform
+    random centres, rejected unless the ellipse grown by `grow` (the largest
+    shape parameter) and a `gap` keeps clear of the cell boundary and of the
+    grown earlier ones.  Returns (count, 5): cx, cy, a, b, theta."""
+    g = rng(seed)
+    s = g.uniform(*spread, size=count)
+    kap = g.uniform(*aspect, size=count)          # b / a
+    th = g.uniform(0.0, np.pi, size=count)
+    area = fraction * s ** 2 / np.sum(s ** 2)      # pi a b each
+    a = np.sqrt(area / (np.pi * kap))
+    b = kap * a
+    order = np.argsort(-area)
+    t = np.linspace(0.0, 2.0 * np.pi, 96, endpoint=False)
+    placed = []
+
+    def boundary(c, aa, bb, tt, f):
+        R = np.array([[np.cos(tt), -np.sin(tt)], [np.sin(tt), np.cos(tt)]])
+        return c + (R @ np.stack([f * aa * np.cos(t), f * bb * np.sin(t)])).T
+
+    def inside(pts, c, aa, bb, tt, f):
+        R = np.array([[np.cos(tt), -np.sin(tt)], [np.sin(tt), np.cos(tt)]])
+        q = (pts - c) @ R
+        return (q[:, 0] / (f * aa)) ** 2 + (q[:, 1] / (f * bb)) ** 2 <= 1.0
+
+    for i in order:
+        for _ in range(tries):
+            c = g.uniform(0.0, 1.0, size=2)
+            f = grow * (1.0 + gap / max(a[i], 1e-12))
+            B = boundary(c, a[i], b[i], th[i], f)
+            if B.min() < gap or B.max() > 1.0 - gap:
+                continue
+            ok = True
+            for (cj, aj, bj, tj) in placed:
+                fj = grow * (1.0 + gap / aj)
+                if inside(B, cj, aj, bj, tj, fj).any() or inside(boundary(cj, aj, bj, tj, fj), c, a[i], b[i], th[i], f).any():
+                    ok = False
+                    break
+            if ok:
+                placed.append((c, a[i], b[i], th[i]))
+                break
+        else:
+            raise RuntimeError("inclusion layout: no room left")
+    return np.array([[c[0], c[1], aa, bb, tt] for c, aa, bb, tt in placed])
+
+
+def inclusion_mu(seed, P, lo=0.5, hi=1.2):
+    """Inclusion scale zeta ~ U[lo, hi] (Sec. 4.1: 0.5 to 1.2), one per point."""
+    return rng(seed).uniform(lo, hi, size=(P, 1))
+
+
+def inclusion_training_mu(seed, count, lo=0.5, hi=1.2):
+    return sobol_points(seed, count, [lo], [hi])
+
+
 def uneven_steps(seed, P, lo=5, hi=40):
     """Per-point step counts, uniform in [lo, hi]."""
     return rng(seed).integers(lo, hi + 1, size=P)
