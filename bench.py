@@ -38,7 +38,7 @@ WORKLOADS = {
                                             train_seed=1, timed=20, warm=20,
                                             variants=['fp64', 'fp64_phased', 'fp64_staged', 'fp32_phased', 'bf16',
                                                       'bf16_phased', 'fp64_mlp_phased', 'fp32_mlp_phased',
-                                                      'bf16_mlp', 'bf16_mlp_phased']),
+                                                      'bf16_mlp', 'bf16_mlp_phased', 'bf16_mlp_a64_phased']),
     # small case: n = 20, m = 120, 64 points, 10-step monotone paths
     'onevoid_n20_m120_P64_monotone10': dict(rom='onevoid_n20_m120', cell='onevoid', P=64, steps=10,
                                             path='monotone', rho=(0.02, 0.05), seed=0, train_points=4096,
@@ -49,7 +49,7 @@ WORKLOADS = {
     # 16384 points, 20-step load / unload paths: the reduced-precision contraction
     'fourvoid_n100_m1500_P16384_cyclic20': dict(rom='fourvoid_n100_m1500', cell='fourvoid', P=16384, steps=20,
                                                 path='cyclic', rho=(0.02, 0.08), seed=0, timed=3, warm=1,
-                                                variants=['fp64', 'fp32', 'bf16']),
+                                                variants=['fp64', 'fp32', 'bf16', 'bf16_a64']),
     # two phases: the n = 20 one-void cell lined with a stiff elastic coating,
     # 16384 points, 10-step monotone paths; beside it the single-phase cell
     # at the same size (the cost of a material per ECM point)
@@ -142,7 +142,7 @@ def gpu_run(w, steps, warmup, opts, rom_file):
             rb.step(Fb[k], opts)
             if record:  # device-side copies, no synchronisation
                 rec.append((rb.iters.clone(), (rb.status == 0).sum() + (rb.status == 3).sum(), rb.Pbar.clone(),
-                            rb.substeps().clone()))
+                            rb.substeps().clone(), rb.Abar.clone()))
             k += 1
         return rec
 
@@ -165,9 +165,10 @@ def gpu_run(w, steps, warmup, opts, rom_file):
     max_it = int(max(int(r[0].max()) for r in rec))
     Pbars = torch.stack([r[2] for r in rec]).cpu().numpy()
     subs = torch.stack([r[3] for r in rec]).cpu().numpy()
+    Abars = torch.stack([r[4] for r in rec]).cpu().numpy()
     rb.close()
     return dict(elapsed=t1 - t0, evals=evals, converged=conv, max_iter=max_it, kern_ms=kern_ms,
-                launches=launches, n=n, m=m, Pbar=Pbars, sub=subs, K=K)
+                launches=launches, n=n, m=m, Pbar=Pbars, Abar=Abars, sub=subs, K=K)
 
 
 def same_path(g, ref):
@@ -429,15 +430,16 @@ def flops_per_eval(n, m):
     return m * (8.0 * n * n + 80.0 * n + C_CM + C_W) + 2.0 / 3.0 * n ** 3 + 10.0 * n * n
 
 
-def stage_roofline(n, m, evals, point_steps, contraction, kern_ms):
+def stage_roofline(n, m, evals, point_steps, contraction, kern_ms, refine_evals=0):
     """Sum over the stages of max(flops / peak of the stage's unit, bytes /
     HBM bandwidth) for a run of `evals` point-evaluations, against its kernel
     time: the contraction of K and C (8 n^2 + 32 n per ECM point) at the peak
     of its precision, everything else at the FP64 peak; the history read and
     committed once per point-step (2 x 48 m bytes) is the algorithmic HBM
-    traffic."""
+    traffic.  `refine_evals` FP64 evaluations more (abar_f64) count whole at
+    the FP64 peak."""
     c_flops = evals * m * (8.0 * n * n + 32.0 * n)
-    r_flops = evals * flops_per_eval(n, m) - c_flops
+    r_flops = (evals + refine_evals) * flops_per_eval(n, m) - c_flops
     t_c = c_flops / (PEAK[contraction] * 1e12)
     t_r = r_flops / (PEAK['f64'] * 1e12)
     t_b = point_steps * 2 * 48.0 * m / (HBM_TBS * 1e12)
@@ -596,8 +598,8 @@ def run_forms(workload, variants, steps, warmup, log):
     res = {}
     n = m = 0
     for v in variants:
-        # <precision>[_mlp][_phased[K[eE]] | _staged]  (K: phased evaluations, E: early hand-over,
-        # -1 none; library defaults when left out)
+        # <precision>[_mlp][_a64][_phased[K[eE]] | _staged]  (a64: Abar from an FP64 evaluation at the
+        # returned state; K: phased evaluations, E: early hand-over, -1 none; library defaults when left out)
         vb = v
         dt = {'fp64': L.DT_F64, 'fp32': L.DT_F32, 'bf16': L.DT_BF16}[vb.split('_')[0]]
         last = vb.split('_')[-1]
@@ -613,6 +615,8 @@ def run_forms(workload, variants, steps, warmup, log):
             opts = L.rom_default_opts(mode=L.MODE_STAGED, contraction=dt)
         else:
             opts = L.rom_default_opts(contraction=dt, max_substeps=SUBSTEPS, **ph)
+        if '_a64' in vb:
+            opts.abar_f64 = 1
         log(f"[bench] {workload}: {v}")
         g = gpu_run(w, steps, warmup, opts, rom_file)
         n, m = g['n'], g['m']
@@ -627,7 +631,8 @@ def run_forms(workload, variants, steps, warmup, log):
                  converged_fraction=g['converged'] / (P * steps),
                  kernel_ms_per_step=g['kern_ms'] / steps)
         prec = {'fp64': 'f64', 'fp32': 'f32', 'bf16': 'bf16'}[v.split('_')[0]]
-        d['stage_roofline'] = stage_roofline(n, m, g['evals'], P * steps, prec, g['kern_ms'])
+        d['stage_roofline'] = stage_roofline(n, m, g['evals'], P * steps, prec, g['kern_ms'],
+                                             refine_evals=g['converged'] if '_a64' in v else 0)
         if ref is not None and v != 'fp64':
             # Deviation from plain FP64 over every timed point-step that followed the
             # same loading path (the same converged sub-steps since the start of the
@@ -647,6 +652,10 @@ def run_forms(workload, variants, steps, warmup, log):
             d['other_path_points'] = int((~same).any(axis=0).sum())
             d['max_rel_diff_Pbar_vs_fp64_other_path'] = float(dev[~same].max()) if (~same).any() else None
             d['max_rel_diff_Pbar_vs_fp64'] = float(dev.max())
+            adev = np.abs(g['Abar'] - ref['Abar']).max(axis=-1) / np.abs(ref['Abar']).max()
+            d['max_rel_diff_Abar_vs_fp64_same_path'] = float(adev[same].max()) if same.any() else None
+            d['median_rel_diff_Abar_vs_fp64_same_path'] = float(np.median(adev[same])) if same.any() else None
+            d['p999_rel_diff_Abar_vs_fp64_same_path'] = float(np.quantile(adev[same], 0.999)) if same.any() else None
         out_var[v] = d
 
     # head: the learned + reduced-precision form (else the reduced-precision

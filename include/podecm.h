@@ -103,7 +103,12 @@ typedef struct rom_opts {
                            the previous evaluation's (slow convergence: likely to fail the plain step and be cut
                            into sub-steps) go to a fused kernel on a side stream, beside the remaining phased
                            evaluations (0: 3; -1: none; used when below phased_evals) */
-  int32_t reserved[1];
+  int32_t abar_f64;     /* FP32 / BF16 contraction, fused and phased forms: 1 forms Abar (and the K*^-1 C kept for
+                           the shape sensitivities) at the converged points from one more evaluation at the
+                           returned state with the FP64 contraction, so that K* is the FP64 K there (Sec. 3.3);
+                           the final commit of those points follows that evaluation.  0 (default): K*, C and
+                           sum w|J| A of the last evaluation, in the contraction precision.  No effect with the
+                           FP64 contraction. */
   rom_mlp_handle mlp;   /* network for ROM_WARM_MLP (see below), else NULL */
   const int32_t* active;  /* device i32 [batch] or NULL: points with active[p] == 0 are skipped, their state
                              and outputs untouched (fused and phased forms) */
@@ -210,6 +215,25 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
  */
 int rom_homogenized_stress_tangent(rom_handle h, int32_t batch, const void* state_dev,
                                    double* Pbar_dev, double* Abar_dev, hipStream_t stream);
+
+/*
+ * rom_commit_trial -- commit the trial state left by the last rom_step on
+ * this state, a step made with opts.commit = 0 to Fbar_dev: where status_dev
+ * reports convergence (ROM_ST_CONVERGED or ROM_ST_FALLBACK) the trial r, the
+ * trial history and Fbar become the committed ones, the internal variables
+ * of the last converged load step from which the next one starts
+ * (Appendix A).  The state is then the one a step with opts.commit = 1 to the
+ * same Fbar from the same committed state leaves (the same Newton map from
+ * the same start).  The two-scale loop (Sec. 4.2) commits the RVE solves of
+ * its converged macro iteration this way instead of solving them again.
+ * Other points keep their committed state.  Asynchronous on `stream`.
+ *   Fbar_dev   : f64 [batch][4] device, the load of that step.
+ *   status_dev : i32 [batch] device, the statuses that step returned.
+ * The trial step must have been made without load-step cutting (cutting
+ * commits its converged sub-steps in place, so it runs with commit only).
+ */
+int rom_commit_trial(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_dev,
+                     const int32_t* status_dev, hipStream_t stream);
 
 /*
  * rom_step_noalloc -- for callers that cannot allocate device memory or

@@ -40,7 +40,8 @@ FIELD_FBAR_COMMITTED, FIELD_R_GUESS, FIELD_SUBSTEPS = 8, 9, 10
 NFIELDS = 11
 
 EXPORTS = ['rom_default_opts', 'rom_load', 'rom_load_file', 'rom_free', 'rom_info', 'rom_state_bytes',
-           'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_step_noalloc', 'rom_homogenized_stress_tangent', 'rom_shape_sensitivity',
+           'rom_state_offsets', 'rom_state_init', 'rom_step', 'rom_step_noalloc', 'rom_homogenized_stress_tangent',
+           'rom_commit_trial', 'rom_shape_sensitivity',
            'rom_timing_enable', 'rom_timing_read', 'rom_mlp_create', 'rom_mlp_free', 'rom_mlp_param_count',
            'rom_mlp_set_params', 'rom_mlp_get_params', 'rom_mlp_set_scaling', 'rom_mlp_forward',
            'rom_mlp_gradients', 'rom_mlp_train_step', 'rom_mlp_infer', 'rom_mlp_train_epoch', 'rom_mlp_fit_scaling',
@@ -68,7 +69,7 @@ class rom_opts(ctypes.Structure):
                 ('commit', ctypes.c_int32), ('contraction', ctypes.c_int32), ('mode', ctypes.c_int32),
                 ('warm_start', ctypes.c_int32), ('split', ctypes.c_int32), ('grid_per_cu', ctypes.c_int32),
                 ('max_substeps', ctypes.c_int32), ('phased_evals', ctypes.c_int32), ('phased_early', ctypes.c_int32),
-                ('reserved', ctypes.c_int32 * 1),
+                ('abar_f64', ctypes.c_int32),
                 ('mlp', ctypes.c_void_p), ('active', ctypes.c_void_p)]
 
 
@@ -113,6 +114,7 @@ def lib():
         L.rom_step_noalloc.argtypes = [vp, i32, vp, vp, ctypes.POINTER(rom_opts), vp, vp, vp, vp]
         L.rom_shape_sensitivity.argtypes = [vp, i32, vp, vp, vp, vp]
         L.rom_homogenized_stress_tangent.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.rom_commit_trial.argtypes = [vp, i32, vp, vp, vp, vp]
         L.rom_timing_enable.argtypes = [vp, ctypes.c_int]
         L.rom_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         fp = ctypes.POINTER(ctypes.c_float)
@@ -221,6 +223,10 @@ def rom_step_noalloc(h, batch, Fbar_ptr, state_ptr, opts, status_ptr, iters_ptr,
     return _check(lib().rom_step_noalloc(h, batch, Fbar_ptr, state_ptr,
                                          ctypes.byref(opts) if opts is not None else None,
                                          status_ptr, iters_ptr, res_ptr, stream), 'rom_step_noalloc')
+
+
+def rom_commit_trial(h, batch, Fbar_ptr, state_ptr, status_ptr, stream):
+    return _check(lib().rom_commit_trial(h, batch, Fbar_ptr, state_ptr, status_ptr, stream), 'rom_commit_trial')
 
 
 def rom_homogenized_stress_tangent(h, batch, state_ptr, Pbar_ptr, Abar_ptr, stream):

@@ -7,7 +7,8 @@ the method happens here.
 import torch
 
 from . import (FIELD_ABAR, FIELD_FBAR_COMMITTED, FIELD_H_COMMITTED, FIELD_H_TRIAL, FIELD_MU_OK, FIELD_PBAR, FIELD_R_COMMITTED,
-               FIELD_R_TRIAL, FIELD_SUBSTEPS, FIELD_TRANSFORM, rom_default_opts, rom_free, rom_homogenized_stress_tangent,
+               FIELD_R_TRIAL, FIELD_SUBSTEPS, FIELD_TRANSFORM, rom_commit_trial, rom_default_opts, rom_free,
+               rom_homogenized_stress_tangent,
                rom_info, rom_load_file, rom_shape_sensitivity, rom_state_bytes, rom_state_init, rom_state_offsets,
                rom_step)
 
@@ -54,6 +55,14 @@ class RomBatch:
                                        self.Abar.data_ptr(), self.stream.cuda_stream)
         self._keep = Fb  # keep alive until the stream has consumed it
         return self.status, self.iters, self.resnorm
+
+    def commit_trial(self, Fbar):
+        """Commit the trial state of the last step (made with commit = 0 to
+        the same Fbar) at the points its status reports converged."""
+        Fb = torch.as_tensor(Fbar, dtype=torch.float64, device=self.device).reshape(self.P, 4).contiguous()
+        rom_commit_trial(self.h, self.P, Fb.data_ptr(), self.state.data_ptr(), self.status.data_ptr(),
+                         self.stream.cuda_stream)
+        self._keep_c = Fb
 
     def shape_sensitivity(self, Fbar):
         """dPbar/dmu (P, 4, n_mu) at the returned state of the last step, which

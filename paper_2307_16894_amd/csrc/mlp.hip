@@ -24,6 +24,8 @@ struct rom_mlp {
   int64_t nparam;          // unpadded count (host layout)
   float* P;                // [npad] FP32 master (padded)
   uint16_t* Pb;            // [npad] BF16 copy
+  uint16_t* WT;            // [npad] BF16 weights transposed per layer ([N][K] at off_w), for the fused inference
+  int wt_stale;            // WT predates the last change of Pb
   float* Mo;               // [npad] Adam first moment
   float* Vo;               // [npad] Adam second moment
   float* G;                // [npad] gradient
@@ -328,6 +330,88 @@ __global__ void k_adam(long count, float* __restrict__ P, uint16_t* __restrict__
   Pb[i] = bf16_bits(p);
 }
 
+// Fused BF16 inference (padded input and hidden widths up to MI_KMAX): one
+// workgroup per MI_ROWS batch rows runs the four layers with the layer inputs
+// in LDS as BF16.  Per output tile it issues the layer-by-layer path's MFMA
+// with the same operands in the same lanes and the same inner-index order
+// (k = k0 + 8 g + t), then adds the bias, applies SiLU and rounds to BF16 as
+// that path's kernels do: the predictions are the same bit for bit.  The
+// weights come from the transposed copy WT, so a lane's eight inner indices
+// are one 16-byte load.
+constexpr int MI_ROWS = 16, MI_KMAX = 256, MI_LDA = MI_KMAX + 8;  // LDS row stride: 16 bytes of padding
+
+struct MlpLayout {
+  int K[4], N[4];
+  long off_w[4], off_b[4];
+};
+
+__global__ __launch_bounds__(256) void k_mlp_infer(int B, int n_in, int n_out, MlpLayout d,
+                                                   const float* __restrict__ X, const float* __restrict__ xm,
+                                                   const float* __restrict__ xs, const uint16_t* __restrict__ WT,
+                                                   const float* __restrict__ P, const float* __restrict__ ym,
+                                                   const float* __restrict__ ys, float* __restrict__ Y) {
+  __shared__ __attribute__((aligned(16))) uint16_t act[2][MI_ROWS * MI_LDA];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int row0 = blockIdx.x * MI_ROWS;
+  // scaled input x_hat = (x - mean) / std, zero padded
+  for (int i = tid; i < MI_ROWS * d.K[0]; i += 256) {
+    const int r = i / d.K[0], k = i - r * d.K[0], row = row0 + r;
+    const float v = (row < B && k < n_in) ? (X[(long)row * n_in + k] - xm[k]) / xs[k] : 0.f;
+    act[0][r * MI_LDA + k] = bf16_bits(v);
+  }
+  __syncthreads();
+  for (int l = 0; l < 4; ++l) {
+    const int K = d.K[l], N = d.N[l], NT = N / 16;
+    const uint16_t* Ain = act[l & 1];
+    uint16_t* Aout = act[(l + 1) & 1];
+    const uint16_t* W = WT + d.off_w[l];
+    const float* bias = P + d.off_b[l];
+    f4 acc[MI_KMAX / 64];
+#pragma unroll
+    for (int u = 0; u < MI_KMAX / 64; ++u) acc[u] = (f4){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const bf8 a = *reinterpret_cast<const bf8*>(Ain + c * MI_LDA + k0 + 8 * g);
+#pragma unroll
+      for (int u = 0; u < MI_KMAX / 64; ++u) {
+        const int t = wave + 4 * u;  // column tiles dealt to the waves in turn
+        if (t < NT) {
+          const bf8 b = *reinterpret_cast<const bf8*>(W + (long)(16 * t + c) * K + k0 + 8 * g);
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[u], 0, 0, 0);
+        }
+      }
+    }
+    // accumulator layout: row 4 g + r, column c of the tile
+#pragma unroll
+    for (int u = 0; u < MI_KMAX / 64; ++u) {
+      const int t = wave + 4 * u;
+      if (t >= NT) continue;
+      const int n = 16 * t + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = 4 * g + r;
+        const float z = acc[u][r] + bias[n];
+        if (l < 3) {
+          Aout[rr * MI_LDA + n] = bf16_bits(silu_f(z));
+        } else if (n < n_out && row0 + rr < B) {
+          Y[(long)(row0 + rr) * n_out + n] = ym[n] + ys[n] * z;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// WT[l][n][k] = Pb[l][k][n]
+__global__ void k_transpose_w(MlpLayout d, const uint16_t* __restrict__ Pb, uint16_t* __restrict__ WT) {
+  const int l = blockIdx.y;
+  const long count = (long)d.K[l] * d.N[l];
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int n = (int)(i / d.K[l]), k = (int)(i - (long)n * d.K[l]);
+  WT[d.off_w[l] + i] = Pb[d.off_w[l] + (long)k * d.N[l] + n];
+}
+
 __global__ void k_to_bf16(long count, const float* __restrict__ P, uint16_t* __restrict__ Pb) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i < count) Pb[i] = bf16_bits(P[i]);
@@ -375,7 +459,7 @@ struct DeviceGuard {
 
 void mlp_release(rom_mlp* m) {
   if (!m) return;
-  void* bufs[] = {m->P, m->Pb, m->Mo, m->Vo, m->G, m->xm, m->xs, m->ym, m->ys, m->dZ, m->dA, m->loss_part,
+  void* bufs[] = {m->P, m->Pb, m->WT, m->Mo, m->Vo, m->G, m->xm, m->xs, m->ym, m->ys, m->dZ, m->dA, m->loss_part,
                   m->kpart, m->cpart, m->spart, m->loss_one};
   for (void* b : bufs) (void)hipFree(b);
   for (int l = 0; l < 4; ++l) {
@@ -430,6 +514,7 @@ int mlp_train_step(rom_mlp* m, int B, const float* X, const float* Y, const int*
   m->t += 1;
   const float c1 = 1.0f - powf(0.9f, (float)m->t), c2 = 1.0f - powf(0.999f, (float)m->t);
   k_adam<<<nblk(m->npad), 256, 0, s>>>(m->npad, m->P, m->Pb, m->Mo, m->Vo, m->G, lr, c1, c2);
+  m->wt_stale = 1;
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 
@@ -470,6 +555,8 @@ int rom_mlp_create(int32_t n_in, int32_t width, int32_t n_out, int32_t max_batch
   };
   al((void**)&m->P, 4 * o);
   al((void**)&m->Pb, 2 * o);
+  al((void**)&m->WT, 2 * o);
+  m->wt_stale = 1;
   al((void**)&m->Mo, 4 * o);
   al((void**)&m->Vo, 4 * o);
   al((void**)&m->G, 4 * o);
@@ -530,6 +617,7 @@ int rom_mlp_set_params(rom_mlp_handle m, const float* host, int64_t count) {
   }
   if (hipMemcpy(m->P, pad.data(), 4 * m->npad, hipMemcpyHostToDevice) != hipSuccess) return ROM_EHIP;
   k_to_bf16<<<nblk(m->npad), 256>>>(m->npad, m->P, m->Pb);
+  m->wt_stale = 1;
   if (hipMemset(m->Mo, 0, 4 * m->npad) != hipSuccess || hipMemset(m->Vo, 0, 4 * m->npad) != hipSuccess)
     return ROM_EHIP;
   m->t = 0;
@@ -571,6 +659,24 @@ int rom_mlp_forward(rom_mlp_handle m, int32_t B, const float* X, float* Y, int32
   if (B == 0) return ROM_OK;
   if (!X || !Y) return ROM_EINVAL;
   DeviceGuard guard(m->device);
+  if (prec == ROM_DT_BF16 && m->K[0] <= MI_KMAX && m->width <= MI_KMAX && m->N[3] <= MI_KMAX) {
+    MlpLayout d;
+    for (int l = 0; l < 4; ++l) {
+      d.K[l] = m->K[l];
+      d.N[l] = m->N[l];
+      d.off_w[l] = m->off_w[l];
+      d.off_b[l] = m->off_b[l];
+    }
+    if (m->wt_stale) {
+      long most = 0;
+      for (int l = 0; l < 4; ++l) most = most > (long)d.K[l] * d.N[l] ? most : (long)d.K[l] * d.N[l];
+      k_transpose_w<<<dim3(nblk(most), 4), 256, 0, s>>>(d, m->Pb, m->WT);
+      m->wt_stale = 0;
+    }
+    k_mlp_infer<<<(B + MI_ROWS - 1) / MI_ROWS, 256, 0, s>>>(B, m->n_in, m->n_out, d, X, m->xm, m->xs, m->WT, m->P,
+                                                           m->ym, m->ys, Y);
+    return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+  }
   k_scale_in<<<nblk((long)B * m->K[0]), 256, 0, s>>>(B, m->n_in, m->K[0], X, nullptr, m->xm, m->xs, m->A32[0],
                                                      m->A16[0]);
   int rc = mlp_forward_scaled(m, B, prec, s);

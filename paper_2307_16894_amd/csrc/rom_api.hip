@@ -117,6 +117,7 @@ int rom_default_opts(rom_opts* o) {
   o->max_substeps = 0;
   o->phased_evals = 0;
   o->phased_early = 0;
+  o->abar_f64 = 0;
   o->mlp = nullptr;
   o->active = nullptr;
   return ROM_OK;
@@ -312,6 +313,7 @@ int rom_step(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_de
     rom_default_opts(&o);
   if (o.max_iter < 1 || o.max_iter > 1000 || !(o.tol >= 0.0)) return ROM_EINVAL;
   if (o.contraction < ROM_DT_F64 || o.contraction > ROM_DT_BF16) return ROM_EINVAL;
+  if (o.abar_f64 != 0 && o.abar_f64 != 1) return ROM_EINVAL;
   if (o.warm_start != ROM_WARM_PREV && o.warm_start != ROM_WARM_MLP) return ROM_EINVAL;
   if (o.warm_start == ROM_WARM_MLP && !o.mlp) return ROM_EINVAL;
   DeviceGuard guard(h->device);
@@ -346,6 +348,7 @@ int rom_step_noalloc(rom_handle h, int32_t batch, const double* Fbar_dev, void* 
     rom_default_opts(&o);
   if (o.max_iter < 1 || o.max_iter > 1000 || !(o.tol >= 0.0)) return ROM_EINVAL;
   if (o.contraction < ROM_DT_F64 || o.contraction > ROM_DT_BF16) return ROM_EINVAL;
+  if (o.abar_f64 != 0 && o.abar_f64 != 1) return ROM_EINVAL;
   if (o.warm_start != ROM_WARM_PREV && o.warm_start != ROM_WARM_MLP) return ROM_EINVAL;
   if (o.warm_start == ROM_WARM_MLP && !o.mlp) return ROM_EINVAL;
   if (o.grid_per_cu < 0 || o.grid_per_cu > 64) return ROM_EINVAL;
@@ -385,6 +388,15 @@ int rom_warm_samples(rom_handle h, int32_t batch, const void* state_dev, const f
   DeviceGuard guard(h->device);
   return rom_launch_warm_samples(h, batch, state_dev, X_feat_dev, r_before_dev, status_dev, X_out_dev, Y_out_dev,
                                  count_dev, stream);
+}
+
+int rom_commit_trial(rom_handle h, int32_t batch, const double* Fbar_dev, void* state_dev,
+                     const int32_t* status_dev, hipStream_t stream) {
+  if (!h || batch < 0) return ROM_EINVAL;
+  if (batch == 0) return ROM_OK;
+  if (!Fbar_dev || !state_dev || !status_dev) return ROM_EINVAL;
+  DeviceGuard guard(h->device);
+  return rom_launch_commit_trial(h, batch, Fbar_dev, state_dev, status_dev, stream);
 }
 
 int rom_path_gather(int32_t batch, const double* paths, int32_t max_steps, const int32_t* nsteps,

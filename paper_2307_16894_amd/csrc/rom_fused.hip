@@ -1,5 +1,6 @@
 // Dispatcher of the fused online solve: argument set-up, the learned warm
 // start, the work list of the persistent form, and the per-tile-count launch.
+#include <float.h>
 #include <string.h>
 
 #include "rom_fused.h"
@@ -140,6 +141,34 @@ int rom_phased_cs(int T, const FusedArgs& a, int prec, int split, int P, hipStre
   }
 }
 
+// opts.abar_f64 with a reduced-precision contraction: the step defers the
+// final commit of its converged points, and FP64 launches then evaluate each
+// of them once more at its trial r (from the same committed history and
+// Fbar), form Pbar, Abar and K*^-1 C from that FP64 contraction and
+// elimination, and commit: the phased kinematics, material and contraction
+// kernels over the list of those points where the ROM has them (n <= 75),
+// else the FP64 fused kernel over the batch (points not converged return).
+bool rom_refines_abar(const rom_opts& o) { return o.abar_f64 && o.contraction != ROM_DT_F64; }
+
+int rom_refine_abar(const rom_model* h, const FusedArgs& a, int split, int P, void* state, hipStream_t s) {
+  const int T = rom_fused_tiles(h->n);
+  if (h->npad <= ROM_PHASED_NPAD) return rom_refine_abar_phased(h, a, T <= 5 ? split : 1, P, state, s);
+  FusedArgs r = a;
+  r.refine = 1;
+  r.defer = 0;
+  r.resume = 0;
+  r.max_iter = 1;
+  r.fixed = 0;
+  r.tol = DBL_MAX;  // the one evaluation stops as converged (a finite ||f||)
+  r.max_sub = 0;
+  r.dr = nullptr;
+  r.list = nullptr;
+  r.nlist = nullptr;
+  r.counter = nullptr;
+  // the FP64 accumulators of the point split fit up to five column tiles
+  return rom_fused_launch(T, r, ROM_DT_F64, T <= 5 ? split : 1, 0, P, s);
+}
+
 int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
                           int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
   FusedArgs a;
@@ -159,8 +188,11 @@ int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, 
     grid = o.grid_per_cu * h->ncu;
     if (hipGetLastError() != hipSuccess) return ROM_EHIP;
   }
+  const bool refine = rom_refines_abar(o);
+  a.defer = refine ? 1 : 0;
   if (rom_timing_mark(h, 0, s) != ROM_OK) return ROM_EHIP;
   rc = rom_fused_launch(rom_fused_tiles(h->n), a, o.contraction, split, grid, P, s);
+  if (rc == ROM_OK && refine) rc = rom_refine_abar(h, a, split, P, state, s);
   if (rom_timing_mark(h, 1, s) != ROM_OK) return ROM_EHIP;
   return rc;
 }
@@ -186,5 +218,9 @@ int rom_launch_step_noalloc(rom_model* h, int P, const double* Fbar, void* state
   a.nlist = cnt;
   a.counter = cnt + 1;
   const int grid = (o.grid_per_cu > 0 ? o.grid_per_cu : 2) * h->ncu;
-  return rom_fused_launch(rom_fused_tiles(h->n), a, o.contraction, split, grid, P, s);
+  const bool refine = rom_refines_abar(o);
+  a.defer = refine ? 1 : 0;
+  rc = rom_fused_launch(rom_fused_tiles(h->n), a, o.contraction, split, grid, P, s);
+  if (rc == ROM_OK && refine) rc = rom_refine_abar(h, a, split, P, state, s);  // work lists in the state: no scratch
+  return rc;
 }

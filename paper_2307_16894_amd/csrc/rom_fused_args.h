@@ -52,6 +52,9 @@ struct FusedArgs {
   int* early;        // points handed to the fused kernel on the side stream
   int* cearly;       // their count (device)
   int resume;        // fused kernel: start each point from phi / phd (evaluation phi[0] of attempt 0)
+  int defer;         // converged points leave their final commit to a refining launch
+  int refine;        // fused kernel: one evaluation at the trial r of each point the step reported converged,
+                     // its effective quantities, and the commit (statuses, counts and norms kept)
 };
 
 // per tile-count entry points (rom_fused_t<T>.hip): launch with the given
@@ -75,3 +78,6 @@ int rom_fused_prepare(rom_model* h, int P, const double* Fbar, void* state, cons
                       int32_t* it_out, double* res_out, hipStream_t s, FusedArgs& a, int& split);
 int rom_fused_launch(int T, const FusedArgs& a, int prec, int split, int grid, int P, hipStream_t s);
 int rom_phased_cs(int T, const FusedArgs& a, int prec, int split, int P, hipStream_t s);
+bool rom_refines_abar(const rom_opts& o);
+int rom_refine_abar(const rom_model* h, const FusedArgs& a, int split, int P, void* state, hipStream_t s);
+int rom_refine_abar_phased(const rom_model* h, const FusedArgs& a, int split, int P, void* state, hipStream_t s);

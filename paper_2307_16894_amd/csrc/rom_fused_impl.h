@@ -299,10 +299,7 @@ __device__ __forceinline__ void make_ops(Ops<T>& O, double (&fpart)[T], bool do_
   if constexpr (PREC != PREC_F64) {
     if (do_f) {
 #pragma unroll
-      for (int J = 0; J < T; ++J) {
-        const int col = 16 * J + c_col;
-        fpart[J] = fma(col < n ? L.a[J] : 0.0, xw, fpart[J]);
-      }
+      for (int J = 0; J < T; ++J) fpart[J] = fma(L.a[J], xw, fpart[J]);  // columns n and above: never read
     }
   }
 }
@@ -422,11 +419,12 @@ __device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T],
       const int col = 16 * J + c_col, dc = col - pd.nb;
       const bool ecol = dc >= 1 && dc <= 4, wcol = dc == 0;
       const int ek = (dc - 1) >> 1, el = (dc - 1) & 1;
+      // f partials of every lane (those of the columns n and above are never read)
       if (do_f) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) fpart[J] = fma(col < n ? cur.g[h][b] : 0.0, Wv[h][b], fpart[J]);
+          for (int b = 0; b < 4; ++b) fpart[J] = fma(cur.g[h][b], Wv[h][b], fpart[J]);
       }
       bf8 Bop;
 #pragma unroll
@@ -869,14 +867,17 @@ __device__ __forceinline__ void finish_point(const FusedArgs& a, int p, const do
                                              int status, bool fell_back, int iters, double rn, unsigned int sub,
                                              int tid) {
   const int n = a.n, m = a.m;
-  for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i];
-  if (tid == 0) {
-    a.st_out[p] = (status == ROM_ST_CONVERGED && fell_back) ? ROM_ST_FALLBACK : status;
-    a.it_out[p] = iters;
-    a.res_out[p] = rn;
-    a.sub[p] = sub;
+  if (!a.refine) {
+    for (int i = tid; i < n; i += 256) a.rt[(size_t)p * n + i] = sR[i];
+    if (tid == 0) {
+      a.st_out[p] = (status == ROM_ST_CONVERGED && fell_back) ? ROM_ST_FALLBACK : status;
+      a.it_out[p] = iters;
+      a.res_out[p] = rn;
+      a.sub[p] = sub;
+    }
   }
-  if (a.commit && status == ROM_ST_CONVERGED) {
+  // a refining launch commits every point it evaluates: the step judged them converged
+  if (a.commit && (a.refine || (!a.defer && status == ROM_ST_CONVERGED))) {
     if (tid < 4) a.fbc[4 * (size_t)p + tid] = Fb[tid];
     for (int i = tid; i < n; i += 256) a.rc[(size_t)p * n + i] = sR[i];
     double* hcw = a.hc + (size_t)p * 6 * m;
@@ -931,6 +932,10 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = a.n, m = a.m;
   if (a.active && !a.active[p]) return;  // skipped: state and outputs untouched
+  if (a.refine) {
+    const int s0 = a.st_out[p];
+    if (s0 != ROM_ST_CONVERGED && s0 != ROM_ST_FALLBACK) return;
+  }
   if (!a.muok[p]) {
     bad_mu_outputs(a, p, tid);
     return;
@@ -949,7 +954,7 @@ __device__ void solve_point(const FusedArgs& a, const int p, double* smem) {
   for (int i = tid; i < NPAD; i += 256) {
     double v = 0.0;
     if (i < n) {
-      if (it0 > 0) {
+      if (it0 > 0 || a.refine) {
         v = a.rt[(size_t)p * n + i];
       } else {
         v = a.rc[(size_t)p * n + i];
@@ -1175,6 +1180,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cs_waves<T,
     }
   }
   const double rn = assemble<T, PREC, SPLIT>(E, sK, sC, sX, n, tid, lane, wave, k_row, c_col);
+  if (a.refine) {
+    // effective quantities of a point the step reported converged, at its
+    // returned state, and the commit the step left to this launch
+    gauss_jordan<T>(sK, n, sL, sPv, sOrd, sPiv);
+    write_effective<T>(a, p, sK, sC, sOrd, n, tid);
+    const double Fb[4] = {a.Fbar[4 * (size_t)p], a.Fbar[4 * (size_t)p + 1], a.Fbar[4 * (size_t)p + 2],
+                          a.Fbar[4 * (size_t)p + 3]};
+    finish_point(a, p, sR, Fb, ROM_ST_CONVERGED, false, 0, rn, 0u, tid);
+    return;
+  }
   int status;
   const bool stop = eval_status(a, it, rn, status);
   if (it == 0) rn0 = rn;

@@ -152,7 +152,48 @@ int launch_mat(const FusedArgs& a, int prec, int P, int m, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 
+// the points a step reported converged (the refining launches of abar_f64)
+__global__ void k_list_converged(int P, const int* __restrict__ st, const int* __restrict__ active,
+                                 int* __restrict__ list, int* __restrict__ cnt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  if (active && !active[p]) return;
+  const int v = st[p];
+  if (v == ROM_ST_CONVERGED || v == ROM_ST_FALLBACK) list[atomicAdd(cnt, 1)] = p;
+}
+
 }  // namespace
+
+// abar_f64 after a reduced-precision step, as phased launches: the converged
+// points listed, then one FP64 kinematics, material and contraction launch
+// over them (the contraction kernel's refining branch eliminates, writes the
+// effective quantities and commits).
+int rom_refine_abar_phased(const rom_model* h, const FusedArgs& a, int split, int P, void* state, hipStream_t s) {
+  const StateLayout L = rom_state_layout(h, P);
+  int* cnt = field<int>(state, L, F_COUNT) + 8;
+  int* list = field<int>(state, L, F_LIST);
+  FusedArgs b = a;
+  b.refine = 1;
+  b.defer = 0;
+  b.resume = 0;
+  b.dr = nullptr;
+  b.rec = field<double>(state, L, F_REC);
+  b.hkin = field<double>(state, L, F_HKIN);
+  b.phi = field<int>(state, L, F_PHI);
+  b.phd = field<double>(state, L, F_PHD);
+  b.lin = list;
+  b.cin = cnt;
+  // the material kernel clears the count of the list a contraction launch
+  // fills next: give it the second list's slot (the refining contraction
+  // lists nothing)
+  b.lout = field<int>(state, L, F_LIST2);
+  b.cout = cnt + 1;
+  k_zero6<<<1, 64, 0, s>>>(cnt);
+  k_list_converged<<<(P + 255) / 256, 256, 0, s>>>(P, a.st_out, a.active, list, cnt);
+  if (hipGetLastError() != hipSuccess) return ROM_EHIP;
+  const int rc = launch_mat(b, ROM_DT_F64, P, h->m, s);
+  return rc == ROM_OK ? rom_phased_cs(rom_fused_tiles(h->n), b, ROM_DT_F64, split, P, s) : rc;
+}
 
 int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
                            int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
@@ -190,6 +231,8 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
   a.hand = hand;
   a.chand = cnt + 2;
   const int T = rom_fused_tiles(h->n);
+  const bool refine = rom_refines_abar(o);
+  a.defer = refine ? 1 : 0;
   if (rom_timing_mark(h, 0, s) != ROM_OK) return ROM_EHIP;
   // from here every exit goes through the join and the stop mark below
   k_zero6<<<1, 64, 0, s>>>(cnt);
@@ -247,6 +290,7 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
       if (rc == ROM_OK) rc = ROM_EHIP;
     }
   }
+  if (rc == ROM_OK && refine) rc = rom_refine_abar(h, a, split, P, state, s);
   if (rom_timing_mark(h, 1, s) != ROM_OK && rc == ROM_OK) rc = ROM_EHIP;
   return rc;
 }

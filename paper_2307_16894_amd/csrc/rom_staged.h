@@ -11,3 +11,5 @@ int rom_launch_path_gather(int P, const double* paths, int max_steps, const int*
 int rom_launch_path_advance(int P, const int* active, int* step, hipStream_t s);
 int rom_launch_warm_samples(const rom_model* h, int P, const void* state, const float* X_feat, const double* r_before,
                             const int* status, float* X_out, float* Y_out, int* count, hipStream_t s);
+int rom_launch_commit_trial(const rom_model* h, int P, const double* Fbar, void* state, const int* status,
+                            hipStream_t s);

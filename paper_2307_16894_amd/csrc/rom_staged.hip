@@ -567,22 +567,40 @@ __global__ __launch_bounds__(256) void k_finish(int n, int m, int commit, const 
   for (int i = tid; i < 6 * m; i += 256) hc[(size_t)p * 6 * m + i] = ht[(size_t)p * 6 * m + i];
 }
 
+// Commit of a trial step's state at its converged points (status converged,
+// or converged after the warm start fell back): r, history and Fbar, the
+// copies the step itself makes with commit set.  One workgroup per point.
+__global__ __launch_bounds__(256) void k_commit_trial(int n, int m, const double* __restrict__ Fbar,
+                                                      const int* __restrict__ status, double* __restrict__ fbc,
+                                                      const double* __restrict__ rt, double* __restrict__ rc,
+                                                      const double* __restrict__ ht, double* __restrict__ hc) {
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int st = status[p];
+  if (st != ROM_ST_CONVERGED && st != ROM_ST_FALLBACK) return;
+  if (tid < 4) fbc[4 * (size_t)p + tid] = Fbar[4 * (size_t)p + tid];
+  for (int i = tid; i < n; i += 256) rc[(size_t)p * n + i] = rt[(size_t)p * n + i];
+  for (int i = tid; i < 6 * m; i += 256) hc[(size_t)p * 6 * m + i] = ht[(size_t)p * 6 * m + i];
+}
+
 // Inputs of the warm-start network for the step to Fbar: mu, Fbar - Fbar_committed,
 // r_committed and eight statistics of the committed plastic state weighted by
 // w_q |det F_mu|: mean / max / standard deviation of xi, yielded fraction,
 // mean of F^pl - I.  One block per point.
-__global__ __launch_bounds__(256) void k_features(int n, int m, int n_mu, const double* __restrict__ mu,
+// One wave per point (four points per workgroup): the lanes walk the ECM
+// points with stride 64 and the nine sums are reduced across the wave.
+__global__ __launch_bounds__(256) void k_features(int P, int n, int m, int n_mu, const double* __restrict__ mu,
                                                   const double* __restrict__ Fbar, const double* __restrict__ fbc,
                                                   const double* __restrict__ rc, const double* __restrict__ hc,
                                                   const double* __restrict__ tmu, float* __restrict__ X) {
-  const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lane = threadIdx.x & 63, p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= P) return;
   const int nf = n_mu + 4 + n + 8;
   float* x = X + (size_t)p * nf;
-  __shared__ double red[4][10];
   double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // sum w, w xi, w xi^2, w [xi>0], w (Fp - I) (4), max xi
   const double* h = hc + (size_t)p * 6 * m;
   const double* t = tmu + (size_t)p * 5 * m;
-  for (int q = tid; q < m; q += 256) {
+  for (int q = lane; q < m; q += 64) {
     const double w = t[4 * m + q], xi = h[5 * m + q];
     s[0] += w;
     s[1] += w * xi;
@@ -595,32 +613,23 @@ __global__ __launch_bounds__(256) void k_features(int n, int m, int n_mu, const 
     s[8] = fmax(s[8], xi);
   }
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    double v = s[k];
+  for (int k = 0; k < 9; ++k)
     for (int o = 32; o > 0; o >>= 1) {
-      const double u = __shfl_xor(v, o);
-      v = (k == 8) ? fmax(v, u) : v + u;
+      const double u = __shfl_xor(s[k], o);
+      s[k] = (k == 8) ? fmax(s[k], u) : s[k] + u;
     }
-    if (lane == 0) red[wave][k] = v;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double tot[9];
-    for (int k = 0; k < 9; ++k) {
-      tot[k] = red[0][k];
-      for (int w = 1; w < 4; ++w) tot[k] = (k == 8) ? fmax(tot[k], red[w][k]) : tot[k] + red[w][k];
-    }
-    const double W = tot[0], mean = tot[1] / W;
+  if (lane == 0) {
+    const double W = s[0], mean = s[1] / W;
     float* st = x + n_mu + 4 + n;
     st[0] = (float)mean;
-    st[1] = (float)tot[8];
-    st[2] = (float)sqrt(fmax(tot[2] / W - mean * mean, 0.0));
-    st[3] = (float)(tot[3] / W);
-    for (int k = 0; k < 4; ++k) st[4 + k] = (float)(tot[4 + k] / W);
+    st[1] = (float)s[8];
+    st[2] = (float)sqrt(fmax(s[2] / W - mean * mean, 0.0));
+    st[3] = (float)(s[3] / W);
+    for (int k = 0; k < 4; ++k) st[4 + k] = (float)(s[4 + k] / W);
   }
-  if (tid < n_mu) x[tid] = (float)mu[(size_t)p * n_mu + tid];
-  if (tid < 4) x[n_mu + tid] = (float)(Fbar[4 * (size_t)p + tid] - fbc[4 * (size_t)p + tid]);
-  for (int i = tid; i < n; i += 256) x[n_mu + 4 + i] = (float)rc[(size_t)p * n + i];
+  if (lane < n_mu) x[lane] = (float)mu[(size_t)p * n_mu + lane];
+  if (lane < 4) x[n_mu + lane] = (float)(Fbar[4 * (size_t)p + lane] - fbc[4 * (size_t)p + lane]);
+  for (int i = lane; i < n; i += 64) x[n_mu + 4 + i] = (float)rc[(size_t)p * n + i];
 }
 
 __global__ void k_path_gather(int P, const double* __restrict__ paths, int max_steps, const int* __restrict__ nsteps,
@@ -655,7 +664,7 @@ int rom_launch_path_advance(int P, const int* active, int* step, hipStream_t s) 
 int rom_launch_features(const rom_model* h, int P, const double* Fbar, const void* state, float* X, hipStream_t s) {
   const StateLayout L = rom_state_layout(h, P);
   void* st = const_cast<void*>(state);
-  k_features<<<P, 256, 0, s>>>(h->n, h->m, h->n_mu, field<double>(st, L, F_MU), Fbar, field<double>(st, L, F_FBC),
+  k_features<<<(P + 3) / 4, 256, 0, s>>>(P, h->n, h->m, h->n_mu, field<double>(st, L, F_MU), Fbar, field<double>(st, L, F_FBC),
                                field<double>(st, L, F_RC), field<double>(st, L, F_HC), field<double>(st, L, F_TMU), X);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
@@ -708,6 +717,15 @@ int rom_launch_warm_samples(const rom_model* h, int P, const void* state, const 
   void* st = const_cast<void*>(state);
   k_warm_samples<<<1, 1024, 0, s>>>(P, h->n, rom_n_features(h), X_feat, field<double>(st, L, F_RC), r_before, status,
                                     X_out, Y_out, count);
+  return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+}
+
+int rom_launch_commit_trial(const rom_model* h, int P, const double* Fbar, void* state, const int* status,
+                            hipStream_t s) {
+  const StateLayout L = rom_state_layout(h, P);
+  k_commit_trial<<<P, 256, 0, s>>>(h->n, h->m, Fbar, status, field<double>(state, L, F_FBC),
+                                   field<double>(state, L, F_RT), field<double>(state, L, F_RC),
+                                   field<double>(state, L, F_HT), field<double>(state, L, F_HC));
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 

@@ -8,9 +8,10 @@ Pbar and Abar, assembles the residual, and either stops (the prescribed
 values are in place and ||f_ext - f_int||_2 <= max(tol_rel ||f_ext||_2,
 tol_abs) over the free dofs) or solves the banded macro system; a change of
 the prescribed values enters that solve through the tangent (K_ff du_f =
-r_f - K_fd du_d).  A converged step is committed by solving the RVEs once
-more at the final Fbar with commit = 1 (the same Newton map from the same
-start, so the same state).  All arithmetic runs in the library's kernels;
+r_f - K_fd du_d).  A converged step commits the RVE trial states of its last
+iteration, which were solved at the final Fbar (rom_commit_trial: the state a
+solve with commit = 1 from the same start would leave).  All arithmetic runs
+in the library's kernels;
 this module moves pointers and reads back the two norms, the RVE status
 and the solve's info flag once per macro iteration.
 """
@@ -107,9 +108,7 @@ class Fe2Solver:
                 break
             self.applied = target.copy()
         if status == ST_OK:
-            st, _, _ = self._rve(1, rve_tol, rve_max_iter)
-            if bool((st != 0).any()):
-                status = ST_RVE_FAILED
+            self.rb.commit_trial(self.F)
         rom_fe2_compliance(self.h, Tbar, self.u.data_ptr(), self.C.data_ptr(), s)
         return dict(status=status, macro_iters=it + 1, rve_evals=evals, C=float(self.C.item()))
 

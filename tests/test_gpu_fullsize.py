@@ -62,8 +62,13 @@ def test_fixed_iteration_parity_full_size(gpu):
             assert rel(g[k]['Abar'][p], ref[k]['Abar'].reshape(-1)) < 1e-10, (p, k)
 
 
-@pytest.mark.parametrize("dt,tol_P,tol_A", [(L.DT_F64, 1e-6, 1e-6), (L.DT_BF16, 1e-5, 3e-2)])
-def test_converged_paths_full_size(gpu, dt, tol_P, tol_A):
+# BF16 with abar_f64: K*, C and sum w|J| A of Abar from an FP64 evaluation at
+# the returned state, so Abar differs from the oracle's only as far as the two
+# converged states do (BF16 Newton takes other iterates than FP64 and stops at
+# another point within the tolerance: the bound of Pbar)
+@pytest.mark.parametrize("dt,abar,tol_P,tol_A", [(L.DT_F64, 0, 1e-6, 1e-6), (L.DT_BF16, 0, 1e-5, 3e-2),
+                                                 (L.DT_BF16, 1, 1e-5, 1e-5)])
+def test_converged_paths_full_size(gpu, dt, abar, tol_P, tol_A):
     """Plain Newton with load-step cutting (depth 4), as the benchmark runs it:
     every point-step of the batch converges, and the sampled points agree with
     the oracle to the Newton tolerance on every step of the same loading path
@@ -73,7 +78,7 @@ def test_converged_paths_full_size(gpu, dt, tol_P, tol_A):
     step differently, after which it integrates its plastic flow over other
     increments: those point-steps are counted, not compared."""
     K = W['steps']
-    g = run_gpu(L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt, max_substeps=4), K)
+    g = run_gpu(L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt, max_substeps=4, abar_f64=abar), K)
     conv = np.mean([(rec['status'] == 0).mean() for rec in g])
     print(f"contraction {dt}: converged fraction {conv:.6f}")
     assert conv > 0.9995
@@ -176,12 +181,13 @@ def test_fourvoid_fixed_iteration_parity_full_size(gpu):
             assert rel(g[k]['Abar'][i], ref[k]['Abar'].reshape(-1)) < 1e-10, (p, k)
 
 
-@pytest.mark.parametrize("dt,tol_A", [(L.DT_F32, 1e-4), (L.DT_BF16, 3e-2)])
-def test_fourvoid_reduced_precision_full_size(gpu, dt, tol_A):
+@pytest.mark.parametrize("dt,abar,tol_A", [(L.DT_F32, 0, 1e-4), (L.DT_BF16, 0, 3e-2), (L.DT_BF16, 1, 1e-5)])
+def test_fourvoid_reduced_precision_full_size(gpu, dt, abar, tol_A):
     """FP32 / BF16 contraction at n = 100: converged to the same 1e-8 residual,
-    Pbar within 1e-5 of the FP64 oracle, Abar within the dtype's bound."""
+    Pbar within 1e-5 of the FP64 oracle, Abar within the dtype's bound (with
+    abar_f64, the FP64 evaluation at the returned state runs the tile split)."""
     K = 3
-    g = run_gpu4(L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt, max_substeps=4), K)
+    g = run_gpu4(L.rom_default_opts(mode=L.MODE_FUSED, contraction=dt, max_substeps=4, abar_f64=abar), K)
     assert all((rec['all_status'] == 0).mean() > 0.999 for rec in g)
     eP, eA = [], []
     for i, p in enumerate(SAMPLE4[:2]):
@@ -193,3 +199,70 @@ def test_fourvoid_reduced_precision_full_size(gpu, dt, tol_A):
     print(f"four-void contraction {dt}: max rel err Pbar {max(eP):.2e}, Abar {max(eA):.2e}")
     assert max(eP) < 1e-5
     assert max(eA) < tol_A
+
+
+@pytest.mark.parametrize("mode", [L.MODE_FUSED, L.MODE_PHASED])
+def test_abar_f64_refinement_full_size(gpu, mode):
+    """abar_f64 changes Abar only: against the same BF16 step without it the
+    statuses, evaluation counts, sub-step records, r and the committed state
+    are equal bit for bit and Pbar to rounding.  Abar is then the FP64 one at
+    the state the BF16 Newton loop returned: the oracle evaluated once at that
+    r, from the committed history the step started from, agrees to 1e-10 at
+    the sampled points whose full step converged (Abar of the plain BF16 step
+    differs there by its contraction precision)."""
+    K = 6
+    mu, paths = inputs(W)
+    rom = ROM(rom_path(W['rom']))
+    a, b = RomBatch(rom_path(W['rom']), mu), RomBatch(rom_path(W['rom']), mu)
+    plain = L.rom_default_opts(mode=mode, contraction=L.DT_BF16, max_substeps=4)
+    refined = L.rom_default_opts(mode=mode, contraction=L.DT_BF16, max_substeps=4, abar_f64=1)
+    worst, worst_plain, checked = 0.0, 0.0, 0
+    for k in range(K):
+        print(f"[gpu] abar_f64 mode={mode} P={W['P']} step {k}", flush=True)
+        Fb = torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda()
+        hist0 = b.history().cpu().numpy()[SAMPLE].copy()
+        sa = [t.clone() for t in a.step(Fb, plain)]
+        torch.cuda.synchronize()
+        sb = [t.clone() for t in b.step(Fb, refined)]
+        torch.cuda.synchronize()
+        for x, y in zip(sa, sb):
+            assert torch.equal(x, y), k
+        assert torch.equal(a.substeps(), b.substeps())
+        assert torch.equal(a.r(), b.r()) and torch.equal(a.r(trial=True), b.r(trial=True))
+        assert torch.equal(a.history(), b.history()) and torch.equal(a.fbar_committed(), b.fbar_committed())
+        assert torch.allclose(a.Pbar, b.Pbar, rtol=0, atol=1e-13 * a.Pbar.abs().max().item())
+        st, sub = sb[0].cpu().numpy(), b.substeps().cpu().numpy().view(np.uint32)
+        rt, Ab, Ap = b.r(trial=True).cpu().numpy(), b.Abar.cpu().numpy(), a.Abar.cpu().numpy()
+        for i, p in enumerate(SAMPLE):
+            if st[p] != 0 or sub[p] != 1 << 31:  # the full step converged: it started from hist0
+                continue
+            Finv, J = rom.transformation(mu[p])
+            h = hist0[i]
+            ref = rom.step(rt[p], (h[0:4].T.reshape(-1, 2, 2), h[4], h[5]), paths[p, k], Finv, J, max_iter=1,
+                           fixed=True)['Abar'].reshape(-1)
+            worst = max(worst, rel(Ab[p], ref))
+            worst_plain = max(worst_plain, rel(Ap[p], ref))
+            checked += 1
+    print(f"Abar against the oracle at the returned state, {checked} point-steps: refined {worst:.2e}, "
+          f"plain BF16 {worst_plain:.2e}")
+    assert checked >= 0.5 * K * len(SAMPLE)
+    assert worst < 1e-10
+    assert worst_plain > 1e-6  # the comparison sees the BF16 contraction
+    a.close()
+    b.close()
+
+
+def test_abar_f64_fused_equals_phased(gpu):
+    K = 3
+    mu, paths = inputs(W)
+    fu, ph = RomBatch(rom_path(W['rom']), mu), RomBatch(rom_path(W['rom']), mu)
+    for k in range(K):
+        print(f"[gpu] abar_f64 fused vs phased step {k}", flush=True)
+        Fb = torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda()
+        fu.step(Fb, L.rom_default_opts(mode=L.MODE_FUSED, contraction=L.DT_BF16, max_substeps=4, abar_f64=1))
+        ph.step(Fb, L.rom_default_opts(mode=L.MODE_PHASED, contraction=L.DT_BF16, max_substeps=4, abar_f64=1))
+        torch.cuda.synchronize()
+        assert torch.equal(fu.Pbar, ph.Pbar) and torch.equal(fu.Abar, ph.Abar), k
+        assert torch.equal(fu.history(), ph.history()), k
+    fu.close()
+    ph.close()

@@ -182,3 +182,30 @@ def test_load_step_cutting_parity(gpu, form):
             assert rel_err(rc[p], r_c) < TOL and rel_err(fbc[p], np.asarray(F_c).reshape(-1)) < 1e-15, (p, k)
             assert rel_err(hc[p][0:4].T.reshape(-1, 2, 2), h_c[0]) < TOL, (p, k)
     rb.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_commit_trial_equals_committing_step(gpu, mode):
+    """A trial step (commit = 0) followed by rom_commit_trial leaves the state
+    a committing step to the same Fbar leaves, bit for bit, over three load
+    steps; points that did not converge keep their committed state."""
+    from paper_2307_16894_amd import batch as B
+    from paper_2307_16894_amd import rom_default_opts
+    P, K = 64, 3
+    mu = workloads.one_void_mu(31, P)
+    paths = workloads.monotone_paths(31, P, K, (0.01, 0.03))
+    a, b = B.RomBatch(rom_path('onevoid_n20_m120'), mu), B.RomBatch(rom_path('onevoid_n20_m120'), mu)
+    for k in range(K):
+        print(f"[gpu] commit_trial mode={mode} step {k}", flush=True)
+        F = torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda()
+        # a low cap leaves some points unconverged at the larger increments
+        o = dict(mode=mode, tol=1e-10, max_iter=4)
+        st_a, _, _ = a.step(F, rom_default_opts(commit=1, **o))
+        b.step(F, rom_default_opts(commit=0, **o))
+        b.commit_trial(F)
+        torch.cuda.synchronize()
+        assert np.array_equal(st_a.cpu().numpy(), b.status.cpu().numpy())
+        for view in (lambda x: x.r(), lambda x: x.history(), lambda x: x._view(B.FIELD_FBAR_COMMITTED, (P, 4))):
+            assert torch.equal(view(a), view(b)), k
+    a.close()
+    b.close()
