@@ -91,6 +91,24 @@ def test_bf16_forward_matches_oracle(net):
         assert err < tol, (prec, err)
 
 
+def test_single_launch_inference_equals_layer_path(net):
+    """BF16 inference (one launch for the four layers) against the
+    layer-by-layer forward of the training path, bit for bit: with the output
+    scaling the identity, the training loss of the inference's own
+    predictions as targets is exactly zero."""
+    ws, dims, X, Y = net
+    L.rom_mlp_set_scaling(ws.h, X.mean(0), X.std(0) * 2, np.zeros(40), np.ones(40))
+    s = torch.cuda.current_stream().cuda_stream
+    Xd = torch.from_numpy(X).cuda()
+    out = torch.zeros(300, 40, dtype=torch.float32, device='cuda')
+    L.rom_mlp_infer(ws.h, 300, Xd.data_ptr(), out.data_ptr(), L.DT_BF16, s)
+    loss = torch.full((1,), -1.0, dtype=torch.float32, device='cuda')
+    L.rom_mlp_gradients(ws.h, 300, Xd.data_ptr(), out.data_ptr(), L.DT_BF16, None, loss.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all() and out.abs().max().item() > 0
+    assert loss.item() == 0.0
+
+
 def test_adam_step_matches_oracle(net):
     ws, dims, X, Y = net
     L.rom_mlp_set_scaling(ws.h, np.zeros(54), np.ones(54), np.zeros(40), np.ones(40))
