@@ -26,9 +26,10 @@
 //   sum_q w|J| P  and  sum_q w|J| A        (eqs. eff_stress_1, eff_stiffness_1).
 // Only the tiles I <= J are contracted (K and the padding blocks are symmetric
 // or above the diagonal); the rest of K is mirrored.  The padding block
-// starts at pad_base(n): n, or the next tile boundary when the rows n .. n + 3
-// would cross one (n mod 16 >= 13), since an entry of those rows against the
-// columns n .. n + 4 would then fall in a tile below the diagonal.
+// starts at pad_base(n): n, or the next tile boundary when the block would
+// cross one (n mod 16 >= 12), so that it lies in the last tile row and column
+// (an entry of its rows against its columns in a tile below the diagonal
+// would not be contracted).
 //   FP64  v_mfma_f64_16x16x4f64 (H = D [G | V] on v_mfma_f64_4x4x4f64);
 //   FP32  v_mfma_f32_16x16x4f32 on FP32 operands, FP32 accumulation;
 //   BF16  v_mfma_f32_16x16x32_bf16, eight ECM points per instruction, FP32
@@ -191,9 +192,11 @@ constexpr bool owns(int J) {
 //     F_mu[l][s] (the entries of T^-1, right multiplication by F_mu) in place
 //     of G, so that H = D V = E there.
 // First row / column of the padding block: n, or the next tile boundary when
-// the four padding rows would cross one (n mod 16 >= 13), so that every
-// padding entry lies in tiles I <= J; the columns in between are zero.
-__host__ __device__ __forceinline__ int pad_base(int n) { return (n & 15) <= 12 ? n : (n + 15) & ~15; }
+// its five columns would cross one (n mod 16 >= 12), so that the whole block
+// lies in the last tile row and column (every padding entry in tiles I <= J;
+// tiles 0 .. T - 2 hold gradient entries only); the columns in between are
+// zero.
+__host__ __device__ __forceinline__ int pad_base(int n) { return (n & 15) <= 11 ? n : (n + 15) & ~15; }
 
 struct Pad {
   int nb;       // pad_base(n)
@@ -427,27 +430,44 @@ __device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T],
           for (int b = 0; b < 4; ++b) fpart[J] = fma(cur.g[h][b], Wv[h][b], fpart[J]);
       }
       bf8 Bop;
+      if (J < T - 1) {
+        // tiles left of the padding block (resolved at compile time): G in
+        // both operands, the same arithmetic as below without the selects
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        float g[4];
+        for (int h = 0; h < 2; ++h) {
+          float g[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) g[c] = (float)cur.g[h][c];
-        float gb[4];
+          for (int c = 0; c < 4; ++c) g[c] = (float)cur.g[h][c];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          // V[c][(ek, el)] for c = (k', s): F_mu[el][s] when k' = ek
-          const float fv = el ? Fm[h][2 + (c & 1)] : Fm[h][c & 1];
-          gb[c] = ecol ? (((c >> 1) == ek) ? fv : 0.0f) : g[c];
+          for (int b = 0; b < 4; ++b) {
+            const float hv = D[h][4 * b] * g[0] + D[h][4 * b + 1] * g[1] + D[h][4 * b + 2] * g[2] + D[h][4 * b + 3] * g[3];
+            Aop[J][4 * h + b] = (__bf16)g[b];
+            Bop[4 * h + b] = (__bf16)hv;
+          }
         }
+      } else {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          float av = g[b];
-          if (J == pd.In && apad)
-            av = ((arow >> 1) == (b >> 1)) ? (aodd ? Fm[h][2 + (b & 1)] : Fm[h][b & 1]) : 0.0f;
-          float hv = D[h][4 * b] * gb[0] + D[h][4 * b + 1] * gb[1] + D[h][4 * b + 2] * gb[2] + D[h][4 * b + 3] * gb[3];
-          if (wcol) hv = (float)Wv[h][b];
-          Aop[J][4 * h + b] = (__bf16)av;
-          Bop[4 * h + b] = (__bf16)hv;
+        for (int h = 0; h < 2; ++h) {
+          float g[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) g[c] = (float)cur.g[h][c];
+          float gb[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            // V[c][(ek, el)] for c = (k', s): F_mu[el][s] when k' = ek
+            const float fv = el ? Fm[h][2 + (c & 1)] : Fm[h][c & 1];
+            gb[c] = ecol ? (((c >> 1) == ek) ? fv : 0.0f) : g[c];
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            float av = g[b];
+            if (apad)  // this branch is the last tile, the tile row of the padding block
+              av = ((arow >> 1) == (b >> 1)) ? (aodd ? Fm[h][2 + (b & 1)] : Fm[h][b & 1]) : 0.0f;
+            float hv = D[h][4 * b] * gb[0] + D[h][4 * b + 1] * gb[1] + D[h][4 * b + 2] * gb[2] + D[h][4 * b + 3] * gb[3];
+            if (wcol) hv = (float)Wv[h][b];
+            Aop[J][4 * h + b] = (__bf16)av;
+            Bop[4 * h + b] = (__bf16)hv;
+          }
         }
       }
       if (owns<T, W, TW>(J)) {

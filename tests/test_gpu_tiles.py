@@ -2,12 +2,13 @@
 tiles) and n = 80 (six) as the leading modes of the four-void n = 100 ROM (a
 truncated POD basis keeps the same ECM rule, which integrates the smaller
 span as well), and the full four-void n = 60 (five tiles) and n = 120 (eight,
-the widest the kernels are built for) ROMs, and n = 45, 63, 95 (n mod 16 >= 13,
-where the rows carrying the effective stress and stiffness start at the next
-tile boundary).  Fixed-iteration FP64 parity with the oracle for the fused
-form with each wave split it supports and for the phased form (up to five
-tiles); at n = 120, 45 and 63 also the reduced-precision contractions, solved
-to 1e-8 and compared on the effective stress."""
+the widest the kernels are built for) ROMs, and n = 28, 44, 45, 60, 63, 95
+(n mod 16 >= 12, where the rows and columns carrying the residual, the
+effective stress and stiffness start at the next tile boundary, so that they
+lie in the last tile).  Fixed-iteration FP64 parity with the oracle for the
+fused form with each wave split it supports and for the phased form (up to
+five tiles); at n = 120, 28, 44, 45, 60 and 63 also the reduced-precision
+contractions, solved to 1e-8 and compared on the effective stress."""
 import functools
 import os
 
@@ -28,8 +29,9 @@ pytestmark = pytest.mark.gpu
 P, K, IT = 2, 2, 3
 CASES = [('fourvoid_n100_m1500', 50), ('fourvoid_n60_m800', None), ('fourvoid_n100_m1500', 80),
          ('fourvoid_n120_m2000', None),
-         # n mod 16 >= 13: the padding rows start at the next tile boundary
-         ('fourvoid_n100_m1500', 45), ('fourvoid_n100_m1500', 63), ('fourvoid_n100_m1500', 95)]
+         # n mod 16 >= 12: the padding block starts at the next tile boundary
+         ('fourvoid_n100_m1500', 45), ('fourvoid_n100_m1500', 63), ('fourvoid_n100_m1500', 95),
+         ('fourvoid_n100_m1500', 28), ('fourvoid_n100_m1500', 44)]
 
 
 @pytest.fixture(scope='module')
@@ -98,11 +100,13 @@ def test_fixed_iteration_parity_every_tile_count(gpu, roms, case):
         rb.close()
 
 
-@pytest.mark.parametrize("case,prec", [(3, L.DT_BF16), (4, L.DT_BF16), (4, L.DT_F32), (5, L.DT_BF16)])
+@pytest.mark.parametrize("case,prec", [(3, L.DT_BF16), (4, L.DT_BF16), (4, L.DT_F32), (5, L.DT_BF16),
+                                       (1, L.DT_BF16), (7, L.DT_BF16), (7, L.DT_F32), (8, L.DT_BF16)])
 def test_reduced_precision_contraction(gpu, roms, case, prec):
-    """n = 120 (the widest) and n = 45, 63 (padding at the next tile
-    boundary): the BF16 / FP32 contraction (point split, FP32 accumulators)
-    solved to 1e-8 like the oracle; effective stress within 1e-5."""
+    """n = 120 (the widest) and n = 28, 44, 45, 60, 63 (padding at the next
+    tile boundary): the BF16 / FP32 contraction (point split, FP32
+    accumulators) solved to 1e-8 like the oracle; effective stress within
+    1e-5."""
     path = roms[CASES[case]]
     n = artifact.read(path)['n']
     seed = 70 + case
