@@ -75,9 +75,15 @@ enum {
   F_RC = 0, F_RT, F_HC, F_HT, F_TMU, F_PBAR, F_ABAR, F_MUOK, F_FBC, F_RG, F_SUB,
   F_DONE, F_STATUS, F_ITERS, F_RES, F_COUNT, F_XF, F_DR, F_MU, F_LIST,
   F_D, F_W, F_K, F_F, F_PIV,
-  F_REC, F_PHI, F_PHD, F_LIST2, F_LIST3, F_LIST4, F_HKIN, F_ZK,
+  F_REC, F_PHI, F_PHD, F_LIST2, F_LIST3, F_LIST4, F_HKIN, F_ZK, F_SYS,
   F_NFIELDS
 };
+
+// Phased form up to ROM_SOLVE_NPAD columns: the system [K | f | C] of each
+// point (npad columns of n rows) with the effective-quantity rows and ||f||
+// (24 doubles), handed from the contraction launch to the solve launch.
+#define ROM_SOLVE_NPAD 64
+__host__ __device__ inline size_t rom_sys_stride(int npad, int n) { return (size_t)npad * n + 24; }
 
 // per-point inputs of the warm-start network: mu, Fbar - Fbar_committed, r, 8 statistics
 static inline int rom_n_features(const rom_model* h) { return h->n_mu + 4 + h->n + 8; }
@@ -126,6 +132,7 @@ static inline StateLayout rom_state_layout(const rom_model* h, size_t P) {
   sz[F_LIST4] = P * 4;
   sz[F_HKIN] = (h->npad <= ROM_PHASED_NPAD) ? P * 4 * m * 8 : 0;
   sz[F_ZK] = P * n * 4 * 8;  // K*^-1 C at the returned state (shape sensitivities)
+  sz[F_SYS] = (h->npad <= ROM_SOLVE_NPAD) ? P * rom_sys_stride(h->npad, (int)n) * 8 : 0;
   StateLayout L;
   size_t o = 0;
   for (int i = 0; i < F_NFIELDS; ++i) {

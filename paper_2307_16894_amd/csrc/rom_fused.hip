@@ -169,6 +169,15 @@ int rom_refine_abar(const rom_model* h, const FusedArgs& a, int split, int P, vo
   return rom_fused_launch(T, r, ROM_DT_F64, T <= 5 ? split : 1, 0, P, s);
 }
 
+int rom_phased_solve(int T, const FusedArgs& a, int P, hipStream_t s) {
+  switch (T) {
+    case 2: return rom_phased_solve_2(a, P, s);
+    case 3: return rom_phased_solve_3(a, P, s);
+    case 4: return rom_phased_solve_4(a, P, s);
+    default: return ROM_EUNSUPPORTED;
+  }
+}
+
 int rom_launch_step_fused(rom_model* h, int P, const double* Fbar, void* state, const rom_opts& o,
                           int32_t* st_out, int32_t* it_out, double* res_out, hipStream_t s) {
   FusedArgs a;

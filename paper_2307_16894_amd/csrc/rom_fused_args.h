@@ -52,6 +52,8 @@ struct FusedArgs {
   int* early;        // points handed to the fused kernel on the side stream
   int* cearly;       // their count (device)
   int resume;        // fused kernel: start each point from phi / phd (evaluation phi[0] of attempt 0)
+  double* sys;       // phased form up to ROM_SOLVE_NPAD columns: the contraction launch leaves the system of
+                     // each point here [P][rom_sys_stride] and a solve launch eliminates (NULL: in place)
   int defer;         // converged points leave their final commit to a refining launch
   int refine;        // fused kernel: one evaluation at the trial r of each point the step reported converged,
                      // its effective quantities, and the commit (statuses, counts and norms kept)
@@ -64,6 +66,7 @@ struct FusedArgs {
 #define ROM_FUSED_DECL(T)                                                                              \
   int rom_fused_launch_##T(const FusedArgs& a, int prec, int split, int grid, int P, hipStream_t s);  \
   int rom_phased_cs_##T(const FusedArgs& a, int prec, int split, int P, hipStream_t s);               \
+  int rom_phased_solve_##T(const FusedArgs& a, int P, hipStream_t s);                                  \
   int rom_fused_setup_##T();
 ROM_FUSED_DECL(2)
 ROM_FUSED_DECL(3)
@@ -78,6 +81,7 @@ int rom_fused_prepare(rom_model* h, int P, const double* Fbar, void* state, cons
                       int32_t* it_out, double* res_out, hipStream_t s, FusedArgs& a, int& split);
 int rom_fused_launch(int T, const FusedArgs& a, int prec, int split, int grid, int P, hipStream_t s);
 int rom_phased_cs(int T, const FusedArgs& a, int prec, int split, int P, hipStream_t s);
+int rom_phased_solve(int T, const FusedArgs& a, int P, hipStream_t s);
 bool rom_refines_abar(const rom_opts& o);
 int rom_refine_abar(const rom_model* h, const FusedArgs& a, int split, int P, void* state, hipStream_t s);
 int rom_refine_abar_phased(const rom_model* h, const FusedArgs& a, int split, int P, void* state, hipStream_t s);

@@ -1210,6 +1210,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cs_waves<T,
     finish_point(a, p, sR, Fb, ROM_ST_CONVERGED, false, 0, rn, 0u, tid);
     return;
   }
+  if (a.sys) {
+    // the elimination and what follows run in the solve launch: the system
+    // by columns of n rows, then the effective-quantity rows and ||f||
+    double* sy = a.sys + (size_t)p * rom_sys_stride(NPAD, n);
+    const int nb = pad_base(n), ncol = nb + 5;
+    for (int e = tid; e < ncol * n; e += 256) {
+      const int c = e / n, r = e - c * n;
+      sy[e] = sK[r * LD + c];
+    }
+    double* ex = sy + (size_t)NPAD * n;
+    if (tid < 4) ex[tid] = sK[(nb + tid) * LD + nb];
+    else if (tid < 20) ex[tid] = sK[(nb + ((tid - 4) >> 2)) * LD + nb + 1 + ((tid - 4) & 3)];
+    else if (tid == 20) ex[20] = rn;
+    return;
+  }
   int status;
   const bool stop = eval_status(a, it, rn, status);
   if (it == 0) rn0 = rn;
@@ -1236,6 +1251,145 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(cs_waves<T,
     }
   }
   if (tid == 0) {
+    a.phi[2 * (size_t)p] = next;
+    a.phi[2 * (size_t)p + 1] = fell_back ? 1 : 0;
+    a.phd[2 * (size_t)p] = rn0;
+    a.phd[2 * (size_t)p + 1] = rn;
+    // a point converging slowly at the early hand-over goes to the side stream
+    const bool slow = a.ph_early > 0 && next == a.ph_early && it > 0 && !(rn <= a.ph_slow * rn_prev);
+    if (next > 0 && next < a.ph_k && !slow)
+      a.lout[atomicAdd(a.cout, 1)] = p;
+    else if (slow)
+      a.early[atomicAdd(a.cearly, 1)] = p;
+    else
+      a.hand[atomicAdd(a.chand, 1)] = p;
+  }
+}
+
+// Step K of the one-wave elimination of the solve launch (K a constant): the
+// lane's row in registers with the right-hand sides in x[0 .. 4] and column j
+// of K in x[5 + j]; pivot row, multipliers and fma per entry as in
+// gauss_jordan(); columns left of the pivot column are not updated (no later
+// step and no right-hand side reads them).
+template <int NPAD, int K>
+__device__ __forceinline__ void solve_step(double (&x)[NPAD], int n, int lane, bool& piv, int& kp, double& pvr) {
+  if (K >= n) return;
+  const unsigned int key = pivot_key(x[5 + K], lane < n && !piv);
+  const unsigned int M = wave_max_u32(key);
+  const int pr = __builtin_ctzll(__ballot(key == M));
+  const double pv = readlane_d(x[5 + K], pr);
+  const double inv = 1.0 / pv;
+  const double mlt = (lane == pr) ? 0.0 : x[5 + K] * inv;
+  if (lane == pr) {
+    piv = true;
+    kp = K;
+    pvr = pv;
+  }
+  // the pivot row's entries read from its lane into scalar registers
+#pragma unroll
+  for (int c = 0; c < NPAD; ++c)
+    if (c < 5 || c > 5 + K) x[c] = fma(-mlt, readlane_d(x[c], pr), x[c]);
+}
+
+template <int NPAD, int... Ks>
+__device__ __forceinline__ void solve_steps(std::integer_sequence<int, Ks...>, double (&x)[NPAD], int n, int lane,
+                                            bool& piv, int& kp, double& pvr) {
+  (solve_step<NPAD, Ks>(x, n, lane, piv, kp, pvr), ...);
+}
+
+// Phased form up to ROM_SOLVE_NPAD columns, solve launch: one wave per listed
+// point takes the system [K | f | C] the contraction launch left in HBM and
+// runs the elimination of gauss_jordan() -- the same pivot rows (same key,
+// lowest row on ties), multipliers and fma per entry, so the same results bit
+// for bit -- with the lane's row in registers and the steps unrolled, so that
+// the pivot column is a fixed register in each; every lane reads the pivot
+// row's entries from the pivot lane (scalar registers), and no workgroup
+// barrier is taken.  Then the status, the
+// Newton update or the effective quantities and the commit, and the lists,
+// as the contraction kernel does them in place.
+template <int T>
+__global__ __launch_bounds__(256) void k_ph_s(const FusedArgs a) {
+  constexpr int NPAD = 16 * T;
+  static_assert(NPAD <= ROM_SOLVE_NPAD && NPAD <= 64, "one row per lane");
+  __shared__ double sZ[4][64 * 4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 4 + wave;
+  if (idx >= *a.cin) return;
+  const int p = __builtin_amdgcn_readfirstlane(a.lin[idx]);
+  const int n = a.n, nb = pad_base(n), ncol = nb + 5;
+  const double* sy = a.sys + (size_t)p * rom_sys_stride(NPAD, n);
+  const double* ex = sy + (size_t)NPAD * n;  // sum w|J| P (4), sum w|J| A (16), ||f||
+  const double rn = ex[20];
+  const int it = __builtin_amdgcn_readfirstlane(a.phi[2 * (size_t)p]);
+  bool fell_back = __builtin_amdgcn_readfirstlane(a.phi[2 * (size_t)p + 1]) != 0;
+  double rn0 = a.phd[2 * (size_t)p];
+  const double rn_prev = a.phd[2 * (size_t)p + 1];
+  double* rt = a.rt + (size_t)p * n;
+  int status;
+  const bool stop = eval_status(a, it, rn, status);
+  if (it == 0) rn0 = rn;
+  int next = it + 1;
+  if (!stop && a.dr && !fell_back && it == 2 && !(rn <= 0.1 * rn0)) {
+    // the warm start is dropped: the next evaluation starts from the committed r
+    fell_back = true;
+    for (int i = lane; i < n; i += 64) rt[i] = a.rc[(size_t)p * n + i];
+  } else if (stop && !(status == ROM_ST_CONVERGED || a.max_sub == 0)) {
+    next = 0;  // failed attempt: the fused kernel redoes the point with load-step cutting
+    fell_back = false;
+  } else {
+    // registers: the right-hand sides (f, C) first, then the columns of K
+    double x[NPAD];
+#pragma unroll
+    for (int y = 0; y < 5; ++y) x[y] = (lane < n) ? sy[(size_t)(nb + y) * n + lane] : 0.0;
+#pragma unroll
+    for (int c = 0; c + 5 < NPAD; ++c) x[5 + c] = (lane < n && c < n) ? sy[(size_t)c * n + lane] : 0.0;
+    bool piv = false;
+    int kp = 0;        // the step at which this lane's row was the pivot row
+    double pvr = 1.0;  // and its pivot
+    solve_steps<NPAD>(std::make_integer_sequence<int, NPAD - 5>{}, x, n, lane, piv, kp, pvr);
+    // unknown kp of the right-hand sides y, divided by the row's pivot
+    const double rinv = (lane < n) ? 1.0 / pvr : 0.0;
+    double xs[5];
+#pragma unroll
+    for (int y = 0; y < 5; ++y) xs[y] = x[y] * rinv;
+    if (!stop) {
+      if (lane < n) rt[kp] = rt[kp] - xs[0];
+    } else {
+      // effective quantities at the returned state (Sec. 3.3), K*^-1 C kept
+      if (lane < n) {
+#pragma unroll
+        for (int y = 0; y < 4; ++y) sZ[wave][4 * kp + y] = xs[1 + y];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const double inv_area = a.inv_area;
+      if (lane < 4) {
+        a.Pbar[4 * (size_t)p + lane] = ex[lane] * inv_area;
+      } else if (lane < 20) {
+        const int e = lane - 4, xx = e >> 2, yy = e & 3;
+        double acc2 = ex[4 + e];
+        for (int i = 0; i < n; ++i) acc2 = fma(-sy[(size_t)(nb + 1 + xx) * n + i], sZ[wave][4 * i + yy], acc2);
+        a.Abar[16 * (size_t)p + e] = acc2 * inv_area;
+      }
+      for (int e = lane; e < 4 * n; e += 64) a.zk[(size_t)p * 4 * n + e] = sZ[wave][e];
+      // outputs of the finished step and the commit of a converged one
+      if (lane == 0) {
+        a.st_out[p] = (status == ROM_ST_CONVERGED && fell_back) ? ROM_ST_FALLBACK : status;
+        a.it_out[p] = it + 1;
+        a.res_out[p] = rn;
+        a.sub[p] = (status == ROM_ST_CONVERGED) ? (1u << 31) : 0u;
+      }
+      if (a.commit && !a.defer && status == ROM_ST_CONVERGED) {
+        const int m = a.m;
+        if (lane < 4) a.fbc[4 * (size_t)p + lane] = a.Fbar[4 * (size_t)p + lane];
+        for (int i = lane; i < n; i += 64) a.rc[(size_t)p * n + i] = rt[i];
+        double* hcw = a.hc + (size_t)p * 6 * m;
+        const double* ht = a.ht + (size_t)p * 6 * m;
+        for (int q = lane; q < 6 * m; q += 64) hcw[q] = ht[q];
+      }
+      return;
+    }
+  }
+  if (lane == 0) {
     a.phi[2 * (size_t)p] = next;
     a.phi[2 * (size_t)p + 1] = fell_back ? 1 : 0;
     a.phd[2 * (size_t)p] = rn0;
@@ -1344,6 +1498,16 @@ int phased_cs_prec(const FusedArgs& a, int split, int P, hipStream_t s) {
 }
 
 template <int T>
+int phased_solve(const FusedArgs& a, int P, hipStream_t s) {
+  if constexpr (16 * T > ROM_SOLVE_NPAD) {
+    return ROM_EUNSUPPORTED;
+  } else {
+    k_ph_s<T><<<(P + 3) / 4, 256, 0, s>>>(a);
+    return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
+  }
+}
+
+template <int T>
 int phased_cs(const FusedArgs& a, int prec, int split, int P, hipStream_t s) {
   if (prec == ROM_DT_F64) return phased_cs_prec<T, PREC_F64>(a, split, P, s);
   if (prec == ROM_DT_F32) return phased_cs_prec<T, PREC_F32>(a, split, P, s);
@@ -1373,4 +1537,5 @@ int fused_setup() {
   int rom_phased_cs_##T(const FusedArgs& a, int prec, int split, int P, hipStream_t s) {              \
     return phased_cs<T>(a, prec, split, P, s);                                                         \
   }                                                                                                    \
+  int rom_phased_solve_##T(const FusedArgs& a, int P, hipStream_t s) { return phased_solve<T>(a, P, s); } \
   int rom_fused_setup_##T() { return fused_setup<T>(); }

@@ -8,8 +8,13 @@
 //                forcevector_ecm / stiffnessmatrix_ecm), the lanes packed
 //                across points;
 //   contraction: one workgroup per listed point (the MFMA contraction of the
-//                records, the elimination, the status and Newton update), a
-//                kernel with a register budget of its own.
+//                records, then, up to 64 columns, the system to HBM; wider,
+//                the elimination, status and Newton update in place), a
+//                kernel with a register budget of its own;
+//   solve:       up to 64 columns, one wave per listed point (the
+//                elimination with the row of the lane in registers, the
+//                status, the Newton update or the effective quantities), no
+//                workgroup barrier.
 // After ph_k evaluations the points still running (and any attempt that
 // failed with load-step cutting on) are finished by the fused kernel as a
 // persistent grid, which resumes each point from the state left here.  Points
@@ -183,6 +188,7 @@ int rom_refine_abar_phased(const rom_model* h, const FusedArgs& a, int split, in
   b.phd = field<double>(state, L, F_PHD);
   b.lin = list;
   b.cin = cnt;
+  b.sys = nullptr;  // the refining contraction eliminates in place
   // the material kernel clears the count of the list a contraction launch
   // fills next: give it the second list's slot (the refining contraction
   // lists nothing)
@@ -230,6 +236,8 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
   a.phd = field<double>(state, L, F_PHD);
   a.hand = hand;
   a.chand = cnt + 2;
+  // up to ROM_SOLVE_NPAD columns the elimination runs in a launch of its own
+  a.sys = (h->npad <= ROM_SOLVE_NPAD) ? field<double>(state, L, F_SYS) : nullptr;
   const int T = rom_fused_tiles(h->n);
   const bool refine = rom_refines_abar(o);
   a.defer = refine ? 1 : 0;
@@ -252,6 +260,7 @@ int rom_launch_step_phased(rom_model* h, int P, const double* Fbar, void* state,
     b.cout = cnt + 1 - (e & 1);
     rc = launch_mat(b, o.contraction, P, h->m, s);
     if (rc == ROM_OK) rc = rom_phased_cs(T, b, o.contraction, split, P, s);
+    if (rc == ROM_OK && b.sys) rc = rom_phased_solve(T, b, P, s);
     if (rc == ROM_OK && a.ph_early > 0 && e + 1 == a.ph_early) {
       // fork: the early list to the fused kernel on the side stream
       if (hipEventRecord(h->ev_fork, s) != hipSuccess) {
