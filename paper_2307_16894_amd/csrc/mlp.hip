@@ -10,6 +10,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "rom_common.h"
@@ -63,76 +64,88 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 }
 
 // C[M][N] (ldc) = sum_k A(m, k) B(k, n) (+ bias[n]); A(m, k) = A[m * sa0 + k * sa1],
-// B(k, n) = B[k * sb0 + n * sb1].  Workgroup tile 64 x 64, wave tile 32 x 32
-// (2 x 2 MFMA tiles of 16 x 16), out-of-range operands read as zero.  With
-// gridDim.z > 1 workgroup z sums k in [z kchunk, (z + 1) kchunk) only and
+// B(k, n) = B[k * sb0 + n * sb1], one of sa0 / sa1 and one of sb0 / sb1 equal
+// to 1 (row-major or transposed operands).  Workgroup tile 64 x 64, wave tile
+// 32 x 32 (2 x 2 MFMA tiles of 16 x 16); per step of 32 inner indices the two
+// operand tiles are loaded into LDS with eight contiguous elements per thread
+// along whichever index is contiguous in memory, A as [m][k] and B as [n][k],
+// so that each lane's MFMA operand is one LDS read.  Out-of-range operands
+// read as zero.  The MFMA operands sit in the lanes and the inner index runs
+// in the order of the per-lane global form this replaced (BF16: k = k0 + 8 g
+// + t; FP32: k = k0 + 4 s + g), so the products are the same bit for bit.
+// With gridDim.z > 1 workgroup z sums k in [z kchunk, (z + 1) kchunk) only and
 // writes its product to C + z cstride (kchunk a multiple of 32).
+constexpr int GM_T = 64, GM_K = 32;
+
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* __restrict__ Av, long sa0, long sa1,
                                               const void* __restrict__ Bv, long sb0, long sb1, float* __restrict__ C,
                                               long ldc, const float* __restrict__ bias, int kchunk, long cstride) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  using E = typename std::conditional<BF16, uint16_t, float>::type;
+  constexpr int LDK = GM_K + (BF16 ? 8 : 4);  // padded row (16 bytes)
+  __shared__ __attribute__((aligned(16))) E sA[GM_T * LDK];
+  __shared__ __attribute__((aligned(16))) E sB[GM_T * LDK];
+  const E* A = static_cast<const E*>(Av);
+  const E* B = static_cast<const E*>(Bv);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   C += blockIdx.z * cstride;
   const int g = lane >> 4, c = lane & 15;
-  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  const int mt = blockIdx.y * GM_T, nt = blockIdx.x * GM_T;
+  const int mw = (wave >> 1) * 32, nw = (wave & 1) * 32;
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
-  if constexpr (BF16) {
-    const uint16_t* A = static_cast<const uint16_t*>(Av);
-    const uint16_t* B = static_cast<const uint16_t*>(Bv);
-    for (int k0 = kb; k0 < ke; k0 += 32) {
+  // thread t loads 8 contiguous elements: along k (row r = t / 4, k = 8 (t % 4))
+  // or along m / n (k = t / 8, row 8 (t % 8))
+  const bool a_k = (sa1 == 1), b_k = (sb0 == 1);
+  for (int k0 = kb; k0 < ke; k0 += GM_K) {
+    {
+      const int r = a_k ? tid >> 2 : 8 * (tid & 7), kk = a_k ? 8 * (tid & 3) : tid >> 3;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int rr = a_k ? r : r + e, ki = a_k ? kk + e : kk;
+        const int m = mt + rr, k = k0 + ki;
+        sA[rr * LDK + ki] = (m < M && k < ke) ? A[m * sa0 + k * sa1] : (E)0;
+      }
+    }
+    {
+      const int r = b_k ? tid >> 2 : 8 * (tid & 7), kk = b_k ? 8 * (tid & 3) : tid >> 3;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int rr = b_k ? r : r + e, ki = b_k ? kk + e : kk;
+        const int n = nt + rr, k = k0 + ki;
+        sB[rr * LDK + ki] = (n < N && k < ke) ? B[k * sb0 + n * sb1] : (E)0;
+      }
+    }
+    __syncthreads();
+    if constexpr (BF16) {
       bf8 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int m = m0 + 16 * i + c;
+      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf8*>(sA + (mw + 16 * i + c) * LDK + 8 * g);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = k0 + 8 * g + t;
-          const uint16_t v = (m < M && k < ke) ? A[m * sa0 + k * sa1] : (uint16_t)0;
-          a[i][t] = __builtin_bit_cast(__bf16, v);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = n0 + 16 * j + c;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = k0 + 8 * g + t;
-          const uint16_t v = (n < N && k < ke) ? B[k * sb0 + n * sb1] : (uint16_t)0;
-          b[j][t] = __builtin_bit_cast(__bf16, v);
-        }
-      }
+      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf8*>(sB + (nw + 16 * j + c) * LDK + 8 * g);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-  } else {
-    const float* A = static_cast<const float*>(Av);
-    const float* B = static_cast<const float*>(Bv);
-    for (int k0 = kb; k0 < ke; k0 += 4) {
-      const int k = k0 + g;
-      float a[2], b[2];
+    } else {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int m = m0 + 16 * i + c;
-        a[i] = (m < M && k < ke) ? A[m * sa0 + k * sa1] : 0.f;
+      for (int st = 0; st < GM_K / 4; ++st) {
+        float a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = sA[(mw + 16 * i + c) * LDK + 4 * st + g];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = sB[(nw + 16 * j + c) * LDK + 4 * st + g];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = n0 + 16 * j + c;
-        b[j] = (n < N && k < ke) ? B[k * sb0 + n * sb1] : 0.f;
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    __syncthreads();
   }
   // accumulator layout of the 16 x 16 f32-output MFMAs: row 4 g + r, column c
 #pragma unroll
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* _
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + 16 * i + 4 * g + r, n = n0 + 16 * j + c;
+        const int m = mt + mw + 16 * i + 4 * g + r, n = nt + nw + 16 * j + c;
         if (m < M && n < N) C[m * ldc + n] = acc[i][j][r] + (bias ? bias[n] : 0.f);
       }
 }
