@@ -128,7 +128,15 @@ def _test_mu(spec, seed, count):
     return {0: workloads.one_void_mu, 1: workloads.four_void_mu, 2: workloads.inclusion_mu}[spec['kind']](seed, count)
 
 
-def build(name, outdir, workers, snapshot_cache=None, overrides=None):
+def build(name, outdir, workers, snapshot_cache=None, overrides=None, pod_fn=None, ecm_fn=None, heldout=True):
+    """Offline stage of Algorithm 1 for the ROM `name`: training FOM solves,
+    POD of the fluctuations and of the weighted stress, the ECM rule, the
+    artifact, and (heldout) the ROM's error on held-out FOM paths.  pod_fn and
+    ecm_fn stand in for pod.pod and ecm.greedy (same arguments and results),
+    so that a caller can build the same ROM with another implementation of
+    those two steps; by default the ones of this package."""
+    pod_fn = pod_fn or pod.pod
+    ecm_fn = ecm_fn or ecm.greedy
     spec = dict(ROMS[name])
     spec.update(overrides or {})
     t0 = time.time()
@@ -155,13 +163,13 @@ def build(name, outdir, workers, snapshot_cache=None, overrides=None):
     Fid = auxiliary.transformation(grad_modes, np.zeros(grad_modes.shape[0]))
     pr0 = fem.Problem(m, space, Fid, MAT)
     MV = pod.v_gram(pr0)
-    Phi, lam_w = pod.pod(Sw, MV, spec['n'])
-    B, lam_W = pod.pod(SW, np.repeat(m.qw, 4), spec['L'])
+    Phi, lam_w = pod_fn(Sw, MV, spec['n'])
+    B, lam_W = pod_fn(SW, np.repeat(m.qw, 4), spec['L'])
     Gfull = (pr0.Gop @ Phi).reshape(m.nq, 4, spec['n'])
     Bq = B.reshape(m.nq, 4, spec['L'])
     J = ecm.integrand_matrix(Gfull, Bq, spec['n'], spec['L'])
     J = np.vstack([J, np.ones((1, m.nq))])  # constant integrand: parent area (build's addition)
-    idx, wq, hist = ecm.greedy(J, m.qw, spec['eps'], spec['m'])
+    idx, wq, hist = ecm_fn(J, m.qw, spec['eps'], spec['m'])
     print(f"[{name}] ECM: {idx.size} points, relative residual {hist[-1]:.3e}", flush=True)
     order = np.argsort(idx)
     idx, wq = idx[order], wq[order]
@@ -177,10 +185,12 @@ def build(name, outdir, workers, snapshot_cache=None, overrides=None):
     rom = ROM(path)
     test_mu = _test_mu(spec, spec['seed'] + 7, 4)
     test_paths = _paths(spec, spec['seed'] + 8, 4)
-    with mp.get_context('fork').Pool(workers) as pool:
-        ref = pool.map(_fom_job, [(spec, test_mu[i], test_paths[i]) for i in range(4)])
+    ref = []
+    if heldout:
+        with mp.get_context('fork').Pool(workers) as pool:
+            ref = pool.map(_fom_job, [(spec, test_mu[i], test_paths[i]) for i in range(4)])
     errs = []
-    for i in range(4):
+    for i in range(len(ref)):
         out = rom.run_path(test_mu[i], test_paths[i])
         Pr = np.array([o['Pbar'] for o in out])
         Pf = ref[i][2].reshape(-1, 4)

@@ -21,6 +21,8 @@
 
 #include "podecm.h"
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 struct rom_fe2 {
   int device;
   int nodes, elements, points, dofs, nfixed, nfree, ntop, kl, ldab;
@@ -28,6 +30,8 @@ struct rom_fe2 {
   double width;
   // device
   double *X, *dNdX, *wJ, *Xg, *band, *rhs, *ubuf, *xbuf;  // ubuf, xbuf: the LDS-window solve
+  double *lbuf, *ybuf;  // blocked Cholesky (kl <= its limit): factor panels, solution; null otherwise
+  int* done;            // 1 when the blocked Cholesky has solved the current system
   int *conn, *node_ptr, *node_ent, *dofmap, *fixed, *top;
 };
 
@@ -277,7 +281,9 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_solve(int nf, int kl, int l
                                                            double* __restrict__ rhs, int dofs,
                                                            const int* __restrict__ dofmap, const int* __restrict__ fixed,
                                                            int nfixed, const double* __restrict__ dud,
-                                                           double* __restrict__ u, int* __restrict__ info) {
+                                                           double* __restrict__ u, int* __restrict__ info,
+                                                           const int* __restrict__ done) {
+  if (done && *done) return;  // solved by the blocked Cholesky
   __shared__ double s_mult[256];
   __shared__ int s_piv;
   __shared__ double s_pv;
@@ -797,7 +803,8 @@ __global__ __launch_bounds__(LDS_THREADS_MAX) void k_band_solve_lds(
     int nf, int kl, int ldab, int B, const double* __restrict__ band, const double* __restrict__ rhs_in,
     double* __restrict__ ubuf, double* __restrict__ x, int dofs, const int* __restrict__ dofmap,
     const int* __restrict__ fixed, int nfixed, const double* __restrict__ dud, double* __restrict__ u,
-    int* __restrict__ info) {
+    int* __restrict__ info, const int* __restrict__ done) {
+  if (done && *done) return;  // solved by the blocked Cholesky
   extern __shared__ double lds[];
   if (band_chol_lds(nf, kl, ldab, band, rhs_in, ubuf, x, lds)) {
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -814,12 +821,216 @@ __global__ __launch_bounds__(LDS_THREADS_MAX) void k_band_solve_lds(
   band_lu_lds(nf, kl, ldab, B, band, rhs_in, ubuf, x, dofs, dofmap, fixed, nfixed, dud, u, info, lds);
 }
 
+// Blocked banded Cholesky of the free-dof tangent on FP64 MFMA, one
+// workgroup of 256: the lower band is factored by panels of 16 columns with
+// a window of WP = the next multiple of 16 of kl + 16 rows and columns in
+// LDS, indexed modulo WP (the rows of a finished panel take the rows that
+// enter the window).  Per panel: the 16 x 16 diagonal block factored by one
+// wave, the rows below solved against it (a thread per row), the forward
+// substitution of the right-hand side, the trailing window updated by the
+// panel's outer product (16 x 16 x 4 FP64 MFMA tiles, the waves taking the
+// tiles in turn), the panel stored for the backward substitution, and the
+// entering rows loaded from the band.  Rows past nf are identity rows.  On
+// success u_f += x, u_d += du_d and *done = 1; at a pivot that is not
+// positive *done = 0 and nothing is written (the banded solve that follows
+// then factors the same band).
+constexpr int CB_KL_MAX = 112;  // WP <= 128: a 128 x 129 FP64 window, 129 KB of LDS
+
+__host__ __device__ inline int chol_blk_wp(int kl) { return (kl + 16 + 15) / 16 * 16; }
+inline size_t chol_blk_lds_bytes(int kl) {
+  const int wp = chol_blk_wp(kl);
+  return (size_t)(wp * (wp + 1) + wp + 64) * 8;
+}
+
+__global__ __launch_bounds__(256) void k_band_chol_blk(int nf, int kl, int ldab, const double* __restrict__ band,
+                                                        const double* __restrict__ rhs, double* __restrict__ lbuf,
+                                                        double* __restrict__ y, int dofs, const int* __restrict__ dofmap,
+                                                        const int* __restrict__ fixed, int nfixed,
+                                                        const double* __restrict__ dud, double* __restrict__ u,
+                                                        int* __restrict__ info, int* __restrict__ done) {
+  extern __shared__ double lds[];
+  const int WP = chol_blk_wp(kl), LDW = WP + 1, NBK = WP / 16;
+  double* W = lds;              // [WP][LDW] lower triangle of the window, rows and columns by slot
+  double* sb = lds + WP * LDW;  // [WP] right-hand side by slot
+  double* sd = sb + WP;         // [16] reciprocal diagonal of the panel, [16] panel solution
+  int* sflag = reinterpret_cast<int*>(sd + 32);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int np = (nf + 15) / 16;
+  // A[g][c] of the (identity-extended) lower band, g >= c
+  auto Aval = [&](int g, int c) -> double {
+    if (g >= nf || c >= nf) return (g == c) ? 1.0 : 0.0;
+    if (g - c > kl) return 0.0;
+    return band[(size_t)g * ldab + (c - g + kl)];
+  };
+  // initial window: rows and columns 0 .. WP - 1
+  for (int e = tid; e < WP * WP; e += 256) {
+    const int r = e / WP, c = e - r * WP;
+    W[r * LDW + c] = (r >= c) ? Aval(r, c) : 0.0;
+  }
+  for (int r = tid; r < WP; r += 256) sb[r] = (r < nf) ? rhs[r] : 0.0;
+  if (tid == 0) *sflag = 0;
+  __syncthreads();
+  for (int pi = 0; pi < np; ++pi) {
+    const int p = 16 * pi;
+    const int s0 = p % WP;  // slot of row p (a multiple of 16: the panel's slots are s0 .. s0 + 15)
+    auto slot = [&](int rel) { return (s0 + rel < WP) ? s0 + rel : s0 + rel - WP; };  // rel < WP
+    // 1. the diagonal block, one wave: lane i holds row i
+    if (wave == 0) {
+      double row[16];
+      const int si = slot(lane & 15);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) row[j] = (lane < 16 && j <= lane) ? W[si * LDW + slot(j)] : 0.0;
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const double dkk = __shfl(row[k], k);
+        if (!(dkk > 0.0) || !isfinite(dkk)) bad = true;
+        const double lkk = sqrt(dkk);
+        const double rl = 1.0 / lkk;
+        if (lane == k) row[k] = lkk;
+        if (lane > k && lane < 16) row[k] *= rl;
+        const double lik = row[k];
+#pragma unroll
+        for (int j = k + 1; j < 16; ++j) {
+          const double ljk = __shfl(row[k], j);
+          if (lane >= j && lane < 16) row[j] = fma(-lik, ljk, row[j]);
+        }
+        if (lane == 0) sd[k] = rl;
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j <= lane) W[si * LDW + slot(j)] = row[j];
+      }
+      if (lane == 0 && bad) *sflag = 1;
+    }
+    __syncthreads();
+    if (*sflag) break;
+    // 2. rows 16 .. WP - 1 against the diagonal block: l_r L_dd^T = s_r
+    for (int r = 16 + tid; r < WP; r += 256) {
+      const int sr = slot(r);
+      double l[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        double v = W[sr * LDW + slot(k)];
+        for (int j = 0; j < k; ++j) v = fma(-l[j], W[slot(k) * LDW + slot(j)], v);
+        l[k] = v * sd[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) W[sr * LDW + slot(k)] = l[k];
+    }
+    // 3. forward substitution of the panel's right-hand side (wave 0)
+    if (wave == 0) {
+      double yi = (lane < 16) ? sb[slot(lane)] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const double yk = __shfl(yi, k) * sd[k];  // y_k = (b_k - sum_j<k l_kj y_j) / l_kk
+        if (lane == k) yi = yk;
+        if (lane > k && lane < 16) yi = fma(-W[slot(lane) * LDW + slot(k)], yk, yi);
+      }
+      if (lane < 16) {
+        sd[16 + lane] = yi;
+        if (p + lane < nf) y[p + lane] = yi;
+      }
+    }
+    __syncthreads();
+    // the rest of the right-hand side: b_r -= l_r . y_panel
+    for (int r = 16 + tid; r < WP; r += 256) {
+      const int sr = slot(r);
+      double v = sb[sr];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v = fma(-W[sr * LDW + slot(k)], sd[16 + k], v);
+      sb[sr] = v;
+    }
+    // 4. trailing update, tiles I >= J >= 1 of the window: W_IJ -= L_I L_J^T
+    {
+      const int i = lane & 15, kq = lane >> 4;
+      int t = 0;
+      for (int I = 1; I < NBK; ++I)
+        for (int J = 1; J <= I; ++J, ++t) {
+          if ((t & 3) != wave) continue;
+          const int rI = slot(16 * I), rJ = slot(16 * J);
+          d4 acc;
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) acc[jj] = W[(rI + kq + 4 * jj) * LDW + rJ + i];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int kc = slot(4 * kk + kq);
+            const double a = -W[(rI + i) * LDW + kc];
+            const double b = W[(rJ + i) * LDW + kc];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) W[(rI + kq + 4 * jj) * LDW + rJ + i] = acc[jj];
+        }
+    }
+    __syncthreads();
+    // 5. the panel (rows 0 .. WP - 1 relative, its 16 columns) for the backward substitution
+    double* L = lbuf + (size_t)pi * WP * 16;
+    for (int e = tid; e < WP * 16; e += 256) {
+      const int r = e >> 4, k = e & 15;
+      L[e] = (r >= k) ? W[slot(r) * LDW + slot(k)] : 0.0;
+    }
+    __syncthreads();
+    // 6. rows p + WP .. p + WP + 15 enter the window in the panel's slots
+    for (int e = tid; e < 16 * WP; e += 256) {
+      const int a = e / WP, c = e - a * WP;  // entering row a, window column c (global p + 16 + c)
+      const int g = p + WP + a, gc = p + 16 + c;
+      W[slot(a) * LDW + slot(16 + c)] = (g >= gc) ? Aval(g, gc) : 0.0;  // slot of p + WP + a
+    }
+    for (int a = tid; a < 16; a += 256) sb[slot(a)] = (p + WP + a < nf) ? rhs[p + WP + a] : 0.0;
+    __syncthreads();
+  }
+  if (*sflag) {
+    if (tid == 0) *done = 0;
+    return;
+  }
+  // backward substitution L^T x = y, panels in reverse; x over y in place
+  for (int pi = np - 1; pi >= 0; --pi) {
+    const int p = 16 * pi;
+    const double* L = lbuf + (size_t)pi * WP * 16;
+    // t_k = y_k - sum_r l_rk x_(p + r) over the rows below the panel (16 threads per k)
+    {
+      const int k = tid >> 4, q = tid & 15;
+      double part = 0.0;
+      for (int r = 16 + q; r < WP; r += 16) {
+        const int g = p + r;
+        if (g < nf) part = fma(L[r * 16 + k], y[g], part);
+      }
+      for (int o = 8; o > 0; o >>= 1) part += __shfl_xor(part, o);
+      if (q == 0) sd[16 + k] = ((p + k < nf) ? y[p + k] : 0.0) - part;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double ti = (lane < 16) ? sd[16 + lane] : 0.0;
+      const double ri = (lane < 16) ? 1.0 / L[lane * 16 + lane] : 0.0;
+      for (int k = 15; k >= 0; --k) {
+        const double xk = __shfl(ti, k) * __shfl(ri, k);
+        if (lane == k) ti = xk;
+        if (lane < k) ti = fma(-L[k * 16 + lane], xk, ti);
+      }
+      if (lane < 16 && p + lane < nf) y[p + lane] = ti;
+    }
+    __syncthreads();
+  }
+  for (int d = tid; d < dofs; d += 256) {
+    const int r = dofmap[d];
+    if (r >= 0) u[d] += y[r];
+  }
+  if (dud)
+    for (int j = tid; j < nfixed; j += 256) u[fixed[j]] += dud[j];
+  if (tid == 0) {
+    *info = 0;
+    *done = 1;
+  }
+}
+
 inline unsigned nblk(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 void release(rom_fe2* h) {
   if (!h) return;
-  void* bufs[] = {h->X, h->dNdX, h->wJ, h->Xg, h->band, h->rhs, h->ubuf, h->xbuf, h->conn, h->node_ptr,
-                  h->node_ent, h->dofmap, h->fixed, h->top};
+  void* bufs[] = {h->X, h->dNdX, h->wJ, h->Xg, h->band, h->rhs, h->ubuf, h->xbuf, h->lbuf, h->ybuf, h->done,
+                  h->conn, h->node_ptr, h->node_ent, h->dofmap, h->fixed, h->top};
   for (void* b : bufs) (void)hipFree(b);
   delete h;
 }
@@ -909,6 +1120,15 @@ int rom_fe2_create(int32_t nodes, int32_t elements, const double* X_host, const 
                                   (int)solve_lds_bytes(kl, h->stage)) != hipSuccess)
       ok = false;
   }
+  if (kl <= CB_KL_MAX) {
+    const int wp = chol_blk_wp(kl), np = (nfree + 15) / 16;
+    al((void**)&h->lbuf, 8L * np * wp * 16);
+    al((void**)&h->ybuf, 8L * nfree);
+    al((void**)&h->done, 4);
+    if (ok && hipFuncSetAttribute((const void*)k_band_chol_blk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)chol_blk_lds_bytes(kl)) != hipSuccess)
+      ok = false;
+  }
   al((void**)&h->conn, 32L * elements);
   al((void**)&h->node_ptr, 4L * (nodes + 1));
   al((void**)&h->node_ent, 4L * ent.size());
@@ -987,13 +1207,19 @@ int rom_fe2_solve(rom_fe2_handle h, const double* Abar_dev, const double* res_de
   DeviceGuard guard(h->device);
   k_assemble<<<nblk(h->dofs), 256, 0, s>>>(h->dofs, h->kl, h->ldab, h->node_ptr, h->node_ent, h->conn, h->dofmap,
                                            h->dNdX, h->wJ, Abar_dev, res_dev, dud_dev, h->band, h->rhs);
+  // the blocked Cholesky first; where a pivot is not positive (or the band
+  // is too wide for it) the banded solve below factors the same band
+  if (h->lbuf)
+    k_band_chol_blk<<<1, 256, chol_blk_lds_bytes(h->kl), s>>>(h->nfree, h->kl, h->ldab, h->band, h->rhs, h->lbuf,
+                                                             h->ybuf, h->dofs, h->dofmap, h->fixed, h->nfixed,
+                                                             dud_dev, u_dev, info_dev, h->done);
   if (h->stage > 0)
     k_band_solve_lds<<<1, (4 * (2 * h->kl + 2) + 63) / 64 * 64, solve_lds_bytes(h->kl, h->stage), s>>>(
         h->nfree, h->kl, h->ldab, h->stage, h->band, h->rhs, h->ubuf, h->xbuf, h->dofs, h->dofmap, h->fixed,
-        h->nfixed, dud_dev, u_dev, info_dev);
+        h->nfixed, dud_dev, u_dev, info_dev, h->done);
   else
     k_band_solve<<<1, LU_THREADS, 0, s>>>(h->nfree, h->kl, h->ldab, h->band, h->rhs, h->dofs, h->dofmap, h->fixed,
-                                          h->nfixed, dud_dev, u_dev, info_dev);
+                                          h->nfixed, dud_dev, u_dev, info_dev, h->done);
   return hipGetLastError() == hipSuccess ? ROM_OK : ROM_EHIP;
 }
 
