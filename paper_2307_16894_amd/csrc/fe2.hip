@@ -836,6 +836,13 @@ __global__ __launch_bounds__(LDS_THREADS_MAX) void k_band_solve_lds(
 // then factors the same band).
 constexpr int CB_KL_MAX = 112;  // WP <= 128: a 128 x 129 FP64 window, 129 KB of LDS
 
+// value of lane l (uniform), through scalar registers
+__device__ __forceinline__ double lane_d(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, l), hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __host__ __device__ inline int chol_blk_wp(int kl) { return (kl + 16 + 15) / 16 * 16; }
 inline size_t chol_blk_lds_bytes(int kl) {
   const int wp = chol_blk_wp(kl);
@@ -874,6 +881,18 @@ __global__ __launch_bounds__(256) void k_band_chol_blk(int nf, int kl, int ldab,
     const int p = 16 * pi;
     const int s0 = p % WP;  // slot of row p (a multiple of 16: the panel's slots are s0 .. s0 + 15)
     auto slot = [&](int rel) { return (s0 + rel < WP) ? s0 + rel : s0 + rel - WP; };  // rel < WP
+    // the rows that enter the window after this panel, loaded now (stored in step 6)
+    double pre[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      pre[u] = 0.0;
+      if (e < 16 * WP) {
+        const int a = e / WP, c = e - a * WP, g = p + WP + a, gc = p + 16 + c;
+        if (g >= gc) pre[u] = Aval(g, gc);
+      }
+    }
+    const double preb = (tid < 16 && p + WP + tid < nf) ? rhs[p + WP + tid] : 0.0;
     // 1. the diagonal block, one wave: lane i holds row i
     if (wave == 0) {
       double row[16];
@@ -883,7 +902,7 @@ __global__ __launch_bounds__(256) void k_band_chol_blk(int nf, int kl, int ldab,
       bool bad = false;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        const double dkk = __shfl(row[k], k);
+        const double dkk = lane_d(row[k], k);
         if (!(dkk > 0.0) || !isfinite(dkk)) bad = true;
         const double lkk = sqrt(dkk);
         const double rl = 1.0 / lkk;
@@ -892,7 +911,7 @@ __global__ __launch_bounds__(256) void k_band_chol_blk(int nf, int kl, int ldab,
         const double lik = row[k];
 #pragma unroll
         for (int j = k + 1; j < 16; ++j) {
-          const double ljk = __shfl(row[k], j);
+          const double ljk = lane_d(row[k], j);
           if (lane >= j && lane < 16) row[j] = fma(-lik, ljk, row[j]);
         }
         if (lane == 0) sd[k] = rl;
@@ -924,7 +943,7 @@ __global__ __launch_bounds__(256) void k_band_chol_blk(int nf, int kl, int ldab,
       double yi = (lane < 16) ? sb[slot(lane)] : 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        const double yk = __shfl(yi, k) * sd[k];  // y_k = (b_k - sum_j<k l_kj y_j) / l_kk
+        const double yk = lane_d(yi, k) * sd[k];  // y_k = (b_k - sum_j<k l_kj y_j) / l_kk
         if (lane == k) yi = yk;
         if (lane > k && lane < 16) yi = fma(-W[slot(lane) * LDW + slot(k)], yk, yi);
       }
@@ -973,12 +992,15 @@ __global__ __launch_bounds__(256) void k_band_chol_blk(int nf, int kl, int ldab,
     }
     __syncthreads();
     // 6. rows p + WP .. p + WP + 15 enter the window in the panel's slots
-    for (int e = tid; e < 16 * WP; e += 256) {
-      const int a = e / WP, c = e - a * WP;  // entering row a, window column c (global p + 16 + c)
-      const int g = p + WP + a, gc = p + 16 + c;
-      W[slot(a) * LDW + slot(16 + c)] = (g >= gc) ? Aval(g, gc) : 0.0;  // slot of p + WP + a
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      if (e < 16 * WP) {
+        const int a = e / WP, c = e - a * WP;  // entering row a (slot of p + WP + a), window column c
+        W[slot(a) * LDW + slot(16 + c)] = pre[u];
+      }
     }
-    for (int a = tid; a < 16; a += 256) sb[slot(a)] = (p + WP + a < nf) ? rhs[p + WP + a] : 0.0;
+    if (tid < 16) sb[slot(tid)] = preb;
     __syncthreads();
   }
   if (*sflag) {
@@ -1005,7 +1027,7 @@ __global__ __launch_bounds__(256) void k_band_chol_blk(int nf, int kl, int ldab,
       double ti = (lane < 16) ? sd[16 + lane] : 0.0;
       const double ri = (lane < 16) ? 1.0 / L[lane * 16 + lane] : 0.0;
       for (int k = 15; k >= 0; --k) {
-        const double xk = __shfl(ti, k) * __shfl(ri, k);
+        const double xk = lane_d(ti, k) * lane_d(ri, k);
         if (lane == k) ti = xk;
         if (lane < k) ti = fma(-L[k * 16 + lane], xk, ti);
       }
