@@ -33,7 +33,7 @@
 //   FP64  v_mfma_f64_16x16x4f64 (H = D [G | V] on v_mfma_f64_4x4x4f64);
 //   FP32  v_mfma_f32_16x16x4f32 on FP32 operands, FP32 accumulation;
 //   BF16  v_mfma_f32_16x16x32_bf16, eight ECM points per instruction, FP32
-//         accumulation;
+//         accumulation (H on v_mfma_f32_16x16x16_bf16);
 // in the reduced-precision forms f and sum w|J| P are accumulated separately
 // in FP64, so the residual, the stress, the return map and the solve stay
 // FP64 (K, C and sum w|J| A carry the contraction precision).  Small n: the
@@ -273,15 +273,22 @@ __device__ __forceinline__ void make_ops(Ops<T>& O, double (&fpart)[T], bool do_
   const double dv = rq[R_D + 4 * drow + k_row];
   const double dop = (F64 || (c_col & 3) == 0) ? dv : 0.0;
   const double xa = rq[pd.a_off], xw = rq[R_W + k_row], xv0 = rq[pd.v_off0], xv1 = rq[pd.v_off1];
+  // The padding block lies in the last tile (pad_base), so the other tiles
+  // take G alone, resolved at compile time.  The FP64 tile-split kernels keep
+  // the selects at the run-time tile index In (and In + 1, unused): their
+  // code schedule came out faster that way (264 against 286 ms per step on
+  // the n = 100 four-void workload), while the compile-time form is faster
+  // for every other kernel.
+  constexpr bool PADC = !(PREC == PREC_F64 && TW != 1);
 #pragma unroll
   for (int J = 0; J < T; ++J) {
     double g = L.a[J];
     bool wsel = false;
-    if (J == pd.In) {
+    if (PADC ? (J == T - 1) : (J == pd.In)) {
       g = (pd.v_use & 1) ? ((pd.v_zero & 1) ? 0.0 : xv0) : g;
       wsel = pd.w_use & 1;
     }
-    if (J == pd.In + 1) {
+    if (!PADC && J == pd.In + 1) {
       g = (pd.v_use & 2) ? ((pd.v_zero & 2) ? 0.0 : xv1) : g;
       wsel = pd.w_use & 2;
     }
@@ -296,7 +303,7 @@ __device__ __forceinline__ void make_ops(Ops<T>& O, double (&fpart)[T], bool do_
     }
     O.B[J] = wsel ? xw : h;
     double av = L.a[J];
-    if (J == pd.In) av = pd.a_use ? xa : av;
+    if (PADC ? (J == T - 1) : (J == pd.In)) av = pd.a_use ? xa : av;
     O.A[J] = av;
   }
   if constexpr (PREC != PREC_F64) {
@@ -361,13 +368,20 @@ __device__ __forceinline__ void contract_range(typename Acc<PREC>::type* acc, do
 }
 
 // BF16: eight ECM points per instruction; lane group g = k_row holds points
-// 2g, 2g + 1 of the step, inner index k = 8 g + 4 h + b (point 2g + h,
-// component b).  B = D [G | V] is formed in FP32 on the lanes (D is kept as
-// FP32 in the record of this form) and f in FP64 from the FP64 G loads; the
-// loads of one column tile run while the previous tile is formed.
+// g and g + 4 of the step, inner index k = 8 g + 4 h + b (point g + 4 h,
+// component b).  H = D [G | V] of a column tile comes from two
+// v_mfma_f32_16x16x16_bf16, four points each: rows (point, b), inner index
+// (point, c), A = D block-diagonal (lane 16 g + i holds row i mod 4 of the D
+// of its own point where i / 4 = g, else zeros), B = the lane's G (or V) in
+// bf16, so that lane 16 g + c receives column c of H for its own point; f is
+// accumulated in FP64 from the FP64 G loads.  The loads of one column tile
+// run while the previous tile is formed.
 struct G8 {
   double g[2][4];  // [point h][component b] of one column tile
 };
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
 template <int T>
 __device__ __forceinline__ void load_g8(G8& L, const double* __restrict__ Gb, int qs, int J, int qa, int qb,
@@ -375,10 +389,102 @@ __device__ __forceinline__ void load_g8(G8& L, const double* __restrict__ Gb, in
   constexpr int NPAD = 16 * T;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int ql = qs + 2 * k_row + h;
+    const int ql = qs + k_row + 4 * h;
     const double* Gp = Gb + (size_t)(ql < qb ? ql : qa) * 4 * NPAD + 16 * J + c_col;
 #pragma unroll
     for (int b = 0; b < 4; ++b) L.g[h][b] = Gp[b * NPAD];
+  }
+}
+
+// One step of eight points from qs (FULL: all eight below qb, no selects of
+// dead points), the first column tile of the next step prefetched into cur.
+template <int T, int W, int TW, bool FULL>
+__device__ __forceinline__ void bf16_step(f4* acc, double (&fpart)[T], bool do_f, G8& cur, const double* __restrict__ Gb,
+                                          const double* sQ, int qs, int qa, int qb, const Pad& pd, int k_row,
+                                          int c_col) {
+  const int arow = 16 * pd.In + c_col - pd.nb;  // padding-row offset of this lane in tile In
+  const bool apad = arow >= 0 && arow < 4, aodd = arow & 1;
+  const bool dlane = (c_col >> 2) == k_row;  // lanes holding D in the A operand of the H products
+  bf4 Dh[2];
+  float Fm[2][4];
+  double Wv[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ql = qs + k_row + 4 * h;
+    const bool live = FULL || ql < qb;
+    const double* rq = sQ + (live ? ql : qa) * QS;
+    const float* rf = reinterpret_cast<const float*>(rq + R_D) + 4 * (c_col & 3);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Dh[h][k] = (__bf16)((live && dlane) ? rf[k] : 0.0f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Fm[h][k] = live ? (float)rq[R_FM + k] : 0.0f;
+      Wv[h][k] = live ? rq[R_W + k] : 0.0;
+    }
+  }
+  G8 nxt;
+  bf8 Aop[T];
+  int u = 0;
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+    if (J + 1 < T)
+      load_g8<T>(nxt, Gb, qs, J + 1, qa, qb, k_row, c_col);
+    else
+      load_g8<T>(nxt, Gb, min(qs + 8, qb - 1), 0, qa, qb, k_row, c_col);
+    const int col = 16 * J + c_col, dc = col - pd.nb;
+    const bool ecol = dc >= 1 && dc <= 4, wcol = dc == 0;
+    const int ek = (dc - 1) >> 1, el = (dc - 1) & 1;
+    // f partials of every lane (those of the columns n and above are never read)
+    if (do_f) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) fpart[J] = fma(cur.g[h][b], Wv[h][b], fpart[J]);
+    }
+    bf4 Gh[2];  // B operand of the H products
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float g[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) g[c] = (float)cur.g[h][c];
+      if (J < T - 1) {
+        // tiles left of the padding block (resolved at compile time): G in
+        // both operands
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Gh[h][c] = (__bf16)g[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          // V[c][(ek, el)] for c = (k', s): F_mu[el][s] when k' = ek
+          const float fv = el ? Fm[h][2 + (c & 1)] : Fm[h][c & 1];
+          Gh[h][c] = (__bf16)(ecol ? (((c >> 1) == ek) ? fv : 0.0f) : g[c]);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          float av = g[b];
+          if (apad)  // the last tile is the tile row of the padding block
+            av = ((arow >> 1) == (b >> 1)) ? (aodd ? Fm[h][2 + (b & 1)] : Fm[h][b & 1]) : 0.0f;
+          Aop[J][4 * h + b] = (__bf16)av;
+        }
+      }
+    }
+    if (J < T - 1) Aop[J] = __builtin_shufflevector(Gh[0], Gh[1], 0, 1, 2, 3, 4, 5, 6, 7);
+    if (owns<T, W, TW>(J)) {
+      bf8 Bop;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f4 Hv = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, Dh[h]), __builtin_bit_cast(s4, Gh[h]),
+                                                               (f4){0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Bop[4 * h + b] = (__bf16)((J == T - 1 && wcol) ? (float)Wv[h][b] : Hv[b]);
+      }
+#pragma unroll
+      for (int I = 0; I <= J; ++I) {
+        acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[I], Bop, acc[u], 0, 0, 0);
+        ++u;
+      }
+    }
+    cur = nxt;
   }
 }
 
@@ -389,97 +495,11 @@ __device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T],
   constexpr int NPAD = 16 * T;
   if (qa >= qb) return;
   const double* Gb = Gq + (size_t)q0 * 4 * NPAD;
-  const int arow = 16 * pd.In + c_col - pd.nb;  // padding-row offset of this lane in tile In
-  const bool apad = arow >= 0 && arow < 4, aodd = arow & 1;
-  // E columns: B = D V with V[(k', s)][(k, l)] = delta(k', k) F_mu[l][s] in place of G
-  G8 cur, nxt;
+  G8 cur;
   load_g8<T>(cur, Gb, qa, 0, qa, qb, k_row, c_col);
-  for (int qs = qa; qs < qb; qs += 8) {
-    float D[2][16], Fm[2][4];
-    double Wv[2][4];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int ql = qs + 2 * k_row + h;
-      const bool live = ql < qb;
-      const double* rq = sQ + (live ? ql : qa) * QS;
-      const float* rf = reinterpret_cast<const float*>(rq + R_D);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) D[h][k] = live ? rf[k] : 0.0f;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        Fm[h][k] = live ? (float)rq[R_FM + k] : 0.0f;
-        Wv[h][k] = live ? rq[R_W + k] : 0.0;
-      }
-    }
-    bf8 Aop[T];
-    int u = 0;
-#pragma unroll
-    for (int J = 0; J < T; ++J) {
-      if (J + 1 < T)
-        load_g8<T>(nxt, Gb, qs, J + 1, qa, qb, k_row, c_col);
-      else
-        load_g8<T>(nxt, Gb, min(qs + 8, qb - 1), 0, qa, qb, k_row, c_col);
-      const int col = 16 * J + c_col, dc = col - pd.nb;
-      const bool ecol = dc >= 1 && dc <= 4, wcol = dc == 0;
-      const int ek = (dc - 1) >> 1, el = (dc - 1) & 1;
-      // f partials of every lane (those of the columns n and above are never read)
-      if (do_f) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) fpart[J] = fma(cur.g[h][b], Wv[h][b], fpart[J]);
-      }
-      bf8 Bop;
-      if (J < T - 1) {
-        // tiles left of the padding block (resolved at compile time): G in
-        // both operands, the same arithmetic as below without the selects
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          float g[4];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) g[c] = (float)cur.g[h][c];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const float hv = D[h][4 * b] * g[0] + D[h][4 * b + 1] * g[1] + D[h][4 * b + 2] * g[2] + D[h][4 * b + 3] * g[3];
-            Aop[J][4 * h + b] = (__bf16)g[b];
-            Bop[4 * h + b] = (__bf16)hv;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          float g[4];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) g[c] = (float)cur.g[h][c];
-          float gb[4];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            // V[c][(ek, el)] for c = (k', s): F_mu[el][s] when k' = ek
-            const float fv = el ? Fm[h][2 + (c & 1)] : Fm[h][c & 1];
-            gb[c] = ecol ? (((c >> 1) == ek) ? fv : 0.0f) : g[c];
-          }
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            float av = g[b];
-            if (apad)  // this branch is the last tile, the tile row of the padding block
-              av = ((arow >> 1) == (b >> 1)) ? (aodd ? Fm[h][2 + (b & 1)] : Fm[h][b & 1]) : 0.0f;
-            float hv = D[h][4 * b] * gb[0] + D[h][4 * b + 1] * gb[1] + D[h][4 * b + 2] * gb[2] + D[h][4 * b + 3] * gb[3];
-            if (wcol) hv = (float)Wv[h][b];
-            Aop[J][4 * h + b] = (__bf16)av;
-            Bop[4 * h + b] = (__bf16)hv;
-          }
-        }
-      }
-      if (owns<T, W, TW>(J)) {
-#pragma unroll
-        for (int I = 0; I <= J; ++I) {
-          acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[I], Bop, acc[u], 0, 0, 0);
-          ++u;
-        }
-      }
-      cur = nxt;
-    }
-  }
+  int qs = qa;
+  for (; qs + 8 <= qb; qs += 8) bf16_step<T, W, TW, true>(acc, fpart, do_f, cur, Gb, sQ, qs, qa, qb, pd, k_row, c_col);
+  if (qs < qb) bf16_step<T, W, TW, false>(acc, fpart, do_f, cur, Gb, sQ, qs, qa, qb, pd, k_row, c_col);
 }
 
 template <int T, int PREC, int W, int TW>
