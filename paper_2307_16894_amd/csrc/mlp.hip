@@ -65,56 +65,61 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 
 // C[M][N] (ldc) = sum_k A(m, k) B(k, n) (+ bias[n]); A(m, k) = A[m * sa0 + k * sa1],
 // B(k, n) = B[k * sb0 + n * sb1], one of sa0 / sa1 and one of sb0 / sb1 equal
-// to 1 (row-major or transposed operands).  Workgroup tile 64 x 64, wave tile
-// 32 x 32 (2 x 2 MFMA tiles of 16 x 16); per step of 32 inner indices the two
-// operand tiles are loaded into LDS with eight contiguous elements per thread
-// along whichever index is contiguous in memory, A as [m][k] and B as [n][k],
-// so that each lane's MFMA operand is one LDS read.  Out-of-range operands
-// read as zero.  The MFMA operands sit in the lanes and the inner index runs
-// in the order of the per-lane global form this replaced (BF16: k = k0 + 8 g
-// + t; FP32: k = k0 + 4 s + g), so the products are the same bit for bit.
-// With gridDim.z > 1 workgroup z sums k in [z kchunk, (z + 1) kchunk) only and
-// writes its product to C + z cstride (kchunk a multiple of 32).
-constexpr int GM_T = 64, GM_K = 32;
+// to 1 (row-major or transposed operands).  Workgroup tile TM x TM (64: wave
+// tile 32 x 32 of 2 x 2 MFMA tiles of 16 x 16; 32: one 16 x 16 MFMA tile per
+// wave, four times the workgroups for the small grids of the training
+// products); per step of 32 inner indices the two operand tiles are loaded
+// into LDS with TM / 8 contiguous elements per thread along whichever index is
+// contiguous in memory, A as [m][k] and B as [n][k], so that each lane's MFMA
+// operand is one LDS read.  Out-of-range operands read as zero.  The MFMA
+// operands sit in the lanes and the inner index runs in the order of the
+// per-lane global form this replaced (BF16: k = k0 + 8 g + t; FP32:
+// k = k0 + 4 s + g), whatever the tile, so the products are the same bit for
+// bit.  With gridDim.z > 1 workgroup z sums k in [z kchunk, (z + 1) kchunk)
+// only and writes its product to C + z cstride (kchunk a multiple of 32).
+constexpr int GM_K = 32;
 
-template <bool BF16>
+template <bool BF16, int TM>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* __restrict__ Av, long sa0, long sa1,
                                               const void* __restrict__ Bv, long sb0, long sb1, float* __restrict__ C,
                                               long ldc, const float* __restrict__ bias, int kchunk, long cstride) {
   using E = typename std::conditional<BF16, uint16_t, float>::type;
   constexpr int LDK = GM_K + (BF16 ? 8 : 4);  // padded row (16 bytes)
-  __shared__ __attribute__((aligned(16))) E sA[GM_T * LDK];
-  __shared__ __attribute__((aligned(16))) E sB[GM_T * LDK];
+  constexpr int TW = TM / 32;                 // MFMA tiles per wave and dimension
+  constexpr int EL = TM / 8;                  // elements loaded per thread and operand
+  __shared__ __attribute__((aligned(16))) E sA[TM * LDK];
+  __shared__ __attribute__((aligned(16))) E sB[TM * LDK];
   const E* A = static_cast<const E*>(Av);
   const E* B = static_cast<const E*>(Bv);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   C += blockIdx.z * cstride;
   const int g = lane >> 4, c = lane & 15;
-  const int mt = blockIdx.y * GM_T, nt = blockIdx.x * GM_T;
-  const int mw = (wave >> 1) * 32, nw = (wave & 1) * 32;
-  f4 acc[2][2];
+  const int mt = blockIdx.y * TM, nt = blockIdx.x * TM;
+  const int mw = (wave >> 1) * 16 * TW, nw = (wave & 1) * 16 * TW;
+  f4 acc[TW][TW];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
-  // thread t loads 8 contiguous elements: along k (row r = t / 4, k = 8 (t % 4))
-  // or along m / n (k = t / 8, row 8 (t % 8))
+    for (int j = 0; j < TW; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
+  // thread t loads EL contiguous elements: along k (row r = t / (32 / EL),
+  // k = EL (t % (32 / EL))) or along m / n (k = t / (TM / EL), row EL (t % (TM / EL)))
   const bool a_k = (sa1 == 1), b_k = (sb0 == 1);
+  constexpr int KG = GM_K / EL, RG = TM / EL;
   for (int k0 = kb; k0 < ke; k0 += GM_K) {
     {
-      const int r = a_k ? tid >> 2 : 8 * (tid & 7), kk = a_k ? 8 * (tid & 3) : tid >> 3;
+      const int r = a_k ? tid / KG : EL * (tid % RG), kk = a_k ? EL * (tid % KG) : tid / RG;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < EL; ++e) {
         const int rr = a_k ? r : r + e, ki = a_k ? kk + e : kk;
         const int m = mt + rr, k = k0 + ki;
         sA[rr * LDK + ki] = (m < M && k < ke) ? A[m * sa0 + k * sa1] : (E)0;
       }
     }
     {
-      const int r = b_k ? tid >> 2 : 8 * (tid & 7), kk = b_k ? 8 * (tid & 3) : tid >> 3;
+      const int r = b_k ? tid / KG : EL * (tid % RG), kk = b_k ? EL * (tid % KG) : tid / RG;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < EL; ++e) {
         const int rr = b_k ? r : r + e, ki = b_k ? kk + e : kk;
         const int n = nt + rr, k = k0 + ki;
         sB[rr * LDK + ki] = (n < N && k < ke) ? B[k * sb0 + n * sb1] : (E)0;
@@ -122,36 +127,36 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const void* _
     }
     __syncthreads();
     if constexpr (BF16) {
-      bf8 a[2], b[2];
+      bf8 a[TW], b[TW];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf8*>(sA + (mw + 16 * i + c) * LDK + 8 * g);
+      for (int i = 0; i < TW; ++i) a[i] = *reinterpret_cast<const bf8*>(sA + (mw + 16 * i + c) * LDK + 8 * g);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf8*>(sB + (nw + 16 * j + c) * LDK + 8 * g);
+      for (int j = 0; j < TW; ++j) b[j] = *reinterpret_cast<const bf8*>(sB + (nw + 16 * j + c) * LDK + 8 * g);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TW; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < TW; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     } else {
 #pragma unroll
       for (int st = 0; st < GM_K / 4; ++st) {
-        float a[2], b[2];
+        float a[TW], b[TW];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = sA[(mw + 16 * i + c) * LDK + 4 * st + g];
+        for (int i = 0; i < TW; ++i) a[i] = sA[(mw + 16 * i + c) * LDK + 4 * st + g];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = sB[(nw + 16 * j + c) * LDK + 4 * st + g];
+        for (int j = 0; j < TW; ++j) b[j] = sB[(nw + 16 * j + c) * LDK + 4 * st + g];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TW; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < TW; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     }
     __syncthreads();
   }
   // accumulator layout of the 16 x 16 f32-output MFMAs: row 4 g + r, column c
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TW; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = mt + mw + 16 * i + 4 * g + r, n = nt + nw + 16 * j + c;
@@ -432,11 +437,19 @@ __global__ void k_to_bf16(long count, const float* __restrict__ P, uint16_t* __r
 
 inline unsigned nblk(long count, int bs = 256) { return (unsigned)((count + bs - 1) / bs); }
 
+// output tile: 64 x 64 while that fills the compute units, else 32 x 32
+inline bool gemm_small_tiles(int M, int N) { return (long)((N + 63) / 64) * ((M + 63) / 64) < 256; }
+
 template <bool BF16>
 void gemm(int M, int N, int K, const void* A, long sa0, long sa1, const void* B, long sb0, long sb1, float* C,
           long ldc, const float* bias, hipStream_t s) {
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
-  k_gemm<BF16><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, C, ldc, bias, K + 31, 0);
+  if (gemm_small_tiles(M, N)) {
+    dim3 grid((N + 31) / 32, (M + 31) / 32);
+    k_gemm<BF16, 32><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, C, ldc, bias, K + 31, 0);
+  } else {
+    dim3 grid((N + 63) / 64, (M + 63) / 64);
+    k_gemm<BF16, 64><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, C, ldc, bias, K + 31, 0);
+  }
 }
 
 // C[M][N] (dense, ldc = N, no bias) with a long inner dimension: the grid of
@@ -444,7 +457,9 @@ void gemm(int M, int N, int K, const void* A, long sa0, long sa1, const void* B,
 // products land in kpart and are then added in slice order
 void gemm_split(rom_mlp* m, int M, int N, int K, const float* A, long sa0, long sa1, const float* B, long sb0,
                 long sb1, float* C, hipStream_t s) {
-  const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
+  const bool small = gemm_small_tiles(M, N);
+  const int TM = small ? 32 : 64;
+  const int tiles = ((N + TM - 1) / TM) * ((M + TM - 1) / TM);
   int S = (256 + tiles - 1) / tiles;
   S = S < K / 128 ? S : K / 128;
   S = S < MLP_KSPLIT ? S : MLP_KSPLIT;
@@ -454,8 +469,11 @@ void gemm_split(rom_mlp* m, int M, int N, int K, const float* A, long sa0, long 
   }
   const int kchunk = ((K + S - 1) / S + 31) / 32 * 32;
   S = (K + kchunk - 1) / kchunk;
-  dim3 grid((N + 63) / 64, (M + 63) / 64, S);
-  k_gemm<false><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, m->kpart, N, nullptr, kchunk, (long)M * N);
+  dim3 grid((N + TM - 1) / TM, (M + TM - 1) / TM, S);
+  if (small)
+    k_gemm<false, 32><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, m->kpart, N, nullptr, kchunk, (long)M * N);
+  else
+    k_gemm<false, 64><<<grid, 256, 0, s>>>(M, N, K, A, sa0, sa1, B, sb0, sb1, m->kpart, N, nullptr, kchunk, (long)M * N);
   k_sum_slices<<<nblk((long)M * N), 256, 0, s>>>((long)M * N, S, (long)M * N, m->kpart, C);
 }
 
