@@ -546,12 +546,12 @@ def main(argv=None):
         variants=out_var,
         warm_start=r['warm_start'],
         # the plain FP64 step against the FP64 peak (its kernels: the fused
-        # kernel, or the phased step's material, contraction and finishing
-        # launches on both streams); algorithmic flops per point-evaluation as
-        # in flops_per_eval
+        # kernel, or the phased step's kinematics, material, contraction,
+        # solve and finishing launches on both streams); algorithmic flops
+        # per point-evaluation as in flops_per_eval
         roofline=dict(bound="mfma",
                       kernel=("k_fused<fp64>" if rf_form == 'fused' else
-                              "phased step <fp64>: k_ph_mat + k_ph_cs + k_fused_queue"),
+                              "phased step <fp64>: k_ph_kin + k_ph_mat + k_ph_cs + k_ph_s + k_fused_queue"),
                       achieved=achieved, peak=PEAK['f64'],
                       unit="TFLOP/s", frac=achieved / PEAK['f64'],
                       traffic=measured_traffic(a.workload, rf_form),
