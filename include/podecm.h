@@ -96,13 +96,15 @@ typedef struct rom_opts {
                            (the material-model appendix: the global Newton solve may need much smaller load steps).
                            The point fails when a stride of 1 / 2^D fails; its committed state is then the last
                            converged sub-step.  iters counts the evaluations of all attempts. */
-  int32_t phased_evals; /* phased form: evaluations made by the phased launches (0: 6, at most max_iter); the
-                           rest of the step runs in the fused kernel, and so does an attempt that fails with
-                           load-step cutting on (from its start) */
+  int32_t phased_evals; /* phased form: evaluations made by the phased launches (0: 6, or 4 with the learned
+                           warm start, which needs fewer; at most max_iter); the rest of the step runs in the
+                           fused kernel, and so does an attempt that fails with load-step cutting on (from its
+                           start) */
   int32_t phased_early; /* phased form: after this many evaluations the points whose ||f|| stayed above 0.3 of
                            the previous evaluation's (slow convergence: likely to fail the plain step and be cut
                            into sub-steps) go to a fused kernel on a side stream, beside the remaining phased
-                           evaluations (0: 3; -1: none; used when below phased_evals) */
+                           evaluations (0: 3, or none with the learned warm start; -1: none; used when below
+                           phased_evals) */
   int32_t abar_f64;     /* FP32 / BF16 contraction, fused and phased forms: 1 forms Abar (and the K*^-1 C kept for
                            the shape sensitivities) at the converged points from one more evaluation at the
                            returned state with the FP64 contraction, so that K* is the FP64 K there (Sec. 3.3);
