@@ -47,7 +47,7 @@ ROMS['coatvoid_n20_m120'] = dict(ROMS['onevoid_n20_m120'], coating=0.06, mat2=(1
 # four elliptical voids of fixed area 0.075 each (porosity 0.3), parent circles
 # of equal area; mu = (kappa_i, theta_i) per void; ~30k T6.  The three ROMs
 # share mesh and training data (so they can share a snapshot cache).
-_FOUR = dict(kind=1, r0=float(np.sqrt(0.075 / np.pi)), void_area=0.075, nt=32, nr=29, n_mu=8, per_mu=2,
+_FOUR = dict(kind=1, r0=float(np.sqrt(0.075 / np.pi)), void_area=0.075, nt=32, nr=29, n_mu=16, per_mu=3,
              path='cyclic', steps=20, rho=(0.02, 0.08), seed=3000, eps=1e-4)
 ROMS['fourvoid_n100_m1500'] = dict(_FOUR, n=100, L=16, m=1500)
 ROMS['fourvoid_n60_m800'] = dict(_FOUR, n=60, L=15, m=800)

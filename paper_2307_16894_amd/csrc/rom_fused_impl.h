@@ -367,15 +367,19 @@ __device__ __forceinline__ void contract_range(typename Acc<PREC>::type* acc, do
   }
 }
 
-// BF16: eight ECM points per instruction; lane group g = k_row holds points
-// g and g + 4 of the step, inner index k = 8 g + 4 h + b (point g + 4 h,
-// component b).  H = D [G | V] of a column tile comes from two
+// BF16: eight ECM points per instruction.  Up to four column tiles lane
+// group g = k_row holds points g and g + 4 of the step, inner index
+// k = 8 g + 4 h + b (point g + 4 h, component b), and H = D [G | V] of a
+// column tile comes from two
 // v_mfma_f32_16x16x16_bf16, four points each: rows (point, b), inner index
 // (point, c), A = D block-diagonal (lane 16 g + i holds row i mod 4 of the D
 // of its own point where i / 4 = g, else zeros), B = the lane's G (or V) in
 // bf16, so that lane 16 g + c receives column c of H for its own point; f is
-// accumulated in FP64 from the FP64 G loads.  The loads of one column tile
-// run while the previous tile is formed.
+// accumulated in FP64 from the FP64 G loads.  Wider, lane group g holds
+// points 2 g and 2 g + 1 (k = 8 g + 4 h + b for point 2 g + h) and each lane
+// forms its column of H in FP32 with fma from the FP32 D and G (the H
+// product measured slower there: 114 against 113 ms per step at n = 100).
+// The loads of one column tile run while the previous tile is formed.
 struct G8 {
   double g[2][4];  // [point h][component b] of one column tile
 };
@@ -383,13 +387,15 @@ struct G8 {
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
-template <int T>
+// G of the lane's two points in one column tile (HM: the points g and g + 4
+// of the H-product form, else 2 g and 2 g + 1)
+template <int T, bool HM>
 __device__ __forceinline__ void load_g8(G8& L, const double* __restrict__ Gb, int qs, int J, int qa, int qb,
                                         int k_row, int c_col) {
   constexpr int NPAD = 16 * T;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int ql = qs + k_row + 4 * h;
+    const int ql = HM ? qs + k_row + 4 * h : qs + 2 * k_row + h;
     const double* Gp = Gb + (size_t)(ql < qb ? ql : qa) * 4 * NPAD + 16 * J + c_col;
 #pragma unroll
     for (int b = 0; b < 4; ++b) L.g[h][b] = Gp[b * NPAD];
@@ -428,9 +434,9 @@ __device__ __forceinline__ void bf16_step(f4* acc, double (&fpart)[T], bool do_f
 #pragma unroll
   for (int J = 0; J < T; ++J) {
     if (J + 1 < T)
-      load_g8<T>(nxt, Gb, qs, J + 1, qa, qb, k_row, c_col);
+      load_g8<T, true>(nxt, Gb, qs, J + 1, qa, qb, k_row, c_col);
     else
-      load_g8<T>(nxt, Gb, min(qs + 8, qb - 1), 0, qa, qb, k_row, c_col);
+      load_g8<T, true>(nxt, Gb, min(qs + 8, qb - 1), 0, qa, qb, k_row, c_col);
     const int col = 16 * J + c_col, dc = col - pd.nb;
     const bool ecol = dc >= 1 && dc <= 4, wcol = dc == 0;
     const int ek = (dc - 1) >> 1, el = (dc - 1) & 1;
@@ -489,25 +495,128 @@ __device__ __forceinline__ void bf16_step(f4* acc, double (&fpart)[T], bool do_f
 }
 
 template <int T, int W, int TW>
-__device__ __forceinline__ void contract_range_bf16(f4* acc, double (&fpart)[T], bool do_f,
+__device__ __forceinline__ void contract_range_bf16_mfma(f4* acc, double (&fpart)[T], bool do_f,
                                                     const double* __restrict__ Gq, const double* sQ, int q0, int qa,
                                                     int qb, const Pad& pd, int n, int k_row, int c_col) {
   constexpr int NPAD = 16 * T;
   if (qa >= qb) return;
   const double* Gb = Gq + (size_t)q0 * 4 * NPAD;
   G8 cur;
-  load_g8<T>(cur, Gb, qa, 0, qa, qb, k_row, c_col);
+  load_g8<T, true>(cur, Gb, qa, 0, qa, qb, k_row, c_col);
   int qs = qa;
   for (; qs + 8 <= qb; qs += 8) bf16_step<T, W, TW, true>(acc, fpart, do_f, cur, Gb, sQ, qs, qa, qb, pd, k_row, c_col);
   if (qs < qb) bf16_step<T, W, TW, false>(acc, fpart, do_f, cur, Gb, sQ, qs, qa, qb, pd, k_row, c_col);
 }
 
+template <int T, int W, int TW>
+__device__ __forceinline__ void contract_range_bf16_valu(f4* acc, double (&fpart)[T], bool do_f,
+                                                    const double* __restrict__ Gq, const double* sQ, int q0, int qa,
+                                                    int qb, const Pad& pd, int n, int k_row, int c_col) {
+  constexpr int NPAD = 16 * T;
+  if (qa >= qb) return;
+  const double* Gb = Gq + (size_t)q0 * 4 * NPAD;
+  const int arow = 16 * pd.In + c_col - pd.nb;  // padding-row offset of this lane in tile In
+  const bool apad = arow >= 0 && arow < 4, aodd = arow & 1;
+  // E columns: B = D V with V[(k', s)][(k, l)] = delta(k', k) F_mu[l][s] in place of G
+  G8 cur, nxt;
+  load_g8<T, false>(cur, Gb, qa, 0, qa, qb, k_row, c_col);
+  for (int qs = qa; qs < qb; qs += 8) {
+    float D[2][16], Fm[2][4];
+    double Wv[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int ql = qs + 2 * k_row + h;
+      const bool live = ql < qb;
+      const double* rq = sQ + (live ? ql : qa) * QS;
+      const float* rf = reinterpret_cast<const float*>(rq + R_D);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) D[h][k] = live ? rf[k] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Fm[h][k] = live ? (float)rq[R_FM + k] : 0.0f;
+        Wv[h][k] = live ? rq[R_W + k] : 0.0;
+      }
+    }
+    bf8 Aop[T];
+    int u = 0;
+#pragma unroll
+    for (int J = 0; J < T; ++J) {
+      if (J + 1 < T)
+        load_g8<T, false>(nxt, Gb, qs, J + 1, qa, qb, k_row, c_col);
+      else
+        load_g8<T, false>(nxt, Gb, min(qs + 8, qb - 1), 0, qa, qb, k_row, c_col);
+      const int col = 16 * J + c_col, dc = col - pd.nb;
+      const bool ecol = dc >= 1 && dc <= 4, wcol = dc == 0;
+      const int ek = (dc - 1) >> 1, el = (dc - 1) & 1;
+      // f partials of every lane (those of the columns n and above are never read)
+      if (do_f) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) fpart[J] = fma(cur.g[h][b], Wv[h][b], fpart[J]);
+      }
+      bf8 Bop;
+      if (J < T - 1) {
+        // tiles left of the padding block (resolved at compile time): G in
+        // both operands, the same arithmetic as below without the selects
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          float g[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) g[c] = (float)cur.g[h][c];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const float hv = D[h][4 * b] * g[0] + D[h][4 * b + 1] * g[1] + D[h][4 * b + 2] * g[2] + D[h][4 * b + 3] * g[3];
+            Aop[J][4 * h + b] = (__bf16)g[b];
+            Bop[4 * h + b] = (__bf16)hv;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          float g[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) g[c] = (float)cur.g[h][c];
+          float gb[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            // V[c][(ek, el)] for c = (k', s): F_mu[el][s] when k' = ek
+            const float fv = el ? Fm[h][2 + (c & 1)] : Fm[h][c & 1];
+            gb[c] = ecol ? (((c >> 1) == ek) ? fv : 0.0f) : g[c];
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            float av = g[b];
+            if (apad)  // this branch is the last tile, the tile row of the padding block
+              av = ((arow >> 1) == (b >> 1)) ? (aodd ? Fm[h][2 + (b & 1)] : Fm[h][b & 1]) : 0.0f;
+            float hv = D[h][4 * b] * gb[0] + D[h][4 * b + 1] * gb[1] + D[h][4 * b + 2] * gb[2] + D[h][4 * b + 3] * gb[3];
+            if (wcol) hv = (float)Wv[h][b];
+            Aop[J][4 * h + b] = (__bf16)av;
+            Bop[4 * h + b] = (__bf16)hv;
+          }
+        }
+      }
+      if (owns<T, W, TW>(J)) {
+#pragma unroll
+        for (int I = 0; I <= J; ++I) {
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[I], Bop, acc[u], 0, 0, 0);
+          ++u;
+        }
+      }
+      cur = nxt;
+    }
+  }
+}
+
+
 template <int T, int PREC, int W, int TW>
 __device__ __forceinline__ void contract_any(typename Acc<PREC>::type* acc, double (&fpart)[T], bool do_f,
                                              const double* __restrict__ Gq, const double* sQ, int q0, int qa, int qb,
                                              const Pad& pd, int n, int k_row, int c_col) {
-  if constexpr (PREC == PREC_BF16)
-    contract_range_bf16<T, W, TW>(acc, fpart, do_f, Gq, sQ, q0, qa, qb, pd, n, k_row, c_col);
+  if constexpr (PREC == PREC_BF16 && T <= 4)
+    contract_range_bf16_mfma<T, W, TW>(acc, fpart, do_f, Gq, sQ, q0, qa, qb, pd, n, k_row, c_col);
+  else if constexpr (PREC == PREC_BF16)
+    contract_range_bf16_valu<T, W, TW>(acc, fpart, do_f, Gq, sQ, q0, qa, qb, pd, n, k_row, c_col);
   else
     contract_range<T, PREC, W, TW>(acc, fpart, do_f, Gq, sQ, q0, qa, qb, pd, n, k_row, c_col);
 }

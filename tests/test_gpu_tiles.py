@@ -106,13 +106,16 @@ def test_reduced_precision_contraction(gpu, roms, case, prec):
     """n = 120 (the widest) and n = 28, 44, 45, 60, 63 (padding at the next
     tile boundary): the BF16 / FP32 contraction (point split, FP32
     accumulators) solved to 1e-8 like the oracle; effective stress within
-    1e-5."""
+    1e-5.  Where the FP64 oracle's plain Newton step fails (the n = 120 ROM,
+    point 0, second step: the residual grows from 4e-3 to 1.2e-2 over the 15
+    evaluations) the reduced-precision step must fail too."""
     path = roms[CASES[case]]
     n = artifact.read(path)['n']
     seed = 70 + case
     mu, paths = inputs(seed)
     refs = oracle_run(path, seed, False, 15)
     rb = RomBatch(path, mu)
+    converged = 0
     for k in range(K):
         print(f"[gpu] tiles n={n} precision {prec} step {k}", flush=True)
         st, it, _ = rb.step(torch.from_numpy(np.ascontiguousarray(paths[:, k])).cuda(),
@@ -120,6 +123,11 @@ def test_reduced_precision_contraction(gpu, roms, case, prec):
         torch.cuda.synchronize()
         st, Pb = st.cpu().numpy(), rb.Pbar.cpu().numpy()
         for p in range(P):
-            assert st[p] == 0 and refs[p][k]['status'] == 0, (p, k)
+            if refs[p][k]['status'] != 0:
+                assert st[p] != 0, (p, k)
+                continue
+            converged += 1
+            assert st[p] == 0, (p, k)
             assert rel(Pb[p], refs[p][k]['Pbar']) < 1e-5, (p, k, rel(Pb[p], refs[p][k]['Pbar']))
     rb.close()
+    assert converged >= P * K - 1
