@@ -182,7 +182,10 @@ def test_warm_start_gain_and_fallback(gpu):
     mu = workloads.one_void_mu(22, Pte)
     paths = workloads.monotone_paths(22, Pte, K)
     res = {}
-    for name, opts in (('plain', L.rom_default_opts(mode=L.MODE_FUSED)), ('mlp', ws.opts())):
+    # the phased form with its warm-start defaults (four phased evaluations,
+    # then the fused kernel; no early hand-over) gives the fused results bit for bit
+    for name, opts in (('plain', L.rom_default_opts(mode=L.MODE_FUSED)), ('mlp', ws.opts()),
+                       ('mlp_phased', ws.opts(mode=L.MODE_PHASED))):
         rb = RomBatch(rom_path(NAME), mu)
         its, Pb, st = [], [], []
         for k in range(K):
@@ -195,6 +198,8 @@ def test_warm_start_gain_and_fallback(gpu):
         res[name] = (np.array(its), np.array(st), np.array(Pb))
     ip, sp, Pp = res['plain']
     im, sm, Pm = res['mlp']
+    for a, b in zip(res['mlp_phased'], res['mlp']):
+        assert np.array_equal(a, b)
     assert (sp == 0).all() and np.isin(sm, [0, 3]).all()
     assert np.abs(Pm - Pp).max() < 1e-6 * np.abs(Pp).max()
     print(f"mean Newton evaluations: plain {ip.mean():.3f}, learned warm start {im.mean():.3f}, "
